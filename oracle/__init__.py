@@ -1,0 +1,2 @@
+"""CPU oracle of the PPL hot path (test infrastructure only; see ppl_oracle.py)."""
+from .ppl_oracle import *  # noqa: F401,F403

@@ -1,0 +1,240 @@
+"""Plain FP64 CPU oracle of the particle-particle ladder (PPL) hot path.
+
+TEST INFRASTRUCTURE. Only tests/, __graft_entry__.smoke() and the cpu_baseline
+leg of bench.py may import or call anything in this package. The product
+(paper_2603_20912_amd and its HIP library) never imports it and shares no code
+with it: every quantity here is written straight from its definition in the
+paper (Sec. 2, eqs. (ppl-term), (cholesky), (vfunction-chol)) in NumPy float64,
+with no packing, blocking over summation indices or precision tricks.
+
+Conventions (readings of the paper, all stated in the design doc as well):
+  * L[P, p, q], P = 0..naux-1, over all n = o + v orbitals, occupied first.
+  * Chemist's notation: the physicist's <ab|cd> of eq. (ppl-term) is (ac|bd),
+    and eq. (cholesky) builds it as (ac|bd) = sum_P L^P_ac L^P_bd.
+  * Amplitudes and results are t[i][j][a][b] = t_ij^ab (C-contiguous).
+  * The ladder term enters the spin-free closed-shell vector function with
+    coefficient +1 (eq. (vfunction-chol)):
+        R_ij^ab = sum_{c,d} (ac|bd) t_ij^cd.
+  * V_ij^ab = (ia|jb) from the occupied-virtual block of the same L,
+    D_ij^ab = e_i + e_j - e_a - e_b, MP2 start t = V / D.
+  * Linearized doubles (Jacobi) iteration t <- (V + PPL(t)) / D, residual
+    r = ||t_new - t||_F over the full o*o*v*v tensor (absolute, FP64).
+  * Correlation energy E = sum_{ijab} V_ij^ab (2 t_ij^ab - t_ij^ba).
+
+Parity pins of every function live in tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
+    "ppl_sampled", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
+    "jacobi", "fixed_point", "spectral_radius", "nominal_flops",
+]
+
+
+# ---------------------------------------------------------------------------
+# integrals (eq. (cholesky))
+# ---------------------------------------------------------------------------
+def vv_block(L: np.ndarray, o: int) -> np.ndarray:
+    """Virtual-virtual block L[P, o+a, o+c] of the Cholesky vectors."""
+    return L[:, o:, o:]
+
+
+def ov_block(L: np.ndarray, o: int) -> np.ndarray:
+    """Occupied-virtual block L[P, i, o+a] of the Cholesky vectors."""
+    return L[:, :o, o:]
+
+
+def eri_vvvv_for_a(Lvv: np.ndarray, a: int) -> np.ndarray:
+    """W[c, b, d] = (ac|bd) = sum_P L^P_ac L^P_bd for one fixed virtual a (eq. (cholesky)).
+
+    Lvv is the C-contiguous virtual block [P][a][c].
+    """
+    naux, v, _ = Lvv.shape
+    W = Lvv[:, a, :].T @ Lvv.reshape(naux, v * v)        # [c][(b,d)]
+    return W.reshape(v, v, v)
+
+
+# ---------------------------------------------------------------------------
+# the ladder term (eqs. (ppl-term), (vfunction-chol))
+# ---------------------------------------------------------------------------
+def ppl(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
+    """R_ij^ab = sum_cd (ac|bd) t_ij^cd, evaluated one virtual a at a time.
+
+    For each a the integrals (ac|bd) are first summed over P (eq. (cholesky)),
+    then contracted over (c, d) with the amplitudes (eq. (vfunction-chol)).
+    The loop over a only bounds host memory; it touches no summation.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    v = L.shape[1] - o
+    oo = t.shape[0]
+    assert t.shape == (oo, oo, v, v)
+    Lvv = np.ascontiguousarray(vv_block(L, o))
+    R = np.empty_like(t)
+    for a in range(v):
+        W = eri_vvvv_for_a(Lvv, a)                       # [c][b][d]
+        R[:, :, a, :] = np.tensordot(t, W, axes=([2, 3], [0, 2]))  # sum over c, d -> [i][j][b]
+    return R
+
+
+def ppl_loops(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
+    """The same sum written as explicit loops over i, j, a, b, c, d and P (tiny sizes only)."""
+    naux, n, _ = L.shape
+    v = n - o
+    oo = t.shape[0]
+    R = np.zeros((oo, oo, v, v))
+    for i in range(oo):
+        for j in range(oo):
+            for a in range(v):
+                for b in range(v):
+                    s = 0.0
+                    for c in range(v):
+                        for d in range(v):
+                            eri = 0.0
+                            for P in range(naux):
+                                eri += L[P, o + a, o + c] * L[P, o + b, o + d]
+                            s += eri * t[i, j, c, d]
+                    R[i, j, a, b] = s
+    return R
+
+
+def ppl_factored(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
+    """Independent association of the same sum: R_ij = sum_P L^P t_ij (L^P)^T.
+
+    This is the O(x o^2 v^3) order of Sec. 2 (no v^4 intermediate). It shares no
+    intermediate with ppl() and so cross-checks it at realistic sizes.
+    """
+    Lvv = vv_block(np.asarray(L, dtype=np.float64), o)
+    oo = t.shape[0]
+    v = Lvv.shape[1]
+    R = np.zeros_like(t, dtype=np.float64)
+    T = t.reshape(oo * oo, v, v)
+    Rr = R.reshape(oo * oo, v, v)
+    for P in range(Lvv.shape[0]):
+        M = Lvv[P]
+        Rr += np.matmul(np.matmul(M, T), M.T)   # [a][c] t[c][d] [d][b]
+    return R
+
+
+def ppl_sampled(L: np.ndarray, o: int, t: np.ndarray, idx) -> np.ndarray:
+    """R_ij^ab at a list of (i, j, a, b) samples, each from its own (ac|bd) slab.
+
+    For one sample, G[c, d] = (ac|bd) = sum_P L^P_ac L^P_bd and R = sum_cd G[c,d] t_ij^cd.
+    Cost per sample is O(naux v^2), so full-size results can be spot-checked.
+    """
+    Lvv = vv_block(np.asarray(L, dtype=np.float64), o)
+    out = np.empty(len(idx))
+    for k, (i, j, a, b) in enumerate(idx):
+        G = Lvv[:, a, :].T @ Lvv[:, b, :]          # [c][d]
+        out[k] = float(np.sum(G * t[i, j]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# MP2 start, denominators, energy
+# ---------------------------------------------------------------------------
+def mp2_parts(L: np.ndarray, o: int, e_occ: np.ndarray, e_vir: np.ndarray):
+    """V_ij^ab = (ia|jb) = sum_P L^P_ia L^P_jb and D_ij^ab = e_i + e_j - e_a - e_b."""
+    Lov = ov_block(np.asarray(L, dtype=np.float64), o)      # [P][i][a]
+    naux, oo, v = Lov.shape
+    X = Lov.transpose(1, 2, 0).reshape(oo * v, naux)        # [(i,a)][P]
+    V = (X @ X.T).reshape(oo, v, oo, v).transpose(0, 2, 1, 3).copy()  # [i][j][a][b]
+    e_occ = np.asarray(e_occ, dtype=np.float64)
+    e_vir = np.asarray(e_vir, dtype=np.float64)
+    D = (e_occ[:, None, None, None] + e_occ[None, :, None, None]
+         - e_vir[None, None, :, None] - e_vir[None, None, None, :])
+    return V, D
+
+
+def mp2_amplitudes(L, o, e_occ, e_vir) -> np.ndarray:
+    """First-order amplitudes t = V / D."""
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    return V / D
+
+
+def energy(V: np.ndarray, t: np.ndarray) -> float:
+    """E = sum_{ijab} V_ij^ab (2 t_ij^ab - t_ij^ba)."""
+    return float(np.sum(V * (2.0 * t - t.transpose(0, 1, 3, 2))))
+
+
+# ---------------------------------------------------------------------------
+# linearized doubles iteration (the PPL-only vector function with the Fock
+# denominators), its exact fixed point and its contraction rate
+# ---------------------------------------------------------------------------
+def jacobi_sweep(L, o, V, D, t):
+    """One simultaneous update t_new = (V + PPL(t)) / D; returns (t_new, ||t_new - t||_F)."""
+    t_new = (V + ppl(L, o, t)) / D
+    return t_new, float(np.linalg.norm(t_new - t))
+
+
+def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7):
+    """Iterate from t0 (MP2 when None) until r < tol or max_sweeps.
+
+    Returns (t, residual_history, E(t)).
+    """
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    t = V / D if t0 is None else np.array(t0, dtype=np.float64)
+    hist = []
+    for _ in range(max_sweeps):
+        t, r = jacobi_sweep(L, o, V, D, t)
+        hist.append(r)
+        if not np.isfinite(r) or r < tol:
+            break
+    return t, hist, energy(V, t)
+
+
+def fixed_point(L, o, e_occ, e_vir) -> np.ndarray:
+    """Exact solution of t = (V + PPL(t)) / D by one dense linear solve per (i, j).
+
+    With K[(a,b),(c,d)] = (ac|bd), the fixed point obeys (diag(D_ij) - K) t_ij = V_ij.
+    Tiny sizes only (v^2 x v^2 systems).
+    """
+    Lvv = vv_block(np.asarray(L, dtype=np.float64), o)
+    v = Lvv.shape[1]
+    K = np.einsum("Pac,Pbd->abcd", Lvv, Lvv).reshape(v * v, v * v)
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    oo = V.shape[0]
+    t = np.empty_like(V)
+    for i in range(oo):
+        for j in range(oo):
+            A = np.diag(D[i, j].ravel()) - K
+            t[i, j] = np.linalg.solve(A, V[i, j].ravel()).reshape(v, v)
+    return t
+
+
+def spectral_radius(L, o, e_occ, e_vir, iters: int = 200, seed: int = 0) -> float:
+    """Power-iteration estimate of rho of the Jacobi map x -> PPL(x) / D on pair-symmetric x."""
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(V.shape)
+    x = 0.5 * (x + x.transpose(1, 0, 3, 2))
+    x /= np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = ppl(L, o, x) / D
+        lam = float(np.linalg.norm(y))
+        if lam == 0.0:
+            return 0.0
+        x = y / lam
+    return lam
+
+
+# ---------------------------------------------------------------------------
+# flop accounting of the symmetric/antisymmetric pair method (reference counts)
+# ---------------------------------------------------------------------------
+def nominal_flops(o: int, v: int, naux: int) -> dict:
+    """Useful flops of one PPL evaluation in the i<=j / a<=b pair method.
+
+    build    = 2 naux v^2 P+     (G_ab = L_a^T L_b for every a <= b)
+    contract = 2 (P+^2 N+ + P-^2 N-)
+    with P+- = v(v+-1)/2, N+- = o(o+-1)/2; dense = 2 (naux + o^2) v^4.
+    """
+    Pp, Pm = v * (v + 1) // 2, v * (v - 1) // 2
+    Np, Nm = o * (o + 1) // 2, o * (o - 1) // 2
+    build = 2.0 * naux * v * v * Pp
+    contract = 2.0 * (Pp * Pp * Np + Pm * Pm * Nm)
+    dense = 2.0 * (naux + o * o) * float(v) ** 4
+    return {"build": build, "contract": contract, "eval": build + contract, "dense": dense}
