@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Benchmark of the particle-particle ladder (PPL) hot path on one MI355X.
+
+One step = the whole FP64 hot path at (o, v, naux) = (20, 200, 600) with the
+literal input generator (seed 1), all inputs already resident in HBM:
+  * (ia|jb) and the MP2 start in the packed pair space,
+  * the V+- integral build from the Cholesky vectors (one build),
+  * 10 Jacobi sweeps t <- (V + PPL(t)) / D (one contraction + FP64 update,
+    residual and energy each),
+  * one more PPL evaluation R = PPL(t) of the final amplitudes, unpacked to
+    the caller's [o][o][v][v] array.
+value = useful flops of the pair method (one build + 11 contractions) / step
+time. The dominant kernel is the R+ contraction GEMM; its roofline entry uses
+HIP-event timings of its launches inside the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PPL TFLOP/s + % MFMA peak; time-to-converged residual, FP64 vs mixed+learned"
+PEAK_FP64_TFLOPS = 78.6        # MI355X dense FP64 matrix peak
+O_, V_, NAUX_, SEED_ = 20, 200, 600, 1
+SWEEPS = 10
+
+
+def nominal(o, v, naux):
+    Pp, Pm = v * (v + 1) // 2, v * (v - 1) // 2
+    Np, Nm = o * (o + 1) // 2, o * (o - 1) // 2
+    return {"build": 2.0 * naux * v * v * Pp, "contract": 2.0 * (Pp * Pp * Np + Pm * Pm * Nm),
+            "contract_plus": 2.0 * Pp * Pp * Np, "contract_minus": 2.0 * Pm * Pm * Nm}
+
+
+def cpu_baseline(s, o):
+    """Time one oracle PPL evaluation of the same inputs on the host cores."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
+                      or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    V, D = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
+    t = V / D
+    t0 = time.perf_counter()
+    R = O.ppl(s["L"], o, t)
+    dt = time.perf_counter() - t0
+    f = nominal(o, s["v"], s["naux"])
+    assert np.isfinite(R).all()
+    return {"value": (f["build"] + f["contract"]) / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle", "seconds": dt,
+            "sample": f"one full oracle PPL evaluation (integrals + contraction) of the same "
+                      f"({o},{s['v']},{s['naux']}) inputs with MP2 amplitudes, scaled by the pair "
+                      f"method's useful flops of one evaluation"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every box has a single MI355X); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2603_20912_amd as P
+    import ppl_synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    s = ppl_synth.make_system(O_, V_, NAUX_, SEED_, "literal")
+    L = torch.from_numpy(s["L"]).to(dev)
+    eo = torch.from_numpy(s["e_occ"]).to(dev)
+    ev = torch.from_numpy(s["e_vir"]).to(dev)
+    t = torch.zeros((O_, O_, V_, V_), dtype=torch.float64, device=dev)
+    R = torch.empty_like(t)
+    eng = P.PPL(O_, V_, NAUX_, prec="fp64")
+    f = nominal(O_, V_, NAUX_)
+    flops_step = f["build"] + (SWEEPS + 1) * f["contract"]
+
+    def step():
+        eng.iterate(L, eo, ev, t, max_sweeps=SWEEPS, tol=0.0, diverge_factor=0.0, history=False)
+        eng.contract(t, R)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    eng.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = eng.profile_read()
+    eng.profile(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = flops_step / (ms_step * 1e-3) / 1e12
+    assert torch.isfinite(R).all().item()
+
+    cp = prof["contract_plus"]
+    avg_ms = cp["ms"] / max(cp["launches"], 1)
+    fl_launch = cp["flops"] / max(cp["launches"], 1)
+    achieved = fl_launch / (avg_ms * 1e-3) / 1e12
+    kernels = {k: {"launches": d["launches"], "avg_ms": d["ms"] / d["launches"] if d["launches"] else 0.0,
+                   "tflops": (d["flops"] / (d["ms"] * 1e-3) / 1e12) if d["ms"] > 0 and d["flops"] > 0 else None}
+               for k, d in prof.items()}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "PPL FP64 (o=20, v=200, naux=600), literal generator seed 1: "
+                               "V+- build + MP2 start + 10 Jacobi sweeps + 1 evaluation",
+                   "o": O_, "v": V_, "naux": NAUX_, "sweeps": SWEEPS, "precision": "fp64",
+                   "useful_flops_per_step": flops_step,
+                   "pct_fp64_mfma_peak": round(100.0 * value / PEAK_FP64_TFLOPS, 2),
+                   "tile_contract": eng.info["tile_contract"]},
+        "roofline": {"bound": "mfma", "kernel": "R+ contraction GEMM (FP64 MFMA 16x16x4)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": fl_launch, "avg_launch_ms": round(avg_ms, 4)},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, O_)
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

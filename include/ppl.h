@@ -1,0 +1,213 @@
+/*
+ * ppl.h -- C ABI of the MI355X (gfx950) particle-particle ladder library.
+ *
+ * The library evaluates the ladder term of the spin-free closed-shell CCD/CCSD
+ * vector function (Sec. 2, eq. (ppl-term)) with Cholesky-decomposed integrals
+ * (eq. (cholesky)), i.e. eq. (vfunction-chol):
+ *
+ *     R_ij^ab = sum_{c,d} (ac|bd) t_ij^cd,     (ac|bd) = sum_P L^P_ac L^P_bd,
+ *
+ * on one GPU, and iterates the linearized doubles equations
+ * t <- (V + PPL(t)) / D built on it, with V_ij^ab = (ia|jb) and
+ * D_ij^ab = e_i + e_j - e_a - e_b.
+ *
+ * Conventions shared by every entry point:
+ *   - Orbitals are ordered occupied first: p = 0..o-1 occupied, o..o+v-1 virtual.
+ *   - L is a device pointer to FP64 [naux][o+v][o+v], C-contiguous; each
+ *     L[P] must be symmetric (real orbitals, Sec. 2 after eq. (cholesky)).
+ *   - Amplitudes and results are device FP64 [o][o][v][v] (i, j, a, b),
+ *     C-contiguous. Amplitudes must be pair-symmetric, t_ij^ab = t_ji^ba
+ *     (eq. (2)): only the i <= j half is read.
+ *   - Every pointer argument that names device memory is owned by the caller.
+ *     The library never allocates or frees device memory: all its device
+ *     storage lives in one caller-provided workspace (ppl_bind_workspace).
+ *   - Work is enqueued asynchronously on the plan's stream unless stated.
+ *   - Functions return PPL_OK (0) or a negative PPL_E_* code; nothing throws
+ *     or aborts across the ABI, and there is no CPU fallback. ppl_last_error()
+ *     returns a thread-local description of the last failure.
+ *   - A plan is bound to one stream and one device and is not thread-safe.
+ */
+#ifndef PPL_H
+#define PPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define PPL_OK             0
+#define PPL_E_ARG         -1  /* invalid argument (sizes, null pointers, alignment) */
+#define PPL_E_NOMEM       -2  /* budget or workspace too small for even one row batch */
+#define PPL_E_HIP         -3  /* a HIP runtime call or kernel launch failed (or no device) */
+#define PPL_E_NONFINITE   -4  /* NaN/Inf met in inputs or in a residual */
+#define PPL_E_NOCONV      -5  /* iteration hit max_sweeps before reaching tol */
+#define PPL_E_DIVERGED    -6  /* residual grew by more than the guard factor */
+#define PPL_E_STATE       -7  /* call out of order (no workspace bound, V+- not built, ...) */
+#define PPL_E_UNSUPPORTED -8  /* combination not implemented */
+
+/* precision of the two PPL GEMMs (integral build and contraction) */
+typedef enum {
+  PPL_FP64   = 0,  /* FP64 operands, FP64 MFMA, FP64 accumulation */
+  PPL_FP32   = 1,  /* FP32 operands, FP32 MFMA, FP32 accumulation */
+  PPL_BF16X3 = 2   /* x = hi + lo (two bf16 terms), hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+} ppl_prec_t;
+
+typedef struct ppl_plan_s* ppl_plan_t;
+
+/* Problem description (input of ppl_plan). */
+typedef struct {
+  int32_t  o;           /* occupied orbitals, >= 1 */
+  int32_t  v;           /* virtual orbitals, >= 2 */
+  int32_t  naux;        /* Cholesky vectors, >= 1 */
+  int32_t  prec;        /* ppl_prec_t of the PPL GEMMs */
+  int32_t  keep_fp64;   /* prec != FP64: also keep an FP64 copy of V+- for refinement sweeps */
+  int32_t  tile_contract; /* contraction tile id, -1 = planner's choice (see ppl_tile_count) */
+  uint64_t hbm_budget;  /* bytes the workspace may use; 0 = 90% of the device's free memory */
+  void*    stream;      /* hipStream_t every call of this plan enqueues on (NULL = null stream) */
+} ppl_desc_t;
+
+/* What the planner decided (output of ppl_plan_query). */
+typedef struct {
+  uint64_t workspace_bytes;   /* bytes ppl_bind_workspace needs (256-byte aligned base) */
+  uint64_t vpm_bytes;         /* bytes of V+ and V- in the compute precision (all rows) */
+  int32_t  n_batches;         /* V+- row batches; 1 means all rows resident */
+  int32_t  resident;          /* 1: V+- stay resident between calls; 0: rebuilt per contraction */
+  int32_t  a_per_batch;       /* virtual rows a (pairs a<=b) per batch */
+  int32_t  tile_build;        /* tile id of the integral-build GEMM */
+  int32_t  tile_contract;     /* tile id of the contraction GEMM */
+  int32_t  n_plus;            /* N+ = o(o+1)/2 occupied pairs i<=j */
+  int32_t  n_minus;           /* N- = o(o-1)/2 occupied pairs i<j */
+  int32_t  p_plus;            /* P+ = v(v+1)/2 virtual pairs a<=b */
+  int32_t  p_minus;           /* P- = v(v-1)/2 virtual pairs a<b */
+  int32_t  reserved;
+  double   flops_build;       /* useful flops of one integral build: 2 naux v^2 P+ */
+  double   flops_contract;    /* useful flops of one contraction: 2 (P+^2 N+ + P-^2 N-) */
+} ppl_plan_info_t;
+
+/*
+ * ppl_plan: validate sizes and choose the V+- row batches, tiles and the
+ * workspace layout for the symmetric/antisymmetric pair method:
+ *   V+_ab,cd = ((ac|bd) + (ad|bc))/2 (a<=b, c<=d),  V-_ab,cd = ((ac|bd) - (ad|bc))/2 (a<b, c<d).
+ * Pure host logic: allocates no device memory and launches nothing. With
+ * hbm_budget == 0 it queries the free device memory (PPL_E_HIP without a GPU).
+ * Returns PPL_E_ARG for o<1, v<2, naux<1, an unknown precision or sizes whose
+ * byte counts overflow 64 bits, and PPL_E_NOMEM when the budget cannot hold the
+ * fixed buffers plus one batch of V+- rows.
+ */
+int ppl_plan(const ppl_desc_t* desc, ppl_plan_t* out);
+
+/* ppl_plan_query: copy the planner's decisions into *info. */
+int ppl_plan_query(ppl_plan_t plan, ppl_plan_info_t* info);
+
+/*
+ * ppl_bind_workspace: hand the plan `bytes` of device memory at `dptr`
+ * (256-byte aligned, at least info.workspace_bytes). The caller keeps
+ * ownership and must keep it alive until ppl_destroy; the library only
+ * partitions it. Enqueues a one-time setup (pair tables, zeroed padding).
+ */
+int ppl_bind_workspace(ppl_plan_t plan, void* dptr, uint64_t bytes);
+
+/*
+ * ppl_build_batch: form V+- rows from the Cholesky vectors (eq. (cholesky)).
+ * batch in [0, n_batches) builds one row batch, -1 builds every batch of a
+ * resident plan. The plan remembers L; a non-resident plan rebuilds its
+ * batches from it inside ppl_contract, so L must stay valid until the next
+ * ppl_build_batch or ppl_destroy.
+ */
+int ppl_build_batch(ppl_plan_t plan, const double* L, int32_t batch);
+
+/*
+ * ppl_contract: R = beta * R + alpha * PPL(t2) for one amplitude tensor
+ * (eq. (vfunction-chol)). t2 and R are device FP64 [o][o][v][v]; t2 must be
+ * pair-symmetric; R may not alias t2. The V+- rows must have been built
+ * (PPL_E_STATE otherwise).
+ */
+int ppl_contract(ppl_plan_t plan, const double* t2, double* R, double alpha, double beta);
+
+/* ------------------------------------------------ linearized doubles iteration */
+#define PPL_START_MP2   0  /* start from t = V / D */
+#define PPL_START_GIVEN 1  /* start from the t2 passed in */
+#define PPL_START_GIVEN_CHECKED 2  /* start from t2, but restart from MP2 if its first residual is larger */
+
+typedef struct {
+  int32_t max_sweeps;       /* hard cap on sweeps (all precisions), >= 1 */
+  int32_t start;            /* PPL_START_* */
+  double  tol;              /* stop when the FP64 residual ||t_new - t||_F < tol (0 = never) */
+  double  switch_tol;       /* mixed: go to FP64 sweeps when the residual < switch_tol */
+  double  stagnation;       /* mixed: go to FP64 sweeps when r_n / r_{n-1} > stagnation */
+  int32_t min_fp64_sweeps;  /* mixed: at least this many FP64 sweeps after the switch */
+  int32_t fail_on_noconv;   /* 1: return PPL_E_NOCONV when max_sweeps is reached (else OK) */
+  double  diverge_factor;   /* PPL_E_DIVERGED when r > diverge_factor * r_first (0 = off) */
+  double* history;          /* optional host array of max_sweeps residuals (NULL = none) */
+} ppl_iter_opts_t;
+
+typedef struct {
+  int32_t sweeps_lp;        /* sweeps done with the low-precision GEMMs */
+  int32_t sweeps_fp64;      /* sweeps done with the FP64 GEMMs */
+  int32_t status;           /* PPL_OK / PPL_E_NOCONV / PPL_E_DIVERGED / PPL_E_NONFINITE */
+  int32_t restarted_mp2;    /* 1 if a PPL_START_GIVEN_CHECKED start was rejected */
+  double  residual;         /* last FP64-update residual ||t_new - t||_F */
+  double  energy;           /* E = sum V (2 t_ij^ab - t_ij^ba) of the final t */
+  double  energy_start;     /* the same energy of the starting amplitudes */
+  double  first_residual;   /* residual of the first sweep */
+} ppl_iter_report_t;
+
+/* Fill *opts with the defaults: 100 sweeps, MP2 start, tol 1e-7, switch_tol 1e-5,
+ * stagnation 0.95, min_fp64_sweeps 2, fail_on_noconv 1, diverge_factor 1e3. */
+void ppl_iter_opts_default(ppl_iter_opts_t* opts);
+
+/*
+ * ppl_iterate: Jacobi sweeps t <- (V + PPL(t)) / D from an MP2 or given start,
+ * all in the packed pair space; the update, residual and energy are FP64.
+ * With a low-precision plan and keep_fp64 the sweeps first use the
+ * low-precision GEMMs, then switch to FP64 (switch_tol / stagnation) and run
+ * FP64 sweeps to tol. L, e_occ [o], e_vir [v] and t2 are device FP64; t2
+ * holds the start (PPL_START_GIVEN*) on entry and the last iterate on return.
+ * Synchronous: it reads two scalars back per sweep. Builds V+- itself.
+ */
+int ppl_iterate(ppl_plan_t plan, const double* L, const double* e_occ, const double* e_vir,
+                double* t2, const ppl_iter_opts_t* opts, ppl_iter_report_t* report);
+
+/* ------------------------------------------------ kernel timing (HIP events) */
+#define PPL_PROF_BUILD_GEMM     0  /* integral-build GEMM launches */
+#define PPL_PROF_BUILD_PACK     1  /* G -> V+- packing launches */
+#define PPL_PROF_CONTRACT_PLUS  2  /* R+ = S' V+ GEMM launches */
+#define PPL_PROF_CONTRACT_MINUS 3  /* R- = A' V- GEMM launches */
+#define PPL_PROF_UPDATE         4  /* packed Jacobi update + reductions */
+#define PPL_PROF_OTHER          5  /* staging, packing of t2, unpacking, (ia|jb) */
+#define PPL_PROF_KINDS          6
+
+typedef struct {
+  int64_t launches[PPL_PROF_KINDS];  /* timed launches per kind */
+  double  ms[PPL_PROF_KINDS];        /* summed event time per kind (milliseconds) */
+  double  flops[PPL_PROF_KINDS];     /* summed useful flops of those launches (GEMM kinds) */
+} ppl_profile_t;
+
+/*
+ * ppl_profile_enable: on != 0 starts (and clears) per-launch timing: every
+ * library launch on the plan's stream is bracketed by a pair of HIP events.
+ * on == 0 stops recording. Events are created lazily and kept by the plan.
+ */
+int ppl_profile_enable(ppl_plan_t plan, int on);
+
+/* ppl_profile_read: synchronize the plan's stream and sum the recorded event pairs by kind. */
+int ppl_profile_read(ppl_plan_t plan, ppl_profile_t* out);
+
+/* ppl_destroy: free the plan's host metadata (never the workspace). NULL is a no-op. */
+int ppl_destroy(ppl_plan_t plan);
+
+/* Thread-local text of the last error ("" if none). Valid until the next call on this thread. */
+const char* ppl_last_error(void);
+
+/* Number of contraction tile configurations compiled into the library. */
+int ppl_tile_count(void);
+
+/* Library version string. */
+const char* ppl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPL_H */

@@ -1,0 +1,83 @@
+"""MI355X (gfx950) particle-particle ladder term: Python front end of libppl.
+
+The hot path (integral build from Cholesky vectors, the symmetric/antisymmetric
+pair contraction, the packed Jacobi update) runs in the HIP library; this
+package only marshals torch tensors into its C ABI (include/ppl.h).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_destroy,
+                   ppl_iter_opts_default, ppl_iterate, ppl_last_error, ppl_plan, ppl_plan_query,
+                   ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_version)
+
+__all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace", "ppl_build_batch",
+           "ppl_contract", "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count",
+           "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read"]
+
+
+class PPL:
+    """One planned problem with its device workspace (allocated by torch, owned here)."""
+
+    def __init__(self, o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None,
+                 tile_contract=-1, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("PPL needs a HIP device (no CPU fallback)")
+        self.o, self.v, self.naux = o, v, naux
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.plan = ppl_plan(o, v, naux, prec, keep_fp64, hbm_budget, self.stream, tile_contract)
+        self.info = ppl_plan_query(self.plan)
+        nbytes = int(self.info["workspace_bytes"])
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        ppl_bind_workspace(self.plan, self.workspace)
+
+    def build(self, L, batch=-1):
+        ppl_build_batch(self.plan, L, batch)
+
+    def contract(self, t2, R=None, alpha=1.0, beta=0.0):
+        if R is None:
+            R = torch.empty_like(t2)
+        ppl_contract(self.plan, t2, R, alpha, beta)
+        return R
+
+    def iterate(self, L, e_occ, e_vir, t2, max_sweeps=100, tol=1e-7, start="mp2", switch_tol=1e-5,
+                stagnation=0.95, min_fp64_sweeps=2, diverge_factor=1e3, fail_on_noconv=True,
+                history=True, raise_on_status=True):
+        opts = ppl_iter_opts_default()
+        opts.max_sweeps = int(max_sweeps)
+        opts.tol = float(tol)
+        opts.start = {"mp2": _lib.PPL_START_MP2, "given": _lib.PPL_START_GIVEN,
+                      "checked": _lib.PPL_START_GIVEN_CHECKED}[start]
+        opts.switch_tol = float(switch_tol)
+        opts.stagnation = float(stagnation)
+        opts.min_fp64_sweeps = int(min_fp64_sweeps)
+        opts.diverge_factor = float(diverge_factor)
+        opts.fail_on_noconv = int(bool(fail_on_noconv))
+        hist = (ctypes.c_double * max_sweeps)() if history else None
+        if hist is not None:
+            opts.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        rep = ppl_iterate(self.plan, L, e_occ, e_vir, t2, opts, raise_on_status=raise_on_status)
+        n = rep["sweeps_lp"] + rep["sweeps_fp64"]
+        rep["history"] = list(hist[:n]) if hist is not None else []
+        return rep
+
+    def profile(self, on=True):
+        ppl_profile_enable(self.plan, on)
+
+    def profile_read(self):
+        return ppl_profile_read(self.plan)
+
+    def close(self):
+        if getattr(self, "plan", None) is not None:
+            ppl_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,213 @@
+"""ctypes binding of libppl (include/ppl.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts Python
+arguments (ints, floats, torch tensors) into the C ABI's plain pointers and
+sizes. torch is imported before the library is loaded so that the process
+holds exactly one HIP runtime (the one torch ships), which libppl then shares.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime libppl binds to)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libppl.so")
+
+PPL_OK = 0
+PPL_E_ARG = -1
+PPL_E_NOMEM = -2
+PPL_E_HIP = -3
+PPL_E_NONFINITE = -4
+PPL_E_NOCONV = -5
+PPL_E_DIVERGED = -6
+PPL_E_STATE = -7
+PPL_E_UNSUPPORTED = -8
+ERROR_NAMES = {0: "PPL_OK", -1: "PPL_E_ARG", -2: "PPL_E_NOMEM", -3: "PPL_E_HIP", -4: "PPL_E_NONFINITE",
+               -5: "PPL_E_NOCONV", -6: "PPL_E_DIVERGED", -7: "PPL_E_STATE", -8: "PPL_E_UNSUPPORTED"}
+
+PPL_FP64, PPL_FP32, PPL_BF16X3 = 0, 1, 2
+PREC = {"fp64": PPL_FP64, "fp32": PPL_FP32, "bf16x3": PPL_BF16X3}
+PPL_START_MP2, PPL_START_GIVEN, PPL_START_GIVEN_CHECKED = 0, 1, 2
+
+
+class ppl_desc_t(ctypes.Structure):
+    _fields_ = [("o", ctypes.c_int32), ("v", ctypes.c_int32), ("naux", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("keep_fp64", ctypes.c_int32),
+                ("tile_contract", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class ppl_plan_info_t(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("vpm_bytes", ctypes.c_uint64),
+                ("n_batches", ctypes.c_int32), ("resident", ctypes.c_int32),
+                ("a_per_batch", ctypes.c_int32), ("tile_build", ctypes.c_int32),
+                ("tile_contract", ctypes.c_int32), ("n_plus", ctypes.c_int32),
+                ("n_minus", ctypes.c_int32), ("p_plus", ctypes.c_int32), ("p_minus", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("flops_build", ctypes.c_double),
+                ("flops_contract", ctypes.c_double)]
+
+
+class ppl_iter_opts_t(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("start", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("switch_tol", ctypes.c_double), ("stagnation", ctypes.c_double),
+                ("min_fp64_sweeps", ctypes.c_int32), ("fail_on_noconv", ctypes.c_int32),
+                ("diverge_factor", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+class ppl_iter_report_t(ctypes.Structure):
+    _fields_ = [("sweeps_lp", ctypes.c_int32), ("sweeps_fp64", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("restarted_mp2", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("energy", ctypes.c_double),
+                ("energy_start", ctypes.c_double), ("first_residual", ctypes.c_double)]
+
+
+PPL_PROF_KINDS = 6
+PROF_KINDS = ["build_gemm", "build_pack", "contract_plus", "contract_minus", "update", "other"]
+
+
+class ppl_profile_t(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * PPL_PROF_KINDS), ("ms", ctypes.c_double * PPL_PROF_KINDS),
+                ("flops", ctypes.c_double * PPL_PROF_KINDS)]
+
+
+# name -> (restype, argtypes) of every symbol include/ppl.h declares
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "ppl_plan": (ctypes.c_int, [ctypes.POINTER(ppl_desc_t), ctypes.POINTER(_P)]),
+    "ppl_plan_query": (ctypes.c_int, [_P, ctypes.POINTER(ppl_plan_info_t)]),
+    "ppl_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "ppl_build_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "ppl_contract": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double]),
+    "ppl_iter_opts_default": (None, [ctypes.POINTER(ppl_iter_opts_t)]),
+    "ppl_iterate": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ppl_iter_opts_t),
+                                   ctypes.POINTER(ppl_iter_report_t)]),
+    "ppl_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ppl_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ppl_profile_t)]),
+    "ppl_destroy": (ctypes.c_int, [_P]),
+    "ppl_last_error": (ctypes.c_char_p, []),
+    "ppl_tile_count": (ctypes.c_int, []),
+    "ppl_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class PPLError(RuntimeError):
+    def __init__(self, code, where, detail):
+        self.code = code
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)} ({detail})")
+
+
+def load(path: str = LIB_PATH):
+    """Load libppl.so and declare its prototypes. Raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libppl.so not found at {path}: build it with "
+                           "`python -m paper_2603_20912_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc, where):
+    if rc != PPL_OK:
+        raise PPLError(rc, where, load().ppl_last_error().decode())
+    return rc
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- same names as the C ABI
+def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None, tile_contract=-1):
+    d = ppl_desc_t(o, v, naux, PREC[prec] if isinstance(prec, str) else int(prec), int(bool(keep_fp64)),
+                   int(tile_contract), int(hbm_budget),
+                   _stream_handle(stream) if stream is not False else None)
+    h = ctypes.c_void_p()
+    _check(load().ppl_plan(ctypes.byref(d), ctypes.byref(h)), "ppl_plan")
+    return h
+
+
+def ppl_plan_query(plan) -> dict:
+    info = ppl_plan_info_t()
+    _check(load().ppl_plan_query(plan, ctypes.byref(info)), "ppl_plan_query")
+    return {f: getattr(info, f) for f, _ in ppl_plan_info_t._fields_}
+
+
+def ppl_bind_workspace(plan, ws, nbytes=None):
+    n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
+    _check(load().ppl_bind_workspace(plan, _ptr(ws), n), "ppl_bind_workspace")
+
+
+def ppl_build_batch(plan, L, batch=-1):
+    _check(load().ppl_build_batch(plan, _ptr(L), int(batch)), "ppl_build_batch")
+
+
+def ppl_contract(plan, t2, R, alpha=1.0, beta=0.0):
+    _check(load().ppl_contract(plan, _ptr(t2), _ptr(R), float(alpha), float(beta)), "ppl_contract")
+
+
+def ppl_iter_opts_default() -> ppl_iter_opts_t:
+    o = ppl_iter_opts_t()
+    load().ppl_iter_opts_default(ctypes.byref(o))
+    return o
+
+
+def ppl_iterate(plan, L, e_occ, e_vir, t2, opts: ppl_iter_opts_t | None = None, raise_on_status=True):
+    rep = ppl_iter_report_t()
+    rc = load().ppl_iterate(plan, _ptr(L), _ptr(e_occ), _ptr(e_vir), _ptr(t2),
+                            ctypes.byref(opts) if opts is not None else None, ctypes.byref(rep))
+    if raise_on_status:
+        _check(rc, "ppl_iterate")
+    out = {f: getattr(rep, f) for f, _ in ppl_iter_report_t._fields_}
+    out["rc"] = rc
+    return out
+
+
+def ppl_profile_enable(plan, on=True):
+    _check(load().ppl_profile_enable(plan, int(bool(on))), "ppl_profile_enable")
+
+
+def ppl_profile_read(plan) -> dict:
+    pr = ppl_profile_t()
+    _check(load().ppl_profile_read(plan, ctypes.byref(pr)), "ppl_profile_read")
+    return {k: {"launches": int(pr.launches[i]), "ms": float(pr.ms[i]), "flops": float(pr.flops[i])}
+            for i, k in enumerate(PROF_KINDS)}
+
+
+def ppl_destroy(plan):
+    if plan is not None:
+        load().ppl_destroy(plan)
+
+
+def ppl_last_error() -> str:
+    return load().ppl_last_error().decode()
+
+
+def ppl_tile_count() -> int:
+    return load().ppl_tile_count()
+
+
+def ppl_version() -> str:
+    return load().ppl_version().decode()

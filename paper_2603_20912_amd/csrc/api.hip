@@ -1,0 +1,676 @@
+// C ABI of libppl: planner, workspace binding, build / contract / iterate drivers.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "ppl_internal.h"
+
+namespace ppl {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+// bytes per element of an operand plane and number of planes
+static int elem_bytes(int prec) { return prec == PPL_FP64 ? 8 : (prec == PPL_FP32 ? 4 : 2); }
+static int planes(int prec) { return prec == PPL_BF16X3 ? 2 : 1; }
+static int acc_bytes(int prec) { return prec == PPL_FP64 ? 8 : 4; }
+
+// overflow-checked multiply of non-negative sizes
+static bool mul_ok(uint64_t a, uint64_t b, uint64_t* out) {
+  if (a != 0 && b > UINT64_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+struct Layout {
+  uint64_t cur = 0;
+  Region take(uint64_t bytes) {
+    Region r;
+    r.off = cur;
+    r.bytes = align256(bytes);
+    cur += r.bytes;
+    return r;
+  }
+};
+
+// Split virtual rows a into build steps whose pair count (sum of v - a) stays
+// within cap (at least one row per step).
+static void make_batches(int v, int64_t cap, std::vector<Batch>& out) {
+  out.clear();
+  int a = 0;
+  while (a < v) {
+    int a1 = a;
+    int64_t pairs = 0;
+    while (a1 < v && (a1 == a || pairs + (v - a1) <= cap)) {
+      pairs += v - a1;
+      ++a1;
+    }
+    Batch b;
+    b.a0 = a;
+    b.a1 = a1;
+    b.p0 = pair_plus(a, a, v);
+    b.p1 = (a1 >= v) ? npairs_plus(v) : pair_plus(a1, a1, v);
+    b.q0 = (a < v - 1) ? pair_minus(a, a + 1, v) : npairs_minus(v);
+    b.q1 = (a1 >= v - 1) ? npairs_minus(v) : pair_minus(a1, a1 + 1, v);
+    if (b.q1 < b.q0) b.q1 = b.q0;
+    out.push_back(b);
+    a = a1;
+  }
+}
+
+// Assign every workspace region for a given G cap and residency; returns total bytes.
+static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t max_batch_pairs) {
+  Layout L;
+  const int64_t v = p->v, o = p->o;
+  for (int k = 0; k < 2; ++k) {
+    OperandSet& s = p->ops[k];
+    if (!s.present) continue;
+    const uint64_t w = elem_bytes(s.prec);
+    const int np = planes(s.prec);
+    const int64_t vrows_p = resident ? p->Pp : max_batch_pairs;
+    const int64_t vrows_m = resident ? p->Pm : max_batch_pairs;
+    s.xt = L.take((uint64_t)v * v * p->ldx * w);
+    s.vp = L.take((uint64_t)vrows_p * p->ldp * w);
+    s.vm = L.take((uint64_t)std::max<int64_t>(vrows_m, 1) * p->ldm * w);
+    s.sp = L.take((uint64_t)p->Np * p->ldp * w);
+    s.am = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * w);
+    if (np == 2) {
+      s.xt_lo = L.take(s.xt.bytes);
+      s.vp_lo = L.take(s.vp.bytes);
+      s.vm_lo = L.take(s.vm.bytes);
+      s.sp_lo = L.take(s.sp.bytes);
+      s.am_lo = L.take(s.am.bytes);
+    } else {
+      s.xt_lo = s.vp_lo = s.vm_lo = s.sp_lo = s.am_lo = Region{};
+    }
+  }
+  // build scratch G (accumulator precision) doubles as the (ia|jb) scratch
+  const uint64_t gbytes = std::max<uint64_t>((uint64_t)gcap * v * v * acc_bytes(p->ops[0].prec),
+                                             (uint64_t)(o * v) * (o * v) * 8);
+  p->g = L.take(gbytes);
+  p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
+  p->rm = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+  if (p->ops[0].prec != PPL_FP64) {   // FP64 master amplitudes
+    p->s64 = L.take((uint64_t)p->Np * p->ldp * 8);
+    p->a64 = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+  } else {
+    p->s64 = p->ops[0].sp;
+    p->a64 = p->ops[0].am;
+  }
+  p->bs = L.take((uint64_t)p->Np * p->ldp * 8);     // backup of S'/A' for checked starts
+  p->ba = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+  p->vs = L.take((uint64_t)p->Np * p->ldp * 8);
+  p->va = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+  p->xov = L.take((uint64_t)o * v * p->ldx * 8);
+  p->tab_vp = L.take((uint64_t)p->Pp * 4);
+  p->tab_vm = L.take((uint64_t)std::max<int64_t>(p->Pm, 1) * 4);
+  p->tab_op = L.take((uint64_t)p->Np * 4);
+  p->tab_om = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * 4);
+  p->red = L.take((uint64_t)(kReduceBlocks * 4 + 8) * 8);
+  p->tiles = L.take((uint64_t)p->tiles_host.size() * 4);
+  return L.cur;
+}
+
+static void make_tile_tables(ppl_plan_t p) {
+  p->tiles_host.clear();
+  p->tiles_off.clear();
+  for (const Batch& b : p->batches) {
+    std::vector<int> pre;
+    int nmt, nnt;
+    build_tile_table(p->tile_build, p->v, b.a0, b.a1, pre, nmt, nnt);
+    p->tiles_off.push_back((int64_t)p->tiles_host.size());
+    p->tiles_host.insert(p->tiles_host.end(), pre.begin(), pre.end());
+  }
+}
+
+static int check_plan(ppl_plan_t p) {
+  if (!p) return fail(PPL_E_ARG, "null plan");
+  return PPL_OK;
+}
+
+static int check_bound(ppl_plan_t p) {
+  PPL_TRY(check_plan(p));
+  if (!p->ws) return fail(PPL_E_STATE, "no workspace bound (call ppl_bind_workspace first)");
+  return PPL_OK;
+}
+
+// ---------------------------------------------------------------- launch timing
+// Scoped pair of events around one or more launches of one kind.
+struct ProfScope {
+  ppl_plan_t p;
+  int idx = -1;
+  ProfScope(ppl_plan_t plan, int kind, double flops) : p(plan) {
+    if (!p->prof_on) return;
+    if (p->prof_next + 2 > (int)p->prof_pool.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        p->prof_pool.push_back(e);
+      }
+    }
+    idx = p->prof_next;
+    p->prof_next += 2;
+    if (hipEventRecord(p->prof_pool[idx], p->stream) != hipSuccess) { idx = -1; return; }
+    p->prof_recs.push_back({kind, idx, flops});
+  }
+  ~ProfScope() {
+    if (idx >= 0) (void)hipEventRecord(p->prof_pool[idx + 1], p->stream);
+  }
+};
+
+
+// ------------------------------------------------------------------ build
+static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool staged) {
+  const Batch& b = p->batches[bi];
+  hipStream_t st = p->stream;
+  if (!staged) {
+    ProfScope ps(p, PPL_PROF_OTHER, 0.0);
+    PPL_TRY(stage_vv(st, s.prec, L, p->o, p->v, p->naux, p->ldx, at<void>(p, s.xt),
+                     s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr));
+  }
+  std::vector<int> pre;
+  int nmt, nnt;
+  build_tile_table(p->tile_build, p->v, b.a0, b.a1, pre, nmt, nnt);
+  const int* dpre = at<int>(p, p->tiles) + p->tiles_off[bi];
+  const int64_t nvalid = pre.back();
+  {
+    ProfScope ps(p, PPL_PROF_BUILD_GEMM, 2.0 * p->naux * (double)p->v * p->v * (double)(b.p1 - b.p0));
+    PPL_TRY(gemm_build(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
+                       s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dpre,
+                       nmt, nnt, nvalid));
+  }
+  const int64_t row0p = p->resident ? 0 : b.p0;
+  const int64_t row0m = p->resident ? 0 : b.q0;
+  ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
+  PPL_TRY(pack_vpm(st, s.prec, p->v, b.a0, b.a1, at<void>(p, p->g), at<void>(p, s.vp),
+                   s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp, row0p, at<void>(p, s.vm),
+                   s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm, row0m,
+                   at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+  return PPL_OK;
+}
+
+static int build_all(ppl_plan_t p, OperandSet& s, const double* L) {
+  for (int bi = 0; bi < (int)p->batches.size(); ++bi) PPL_TRY(build_one(p, s, L, bi, bi > 0));
+  s.built = true;
+  return PPL_OK;
+}
+
+// ------------------------------------------------------------------ contraction of packed operands
+// R+ = S' V+^T, R- = A' V-^T with the operand set s (its S'/A' must be current).
+static int contract_packed(ppl_plan_t p, OperandSet& s) {
+  hipStream_t st = p->stream;
+  const void* sp = at<void>(p, s.sp);
+  const void* sp_lo = s.sp_lo.bytes ? at<void>(p, s.sp_lo) : nullptr;
+  const void* am = at<void>(p, s.am);
+  const void* am_lo = s.am_lo.bytes ? at<void>(p, s.am_lo) : nullptr;
+  const int tile = p->tile_contract;
+  const int tile_m = p->Nm > 0 ? contract_tile_default(s.prec, p->Nm) : tile;
+  const double fp = 2.0 * (double)p->Np * p->Pp, fm = 2.0 * (double)p->Nm * p->Pm;
+  if (p->resident) {
+    if (!s.built) return fail(PPL_E_STATE, "V+- not built (call ppl_build_batch first)");
+    {
+      ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, fp * p->Pp);
+      PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, p->Pp, p->ldp, sp, sp_lo, p->ldp,
+                            at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
+                            at<void>(p, p->rp), p->ldp, 0));
+    }
+    ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, fm * p->Pm);
+    if (p->Nm > 0 && p->Pm > 0)
+      PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, p->Pm, p->ldm, am, am_lo, p->ldm,
+                            at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
+                            at<void>(p, p->rm), p->ldm, 0));
+    return PPL_OK;
+  }
+  if (!p->L_last) return fail(PPL_E_STATE, "streaming plan has no Cholesky vectors (call ppl_build_batch)");
+  for (int bi = 0; bi < (int)p->batches.size(); ++bi) {
+    const Batch& b = p->batches[bi];
+    PPL_TRY(build_one(p, s, p->L_last, bi, bi > 0));
+    {
+      ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, 2.0 * (double)p->Np * p->Pp * (double)(b.p1 - b.p0));
+      PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, b.p1 - b.p0, p->ldp, sp, sp_lo, p->ldp,
+                            at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
+                            at<void>(p, p->rp), p->ldp, b.p0));
+    }
+    ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, 2.0 * (double)p->Nm * p->Pm * (double)(b.q1 - b.q0));
+    if (p->Nm > 0 && b.q1 > b.q0)
+      PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, b.q1 - b.q0, p->ldm, am, am_lo, p->ldm,
+                            at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
+                            at<void>(p, p->rm), p->ldm, b.q0));
+  }
+  return PPL_OK;
+}
+
+// refresh the low-precision S'/A' copies of set s from the FP64 master
+static int refresh_operands(ppl_plan_t p, OperandSet& s) {
+  if (s.prec == PPL_FP64) {
+    if (s.sp.off != p->s64.off) {   // FP64 refinement set of a mixed plan: copy the master
+      PPL_TRY(convert_rows(p->stream, PPL_FP64, at<double>(p, p->s64), p->Np, p->Pp, p->ldp,
+                           at<void>(p, s.sp), nullptr));
+      if (p->Nm > 0)
+        PPL_TRY(convert_rows(p->stream, PPL_FP64, at<double>(p, p->a64), p->Nm, p->Pm, p->ldm,
+                             at<void>(p, s.am), nullptr));
+    }
+    return PPL_OK;
+  }
+  PPL_TRY(convert_rows(p->stream, s.prec, at<double>(p, p->s64), p->Np, p->Pp, p->ldp,
+                       at<void>(p, s.sp), s.sp_lo.bytes ? at<void>(p, s.sp_lo) : nullptr));
+  if (p->Nm > 0)
+    PPL_TRY(convert_rows(p->stream, s.prec, at<double>(p, p->a64), p->Nm, p->Pm, p->ldm,
+                         at<void>(p, s.am), s.am_lo.bytes ? at<void>(p, s.am_lo) : nullptr));
+  return PPL_OK;
+}
+
+static int read_red(ppl_plan_t p, double out[4]) {
+  const double* red_out = at<double>(p, p->red) + kReduceBlocks * 4;
+  PPL_HIP_TRY(hipMemcpyAsync(out, red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  PPL_HIP_TRY(hipStreamSynchronize(p->stream));
+  return PPL_OK;
+}
+
+}  // namespace ppl
+
+using namespace ppl;
+
+extern "C" {
+
+const char* ppl_last_error(void) { return g_err; }
+
+const char* ppl_version(void) { return "ppl-mi355x 0.1 (gfx950)"; }
+
+int ppl_tile_count(void) { return contract_tile_count(); }
+
+void ppl_iter_opts_default(ppl_iter_opts_t* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->max_sweeps = 100;
+  o->start = PPL_START_MP2;
+  o->tol = 1e-7;
+  o->switch_tol = 1e-5;
+  o->stagnation = 0.95;
+  o->min_fp64_sweeps = 2;
+  o->fail_on_noconv = 1;
+  o->diverge_factor = 1e3;
+  o->history = nullptr;
+}
+
+int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
+  g_err[0] = 0;
+  if (!d || !out) return fail(PPL_E_ARG, "null argument");
+  *out = nullptr;
+  if (d->o < 1) return fail(PPL_E_ARG, "o must be >= 1 (got %d)", d->o);
+  if (d->v < 2) return fail(PPL_E_ARG, "v must be >= 2 (got %d)", d->v);
+  if (d->naux < 1) return fail(PPL_E_ARG, "naux must be >= 1 (got %d)", d->naux);
+  if (d->v > 32767 || d->o > 32767) return fail(PPL_E_ARG, "o and v must be < 32768");
+  if (d->prec != PPL_FP64 && d->prec != PPL_FP32 && d->prec != PPL_BF16X3)
+    return fail(PPL_E_ARG, "unknown precision %d", d->prec);
+  if (d->tile_contract < -1 || d->tile_contract >= contract_tile_count())
+    return fail(PPL_E_ARG, "tile_contract %d out of range", d->tile_contract);
+  // 64-bit size sanity: the largest products used anywhere
+  {
+    uint64_t x;
+    const uint64_t v = d->v, o = d->o, na = d->naux;
+    const uint64_t Pp = v * (v + 1) / 2;
+    if (!mul_ok(Pp, Pp, &x) || !mul_ok(x, 16, &x) || !mul_ok(v * v, na + 64, &x) ||
+        !mul_ok(x, 16, &x) || !mul_ok(o * o, v * v, &x) || !mul_ok(x, 16, &x))
+      return fail(PPL_E_ARG, "sizes overflow 64-bit byte counts");
+  }
+  ppl_plan_t p = new (std::nothrow) ppl_plan_s();
+  if (!p) return fail(PPL_E_NOMEM, "host allocation failed");
+  p->o = d->o;
+  p->v = d->v;
+  p->naux = d->naux;
+  p->prec = d->prec;
+  p->keep_fp64 = (d->prec != PPL_FP64) && d->keep_fp64;
+  p->stream = (hipStream_t)d->stream;
+  p->Pp = npairs_plus(p->v);
+  p->Pm = npairs_minus(p->v);
+  p->Np = npairs_plus(p->o);
+  p->Nm = npairs_minus(p->o);
+  p->ldp = pad_ld(p->Pp);
+  p->ldm = pad_ld(std::max<int64_t>(p->Pm, 1));
+  p->ldx = pad_ld(p->naux);
+  p->ops[0].prec = p->prec;
+  p->ops[0].present = true;
+  p->ops[1].prec = PPL_FP64;
+  p->ops[1].present = p->keep_fp64 != 0;
+  p->tile_build = 0;
+  p->tile_contract = d->tile_contract >= 0 ? d->tile_contract : contract_tile_default(p->prec, p->Np);
+
+  uint64_t budget = d->hbm_budget;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    hipError_t e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(PPL_E_HIP, "hipMemGetInfo failed: %s (pass an explicit hbm_budget)", hipGetErrorString(e));
+    }
+    budget = (uint64_t)(0.9 * (double)fr);
+  }
+  p->budget = budget;
+
+  // G cap: at most 4 GiB of scratch, at least one full row a = 0 (v pairs)
+  const uint64_t per_pair_g = (uint64_t)p->v * p->v * acc_bytes(p->prec);
+  int64_t gcap = (int64_t)std::max<uint64_t>((uint64_t)p->v, (4ull << 30) / per_pair_g);
+  gcap = std::min<int64_t>(gcap, p->Pp);
+  // try resident
+  make_batches(p->v, gcap, p->batches);
+  make_tile_tables(p);
+  uint64_t need = assign_layout(p, gcap, true, 0);
+  if (need <= budget) {
+    p->resident = true;
+  } else {
+    // streaming: V+- rows of one build step at a time; shrink the step until it fits
+    p->resident = false;
+    bool ok = false;
+    for (int64_t cap = gcap; cap >= p->v; cap = cap / 2) {
+      make_batches(p->v, cap, p->batches);
+      make_tile_tables(p);
+      int64_t maxp = 0;
+      for (const Batch& b : p->batches) maxp = std::max<int64_t>(maxp, b.p1 - b.p0);
+      need = assign_layout(p, cap, false, maxp);
+      if (need <= budget) {
+        ok = true;
+        gcap = cap;
+        break;
+      }
+      if (cap == p->v) break;
+    }
+    if (!ok) {
+      const uint64_t n2 = need;
+      delete p;
+      return fail(PPL_E_NOMEM, "budget %llu B cannot hold one V+- row batch (needs %llu B)",
+                  (unsigned long long)budget, (unsigned long long)n2);
+    }
+  }
+  p->g_pairs_cap = gcap;
+  p->a_per_batch = p->batches.empty() ? 0 : p->batches[0].a1 - p->batches[0].a0;
+  p->ws_bytes_needed = need;
+  *out = p;
+  return PPL_OK;
+}
+
+int ppl_plan_query(ppl_plan_t p, ppl_plan_info_t* info) {
+  PPL_TRY(check_plan(p));
+  if (!info) return fail(PPL_E_ARG, "null info");
+  memset(info, 0, sizeof(*info));
+  info->workspace_bytes = p->ws_bytes_needed;
+  uint64_t vpm = 0;
+  for (int k = 0; k < 2; ++k)
+    if (p->ops[k].present)
+      vpm += ((uint64_t)p->Pp * p->ldp + (uint64_t)p->Pm * p->ldm) * elem_bytes(p->ops[k].prec) *
+             planes(p->ops[k].prec);
+  info->vpm_bytes = vpm;
+  info->n_batches = (int32_t)p->batches.size();
+  info->resident = p->resident ? 1 : 0;
+  info->a_per_batch = p->a_per_batch;
+  info->tile_build = p->tile_build;
+  info->tile_contract = p->tile_contract;
+  info->n_plus = (int32_t)p->Np;
+  info->n_minus = (int32_t)p->Nm;
+  info->p_plus = (int32_t)p->Pp;
+  info->p_minus = (int32_t)p->Pm;
+  const double v = p->v, na = p->naux;
+  info->flops_build = 2.0 * na * v * v * (double)p->Pp;
+  info->flops_contract =
+      2.0 * ((double)p->Pp * p->Pp * p->Np + (double)p->Pm * p->Pm * p->Nm);
+  return PPL_OK;
+}
+
+int ppl_bind_workspace(ppl_plan_t p, void* dptr, uint64_t bytes) {
+  g_err[0] = 0;
+  PPL_TRY(check_plan(p));
+  if (!dptr) return fail(PPL_E_ARG, "null workspace");
+  if (((uintptr_t)dptr) % 256 != 0) return fail(PPL_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < p->ws_bytes_needed)
+    return fail(PPL_E_NOMEM, "workspace of %llu B is smaller than the %llu B the plan needs",
+                (unsigned long long)bytes, (unsigned long long)p->ws_bytes_needed);
+  PPL_HIP_TRY(hipGetDevice(&p->device));
+  p->ws = (char*)dptr;
+  p->ws_bytes = bytes;
+  for (int k = 0; k < 2; ++k) p->ops[k].built = false;
+  hipStream_t st = p->stream;
+  // zero every small region (amplitude rows, results, integrals (ia|jb)): their padding must stay 0
+  const Region* small[] = {&p->ops[0].sp, &p->ops[0].am, &p->ops[0].sp_lo, &p->ops[0].am_lo,
+                           &p->ops[1].sp, &p->ops[1].am, &p->rp,          &p->rm,
+                           &p->s64,       &p->a64,       &p->vs,          &p->va};
+  for (const Region* r : small)
+    if (r->bytes) PPL_TRY(zero_bytes(st, p->ws + r->off, r->bytes));
+  PPL_TRY(fill_tables(st, p->o, p->v, at<int>(p, p->tab_vp), at<int>(p, p->tab_vm), at<int>(p, p->tab_op),
+                      at<int>(p, p->tab_om)));
+  if (!p->tiles_host.empty())
+    PPL_HIP_TRY(hipMemcpyAsync(at<int>(p, p->tiles), p->tiles_host.data(), p->tiles_host.size() * 4,
+                               hipMemcpyHostToDevice, st));
+  PPL_HIP_TRY(hipStreamSynchronize(st));   // the host tile table must not be reused before the copy ends
+  p->setup_done = true;
+  return PPL_OK;
+}
+
+int ppl_build_batch(ppl_plan_t p, const double* L, int32_t batch) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!L) return fail(PPL_E_ARG, "null L");
+  const int nb = (int)p->batches.size();
+  if (batch < -1 || batch >= nb) return fail(PPL_E_ARG, "batch %d out of range [-1, %d)", batch, nb);
+  p->L_last = L;
+  if (!p->resident) return PPL_OK;       // streaming plans build inside ppl_contract
+  for (int k = 0; k < 2; ++k) {
+    OperandSet& s = p->ops[k];
+    if (!s.present) continue;
+    if (batch < 0) {
+      PPL_TRY(build_all(p, s, L));
+    } else {
+      PPL_TRY(build_one(p, s, L, batch, false));
+      // a resident plan counts as built once its last batch is built in order
+      if (batch == nb - 1) s.built = true;
+    }
+  }
+  return PPL_OK;
+}
+
+int ppl_contract(ppl_plan_t p, const double* t2, double* R, double alpha, double beta) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!t2 || !R) return fail(PPL_E_ARG, "null t2 or R");
+  if ((const void*)t2 == (const void*)R) return fail(PPL_E_ARG, "R may not alias t2");
+  OperandSet& s = p->ops[0];
+  const int64_t o = p->o, v = p->v;
+  // S' = (2 - d_cd)(t^cd + t^dc)/2, A' = t^cd - t^dc on the i<=j / i<j rows
+  PPL_TRY(pack_pm(p->stream, p->o, p->v, t2, o * v * v, v * v, v, 1, 1.0, 0.5, 1.0, at<double>(p, p->s64),
+                  p->ldp, at<double>(p, p->a64), p->ldm, at<int>(p, p->tab_op), at<int>(p, p->tab_om),
+                  at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+  PPL_TRY(refresh_operands(p, s));
+  PPL_TRY(contract_packed(p, s));
+  PPL_TRY(unpack_r(p->stream, s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, at<void>(p, p->rp),
+                   p->ldp, at<void>(p, p->rm), p->ldm, R, alpha, beta));
+  return PPL_OK;
+}
+
+int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,
+                const ppl_iter_opts_t* opts, ppl_iter_report_t* rep) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!L || !e_occ || !e_vir || !t2) return fail(PPL_E_ARG, "null device pointer");
+  ppl_iter_opts_t o;
+  if (opts) o = *opts; else ppl_iter_opts_default(&o);
+  if (o.max_sweeps < 1) return fail(PPL_E_ARG, "max_sweeps must be >= 1");
+  if (o.start < PPL_START_MP2 || o.start > PPL_START_GIVEN_CHECKED) return fail(PPL_E_ARG, "bad start");
+  ppl_iter_report_t r;
+  memset(&r, 0, sizeof(r));
+  hipStream_t st = p->stream;
+  double* partials = at<double>(p, p->red);
+  double* red_out = partials + kReduceBlocks * 4;
+  double h[4];
+
+  // integrals: V = (ia|jb) packed into VS / VA, then V+- of every operand set
+  PPL_TRY(stage_ov(st, L, p->o, p->v, p->naux, p->ldx, at<double>(p, p->xov)));
+  const int64_t ov = (int64_t)p->o * p->v;
+  double* vfull = at<double>(p, p->g);
+  PPL_TRY(gemm_store_f64(st, ov, ov, p->ldx, at<double>(p, p->xov), p->ldx, at<double>(p, p->xov), p->ldx,
+                         vfull, ov));
+  PPL_TRY(pack_pm(st, p->o, p->v, vfull, (int64_t)p->v * ov, p->v, ov, 1, 0.5, 0.5, 0.5,
+                  at<double>(p, p->vs), p->ldp, at<double>(p, p->va), p->ldm, at<int>(p, p->tab_op),
+                  at<int>(p, p->tab_om), at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+  PPL_TRY(ppl_build_batch(p, L, -1));
+
+  const int* tabs[4] = {at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp),
+                        at<int>(p, p->tab_vm)};
+  double* s64 = at<double>(p, p->s64);
+  double* a64 = at<double>(p, p->a64);
+  auto load_mp2 = [&]() -> int {
+    return mp2_start(st, p->o, p->v, e_occ, e_vir, at<double>(p, p->vs), at<double>(p, p->va), p->ldp,
+                     p->ldm, s64, a64, tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out);
+  };
+  auto load_given = [&]() -> int {
+    return pack_pm(st, p->o, p->v, t2, (int64_t)p->o * p->v * p->v, (int64_t)p->v * p->v, p->v, 1, 1.0,
+                   0.5, 1.0, s64, p->ldp, a64, p->ldm, tabs[0], tabs[1], tabs[2], tabs[3]);
+  };
+  if (o.start == PPL_START_MP2) PPL_TRY(load_mp2());
+  else PPL_TRY(load_given());
+  PPL_TRY(energy_only(st, p->o, p->v, at<double>(p, p->vs), at<double>(p, p->va), s64, a64, p->ldp, p->ldm,
+                      tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out));
+  PPL_TRY(read_red(p, h));
+  r.energy_start = h[1];
+  if (h[2] != 0.0 || !isfinite(h[1])) {
+    r.status = PPL_E_NONFINITE;
+    if (rep) *rep = r;
+    return fail(PPL_E_NONFINITE, "non-finite start amplitudes");
+  }
+
+  // which operand set a sweep uses
+  const bool mixed = p->ops[0].prec != PPL_FP64;
+  const int fp64_set = mixed ? (p->ops[1].present ? 1 : -1) : 0;
+  bool lp_phase = mixed;
+  int fp64_sweeps = 0;
+  double r_prev = -1.0, r_first = -1.0;
+  int status = PPL_E_NOCONV;
+  int sweeps = 0;
+
+  auto sweep_once = [&](OperandSet& s) -> int {
+    PPL_TRY(refresh_operands(p, s));
+    PPL_TRY(contract_packed(p, s));
+    ProfScope ps(p, PPL_PROF_UPDATE, 0.0);
+    PPL_TRY(update_sweep(st, s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, e_occ, e_vir,
+                         at<double>(p, p->vs), at<double>(p, p->va), at<void>(p, p->rp), at<void>(p, p->rm),
+                         p->ldp, p->ldm, s64, a64, tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out));
+    return read_red(p, h);
+  };
+  auto count_sweep = [&](const OperandSet& s, double rr) {
+    if (o.history && sweeps < o.max_sweeps) o.history[sweeps] = rr;
+    ++sweeps;
+    if (s.prec == PPL_FP64) { ++r.sweeps_fp64; ++fp64_sweeps; } else { ++r.sweeps_lp; }
+    r.residual = rr;
+    r.energy = h[1];
+  };
+
+  // A checked start runs the first sweep from the given amplitudes and from MP2
+  // and keeps whichever has the smaller first residual (both sweeps count).
+  if (o.start == PPL_START_GIVEN_CHECKED && o.max_sweeps >= 2) {
+    OperandSet& s0 = (lp_phase || fp64_set < 0) ? p->ops[0] : p->ops[fp64_set];
+    PPL_TRY(sweep_once(s0));
+    const double r_given = sqrt(fabs(h[0]));
+    const double e_given = h[1];
+    const bool given_ok = h[2] == 0.0 && isfinite(r_given);
+    count_sweep(s0, r_given);
+    // keep the given start's first iterate
+    PPL_TRY(convert_rows(st, PPL_FP64, s64, p->Np, p->Pp, p->ldp, at<void>(p, p->bs), nullptr));
+    if (p->Nm > 0) PPL_TRY(convert_rows(st, PPL_FP64, a64, p->Nm, p->Pm, p->ldm, at<void>(p, p->ba), nullptr));
+    PPL_TRY(load_mp2());
+    PPL_TRY(sweep_once(s0));
+    const double r_mp2 = sqrt(fabs(h[0]));
+    count_sweep(s0, r_mp2);
+    if (given_ok && r_given <= r_mp2) {
+      PPL_TRY(convert_rows(st, PPL_FP64, at<double>(p, p->bs), p->Np, p->Pp, p->ldp, s64, nullptr));
+      if (p->Nm > 0) PPL_TRY(convert_rows(st, PPL_FP64, at<double>(p, p->ba), p->Nm, p->Pm, p->ldm, a64, nullptr));
+      r.residual = r_given;
+      r.energy = e_given;
+    } else {
+      r.restarted_mp2 = 1;
+    }
+    r_first = r.residual;
+    r_prev = r.residual;
+  }
+
+  while (sweeps < o.max_sweeps) {
+    OperandSet& s = (lp_phase || fp64_set < 0) ? p->ops[0] : p->ops[fp64_set];
+    PPL_TRY(sweep_once(s));
+    const double rr = sqrt(fabs(h[0]));
+    count_sweep(s, rr);
+    if (r_first < 0) r_first = rr;
+    if (h[2] != 0.0 || !isfinite(rr) || !isfinite(h[1])) { status = PPL_E_NONFINITE; break; }
+    if (o.diverge_factor > 0 && rr > o.diverge_factor * r_first) { status = PPL_E_DIVERGED; break; }
+    if (lp_phase) {
+      const bool stagnant = r_prev > 0 && rr / r_prev > o.stagnation;
+      if (fp64_set >= 0 && (rr < o.switch_tol || stagnant)) lp_phase = false;
+      else if (fp64_set < 0 && o.tol > 0 && rr < o.tol) { status = PPL_OK; break; }
+    } else {
+      const int need = mixed ? o.min_fp64_sweeps : 0;
+      if (o.tol > 0 && rr < o.tol && fp64_sweeps >= need) { status = PPL_OK; break; }
+    }
+    r_prev = rr;
+  }
+  if (o.tol <= 0 && status == PPL_E_NOCONV) status = PPL_OK;   // fixed sweep count requested
+  PPL_TRY(unpack_t(st, p->o, p->v, s64, p->ldp, a64, p->ldm, t2));
+  PPL_HIP_TRY(hipStreamSynchronize(st));
+  r.status = status;
+  if (rep) *rep = r;
+  if (status == PPL_E_NOCONV && !o.fail_on_noconv) return PPL_OK;
+  if (status != PPL_OK)
+    return fail(status, "iteration ended with status %d after %d sweeps (residual %.3e)", status, sweeps,
+                r.residual);
+  return PPL_OK;
+}
+
+int ppl_profile_enable(ppl_plan_t p, int on) {
+  PPL_TRY(check_plan(p));
+  if (on) {
+    if (p->prof_next > 0) PPL_HIP_TRY(hipStreamSynchronize(p->stream));
+    p->prof_recs.clear();
+    p->prof_next = 0;
+  }
+  p->prof_on = on != 0;
+  return PPL_OK;
+}
+
+int ppl_profile_read(ppl_plan_t p, ppl_profile_t* out) {
+  PPL_TRY(check_plan(p));
+  if (!out) return fail(PPL_E_ARG, "null profile");
+  memset(out, 0, sizeof(*out));
+  PPL_HIP_TRY(hipStreamSynchronize(p->stream));
+  for (const auto& r : p->prof_recs) {
+    float ms = 0.f;
+    PPL_HIP_TRY(hipEventElapsedTime(&ms, p->prof_pool[r.ev], p->prof_pool[r.ev + 1]));
+    out->launches[r.kind] += 1;
+    out->ms[r.kind] += ms;
+    out->flops[r.kind] += r.flops;
+  }
+  return PPL_OK;
+}
+
+int ppl_destroy(ppl_plan_t p) {
+  if (!p) return PPL_OK;
+  for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
+  delete p;
+  return PPL_OK;
+}
+
+}  // extern "C"

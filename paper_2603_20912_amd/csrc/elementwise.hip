@@ -1,0 +1,542 @@
+// Memory-bound kernels around the MFMA GEMMs: staging of the Cholesky blocks,
+// packing into the symmetric/antisymmetric pair layout, unpacking of results,
+// the packed Jacobi update with its FP64 residual/energy reductions.
+//
+// Pair layout (i<=j / a<=b, "+"; i<j / a<b, "-"), for pair-symmetric t
+// (t_ij^ab = t_ji^ba, eq. (2)):
+//   s_ij^ab = (t_ij^ab + t_ij^ba)/2 is symmetric in (a,b) and in (i,j),
+//   a_ij^ab = (t_ij^ab - t_ij^ba)/2 is antisymmetric in both,
+// and the ladder term of eq. (vfunction-chol) splits into
+//   R+ = V+ S',  S'[(ij)][(cd)] = (2 - delta_cd) s_ij^cd,
+//   R- = V- A',  A'[(ij)][(cd)] = 2 a_ij^cd,
+// with V+-[(ab)][(cd)] = ((ac|bd) +- (ad|bc))/2, and R = R+ + R- on the
+// (i<=j, a<=b) half, the rest following from the two (anti)symmetries.
+// The Fock denominator D_ij^ab = e_i + e_j - e_a - e_b is symmetric in (a,b) and
+// (i,j), so the update t <- (V + R)/D acts on each part separately.
+#include "ppl_internal.h"
+
+namespace ppl {
+
+static inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+#define PPL_LAUNCH_CHECK() PPL_HIP_TRY(hipGetLastError())
+
+// ------------------------------------------------------------------ fill / tables
+__global__ void zero_kernel(uint4* p, int64_t n16) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += st)
+    p[i] = uint4{0, 0, 0, 0};
+}
+
+int zero_bytes(hipStream_t s, void* p, uint64_t bytes) {
+  if (bytes == 0) return PPL_OK;
+  if (bytes % 16 != 0 || ((uintptr_t)p) % 16 != 0)
+    return fail(PPL_E_ARG, "zero_bytes: unaligned range");
+  const int64_t n16 = (int64_t)(bytes / 16);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n16, 256, 8192)), dim3(256), 0, s, (uint4*)p, n16);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+__global__ void tables_kernel(int n, int* plus, int* minus) {
+  const int64_t total = (int64_t)n * n;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int a = (int)(x / n), b = (int)(x % n);
+    if (a <= b) plus[pair_plus(a, b, n)] = (a << 16) | b;
+    if (a < b) minus[pair_minus(a, b, n)] = (a << 16) | b;
+  }
+}
+
+int fill_tables(hipStream_t s, int o, int v, int* tab_vp, int* tab_vm, int* tab_op, int* tab_om) {
+  hipLaunchKernelGGL(tables_kernel, dim3(grid_for((int64_t)v * v, 256)), dim3(256), 0, s, v, tab_vp, tab_vm);
+  PPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(tables_kernel, dim3(grid_for((int64_t)o * o, 256)), dim3(256), 0, s, o, tab_op, tab_om);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// ------------------------------------------------------------------ precision helpers
+template <int PREC> struct Store;
+template <> struct Store<PPL_FP64> {
+  __device__ static void put(void* hi, void*, int64_t i, double x) { ((double*)hi)[i] = x; }
+};
+template <> struct Store<PPL_FP32> {
+  __device__ static void put(void* hi, void*, int64_t i, double x) { ((float*)hi)[i] = (float)x; }
+};
+template <> struct Store<PPL_BF16X3> {
+  // x -> FP32 (round to nearest), hi = bf16(x32), lo = bf16(x32 - hi); both round to nearest even
+  __device__ static void put(void* hi, void* lo, int64_t i, double x) {
+    const float xf = (float)x;
+    const __bf16 h = (__bf16)xf;
+    const __bf16 l = (__bf16)(xf - (float)h);
+    ((__bf16*)hi)[i] = h;
+    ((__bf16*)lo)[i] = l;
+  }
+};
+
+// ------------------------------------------------------------------ staging (transposing copy)
+// X[r1*R2 + r2][P] = L[P][r1_off + r1][r2_off + r2] for P < naux, 0 for naux <= P < ldx.
+template <int PREC>
+__global__ void __launch_bounds__(256)
+stage_kernel(const double* __restrict__ L, int n, int naux, int r1_off, int r2_off, int R2,
+             int64_t rows, int64_t ldx, void* xh, void* xl) {
+  __shared__ double sh[32][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int P0 = blockIdx.y * 32;
+  const int tid = threadIdx.x;
+  {  // load: 64 consecutive rows for each of 32 vectors P
+    const int rr = tid & 63;
+    const int64_t r = r0 + rr;
+    int64_t src = -1;
+    if (r < rows) {
+      const int64_t r1 = r / R2, r2 = r - r1 * R2;
+      src = (r1_off + r1) * (int64_t)n + r2_off + r2;
+    }
+    for (int pp = tid >> 6; pp < 32; pp += 4) {
+      const int P = P0 + pp;
+      double x = 0.0;
+      if (src >= 0 && P < naux) x = L[(int64_t)P * n * n + src];
+      sh[pp][rr] = x;
+    }
+  }
+  __syncthreads();
+  {  // store: 32 consecutive P for each row
+    const int pp = tid & 31;
+    for (int rr = tid >> 5; rr < 64; rr += 8) {
+      const int64_t r = r0 + rr;
+      const int P = P0 + pp;
+      if (r < rows && P < ldx) Store<PREC>::put(xh, xl, r * ldx + P, sh[pp][rr]);
+    }
+  }
+}
+
+template <int PREC>
+static int stage_launch(hipStream_t s, const double* L, int n, int naux, int r1_off, int r2_off,
+                        int R1, int R2, int64_t ldx, void* xh, void* xl) {
+  const int64_t rows = (int64_t)R1 * R2;
+  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((ldx + 31) / 32));
+  hipLaunchKernelGGL(stage_kernel<PREC>, grid, dim3(256), 0, s, L, n, naux, r1_off, r2_off, R2, rows,
+                     ldx, xh, xl);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+int stage_vv(hipStream_t s, int prec, const double* L, int o, int v, int naux, int64_t ldx, void* xt,
+             void* xt_lo) {
+  const int n = o + v;
+  if (prec == PPL_FP64) return stage_launch<PPL_FP64>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
+  if (prec == PPL_FP32) return stage_launch<PPL_FP32>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
+  if (prec == PPL_BF16X3) return stage_launch<PPL_BF16X3>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
+  return fail(PPL_E_ARG, "stage_vv: unknown precision %d", prec);
+}
+
+int stage_ov(hipStream_t s, const double* L, int o, int v, int naux, int64_t ldx, double* xov) {
+  return stage_launch<PPL_FP64>(s, L, o + v, naux, 0, o, o, v, ldx, xov, nullptr);
+}
+
+// ------------------------------------------------------------------ G -> V+ / V- rows
+// One block per pair (a,b) of the batch; 32 x 32 tiles (cB <= dB) of G_ab and
+// of its transpose are staged through LDS so that both reads and the packed
+// row writes are contiguous.
+template <class Tg, int PREC>
+__global__ void __launch_bounds__(256)
+pack_vpm_kernel(int v, int64_t pair0, const Tg* __restrict__ G, const int* __restrict__ tab_vp,
+                void* vp, void* vp_lo, int64_t ldp, int64_t vp_row0, void* vm, void* vm_lo,
+                int64_t ldm, int64_t vm_row0, int64_t Pp, int64_t Pm) {
+  __shared__ double t1[32][33], t2[32][33];
+  const int64_t pr = pair0 + blockIdx.x;           // global V+ row of this block
+  const int ab = tab_vp[pr];
+  const int a = pair_first(ab), b = pair_second(ab);
+  const Tg* g = G + (int64_t)blockIdx.x * v * v;
+  const int64_t rowp = pr - vp_row0;
+  const bool has_minus = a < b;
+  const int64_t rowm = has_minus ? pair_minus(a, b, v) - vm_row0 : 0;
+  const int tid = threadIdx.x;
+  const int nt = (v + 31) / 32;
+  for (int cb = 0; cb < nt; ++cb) {
+    for (int db = cb; db < nt; ++db) {
+      // t1[c][d] = G[cB+c][dB+d], t2[c][d] = G[dB+d][cB+c]
+      for (int e = tid; e < 1024; e += 256) {
+        const int r = e >> 5, q = e & 31;
+        const int c1 = cb * 32 + r, d1 = db * 32 + q;
+        t1[r][q] = (c1 < v && d1 < v) ? (double)g[(int64_t)c1 * v + d1] : 0.0;
+        const int c2 = db * 32 + r, d2 = cb * 32 + q;   // row d, col c
+        t2[q][r] = (c2 < v && d2 < v) ? (double)g[(int64_t)c2 * v + d2] : 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 256) {
+        const int r = e >> 5, q = e & 31;
+        const int c = cb * 32 + r, d = db * 32 + q;
+        if (c < v && d < v && c <= d) {
+          const double gcd = t1[r][q], gdc = t2[r][q];
+          Store<PREC>::put(vp, vp_lo, rowp * ldp + pair_plus(c, d, v), 0.5 * (gcd + gdc));
+          if (has_minus && c < d)
+            Store<PREC>::put(vm, vm_lo, rowm * ldm + pair_minus(c, d, v), 0.5 * (gcd - gdc));
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // zero padding columns
+  for (int64_t k = Pp + tid; k < ldp; k += 256) Store<PREC>::put(vp, vp_lo, rowp * ldp + k, 0.0);
+  if (has_minus)
+    for (int64_t k = Pm + tid; k < ldm; k += 256) Store<PREC>::put(vm, vm_lo, rowm * ldm + k, 0.0);
+}
+
+int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
+             int64_t ldp, int64_t vp_row0, void* vm, void* vm_lo, int64_t ldm, int64_t vm_row0,
+             const int* tab_vp, const int* tab_vm) {
+  (void)tab_vm;
+  const int64_t p0 = pair_plus(a0, a0, v);
+  const int64_t p1 = (a1 >= v) ? npairs_plus(v) : pair_plus(a1, a1, v);
+  const int64_t npairs = p1 - p0;
+  if (npairs <= 0) return PPL_OK;
+  const int64_t Pp = npairs_plus(v), Pm = npairs_minus(v);
+  dim3 grid((unsigned)npairs);
+  if (prec == PPL_FP64)
+    hipLaunchKernelGGL((pack_vpm_kernel<double, PPL_FP64>), grid, dim3(256), 0, s, v, p0,
+                       (const double*)G, tab_vp, vp, vp_lo, ldp, vp_row0, vm, vm_lo, ldm, vm_row0, Pp, Pm);
+  else if (prec == PPL_FP32)
+    hipLaunchKernelGGL((pack_vpm_kernel<float, PPL_FP32>), grid, dim3(256), 0, s, v, p0,
+                       (const float*)G, tab_vp, vp, vp_lo, ldp, vp_row0, vm, vm_lo, ldm, vm_row0, Pp, Pm);
+  else if (prec == PPL_BF16X3)
+    hipLaunchKernelGGL((pack_vpm_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, p0,
+                       (const float*)G, tab_vp, vp, vp_lo, ldp, vp_row0, vm, vm_lo, ldm, vm_row0, Pp, Pm);
+  else
+    return fail(PPL_E_ARG, "pack_vpm: unknown precision %d", prec);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// ------------------------------------------------------------------ generic (i,j,a,b) -> +/- packing
+__global__ void pack_plus_kernel(const double* __restrict__ X, int64_t si, int64_t sj, int64_t sa,
+                                 int64_t sb, double s_off, double s_diag, double* plus, int64_t Np,
+                                 int64_t Pp, int64_t ldp, const int* __restrict__ tab_op,
+                                 const int* __restrict__ tab_vp) {
+  const int64_t total = Np * ldp;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int64_t q = x / ldp, p = x - q * ldp;
+    double val = 0.0;
+    if (p < Pp) {
+      const int ij = tab_op[q], ab = tab_vp[p];
+      const int i = pair_first(ij), j = pair_second(ij), a = pair_first(ab), b = pair_second(ab);
+      const int64_t base = i * si + j * sj;
+      const double xab = X[base + a * sa + b * sb], xba = X[base + b * sa + a * sb];
+      val = (a == b ? s_diag : s_off) * (xab + xba);
+    }
+    plus[x] = val;
+  }
+}
+
+__global__ void pack_minus_kernel(const double* __restrict__ X, int64_t si, int64_t sj, int64_t sa,
+                                  int64_t sb, double am, double* minus, int64_t Nm, int64_t Pm,
+                                  int64_t ldm, const int* __restrict__ tab_om,
+                                  const int* __restrict__ tab_vm) {
+  const int64_t total = Nm * ldm;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int64_t q = x / ldm, p = x - q * ldm;
+    double val = 0.0;
+    if (p < Pm) {
+      const int ij = tab_om[q], ab = tab_vm[p];
+      const int i = pair_first(ij), j = pair_second(ij), a = pair_first(ab), b = pair_second(ab);
+      const int64_t base = i * si + j * sj;
+      val = am * (X[base + a * sa + b * sb] - X[base + b * sa + a * sb]);
+    }
+    minus[x] = val;
+  }
+}
+
+int pack_pm(hipStream_t s, int o, int v, const double* X, int64_t si, int64_t sj, int64_t sa,
+            int64_t sb, double sp_off, double sp_diag, double am, double* plus, int64_t ldp,
+            double* minus, int64_t ldm, const int* tab_op, const int* tab_om, const int* tab_vp,
+            const int* tab_vm) {
+  const int64_t Np = npairs_plus(o), Nm = npairs_minus(o), Pp = npairs_plus(v), Pm = npairs_minus(v);
+  hipLaunchKernelGGL(pack_plus_kernel, dim3(grid_for(Np * ldp, 256)), dim3(256), 0, s, X, si, sj, sa,
+                     sb, sp_off, sp_diag, plus, Np, Pp, ldp, tab_op, tab_vp);
+  PPL_LAUNCH_CHECK();
+  if (Nm > 0) {
+    hipLaunchKernelGGL(pack_minus_kernel, dim3(grid_for(Nm * ldm, 256)), dim3(256), 0, s, X, si, sj,
+                       sa, sb, am, minus, Nm, Pm, ldm, tab_om, tab_vm);
+    PPL_LAUNCH_CHECK();
+  }
+  return PPL_OK;
+}
+
+// ------------------------------------------------------------------ FP64 rows -> operand precision
+template <int PREC>
+__global__ void convert_kernel(const double* __restrict__ src, int64_t n, void* dh, void* dl) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += st)
+    Store<PREC>::put(dh, dl, x, src[x]);
+}
+
+int convert_rows(hipStream_t s, int prec, const double* src, int64_t rows, int64_t cols, int64_t ld,
+                 void* dst, void* dst_lo) {
+  (void)cols;
+  const int64_t n = rows * ld;
+  if (n <= 0) return PPL_OK;
+  if (prec == PPL_FP32)
+    hipLaunchKernelGGL(convert_kernel<PPL_FP32>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
+  else if (prec == PPL_BF16X3)
+    hipLaunchKernelGGL(convert_kernel<PPL_BF16X3>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
+  else if (prec == PPL_FP64)
+    hipLaunchKernelGGL(convert_kernel<PPL_FP64>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
+  else
+    return fail(PPL_E_ARG, "convert_rows: unknown precision %d", prec);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// ------------------------------------------------------------------ unpack R and t
+template <class Tr>
+__global__ void unpack_r_kernel(int o, int v, const Tr* __restrict__ rp, int64_t ldp,
+                                const Tr* __restrict__ rm, int64_t ldm, double* R, double alpha,
+                                double beta) {
+  const int64_t total = (int64_t)o * o * v * v;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int b = (int)(x % v);
+    const int64_t y = x / v;
+    const int a = (int)(y % v);
+    const int64_t z = y / v;
+    const int j = (int)(z % o), i = (int)(z / o);
+    const int i0 = i < j ? i : j, j0 = i < j ? j : i;
+    const int a0 = a < b ? a : b, b0 = a < b ? b : a;
+    double r = (double)rp[pair_plus(i0, j0, o) * ldp + pair_plus(a0, b0, v)];
+    if (i != j && a != b) {
+      const double m = (double)rm[pair_minus(i0, j0, o) * ldm + pair_minus(a0, b0, v)];
+      r += ((i < j) == (a < b)) ? m : -m;
+    }
+    R[x] = (beta == 0.0) ? alpha * r : alpha * r + beta * R[x];
+  }
+}
+
+int unpack_r(hipStream_t s, int acc_prec, int o, int v, const void* rp, int64_t ldp, const void* rm,
+             int64_t ldm, double* R, double alpha, double beta) {
+  const int64_t total = (int64_t)o * o * v * v;
+  if (acc_prec == PPL_FP64)
+    hipLaunchKernelGGL(unpack_r_kernel<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v,
+                       (const double*)rp, ldp, (const double*)rm, ldm, R, alpha, beta);
+  else
+    hipLaunchKernelGGL(unpack_r_kernel<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v,
+                       (const float*)rp, ldp, (const float*)rm, ldm, R, alpha, beta);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+__global__ void unpack_t_kernel(int o, int v, const double* __restrict__ sp, int64_t ldp,
+                                const double* __restrict__ am, int64_t ldm, double* t2) {
+  const int64_t total = (int64_t)o * o * v * v;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int b = (int)(x % v);
+    const int64_t y = x / v;
+    const int a = (int)(y % v);
+    const int64_t z = y / v;
+    const int j = (int)(z % o), i = (int)(z / o);
+    const int i0 = i < j ? i : j, j0 = i < j ? j : i;
+    const int a0 = a < b ? a : b, b0 = a < b ? b : a;
+    const double spv = sp[pair_plus(i0, j0, o) * ldp + pair_plus(a0, b0, v)];
+    double t = (a == b) ? spv : 0.5 * spv;        // s = S' / (2 - delta_ab)
+    if (i != j && a != b) {
+      const double h = 0.5 * am[pair_minus(i0, j0, o) * ldm + pair_minus(a0, b0, v)];  // a = A'/2
+      t += ((i < j) == (a < b)) ? h : -h;
+    }
+    t2[x] = t;
+  }
+}
+
+int unpack_t(hipStream_t s, int o, int v, const double* sp, int64_t ldp, const double* am,
+             int64_t ldm, double* t2) {
+  const int64_t total = (int64_t)o * o * v * v;
+  hipLaunchKernelGGL(unpack_t_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v, sp, ldp, am,
+                     ldm, t2);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// ------------------------------------------------------------------ reductions
+// Fixed grid (kReduceBlocks x kReduceThreads), grid-stride loops and a fixed
+// tree order: the sums are bitwise reproducible for a given problem size.
+template <int NV>
+__device__ inline void block_reduce_store(double (&vals)[NV], double* partials) {
+  __shared__ double sh[NV][kReduceThreads];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) sh[k][tid] = vals[k];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) sh[k][tid] += sh[k][tid + w];
+    __syncthreads();
+  }
+  if (tid == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) partials[blockIdx.x * 4 + k] = sh[k][0];
+}
+
+__global__ void final_reduce_kernel(const double* __restrict__ partials, int nblocks, double* out) {
+  __shared__ double sh[4][kReduceThreads];
+  const int tid = threadIdx.x;
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = tid; b < nblocks; b += kReduceThreads)
+    for (int k = 0; k < 4; ++k) acc[k] += partials[b * 4 + k];
+  for (int k = 0; k < 4; ++k) sh[k][tid] = acc[k];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int k = 0; k < 4; ++k) sh[k][tid] += sh[k][tid + w];
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int k = 0; k < 4; ++k) out[k] = sh[k][0];
+}
+
+struct PairGeom {
+  int o, v;
+  int64_t Np, Nm, Pp, Pm, ldp, ldm;
+  const int *tab_op, *tab_om, *tab_vp, *tab_vm;
+};
+
+// Denominator of a packed element
+__device__ inline double denom(const double* e_occ, const double* e_vir, int ij, int ab) {
+  return e_occ[pair_first(ij)] + e_occ[pair_second(ij)] - e_vir[pair_first(ab)] - e_vir[pair_second(ab)];
+}
+
+// mode 0: MP2 start   S' = (2-d_ab) VS / D, A' = 2 VA / D, energy of the result
+// mode 1: Jacobi update from R+- (type Tr); residual^2, energy, non-finite count
+// mode 2: energy of the current S'/A' only
+template <int MODE, class Tr>
+__global__ void __launch_bounds__(kReduceThreads)
+sweep_kernel(PairGeom g, const double* __restrict__ e_occ, const double* __restrict__ e_vir,
+             const double* __restrict__ vs, const double* __restrict__ va, const Tr* __restrict__ rp,
+             const Tr* __restrict__ rm, double* sp, double* am, double* partials) {
+  double r2 = 0.0, en = 0.0, bad = 0.0;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // "+" part: weights (2 - d_ij)(2 - d_ab) turn packed sums into full-tensor sums
+  const int64_t totp = g.Np * g.ldp;
+  for (int64_t x = tid0; x < totp; x += st) {
+    const int64_t q = x / g.ldp, p = x - q * g.ldp;
+    if (p >= g.Pp) continue;
+    const int ij = g.tab_op[q], ab = g.tab_vp[p];
+    const bool dij = pair_first(ij) == pair_second(ij), dab = pair_first(ab) == pair_second(ab);
+    const double w = (dij ? 1.0 : 2.0) * (dab ? 1.0 : 2.0);
+    const double wab = dab ? 1.0 : 2.0;             // S' = wab * s
+    const double vsx = vs[x];
+    double snew;
+    if (MODE == 0) {
+      snew = vsx / denom(e_occ, e_vir, ij, ab);
+      sp[x] = wab * snew;
+    } else if (MODE == 1) {
+      snew = (vsx + (double)rp[x]) / denom(e_occ, e_vir, ij, ab);
+      const double sold = sp[x] / wab;
+      const double ds = snew - sold;
+      r2 += w * ds * ds;
+      sp[x] = wab * snew;
+    } else {
+      snew = sp[x] / wab;
+    }
+    if (!isfinite(snew)) bad += 1.0;
+    en += w * vsx * snew;
+  }
+  // "-" part: every packed (i<j, a<b) entry stands for 4 full-tensor entries
+  const int64_t totm = g.Nm * g.ldm;
+  for (int64_t x = tid0; x < totm; x += st) {
+    const int64_t q = x / g.ldm, p = x - q * g.ldm;
+    if (p >= g.Pm) continue;
+    const int ij = g.tab_om[q], ab = g.tab_vm[p];
+    const double vax = va[x];
+    double anew;
+    if (MODE == 0) {
+      anew = vax / denom(e_occ, e_vir, ij, ab);
+      am[x] = 2.0 * anew;
+    } else if (MODE == 1) {
+      anew = (vax + (double)rm[x]) / denom(e_occ, e_vir, ij, ab);
+      const double da = anew - 0.5 * am[x];
+      r2 += 4.0 * da * da;
+      am[x] = 2.0 * anew;
+    } else {
+      anew = 0.5 * am[x];
+    }
+    if (!isfinite(anew)) bad += 1.0;
+    en += 12.0 * vax * anew;                        // E = sum V^S s + 3 sum V^A a (full tensor)
+  }
+  double vals[3] = {r2, en, bad};
+  block_reduce_store<3>(vals, partials);
+}
+
+template <int MODE, class Tr>
+static int sweep_launch(hipStream_t s, const PairGeom& g, const double* e_occ, const double* e_vir,
+                        const double* vs, const double* va, const void* rp, const void* rm,
+                        double* sp, double* am, double* partials, double* red_out) {
+  hipLaunchKernelGGL((sweep_kernel<MODE, Tr>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, g,
+                     e_occ, e_vir, vs, va, (const Tr*)rp, (const Tr*)rm, sp, am, partials);
+  PPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials,
+                     kReduceBlocks, red_out);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+static PairGeom geom(int o, int v, int64_t ldp, int64_t ldm, const int* tab_op, const int* tab_om,
+                     const int* tab_vp, const int* tab_vm) {
+  return PairGeom{o, v, npairs_plus(o), npairs_minus(o), npairs_plus(v), npairs_minus(v), ldp, ldm,
+                  tab_op, tab_om, tab_vp, tab_vm};
+}
+
+int mp2_start(hipStream_t s, int o, int v, const double* e_occ, const double* e_vir, const double* vs,
+              const double* va, int64_t ldp, int64_t ldm, double* sp, double* am, const int* tab_op,
+              const int* tab_om, const int* tab_vp, const int* tab_vm, double* partials,
+              double* red_out) {
+  PairGeom g = geom(o, v, ldp, ldm, tab_op, tab_om, tab_vp, tab_vm);
+  return sweep_launch<0, double>(s, g, e_occ, e_vir, vs, va, nullptr, nullptr, sp, am, partials, red_out);
+}
+
+int update_sweep(hipStream_t s, int acc_prec, int o, int v, const double* e_occ, const double* e_vir,
+                 const double* vs, const double* va, const void* rp, const void* rm, int64_t ldp,
+                 int64_t ldm, double* sp, double* am, const int* tab_op, const int* tab_om,
+                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out) {
+  PairGeom g = geom(o, v, ldp, ldm, tab_op, tab_om, tab_vp, tab_vm);
+  if (acc_prec == PPL_FP64)
+    return sweep_launch<1, double>(s, g, e_occ, e_vir, vs, va, rp, rm, sp, am, partials, red_out);
+  return sweep_launch<1, float>(s, g, e_occ, e_vir, vs, va, rp, rm, sp, am, partials, red_out);
+}
+
+int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va, const double* sp,
+                const double* am, int64_t ldp, int64_t ldm, const int* tab_op, const int* tab_om,
+                const int* tab_vp, const int* tab_vm, double* partials, double* red_out) {
+  PairGeom g = geom(o, v, ldp, ldm, tab_op, tab_om, tab_vp, tab_vm);
+  return sweep_launch<2, double>(s, g, nullptr, nullptr, vs, va, nullptr, nullptr, (double*)sp,
+                                 (double*)am, partials, red_out);
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+nonfinite_kernel(const double* __restrict__ x, int64_t n, double* partials) {
+  double bad = 0.0;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += st)
+    if (!isfinite(x[i])) bad += 1.0;
+  double vals[3] = {0.0, 0.0, bad};
+  block_reduce_store<3>(vals, partials);
+}
+
+int count_nonfinite(hipStream_t s, const double* x, int64_t n, double* partials, double* red_out) {
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, x, n, partials);
+  PPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials,
+                     kReduceBlocks, red_out);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+}  // namespace ppl

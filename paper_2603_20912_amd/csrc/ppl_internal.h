@@ -1,0 +1,205 @@
+// Internal definitions shared by the host side and the kernels of libppl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ppl.h"
+
+namespace ppl {
+
+// ------------------------------------------------------------------ pair indices
+// Row-major packed upper triangles of an n x n index space:
+//   plus : pairs (a, b) with a <= b, index a*n - a(a+1)/2 + b
+//   minus: pairs (a, b) with a <  b, index a*(n-1) - a(a+1)/2 + b - 1
+__host__ __device__ inline int64_t pair_plus(int64_t a, int64_t b, int64_t n) {
+  return a * n - a * (a + 1) / 2 + b;
+}
+__host__ __device__ inline int64_t pair_minus(int64_t a, int64_t b, int64_t n) {
+  return a * (n - 1) - a * (a + 1) / 2 + b - 1;
+}
+__host__ __device__ inline int64_t npairs_plus(int64_t n) { return n * (n + 1) / 2; }
+__host__ __device__ inline int64_t npairs_minus(int64_t n) { return n * (n - 1) / 2; }
+
+// pair tables store (a << 16) | b
+__host__ __device__ inline int pair_first(int packed) { return packed >> 16; }
+__host__ __device__ inline int pair_second(int packed) { return packed & 0xffff; }
+
+// leading dimension of every packed operand row: a multiple of 64 elements,
+// so the GEMM K loop never needs a bounds check (the padding is kept zero)
+__host__ __device__ inline int64_t pad_ld(int64_t k) { return (k + 63) / 64 * 64; }
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+#define PPL_HIP_TRY(expr)                                                                 \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return ::ppl::fail(PPL_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), \
+                         __FILE__, __LINE__);                                             \
+  } while (0)
+#define PPL_TRY(expr)            \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != PPL_OK) return _rc; \
+  } while (0)
+
+// ------------------------------------------------------------------ workspace
+struct Region {
+  uint64_t off = 0, bytes = 0;
+};
+
+// One set of packed operands in one compute precision.
+struct OperandSet {
+  int prec = PPL_FP64;     // element precision of Xt / V+- / S' / A'
+  bool present = false;
+  Region xt, xt_lo;        // staged virtual block of L, transposed to [(a,c)][P]; lo plane for BF16X3
+  Region vp, vp_lo;        // V+ rows [rows][ldp]
+  Region vm, vm_lo;        // V- rows [rows][ldm]
+  Region sp, sp_lo;        // S' [N+][ldp]
+  Region am, am_lo;        // A' [N-][ldm]
+  bool built = false;      // resident V+- complete
+};
+
+struct Batch {
+  int a0, a1;              // virtual rows a in [a0, a1)
+  int64_t p0, p1;          // V+ rows [p0, p1)
+  int64_t q0, q1;          // V- rows [q0, q1)
+};
+
+}  // namespace ppl
+
+struct ppl_plan_s {
+  // problem
+  int o = 0, v = 0, naux = 0, prec = PPL_FP64, keep_fp64 = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  uint64_t budget = 0;
+  // pair counts and padded leading dimensions
+  int64_t Pp = 0, Pm = 0, Np = 0, Nm = 0;
+  int64_t ldp = 0, ldm = 0, ldx = 0;   // row lengths of +, - operands and of Xt (K = naux)
+  // batching
+  bool resident = true;
+  std::vector<ppl::Batch> batches;
+  int a_per_batch = 0;
+  int64_t g_pairs_cap = 0;             // pairs (a<=b) one build step may hold in G
+  // tiles
+  int tile_build = 0, tile_contract = 0;
+  // workspace
+  uint64_t ws_bytes_needed = 0;
+  char* ws = nullptr;
+  uint64_t ws_bytes = 0;
+  ppl::OperandSet ops[2];              // [0] = compute precision, [1] = FP64 refinement copy (if any)
+  ppl::Region g;                       // build scratch G [pairs][v][v] (also the V-setup scratch)
+  ppl::Region rp, rm;                  // R+ [N+][ldp], R- [N-][ldm] (accumulator type of the GEMM)
+  ppl::Region s64, a64;                // FP64 master amplitudes in S'/A' form when ops[*] are not FP64
+  ppl::Region vs, va;                  // packed (ia|jb): VS [N+][ldp], VA [N-][ldm] (FP64)
+  ppl::Region bs, ba;                  // FP64 copy of S'/A' kept across the two first sweeps of a checked start
+  ppl::Region xov;                     // staged occupied-virtual block [(i,a)][ldx] (FP64)
+  ppl::Region tab_vp, tab_vm, tab_op, tab_om;  // pair tables (int32)
+  ppl::Region red;                     // reduction partials
+  ppl::Region tiles;                   // per-batch tile prefix tables of the build GEMM (int32)
+  std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
+  std::vector<int64_t> tiles_off;      // element offset of each batch's table in `tiles`
+  const double* L_last = nullptr;
+  bool setup_done = false;
+  // kernel timing
+  struct ProfRec {
+    int kind;
+    int ev;          // index of the first of two events in prof_pool
+    double flops;
+  };
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_pool;
+  std::vector<ProfRec> prof_recs;
+  int prof_next = 0;
+};
+
+namespace ppl {
+
+template <class T>
+inline T* at(ppl_plan_t p, const Region& r) {
+  return reinterpret_cast<T*>(p->ws + r.off);
+}
+
+// ------------------------------------------------------------------ kernels (launchers)
+// All launchers enqueue on the given stream and return PPL_OK or PPL_E_HIP.
+
+// Dense NT GEMM, C[M][N] = alpha * sum_k A[m][k] B[n][k] + beta * C (FP64 only; used
+// for the occupied-virtual integrals). K must be padded to ld with zeros.
+int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double* C, int64_t ldc);
+
+// Contraction C[N][P] = sum_k S[n][k] V[p][k] for one operand set (R+ or R-).
+// Output in the accumulator precision (double for FP64, float otherwise).
+int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
+                  const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
+                  int64_t ldv, void* C, int64_t ldc, int64_t c_col0);
+
+// Integral build G[pair(a,b) - pair(a0,a0)][c][d] = sum_P Xt[(a,c)][P] Xt[(b,d)][P]
+// for a in [a0, a1), b in [a, v).
+int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,
+               const void* Xt, const void* Xt_lo, int64_t ldx, void* G, const int* tile_prefix,
+               int n_mtiles, int n_ntiles, int64_t n_valid_tiles);
+// host helper: number of valid tiles and per-row-tile prefix of a build step
+void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& prefix, int& n_mtiles,
+                      int& n_ntiles);
+int build_tile_dims(int tile, int* bm, int* bn);
+int contract_tile_count();
+int contract_tile_default(int prec, int64_t Nrows);
+
+// staging: Xt[(a,c)][P] = L[P][o+a][o+c] in the operand precision (zero padding up to ldx)
+int stage_vv(hipStream_t s, int prec, const double* L, int o, int v, int naux, int64_t ldx, void* xt,
+             void* xt_lo);
+// staging: Xov[(i,a)][P] = L[P][i][o+a] (FP64)
+int stage_ov(hipStream_t s, const double* L, int o, int v, int naux, int64_t ldx, double* xov);
+// pack G (accumulator precision) into V+ / V- rows of one batch (operand precision)
+int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
+             int64_t ldp, int64_t vp_row0, void* vm, void* vm_lo, int64_t ldm, int64_t vm_row0,
+             const int* tab_vp, const int* tab_vm);
+// pair tables
+int fill_tables(hipStream_t s, int o, int v, int* tab_vp, int* tab_vm, int* tab_op, int* tab_om);
+// generic pack of an (i,j,a,b)-indexed FP64 tensor into + / - packed rows:
+//   plus [q(i<=j)][p(a<=b)] = (a<b ? sp_off : sp_diag) * (X^ab + X^ba)
+//   minus[q(i<j)][p(a<b)]   = am * (X^ab - X^ba)
+int pack_pm(hipStream_t s, int o, int v, const double* X, int64_t si, int64_t sj, int64_t sa,
+            int64_t sb, double sp_off, double sp_diag, double am, double* plus, int64_t ldp,
+            double* minus, int64_t ldm, const int* tab_op, const int* tab_om, const int* tab_vp,
+            const int* tab_vm);
+// convert FP64 packed rows to an operand precision (FP32 or BF16 hi/lo), zero padding kept
+int convert_rows(hipStream_t s, int prec, const double* src, int64_t rows, int64_t cols, int64_t ld,
+                 void* dst, void* dst_lo);
+// unpack R = beta R + alpha (R+ +- R-) into [o][o][v][v]
+int unpack_r(hipStream_t s, int acc_prec, int o, int v, const void* rp, int64_t ldp, const void* rm,
+             int64_t ldm, double* R, double alpha, double beta);
+// packed amplitudes S'/A' (FP64) back to the full pair-symmetric t2
+int unpack_t(hipStream_t s, int o, int v, const double* sp, int64_t ldp, const double* am,
+             int64_t ldm, double* t2);
+// MP2 start S' = (2 - delta_ab) VS / D, A' = 2 VA / D (red_out[1] = its energy)
+int mp2_start(hipStream_t s, int o, int v, const double* e_occ, const double* e_vir, const double* vs,
+              const double* va, int64_t ldp, int64_t ldm, double* sp, double* am, const int* tab_op,
+              const int* tab_om, const int* tab_vp, const int* tab_vm, double* partials,
+              double* red_out);
+// Jacobi update in packed space with FP64 residual^2 / energy partial sums
+// (red_out[0] = r^2, red_out[1] = E, red_out[2] = non-finite count)
+int update_sweep(hipStream_t s, int acc_prec, int o, int v, const double* e_occ, const double* e_vir,
+                 const double* vs, const double* va, const void* rp, const void* rm, int64_t ldp,
+                 int64_t ldm, double* sp, double* am, const int* tab_op, const int* tab_om,
+                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out);
+// energy of the current packed amplitudes (red_out[1] = E)
+int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va, const double* sp,
+                const double* am, int64_t ldp, int64_t ldm, const int* tab_op, const int* tab_om,
+                const int* tab_vp, const int* tab_vm, double* partials, double* red_out);
+// zero a device range (a fill kernel, never hipMemsetAsync)
+int zero_bytes(hipStream_t s, void* p, uint64_t bytes);
+// count non-finite values of an FP64 array (red_out[2])
+int count_nonfinite(hipStream_t s, const double* x, int64_t n, double* partials, double* red_out);
+
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+}  // namespace ppl

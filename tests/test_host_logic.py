@@ -1,0 +1,134 @@
+"""CPU tests of the host side of libppl: the library loads, exports every
+symbol the header declares, and the planner's decisions, byte accounting and
+error codes behave as documented. No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppl.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2603_20912_amd as P
+    from paper_2603_20912_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libppl.so is not built (run python -m paper_2603_20912_amd.build)")
+    _lib.load()
+    return P
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(ppl_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol(P):
+    from paper_2603_20912_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 10, names
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"libppl.so does not export {n}"
+    # and the binding declares a prototype for each of them
+    assert set(names) <= set(_lib.SIGNATURES), set(names) - set(_lib.SIGNATURES)
+
+
+def plan_info(P, *args, **kw):
+    kw.setdefault("stream", 0)
+    h = P.ppl_plan(*args, **kw)
+    try:
+        return P.ppl_plan_query(h)
+    finally:
+        P.ppl_destroy(h)
+
+
+def test_pair_counts_and_flops(P):
+    for o, v, naux in [(5, 20, 60), (20, 200, 600), (1, 2, 1), (7, 33, 5)]:
+        i = plan_info(P, o, v, naux, hbm_budget=1 << 40)
+        assert i["p_plus"] == v * (v + 1) // 2 and i["p_minus"] == v * (v - 1) // 2
+        assert i["n_plus"] == o * (o + 1) // 2 and i["n_minus"] == o * (o - 1) // 2
+        assert i["flops_build"] == 2.0 * naux * v * v * i["p_plus"]
+        assert i["flops_contract"] == 2.0 * (i["p_plus"] ** 2 * i["n_plus"] + i["p_minus"] ** 2 * i["n_minus"])
+
+
+def test_resident_when_budget_allows(P):
+    i = plan_info(P, 20, 200, 600, hbm_budget=64 << 30)
+    assert i["resident"] == 1
+    assert i["workspace_bytes"] <= 64 << 30
+    # FP64 V+- of (20, 200, 600): P+ rows of ldp + P- rows of ldm doubles
+    ldp = (20100 + 63) // 64 * 64
+    ldm = (19900 + 63) // 64 * 64
+    assert i["vpm_bytes"] == (20100 * ldp + 19900 * ldm) * 8
+    assert i["workspace_bytes"] > i["vpm_bytes"]
+
+
+def test_budget_forces_streaming_batches(P):
+    i = plan_info(P, 20, 200, 600, hbm_budget=1 << 30)
+    assert i["resident"] == 0 and i["n_batches"] > 1
+    assert i["workspace_bytes"] <= 1 << 30
+
+
+def test_budget_too_small_is_nomem(P):
+    with pytest.raises(P.PPLError) as e:
+        plan_info(P, 20, 200, 600, hbm_budget=1 << 20)
+    assert e.value.code == -2
+
+
+def test_mixed_precision_keeps_both_copies(P):
+    f64 = plan_info(P, 40, 400, 1200, prec="fp64", hbm_budget=280 << 30)
+    mix = plan_info(P, 40, 400, 1200, prec="bf16x3", keep_fp64=True, hbm_budget=280 << 30)
+    lp = plan_info(P, 40, 400, 1200, prec="bf16x3", keep_fp64=False, hbm_budget=280 << 30)
+    assert mix["vpm_bytes"] == f64["vpm_bytes"] + lp["vpm_bytes"]
+    assert lp["vpm_bytes"] * 2 == f64["vpm_bytes"]      # hi + lo bf16 planes = 4 bytes per element
+    assert mix["workspace_bytes"] < 280 << 30 and mix["resident"] == 1
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(o=0, v=10, naux=5), -1), (dict(o=2, v=1, naux=5), -1), (dict(o=2, v=10, naux=0), -1),
+    (dict(o=2, v=10, naux=5, prec=7), -1), (dict(o=2, v=10, naux=5, tile_contract=99), -1),
+    (dict(o=2, v=40000, naux=5), -1),
+])
+def test_invalid_arguments(P, args, code):
+    kw = dict(hbm_budget=1 << 30, stream=0)
+    kw.update(args)
+    with pytest.raises(P.PPLError) as e:
+        h = P.ppl_plan(kw.pop("o"), kw.pop("v"), kw.pop("naux"), **kw)
+        P.ppl_destroy(h)
+    assert e.value.code == code
+
+
+def test_calls_out_of_order_are_state_errors(P):
+    from paper_2603_20912_amd import _lib
+    lib = _lib.load()
+    h = P.ppl_plan(3, 8, 6, hbm_budget=1 << 30, stream=0)
+    try:
+        # no workspace bound: every device entry point refuses before touching HIP
+        assert lib.ppl_build_batch(h, ctypes.c_void_p(256), -1) == -7
+        assert lib.ppl_contract(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1.0, 0.0) == -7
+        assert "workspace" in P.ppl_last_error()
+        # misaligned workspace is an argument error
+        assert lib.ppl_bind_workspace(h, ctypes.c_void_p(300), 1 << 30) == -1
+    finally:
+        P.ppl_destroy(h)
+
+
+def test_iteration_defaults(P):
+    o = P.ppl_iter_opts_default()
+    assert o.max_sweeps == 100 and o.tol == 1e-7 and o.min_fp64_sweeps == 2
+    assert o.start == 0 and abs(o.stagnation - 0.95) < 1e-15
+
+
+def test_product_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2603_20912_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "ppl_oracle" not in txt, f
