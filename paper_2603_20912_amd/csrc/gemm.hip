@@ -17,11 +17,12 @@
 // loop never tests bounds; rows beyond M / N are clamped on load and masked
 // on store.
 //
-// Fragment layouts (16x16 output blocks, 64 lanes, l = lane):
-//   f64 16x16x4 / f32 16x16x4: lane l holds A[l%16][l/16], B[l/16][l%16],
-//                              and D[4*(l/16)+r][l%16] for r = 0..3;
-//   bf16 16x16x32:             lane l holds A[l%16][8*(l/16)+0..7],
-//                              B[8*(l/16)+0..7][l%16], D as above.
+// Fragment layouts (16x16 output blocks, 64 lanes, l = lane, r = 0..3), as
+// measured on gfx950 with one-hot operands:
+//   f64 16x16x4:   lane l holds A[l%16][l/16], B[l/16][l%16], D[4*r + l/16][l%16];
+//   f32 16x16x4:   lane l holds A[l%16][l/16], B[l/16][l%16], D[4*(l/16) + r][l%16];
+//   bf16 16x16x32: lane l holds A[l%16][8*(l/16)+0..7], B[8*(l/16)+0..7][l%16],
+//                  D[4*(l/16) + r][l%16].
 #include "ppl_internal.h"
 
 namespace ppl {
@@ -40,10 +41,23 @@ __device__ inline f4 mfma16(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// accumulator type and the row (within a 16x16 block) of accumulator register r of lane l
 template <class T> struct AccOf;
-template <> struct AccOf<double> { using type = double; using vec = d4; };
-template <> struct AccOf<float> { using type = float; using vec = f4; };
-template <> struct AccOf<__bf16> { using type = float; using vec = f4; };
+template <> struct AccOf<double> {
+  using type = double;
+  using vec = d4;
+  __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct AccOf<float> {
+  using type = float;
+  using vec = f4;
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <> struct AccOf<__bf16> {
+  using type = float;
+  using vec = f4;
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 // Spread a launch over the 8 XCDs so that each XCD walks a contiguous run of
 // logical tiles: consecutive workgroup ids land on different XCDs, so logical
@@ -227,7 +241,7 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
   for (int i = 0; i < WM; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t m = m0 + wm * WM * 16 + i * 16 + 4 * (lane >> 4) + r;
+      const int64_t m = m0 + wm * WM * 16 + i * 16 + AccOf<T>::row(lane, r);
       int64_t base;
       bool ok;
       epi.row(m, base, ok);
@@ -364,7 +378,7 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
   for (int i = 0; i < WM; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t m = m0 + wm * WM * 16 + i * 16 + 4 * (lane >> 4) + r;
+      const int64_t m = m0 + wm * WM * 16 + i * 16 + AccOf<__bf16>::row(lane, r);
       int64_t base;
       bool ok;
       epi.row(m, base, ok);
