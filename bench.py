@@ -99,6 +99,11 @@ def main():
         eng.iterate(L, eo, ev, t, max_sweeps=SWEEPS, tol=0.0, diverge_factor=0.0, history=False)
         eng.contract(t, R)
 
+    # one-time setup outside the timed region: build V+- once and let the
+    # library's autotuner pick the contraction tiles and split-K counts
+    eng.build(L)
+    eng.autotune(reps=2)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -132,7 +137,7 @@ def main():
                    "o": O_, "v": V_, "naux": NAUX_, "sweeps": SWEEPS, "precision": "fp64",
                    "useful_flops_per_step": flops_step,
                    "pct_fp64_mfma_peak": round(100.0 * value / PEAK_FP64_TFLOPS, 2),
-                   "tile_contract": eng.info["tile_contract"]},
+                   "contract_config": list(eng.contract_config())},
         "roofline": {"bound": "mfma", "kernel": "R+ contraction GEMM (FP64 MFMA 16x16x4)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,

@@ -81,7 +81,9 @@ typedef struct {
   int32_t  n_minus;           /* N- = o(o-1)/2 occupied pairs i<j */
   int32_t  p_plus;            /* P+ = v(v+1)/2 virtual pairs a<=b */
   int32_t  p_minus;           /* P- = v(v-1)/2 virtual pairs a<b */
-  int32_t  reserved;
+  int32_t  splits_contract;   /* split-K slices of the R+ contraction GEMM (1 = none) */
+  int32_t  tile_contract_minus;   /* tile id of the R- contraction GEMM */
+  int32_t  splits_contract_minus; /* split-K slices of the R- contraction GEMM */
   double   flops_build;       /* useful flops of one integral build: 2 naux v^2 P+ */
   double   flops_contract;    /* useful flops of one contraction: 2 (P+^2 N+ + P-^2 N-) */
 } ppl_plan_info_t;
@@ -169,6 +171,24 @@ void ppl_iter_opts_default(ppl_iter_opts_t* opts);
  */
 int ppl_iterate(ppl_plan_t plan, const double* L, const double* e_occ, const double* e_vir,
                 double* t2, const ppl_iter_opts_t* opts, ppl_iter_report_t* report);
+
+/* ------------------------------------------------ contraction tile configuration */
+/*
+ * ppl_set_contract_config: choose the tile id (0 .. ppl_tile_count()-1) and the
+ * split-K slice count (1 .. 4) of the R+ and R- contraction GEMMs. Split-K
+ * slices are summed in slice order, so a fixed configuration gives bitwise
+ * reproducible results. PPL_E_ARG for out-of-range values.
+ */
+int ppl_set_contract_config(ppl_plan_t plan, int32_t tile_plus, int32_t splits_plus,
+                            int32_t tile_minus, int32_t splits_minus);
+
+/*
+ * ppl_autotune: time every (tile, split-K) candidate of both contraction GEMMs
+ * `reps` times on the bound workspace with HIP events (V+- must be built;
+ * operand values do not matter) and keep the fastest of each. Synchronous.
+ * best_ms (optional, 2 doubles) receives the winning average times.
+ */
+int ppl_autotune(ppl_plan_t plan, int32_t reps, double* best_ms);
 
 /* ------------------------------------------------ kernel timing (HIP events) */
 #define PPL_PROF_BUILD_GEMM     0  /* integral-build GEMM launches */

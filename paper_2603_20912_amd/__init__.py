@@ -13,11 +13,13 @@ import torch
 from . import _lib
 from ._lib import (PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_destroy,
                    ppl_iter_opts_default, ppl_iterate, ppl_last_error, ppl_plan, ppl_plan_query,
-                   ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_version)
+                   ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_version,
+                   ppl_set_contract_config, ppl_autotune)
 
 __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace", "ppl_build_batch",
            "ppl_contract", "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count",
-           "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read"]
+           "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read",
+           "ppl_set_contract_config", "ppl_autotune"]
 
 
 class PPL:
@@ -64,6 +66,19 @@ class PPL:
         n = rep["sweeps_lp"] + rep["sweeps_fp64"]
         rep["history"] = list(hist[:n]) if hist is not None else []
         return rep
+
+    def contract_config(self):
+        i = ppl_plan_query(self.plan)
+        return (i["tile_contract"], i["splits_contract"], i["tile_contract_minus"], i["splits_contract_minus"])
+
+    def set_contract_config(self, tile_plus, splits_plus, tile_minus, splits_minus):
+        ppl_set_contract_config(self.plan, tile_plus, splits_plus, tile_minus, splits_minus)
+        self.info = ppl_plan_query(self.plan)
+
+    def autotune(self, reps=3):
+        best = ppl_autotune(self.plan, reps)
+        self.info = ppl_plan_query(self.plan)
+        return best
 
     def profile(self, on=True):
         ppl_profile_enable(self.plan, on)

@@ -45,7 +45,8 @@ class ppl_plan_info_t(ctypes.Structure):
                 ("a_per_batch", ctypes.c_int32), ("tile_build", ctypes.c_int32),
                 ("tile_contract", ctypes.c_int32), ("n_plus", ctypes.c_int32),
                 ("n_minus", ctypes.c_int32), ("p_plus", ctypes.c_int32), ("p_minus", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("flops_build", ctypes.c_double),
+                ("splits_contract", ctypes.c_int32), ("tile_contract_minus", ctypes.c_int32),
+                ("splits_contract_minus", ctypes.c_int32), ("flops_build", ctypes.c_double),
                 ("flops_contract", ctypes.c_double)]
 
 
@@ -83,6 +84,9 @@ SIGNATURES = {
     "ppl_iter_opts_default": (None, [ctypes.POINTER(ppl_iter_opts_t)]),
     "ppl_iterate": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ppl_iter_opts_t),
                                    ctypes.POINTER(ppl_iter_report_t)]),
+    "ppl_set_contract_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_int32]),
+    "ppl_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "ppl_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppl_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ppl_profile_t)]),
     "ppl_destroy": (ctypes.c_int, [_P]),
@@ -183,6 +187,17 @@ def ppl_iterate(plan, L, e_occ, e_vir, t2, opts: ppl_iter_opts_t | None = None, 
     out = {f: getattr(rep, f) for f, _ in ppl_iter_report_t._fields_}
     out["rc"] = rc
     return out
+
+
+def ppl_set_contract_config(plan, tile_plus, splits_plus, tile_minus, splits_minus):
+    _check(load().ppl_set_contract_config(plan, int(tile_plus), int(splits_plus), int(tile_minus),
+                                          int(splits_minus)), "ppl_set_contract_config")
+
+
+def ppl_autotune(plan, reps=3):
+    best = (ctypes.c_double * 2)()
+    _check(load().ppl_autotune(plan, int(reps), best), "ppl_autotune")
+    return float(best[0]), float(best[1])
 
 
 def ppl_profile_enable(plan, on=True):

@@ -110,6 +110,8 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   p->g = L.take(gbytes);
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
   p->rm = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+  // split-K slices for up to kMaxSplits (autotuning may pick any count), sized for FP64
+  p->part = L.take(std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8);
   if (p->ops[0].prec != PPL_FP64) {   // FP64 master amplitudes
     p->s64 = L.take((uint64_t)p->Np * p->ldp * 8);
     p->a64 = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
@@ -223,8 +225,8 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
   const void* sp_lo = s.sp_lo.bytes ? at<void>(p, s.sp_lo) : nullptr;
   const void* am = at<void>(p, s.am);
   const void* am_lo = s.am_lo.bytes ? at<void>(p, s.am_lo) : nullptr;
-  const int tile = p->tile_contract;
-  const int tile_m = p->Nm > 0 ? contract_tile_default(s.prec, p->Nm) : tile;
+  const int tile = p->tile_contract, tile_m = p->tile_m;
+  void* part = p->part.bytes ? at<void>(p, p->part) : nullptr;
   const double fp = 2.0 * (double)p->Np * p->Pp, fm = 2.0 * (double)p->Nm * p->Pm;
   if (p->resident) {
     if (!s.built) return fail(PPL_E_STATE, "V+- not built (call ppl_build_batch first)");
@@ -232,13 +234,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, fp * p->Pp);
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, p->Pp, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, 0));
+                            at<void>(p, p->rp), p->ldp, 0, p->split_p, part, p->ldp));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, fm * p->Pm);
     if (p->Nm > 0 && p->Pm > 0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, p->Pm, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, 0));
+                            at<void>(p, p->rm), p->ldm, 0, p->split_m, part, p->ldm));
     return PPL_OK;
   }
   if (!p->L_last) return fail(PPL_E_STATE, "streaming plan has no Cholesky vectors (call ppl_build_batch)");
@@ -249,13 +251,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, 2.0 * (double)p->Np * p->Pp * (double)(b.p1 - b.p0));
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, b.p1 - b.p0, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, b.p0));
+                            at<void>(p, p->rp), p->ldp, b.p0, p->split_p, part, p->ldp));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, 2.0 * (double)p->Nm * p->Pm * (double)(b.q1 - b.q0));
     if (p->Nm > 0 && b.q1 > b.q0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, b.q1 - b.q0, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, b.q0));
+                            at<void>(p, p->rm), p->ldm, b.q0, p->split_m, part, p->ldm));
   }
   return PPL_OK;
 }
@@ -354,7 +356,17 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   p->ops[1].prec = PPL_FP64;
   p->ops[1].present = p->keep_fp64 != 0;
   p->tile_build = 0;
-  p->tile_contract = d->tile_contract >= 0 ? d->tile_contract : contract_tile_default(p->prec, p->Np);
+  {
+    int t = d->tile_contract, sp = 1;
+    contract_choose(p->prec, p->Np, p->Pp, p->ldp, kMaxSplits, &t, &sp);
+    p->tile_contract = t;
+    p->split_p = sp;
+    t = -1;
+    sp = 1;
+    if (p->Nm > 0) contract_choose(p->prec, p->Nm, p->Pm, p->ldm, kMaxSplits, &t, &sp);
+    p->tile_m = t < 0 ? 0 : t;
+    p->split_m = sp;
+  }
 
   uint64_t budget = d->hbm_budget;
   if (budget == 0) {
@@ -429,6 +441,9 @@ int ppl_plan_query(ppl_plan_t p, ppl_plan_info_t* info) {
   info->n_minus = (int32_t)p->Nm;
   info->p_plus = (int32_t)p->Pp;
   info->p_minus = (int32_t)p->Pm;
+  info->splits_contract = p->split_p;
+  info->tile_contract_minus = p->tile_m;
+  info->splits_contract_minus = p->split_m;
   const double v = p->v, na = p->naux;
   info->flops_build = 2.0 * na * v * v * (double)p->Pp;
   info->flops_contract =
@@ -637,6 +652,82 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   if (status != PPL_OK)
     return fail(status, "iteration ended with status %d after %d sweeps (residual %.3e)", status, sweeps,
                 r.residual);
+  return PPL_OK;
+}
+
+int ppl_set_contract_config(ppl_plan_t p, int32_t tp, int32_t sp, int32_t tm, int32_t sm) {
+  PPL_TRY(check_plan(p));
+  const int nt = contract_tile_count();
+  if (tp < 0 || tp >= nt || tm < 0 || tm >= nt) return fail(PPL_E_ARG, "tile id out of range [0, %d)", nt);
+  if (sp < 1 || sp > kMaxSplits || sm < 1 || sm > kMaxSplits)
+    return fail(PPL_E_ARG, "split count out of range [1, %d]", kMaxSplits);
+  p->tile_contract = tp;
+  p->split_p = sp;
+  p->tile_m = tm;
+  p->split_m = sm;
+  return PPL_OK;
+}
+
+int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (reps < 1) return fail(PPL_E_ARG, "reps must be >= 1");
+  OperandSet& s = p->ops[0];
+  if (!p->resident || !s.built) return fail(PPL_E_STATE, "autotune needs a resident plan with V+- built");
+  hipStream_t st = p->stream;
+  hipEvent_t e0, e1;
+  PPL_HIP_TRY(hipEventCreate(&e0));
+  PPL_HIP_TRY(hipEventCreate(&e1));
+  void* part = at<void>(p, p->part);
+  const int nt = contract_tile_count();
+  double best[2] = {1e300, 1e300};
+  int bt[2] = {p->tile_contract, p->tile_m}, bs[2] = {p->split_p, p->split_m};
+  int rc = PPL_OK;
+  for (int which = 0; which < 2 && rc == PPL_OK; ++which) {
+    const bool plus = which == 0;
+    const int64_t Nr = plus ? p->Np : p->Nm, Pr = plus ? p->Pp : p->Pm, ld = plus ? p->ldp : p->ldm;
+    if (Nr <= 0 || Pr <= 0) continue;
+    const void* A = at<void>(p, plus ? s.sp : s.am);
+    const void* A_lo = (plus ? s.sp_lo : s.am_lo).bytes ? at<void>(p, plus ? s.sp_lo : s.am_lo) : nullptr;
+    const void* V = at<void>(p, plus ? s.vp : s.vm);
+    const void* V_lo = (plus ? s.vp_lo : s.vm_lo).bytes ? at<void>(p, plus ? s.vp_lo : s.vm_lo) : nullptr;
+    void* C = at<void>(p, plus ? p->rp : p->rm);
+    for (int t = 0; t < nt && rc == PPL_OK; ++t) {
+      for (int sp = 1; sp <= kMaxSplits && rc == PPL_OK; ++sp) {
+        if (sp > 1 && contract_jobs(t, s.prec, Nr, Pr, ld, sp) == contract_jobs(t, s.prec, Nr, Pr, ld, sp - 1))
+          continue;   // same effective split count as a smaller request
+        rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld);
+        if (rc != PPL_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PPL_E_HIP, "event record failed"); break; }
+        for (int r = 0; r < reps && rc == PPL_OK; ++r)
+          rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld);
+        if (rc != PPL_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = fail(PPL_E_HIP, "event timing failed");
+          break;
+        }
+        const double avg = ms / reps;
+        if (avg < best[which]) {
+          best[which] = avg;
+          bt[which] = t;
+          bs[which] = sp;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PPL_OK) return rc;
+  p->tile_contract = bt[0];
+  p->split_p = bs[0];
+  p->tile_m = bt[1];
+  p->split_m = bs[1];
+  if (best_ms) {
+    best_ms[0] = best[0] < 1e300 ? best[0] : 0.0;
+    best_ms[1] = best[1] < 1e300 ? best[1] : 0.0;
+  }
   return PPL_OK;
 }
 

@@ -23,6 +23,8 @@
 //   f32 16x16x4:   lane l holds A[l%16][l/16], B[l/16][l%16], D[4*(l/16) + r][l%16];
 //   bf16 16x16x32: lane l holds A[l%16][8*(l/16)+0..7], B[8*(l/16)+0..7][l%16],
 //                  D[4*(l/16) + r][l%16].
+#include <cmath>
+
 #include "ppl_internal.h"
 
 namespace ppl {
@@ -68,13 +70,28 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t total) {
 }
 
 // ------------------------------------------------------------------ tile maps
-struct MapGrid {         // dense grid, logical order: row tile fastest (tiles sharing B rows adjacent)
+struct TileJob {
+  int64_t m0, n0;        // first row / column of the C tile
+  int64_t kc0, kc1;      // K chunks [kc0, kc1) of this job
+  int split;             // split-K slice written by this job
+};
+
+// Dense grid with an optional split of K into `splits` slices. Logical order:
+// row tile fastest, then split, then column tile, so jobs that read the same
+// B rows run next to each other on one XCD.
+struct MapGrid {
   int64_t n_mt, n_nt;
   int bm, bn;
-  __device__ bool operator()(int64_t bid, int64_t& m0, int64_t& n0) const {
-    const int64_t t = xcd_remap(bid, n_mt * n_nt);
-    m0 = (t % n_mt) * bm;
-    n0 = (t / n_mt) * bn;
+  int splits;
+  int64_t nk, kps;       // K chunks in total and per split
+  __device__ bool operator()(int64_t bid, TileJob& j) const {
+    const int64_t t = xcd_remap(bid, n_mt * n_nt * splits);
+    const int64_t r = t / n_mt;
+    j.m0 = (t % n_mt) * bm;
+    j.split = (int)(r % splits);
+    j.n0 = (r / splits) * bn;
+    j.kc0 = j.split * kps;
+    j.kc1 = j.kc0 + kps < nk ? j.kc0 + kps : nk;
     return true;
   }
 };
@@ -84,7 +101,8 @@ struct MapBuild {        // block-upper-triangle of the (a,c) x (b,d) grid: only
   int n_mt;
   int64_t total;
   int v, bm, bn;
-  __device__ bool operator()(int64_t bid, int64_t& m0, int64_t& n0) const {
+  int64_t nk;
+  __device__ bool operator()(int64_t bid, TileJob& j) const {
     const int64_t t = xcd_remap(bid, total);
     int lo = 0, hi = n_mt - 1;              // largest mt with prefix[mt] <= t
     while (lo < hi) {
@@ -94,21 +112,25 @@ struct MapBuild {        // block-upper-triangle of the (a,c) x (b,d) grid: only
     const int mt = lo;
     const int64_t arel = (int64_t)mt * bm / v;          // first a of the row tile, relative to a0
     const int64_t nt_min = arel * v / bn;
-    m0 = (int64_t)mt * bm;
-    n0 = (nt_min + (t - prefix[mt])) * bn;
+    j.m0 = (int64_t)mt * bm;
+    j.n0 = (nt_min + (t - prefix[mt])) * bn;
+    j.kc0 = 0;
+    j.kc1 = nk;
+    j.split = 0;
     return true;
   }
 };
 
 // ------------------------------------------------------------------ epilogues
 template <class Tc>
-struct EpiStore {        // C[m][c_col0 + n] = alpha * acc + beta * C (beta == 0: no read)
+struct EpiStore {        // C[split][m][c_col0 + n] = alpha * acc + beta * C (beta == 0: no read)
   Tc* C;
   int64_t ldc, c_col0, M, N;
   double alpha, beta;
-  __device__ void row(int64_t m, int64_t& base, bool& ok) const {
+  int64_t split_stride;  // elements between split-K slices
+  __device__ void row(int split, int64_t m, int64_t& base, bool& ok) const {
     ok = m < M;
-    base = m * ldc + c_col0;
+    base = split * split_stride + m * ldc + c_col0;
   }
   __device__ void put(int64_t base, bool ok, int64_t n, typename AccOf<Tc>::type x) const {
     if (!ok || n >= N) return;
@@ -124,7 +146,7 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
   int64_t M, N;
   int v, a0;
   // per-row: a, c; per-col: b, d
-  __device__ void row(int64_t m, int64_t& base, bool& ok) const {
+  __device__ void row(int, int64_t m, int64_t& base, bool& ok) const {
     ok = m < M;
     const int64_t arel = m / v, c = m - arel * v;
     // encode a (relative) and c in base: rows are combined with columns in put()
@@ -143,7 +165,7 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
 
 // ------------------------------------------------------------------ the kernel (FP64 / FP32)
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
-__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int64_t lda,
                const T* __restrict__ B, int64_t ldb, Epi epi, Map map) {
   using accv = typename AccOf<T>::vec;
@@ -159,8 +181,9 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
   __shared__ __attribute__((aligned(16))) T sA[2][BM * LDSR];
   __shared__ __attribute__((aligned(16))) T sB[2][BN * LDSR];
 
-  int64_t m0, n0;
-  if (!map(blockIdx.x, m0, n0)) return;
+  TileJob job;
+  if (!map(blockIdx.x, job)) return;
+  const int64_t m0 = job.m0, n0 = job.n0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
 
@@ -175,7 +198,7 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = m0 + r;
     if (gr > M - 1) gr = M - 1;
-    pa[i] = A + gr * lda + kv * VEC;
+    pa[i] = A + gr * lda + kv * VEC + job.kc0 * KC;
     oa[i] = r * LDSR + kv * VEC;
   }
 #pragma unroll
@@ -185,23 +208,9 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = n0 + r;
     if (gr > N - 1) gr = N - 1;
-    pb[i] = B + gr * ldb + kv * VEC;
+    pb[i] = B + gr * ldb + kv * VEC + job.kc0 * KC;
     ob[i] = r * LDSR + kv * VEC;
   }
-
-  uint4 ra[NLA], rb[NLB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i] + k0);
-#pragma unroll
-    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i] + k0);
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA[buf][oa[i]]) = ra[i];
-#pragma unroll
-    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB[buf][ob[i]]) = rb[i];
-  };
 
   accv acc[WM][WN];
 #pragma unroll
@@ -211,14 +220,31 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
 
   const int arow = (wm * WM * 16 + (lane & 15)) * LDSR + (lane >> 4);
   const int brow = (wn * WN * 16 + (lane & 15)) * LDSR + (lane >> 4);
-  const int64_t nk = Kpad / KC;
+  const int64_t nk = job.kc1 - job.kc0;
 
-  gload(0);
-  sstore(0);
+  // chunk 0 straight into LDS buffer 0
+  {
+    uint4 ra[NLA], rb[NLB];
+#pragma unroll
+    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i]);
+#pragma unroll
+    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i]);
+#pragma unroll
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA[0][oa[i]]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB[0][ob[i]]) = rb[i];
+  }
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
+
+  // steady state: chunk kt+1 is fetched into registers while chunk kt is consumed
+  for (int64_t kt = 0; kt + 1 < nk; ++kt) {
     const int buf = (int)(kt & 1);
-    if (kt + 1 < nk) gload((kt + 1) * KC);
+    const int64_t k1 = (kt + 1) * KC;
+    uint4 ra[NLA], rb[NLB];
+#pragma unroll
+    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i] + k1);
+#pragma unroll
+    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i] + k1);
     const T* As = sA[buf];
     const T* Bs = sB[buf];
 #pragma unroll
@@ -233,8 +259,28 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+#pragma unroll
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA[buf ^ 1][oa[i]]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB[buf ^ 1][ob[i]]) = rb[i];
     __syncthreads();
+  }
+  {  // last chunk
+    const int buf = (int)((nk - 1) & 1);
+    const T* As = sA[buf];
+    const T* Bs = sB[buf];
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i] = As[arow + i * 16 * LDSR + kk];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j] = Bs[brow + j * 16 * LDSR + kk];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+    }
   }
 
 #pragma unroll
@@ -244,7 +290,7 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
       const int64_t m = m0 + wm * WM * 16 + i * 16 + AccOf<T>::row(lane, r);
       int64_t base;
       bool ok;
-      epi.row(m, base, ok);
+      epi.row(job.split, m, base, ok);
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int64_t n = n0 + wn * WN * 16 + j * 16 + (lane & 15);
@@ -276,8 +322,9 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
   __shared__ __attribute__((aligned(16))) __bf16 sBh[2][BN * LDSR];
   __shared__ __attribute__((aligned(16))) __bf16 sBl[2][BN * LDSR];
 
-  int64_t m0, n0;
-  if (!map(blockIdx.x, m0, n0)) return;
+  TileJob job;
+  if (!map(blockIdx.x, job)) return;
+  const int64_t m0 = job.m0, n0 = job.n0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
 
@@ -290,7 +337,7 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = m0 + r;
     if (gr > M - 1) gr = M - 1;
-    ga[i] = gr * lda + kv * VEC;
+    ga[i] = gr * lda + kv * VEC + job.kc0 * KC;
     oa[i] = r * LDSR + kv * VEC;
   }
 #pragma unroll
@@ -300,35 +347,9 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = n0 + r;
     if (gr > N - 1) gr = N - 1;
-    gb[i] = gr * ldb + kv * VEC;
+    gb[i] = gr * ldb + kv * VEC + job.kc0 * KC;
     ob[i] = r * LDSR + kv * VEC;
   }
-  uint4 rah[NLA], ral[NLA], rbh[NLB], rbl[NLB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < NLA; ++i) {
-      rah[i] = *reinterpret_cast<const uint4*>(Ah + ga[i] + k0);
-      ral[i] = *reinterpret_cast<const uint4*>(Al + ga[i] + k0);
-    }
-#pragma unroll
-    for (int i = 0; i < NLB; ++i) {
-      rbh[i] = *reinterpret_cast<const uint4*>(Bh + gb[i] + k0);
-      rbl[i] = *reinterpret_cast<const uint4*>(Bl + gb[i] + k0);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < NLA; ++i) {
-      *reinterpret_cast<uint4*>(&sAh[buf][oa[i]]) = rah[i];
-      *reinterpret_cast<uint4*>(&sAl[buf][oa[i]]) = ral[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NLB; ++i) {
-      *reinterpret_cast<uint4*>(&sBh[buf][ob[i]]) = rbh[i];
-      *reinterpret_cast<uint4*>(&sBl[buf][ob[i]]) = rbl[i];
-    }
-  };
-
   f4 acc[WM][WN], accx[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
@@ -340,39 +361,66 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
 
   const int arow = (wm * WM * 16 + (lane & 15)) * LDSR + 8 * (lane >> 4);
   const int brow = (wn * WN * 16 + (lane & 15)) * LDSR + 8 * (lane >> 4);
-  const int64_t nk = Kpad / KC;
+  const int64_t nk = job.kc1 - job.kc0;
 
-  gload(0);
-  sstore(0);
+#define PPL_BF3_LOAD(k0)                                                     \
+  _Pragma("unroll") for (int i = 0; i < NLA; ++i) {                          \
+    rah[i] = *reinterpret_cast<const uint4*>(Ah + ga[i] + (k0));             \
+    ral[i] = *reinterpret_cast<const uint4*>(Al + ga[i] + (k0));             \
+  }                                                                          \
+  _Pragma("unroll") for (int i = 0; i < NLB; ++i) {                          \
+    rbh[i] = *reinterpret_cast<const uint4*>(Bh + gb[i] + (k0));             \
+    rbl[i] = *reinterpret_cast<const uint4*>(Bl + gb[i] + (k0));             \
+  }
+#define PPL_BF3_STORE(buf)                                                   \
+  _Pragma("unroll") for (int i = 0; i < NLA; ++i) {                          \
+    *reinterpret_cast<uint4*>(&sAh[buf][oa[i]]) = rah[i];                    \
+    *reinterpret_cast<uint4*>(&sAl[buf][oa[i]]) = ral[i];                    \
+  }                                                                          \
+  _Pragma("unroll") for (int i = 0; i < NLB; ++i) {                          \
+    *reinterpret_cast<uint4*>(&sBh[buf][ob[i]]) = rbh[i];                    \
+    *reinterpret_cast<uint4*>(&sBl[buf][ob[i]]) = rbl[i];                    \
+  }
+#define PPL_BF3_COMPUTE(buf)                                                                   \
+  _Pragma("unroll") for (int kk = 0; kk < KC; kk += 32) {                                      \
+    bf8 ah[WM], al[WM], bh[WN], bl[WN];                                                        \
+    _Pragma("unroll") for (int i = 0; i < WM; ++i) {                                           \
+      ah[i] = *reinterpret_cast<const bf8*>(&sAh[buf][arow + i * 16 * LDSR + kk]);             \
+      al[i] = *reinterpret_cast<const bf8*>(&sAl[buf][arow + i * 16 * LDSR + kk]);             \
+    }                                                                                          \
+    _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                           \
+      bh[j] = *reinterpret_cast<const bf8*>(&sBh[buf][brow + j * 16 * LDSR + kk]);             \
+      bl[j] = *reinterpret_cast<const bf8*>(&sBl[buf][brow + j * 16 * LDSR + kk]);             \
+    }                                                                                          \
+    _Pragma("unroll") for (int i = 0; i < WM; ++i)                                             \
+    _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                           \
+      accx[i][j] = mfma16(al[i], bh[j], accx[i][j]);                                           \
+      accx[i][j] = mfma16(ah[i], bl[j], accx[i][j]);                                           \
+      acc[i][j] = mfma16(ah[i], bh[j], acc[i][j]);                                             \
+    }                                                                                          \
+  }
+
+  {
+    uint4 rah[NLA], ral[NLA], rbh[NLB], rbl[NLB];
+    PPL_BF3_LOAD(0)
+    PPL_BF3_STORE(0)
+  }
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
+  for (int64_t kt = 0; kt + 1 < nk; ++kt) {
     const int buf = (int)(kt & 1);
-    if (kt + 1 < nk) gload((kt + 1) * KC);
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 32) {
-      bf8 ah[WM], al[WM], bh[WN], bl[WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        ah[i] = *reinterpret_cast<const bf8*>(&sAh[buf][arow + i * 16 * LDSR + kk]);
-        al[i] = *reinterpret_cast<const bf8*>(&sAl[buf][arow + i * 16 * LDSR + kk]);
-      }
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        bh[j] = *reinterpret_cast<const bf8*>(&sBh[buf][brow + j * 16 * LDSR + kk]);
-        bl[j] = *reinterpret_cast<const bf8*>(&sBl[buf][brow + j * 16 * LDSR + kk]);
-      }
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          accx[i][j] = mfma16(al[i], bh[j], accx[i][j]);
-          accx[i][j] = mfma16(ah[i], bl[j], accx[i][j]);
-          acc[i][j] = mfma16(ah[i], bh[j], acc[i][j]);
-        }
-    }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    uint4 rah[NLA], ral[NLA], rbh[NLB], rbl[NLB];
+    PPL_BF3_LOAD((kt + 1) * KC)
+    PPL_BF3_COMPUTE(buf)
+    PPL_BF3_STORE(buf ^ 1)
     __syncthreads();
   }
+  {
+    const int buf = (int)((nk - 1) & 1);
+    PPL_BF3_COMPUTE(buf)
+  }
+#undef PPL_BF3_LOAD
+#undef PPL_BF3_STORE
+#undef PPL_BF3_COMPUTE
 
 #pragma unroll
   for (int i = 0; i < WM; ++i) {
@@ -381,7 +429,7 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
       const int64_t m = m0 + wm * WM * 16 + i * 16 + AccOf<__bf16>::row(lane, r);
       int64_t base;
       bool ok;
-      epi.row(m, base, ok);
+      epi.row(job.split, m, base, ok);
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int64_t n = n0 + wn * WN * 16 + j * 16 + (lane & 15);
@@ -478,41 +526,82 @@ static int launch_bf3(hipStream_t s, int64_t grid, int64_t M, int64_t N, int64_t
   return PPL_OK;
 }
 
+// sum of the split-K slices in slice order: C[m][c_col0 + n] = sum_s P[s][m][n]
+template <class Tc>
+__global__ void splitk_reduce_kernel(const Tc* __restrict__ P, int splits, int64_t split_stride,
+                                     int64_t M, int64_t N, int64_t ldp_, Tc* C, int64_t ldc,
+                                     int64_t c_col0) {
+  const int64_t total = M * N;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int64_t m = x / N, n = x - m * N;
+    Tc acc = P[m * ldp_ + n];
+    for (int sp = 1; sp < splits; ++sp) acc += P[sp * split_stride + m * ldp_ + n];
+    C[m * ldc + c_col0 + n] = acc;
+  }
+}
+
 // dispatch of one precision over the contraction tiles
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad,
                         const void* S, const void* S_lo, int64_t lds_, const void* V,
-                        const void* V_lo, int64_t ldv, void* C, int64_t ldc, int64_t c_col0) {
+                        const void* V_lo, int64_t ldv, void* C, int64_t ldc, int64_t c_col0,
+                        int splits, void* partial, int64_t partial_ld) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  MapGrid map{(Nrows + BM - 1) / BM, (Prows + BN - 1) / BN, BM, BN};
-  const int64_t grid = map.n_mt * map.n_nt;
+  const int KC = prec == PPL_FP64 ? 16 : 32;
+  const int64_t nk = Kpad / KC;
+  if (splits < 1) splits = 1;
+  if (splits > nk) splits = (int)nk;
+  const int64_t kps = (nk + splits - 1) / splits;
+  splits = (int)((nk + kps - 1) / kps);                 // no empty slice
+  const bool direct = splits == 1;
+  if (!direct && !partial) return fail(PPL_E_ARG, "split-K needs a partial buffer");
+  MapGrid map{(Nrows + BM - 1) / BM, (Prows + BN - 1) / BN, BM, BN, splits, nk, kps};
+  const int64_t grid = map.n_mt * map.n_nt * splits;
+  const int64_t pstride = Nrows * partial_ld;
+  int rc = PPL_OK;
   if (prec == PPL_FP64) {
-    EpiStore<double> epi{(double*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0};
-    return launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, grid, Nrows, Prows, Kpad, (const double*)S,
-                                                        lds_, (const double*)V, ldv, epi, map);
+    EpiStore<double> epi = direct ? EpiStore<double>{(double*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
+                                  : EpiStore<double>{(double*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
+    rc = launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, grid, Nrows, Prows, Kpad, (const double*)S, lds_,
+                                                      (const double*)V, ldv, epi, map);
+  } else if (prec == PPL_FP32) {
+    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
+                                 : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
+    rc = launch<float, WM, WN, WAVES_M, WAVES_N, 32>(s, grid, Nrows, Prows, Kpad, (const float*)S, lds_,
+                                                     (const float*)V, ldv, epi, map);
+  } else if (prec == PPL_BF16X3) {
+    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
+                                 : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
+    rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, 32>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
+                                                  (const __bf16*)S_lo, lds_, (const __bf16*)V,
+                                                  (const __bf16*)V_lo, ldv, epi, map);
+  } else {
+    return fail(PPL_E_ARG, "unknown precision %d", prec);
   }
-  if (prec == PPL_FP32) {
-    EpiStore<float> epi{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0};
-    return launch<float, WM, WN, WAVES_M, WAVES_N, 32>(s, grid, Nrows, Prows, Kpad, (const float*)S,
-                                                       lds_, (const float*)V, ldv, epi, map);
-  }
-  if (prec == PPL_BF16X3) {
-    EpiStore<float> epi{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0};
-    return launch_bf3<WM, WN, WAVES_M, WAVES_N, 32>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
-                                                    (const __bf16*)S_lo, lds_, (const __bf16*)V,
-                                                    (const __bf16*)V_lo, ldv, epi, map);
-  }
-  return fail(PPL_E_ARG, "unknown precision %d", prec);
+  if (rc != PPL_OK || direct) return rc;
+  const int64_t total = Nrows * Prows;
+  int64_t g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (prec == PPL_FP64)
+    hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3((unsigned)g), dim3(256), 0, s, (const double*)partial,
+                       splits, pstride, Nrows, Prows, partial_ld, (double*)C, ldc, c_col0);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, (const float*)partial,
+                       splits, pstride, Nrows, Prows, partial_ld, (float*)C, ldc, c_col0);
+  PPL_HIP_TRY(hipGetLastError());
+  return PPL_OK;
 }
 
 int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
                   const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
-                  int64_t ldv, void* C, int64_t ldc, int64_t c_col0) {
+                  int64_t ldv, void* C, int64_t ldc, int64_t c_col0, int splits, void* partial,
+                  int64_t partial_ld) {
   if (Nrows <= 0 || Prows <= 0) return PPL_OK;
-#define PPL_CFG(id, a, b, c, d)                                                               \
-  case id:                                                                                    \
-    return contract_cfg<a, b, c, d>(s, prec, Nrows, Prows, Kpad, S, S_lo, lds_, V, V_lo, ldv, C, \
-                                    ldc, c_col0);
+#define PPL_CFG(id, a, b, c, d)                                                                  \
+  case id:                                                                                       \
+    return contract_cfg<a, b, c, d>(s, prec, Nrows, Prows, Kpad, S, S_lo, lds_, V, V_lo, ldv, C,  \
+                                    ldc, c_col0, splits, partial, partial_ld);
   switch (tile) {
     PPL_CFG(0, 7, 2, 1, 4)
     PPL_CFG(1, 4, 4, 2, 2)
@@ -526,6 +615,46 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
 #undef PPL_CFG
 }
 
+// Workgroups of one contraction launch for a (tile, splits) choice.
+int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits) {
+  const TileCfg& c = kContract[tile];
+  const int KC = prec == PPL_FP64 ? 16 : 32;
+  const int64_t nk = Kpad / KC;
+  if (splits > nk) splits = (int)nk;
+  const int64_t kps = (nk + splits - 1) / splits;
+  splits = (int)((nk + kps - 1) / kps);
+  return ((Nrows + c.bm() - 1) / c.bm()) * ((Prows + c.bn() - 1) / c.bn()) * splits;
+}
+
+// Model choice of (tile, splits): useful work over the work of the padded tiles,
+// times the fill of the last round of workgroups over 256 CUs.
+void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
+                     int* splits_out) {
+  double best = -1.0;
+  int bt = 0, bs = 1;
+  const int fixed = *tile_out;
+  for (int t = 0; t < kNumContract; ++t) {
+    if (fixed >= 0 && t != fixed) continue;
+    const TileCfg& c = kContract[t];
+    const int64_t mp = (Nrows + c.bm() - 1) / c.bm() * c.bm(), np = (Prows + c.bn() - 1) / c.bn() * c.bn();
+    const double pad = (double)Nrows * Prows / ((double)mp * np);
+    for (int sp = 1; sp <= max_splits; ++sp) {
+      const int64_t jobs = contract_jobs(t, prec, Nrows, Prows, Kpad, sp);
+      const double rounds = (double)jobs / 256.0;
+      const double fill = rounds / std::ceil(rounds);
+      // small penalty per extra slice (partial traffic, reduction launch) and for tiny tiles
+      const double score = pad * fill * (1.0 - 0.01 * (sp - 1)) * (c.bm() * c.bn() >= 8192 ? 1.0 : 0.9);
+      if (score > best + 1e-9) {
+        best = score;
+        bt = t;
+        bs = sp;
+      }
+    }
+  }
+  *tile_out = bt;
+  *splits_out = bs;
+}
+
 int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,
                const void* Xt, const void* Xt_lo, int64_t ldx, void* G, const int* tile_prefix,
                int n_mtiles, int n_ntiles, int64_t n_valid_tiles) {
@@ -534,7 +663,8 @@ int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t
   constexpr int WM = 4, WN = 4, WAVES_M = 2, WAVES_N = 2;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
-  MapBuild map{tile_prefix, n_mtiles, n_valid_tiles, v, BM, BN};
+  MapBuild map{tile_prefix, n_mtiles, n_valid_tiles, v, BM, BN, 0};
+  map.nk = Kpad / (prec == PPL_FP64 ? 16 : 32);
   if (prec == PPL_FP64) {
     const double* X = (const double*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<double> epi{(double*)G, M, N, v, a0};
@@ -561,8 +691,8 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
                    const double* B, int64_t ldb, double* C, int64_t ldc) {
   constexpr int WM = 4, WN = 4, WAVES_M = 2, WAVES_N = 2;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  MapGrid map{(M + BM - 1) / BM, (N + BN - 1) / BN, BM, BN};
-  EpiStore<double> epi{C, ldc, 0, M, N, 1.0, 0.0};
+  MapGrid map{(M + BM - 1) / BM, (N + BN - 1) / BN, BM, BN, 1, Kpad / 16, Kpad / 16};
+  EpiStore<double> epi{C, ldc, 0, M, N, 1.0, 0.0, 0};
   return launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, map.n_mt * map.n_nt, M, N, Kpad, A, lda, B,
                                                       ldb, epi, map);
 }

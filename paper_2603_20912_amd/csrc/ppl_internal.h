@@ -89,6 +89,7 @@ struct ppl_plan_s {
   int64_t g_pairs_cap = 0;             // pairs (a<=b) one build step may hold in G
   // tiles
   int tile_build = 0, tile_contract = 0;
+  int split_p = 1, tile_m = 0, split_m = 1;   // split-K of the R+ GEMM; tile and split-K of the R- GEMM
   // workspace
   uint64_t ws_bytes_needed = 0;
   char* ws = nullptr;
@@ -96,6 +97,7 @@ struct ppl_plan_s {
   ppl::OperandSet ops[2];              // [0] = compute precision, [1] = FP64 refinement copy (if any)
   ppl::Region g;                       // build scratch G [pairs][v][v] (also the V-setup scratch)
   ppl::Region rp, rm;                  // R+ [N+][ldp], R- [N-][ldm] (accumulator type of the GEMM)
+  ppl::Region part;                    // split-K slices of one contraction GEMM
   ppl::Region s64, a64;                // FP64 master amplitudes in S'/A' form when ops[*] are not FP64
   ppl::Region vs, va;                  // packed (ia|jb): VS [N+][ldp], VA [N-][ldm] (FP64)
   ppl::Region bs, ba;                  // FP64 copy of S'/A' kept across the two first sweeps of a checked start
@@ -136,9 +138,17 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 
 // Contraction C[N][P] = sum_k S[n][k] V[p][k] for one operand set (R+ or R-).
 // Output in the accumulator precision (double for FP64, float otherwise).
+// splits > 1 splits K into that many slices written to `partial` ([splits][Nrows][partial_ld],
+// accumulator type) and summed in slice order into C.
 int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
                   const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
-                  int64_t ldv, void* C, int64_t ldc, int64_t c_col0);
+                  int64_t ldv, void* C, int64_t ldc, int64_t c_col0, int splits, void* partial,
+                  int64_t partial_ld);
+int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits);
+// *tile_out >= 0 on entry fixes the tile and only chooses the split count
+void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
+                     int* splits_out);
+constexpr int kMaxSplits = 4;
 
 // Integral build G[pair(a,b) - pair(a0,a0)][c][d] = sum_P Xt[(a,c)][P] Xt[(b,d)][P]
 // for a in [a0, a1), b in [a, v).

@@ -41,11 +41,16 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-def gpu_contract(P, s, t, prec="fp64", budget=0, tile=-1, alpha=1.0, beta=0.0, R0=None):
+def gpu_contract(P, s, t, prec="fp64", budget=0, tile=-1, alpha=1.0, beta=0.0, R0=None, config=None,
+                 autotune=False):
     o, v, naux = s["o"], s["v"], s["naux"]
     eng = P.PPL(o, v, naux, prec=prec, hbm_budget=budget, tile_contract=tile)
     L = dev(s["L"])
     eng.build(L)
+    if config is not None:
+        eng.set_contract_config(*config)
+    if autotune:
+        eng.autotune(reps=1)
     R = dev(R0) if R0 is not None else torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
     eng.contract(dev(t), R, alpha, beta)
     torch.cuda.synchronize()
@@ -88,14 +93,31 @@ def test_alpha_beta_accumulate(P):
     assert rel(R, ref) < 1e-12
 
 
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
 @pytest.mark.parametrize("tile", range(6))
-def test_every_contraction_tile(P, tile):
-    say(f"contract fp64 tile {tile} (7,37,50)")
+def test_every_contraction_tile_and_split(P, tile, prec, bound):
+    say(f"contract {prec} tile {tile} splits 1..4 (7,37,50)")
     s = S.make_system(7, 37, 50, 20 + tile)
     t = S.make_amplitudes(7, 37, 30 + tile)
-    R, info = gpu_contract(P, s, t, tile=tile)
-    assert info["tile_contract"] == tile
-    assert rel(R, O.ppl(s["L"], 7, t)) < 1e-12
+    Rref = O.ppl(s["L"], 7, t)
+    first = None
+    for sp in (1, 2, 3, 4):
+        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 6, 5 - sp))
+        assert info["tile_contract"] == tile and info["splits_contract"] == sp
+        assert rel(R, Rref) < bound
+        if prec == "fp64":
+            # different split counts change the summation order only
+            if first is None:
+                first = R
+            assert rel(R, first) < 1e-14
+
+
+def test_autotuned_contraction_matches(P):
+    say("contract fp64 autotuned (12,90,200)")
+    s = S.make_system(12, 90, 200, 60)
+    t = S.make_amplitudes(12, 90, 61)
+    R, info = gpu_contract(P, s, t, autotune=True)
+    assert rel(R, O.ppl(s["L"], 12, t)) < 1e-12
 
 
 def test_streaming_batches_are_bitwise_equal_to_resident(P):
