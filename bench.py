@@ -63,12 +63,31 @@ def cpu_baseline(s, o):
                       f"method's useful flops of one evaluation"}
 
 
+def measured_traffic(config):
+    """HBM bytes per R+ launch from the committed hardware-counter summary, or None
+    when the kernel source or the contraction configuration differs from the one measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "contract_fp64_o20_v200_naux600_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_16"] or list(config) != rec["contract_config"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--contract-config", default="",
+                    help="tile_plus,splits_plus,tile_minus,splits_minus instead of autotuning")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -99,10 +118,20 @@ def main():
         eng.iterate(L, eo, ev, t, max_sweeps=SWEEPS, tol=0.0, diverge_factor=0.0, history=False)
         eng.contract(t, R)
 
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB read, 1 GiB written
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
     # one-time setup outside the timed region: build V+- once and let the
     # library's autotuner pick the contraction tiles and split-K counts
     eng.build(L)
-    eng.autotune(reps=2)
+    if args.contract_config:
+        eng.set_contract_config(*[int(x) for x in args.contract_config.split(",")])
+    else:
+        eng.autotune(reps=2)
 
     for _ in range(args.warmup):
         step()
@@ -140,7 +169,8 @@ def main():
                    "contract_config": list(eng.contract_config())},
         "roofline": {"bound": "mfma", "kernel": "R+ contraction GEMM (FP64 MFMA 16x16x4)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "traffic": measured_traffic(eng.contract_config()),
                      "flops_per_launch": fl_launch, "avg_launch_ms": round(avg_ms, 4)},
         "kernels": kernels,
     }

@@ -172,6 +172,59 @@ void ppl_iter_opts_default(ppl_iter_opts_t* opts);
 int ppl_iterate(ppl_plan_t plan, const double* L, const double* e_occ, const double* e_vir,
                 double* t2, const ppl_iter_opts_t* opts, ppl_iter_report_t* report);
 
+/*
+ * ppl_mp2: first-order amplitudes t = V / D into t2_out [o][o][v][v] (device
+ * FP64), V_ij^ab = (ia|jb) from the occupied-virtual block of L; e_mp2 (host,
+ * optional) receives sum V (2 t_ij^ab - t_ij^ba). Synchronous when e_mp2 != NULL.
+ */
+int ppl_mp2(ppl_plan_t plan, const double* L, const double* e_occ, const double* e_vir, double* t2_out,
+            double* e_mp2);
+
+/* ------------------------------------------------ learned start (MLP) */
+/*
+ * A 4 -> 128 -> 128 -> 1 network with SiLU after both hidden layers maps the
+ * per-element features x = (t_MP2/sigma, D_ij^ab, e_i + e_j, e_a + e_b) of an
+ * instance to f(x); the guess is t = t_MP2 + sigma * f(x). Parameters, Adam
+ * state and training scratch live in one caller-provided device workspace.
+ * Flat parameter order (FP32): W1 [128][4], b1 [128], W2 [128][128], b2 [128],
+ * W3 [128], b3 [1]. All MLP calls enqueue on the stream given at creation;
+ * calls that take a plan must use the same stream as the plan.
+ */
+typedef struct ppl_mlp_s* ppl_mlp_t;
+
+/* width must be 128; max_batch bounds the rows of one training step. */
+int ppl_mlp_create(int32_t width, int64_t max_batch, void* stream, ppl_mlp_t* out);
+int ppl_mlp_workspace_bytes(ppl_mlp_t mlp, uint64_t* bytes);
+int ppl_mlp_bind_workspace(ppl_mlp_t mlp, void* dptr, uint64_t bytes);
+/* number of FP32 parameters (17281 for width 128) */
+int ppl_mlp_param_count(ppl_mlp_t mlp);
+/* uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases from a seeded host generator; resets Adam */
+int ppl_mlp_init(ppl_mlp_t mlp, uint64_t seed);
+/* host <-> device copies of the flat parameter vector (n must equal the count); set resets Adam */
+int ppl_mlp_set_params(ppl_mlp_t mlp, const float* host_params, int64_t n);
+int ppl_mlp_get_params(ppl_mlp_t mlp, float* host_params, int64_t n);
+/*
+ * ppl_mlp_grad: mean-squared-error loss and its gradient for X [n][4], Y [n]
+ * (device FP32) without updating; host_grad receives param_count floats.
+ * Synchronous. Gradient partials are summed in a fixed order.
+ */
+int ppl_mlp_grad(ppl_mlp_t mlp, const float* X, const float* Y, int64_t n, float* host_grad, float* host_loss);
+/* ppl_mlp_train_step: one Adam step (beta 0.9/0.999, eps 1e-8) on the batch; host_loss (optional) syncs. */
+int ppl_mlp_train_step(ppl_mlp_t mlp, const float* X, const float* Y, int64_t n, float lr, float* host_loss);
+/* sigma = RMS of t_mp2 [o][o][v][v] over the whole tensor (host double). Synchronous. */
+int ppl_mlp_sigma(ppl_plan_t plan, const double* t_mp2, double* sigma);
+/*
+ * ppl_mlp_samples: features X [n][4] (and targets Y [n] = (t_star - t_mp2)/sigma
+ * when t_star and Y are not NULL) at the flat element indices idx [n] of the
+ * [o][o][v][v] tensors (device int64).
+ */
+int ppl_mlp_samples(ppl_plan_t plan, const double* t_mp2, const double* t_star, const double* e_occ,
+                    const double* e_vir, double sigma, const int64_t* idx, int64_t n, float* X, float* Y);
+/* ppl_mlp_guess: t2_out = t_mp2 + sigma * f(x) for every element (BF16 MFMA hidden layer). */
+int ppl_mlp_guess(ppl_mlp_t mlp, ppl_plan_t plan, const double* t_mp2, const double* e_occ,
+                  const double* e_vir, double sigma, double* t2_out);
+int ppl_mlp_destroy(ppl_mlp_t mlp);
+
 /* ------------------------------------------------ contraction tile configuration */
 /*
  * ppl_set_contract_config: choose the tile id (0 .. ppl_tile_count()-1) and the

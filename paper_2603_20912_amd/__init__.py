@@ -11,7 +11,10 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_destroy,
+from ._lib import (ppl_mp2, ppl_mlp_create, ppl_mlp_workspace_bytes, ppl_mlp_bind_workspace,
+                   ppl_mlp_param_count, ppl_mlp_init, ppl_mlp_set_params, ppl_mlp_get_params, ppl_mlp_grad,
+                   ppl_mlp_train_step, ppl_mlp_sigma, ppl_mlp_samples, ppl_mlp_guess, ppl_mlp_destroy,
+                   PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_destroy,
                    ppl_iter_opts_default, ppl_iterate, ppl_last_error, ppl_plan, ppl_plan_query,
                    ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_version,
                    ppl_set_contract_config, ppl_autotune)
@@ -19,7 +22,10 @@ from ._lib import (PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, 
 __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace", "ppl_build_batch",
            "ppl_contract", "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count",
            "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read",
-           "ppl_set_contract_config", "ppl_autotune"]
+           "ppl_set_contract_config", "ppl_autotune", "ppl_mp2", "MLP", "ppl_mlp_create",
+           "ppl_mlp_workspace_bytes", "ppl_mlp_bind_workspace", "ppl_mlp_param_count", "ppl_mlp_init",
+           "ppl_mlp_set_params", "ppl_mlp_get_params", "ppl_mlp_grad", "ppl_mlp_train_step",
+           "ppl_mlp_sigma", "ppl_mlp_samples", "ppl_mlp_guess", "ppl_mlp_destroy"]
 
 
 class PPL:
@@ -86,10 +92,64 @@ class PPL:
     def profile_read(self):
         return ppl_profile_read(self.plan)
 
+    def mp2(self, L, e_occ, e_vir, t2_out=None):
+        if t2_out is None:
+            t2_out = torch.empty((self.o, self.o, self.v, self.v), dtype=torch.float64, device=L.device)
+        e = ppl_mp2(self.plan, L, e_occ, e_vir, t2_out)
+        return t2_out, e
+
     def close(self):
         if getattr(self, "plan", None) is not None:
             ppl_destroy(self.plan)
             self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The learned-start network with its device workspace (parameters, Adam state, scratch)."""
+
+    def __init__(self, max_batch=65536, seed=0, stream=None, device="cuda"):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = ppl_mlp_create(128, max_batch, self.stream)
+        self.max_batch = max_batch
+        nbytes = ppl_mlp_workspace_bytes(self.h)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        ppl_mlp_bind_workspace(self.h, self.workspace)
+        ppl_mlp_init(self.h, seed)
+
+    @property
+    def n_params(self):
+        return ppl_mlp_param_count(self.h)
+
+    def get_params(self):
+        return ppl_mlp_get_params(self.h)
+
+    def set_params(self, flat):
+        ppl_mlp_set_params(self.h, flat)
+
+    def grad(self, X, Y):
+        return ppl_mlp_grad(self.h, X, Y)
+
+    def train_step(self, X, Y, lr=1e-3, want_loss=False):
+        return ppl_mlp_train_step(self.h, X, Y, lr, want_loss=want_loss)
+
+    def guess(self, eng, t_mp2, e_occ, e_vir, sigma=None, t2_out=None):
+        if sigma is None:
+            sigma = ppl_mlp_sigma(eng.plan, t_mp2)
+        if t2_out is None:
+            t2_out = torch.empty_like(t_mp2)
+        ppl_mlp_guess(self.h, eng.plan, t_mp2, e_occ, e_vir, sigma, t2_out)
+        return t2_out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ppl_mlp_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

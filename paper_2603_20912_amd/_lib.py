@@ -84,6 +84,21 @@ SIGNATURES = {
     "ppl_iter_opts_default": (None, [ctypes.POINTER(ppl_iter_opts_t)]),
     "ppl_iterate": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ppl_iter_opts_t),
                                    ctypes.POINTER(ppl_iter_report_t)]),
+    "ppl_mp2": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "ppl_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, ctypes.POINTER(_P)]),
+    "ppl_mlp_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    "ppl_mlp_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "ppl_mlp_param_count": (ctypes.c_int, [_P]),
+    "ppl_mlp_init": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "ppl_mlp_set_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "ppl_mlp_get_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "ppl_mlp_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_float)]),
+    "ppl_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_float)]),
+    "ppl_mlp_sigma": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "ppl_mlp_samples": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, ctypes.c_int64, _P, _P]),
+    "ppl_mlp_guess": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P]),
+    "ppl_mlp_destroy": (ctypes.c_int, [_P]),
     "ppl_set_contract_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32]),
     "ppl_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
@@ -209,6 +224,90 @@ def ppl_profile_read(plan) -> dict:
     _check(load().ppl_profile_read(plan, ctypes.byref(pr)), "ppl_profile_read")
     return {k: {"launches": int(pr.launches[i]), "ms": float(pr.ms[i]), "flops": float(pr.flops[i])}
             for i, k in enumerate(PROF_KINDS)}
+
+
+def ppl_mp2(plan, L, e_occ, e_vir, t2_out, want_energy=True):
+    e = ctypes.c_double(0.0)
+    _check(load().ppl_mp2(plan, _ptr(L), _ptr(e_occ), _ptr(e_vir), _ptr(t2_out),
+                          ctypes.byref(e) if want_energy else None), "ppl_mp2")
+    return e.value if want_energy else None
+
+
+def ppl_mlp_create(width=128, max_batch=65536, stream=None):
+    h = ctypes.c_void_p()
+    _check(load().ppl_mlp_create(int(width), int(max_batch), _stream_handle(stream), ctypes.byref(h)),
+           "ppl_mlp_create")
+    return h
+
+
+def ppl_mlp_workspace_bytes(mlp) -> int:
+    b = ctypes.c_uint64(0)
+    _check(load().ppl_mlp_workspace_bytes(mlp, ctypes.byref(b)), "ppl_mlp_workspace_bytes")
+    return int(b.value)
+
+
+def ppl_mlp_bind_workspace(mlp, ws, nbytes=None):
+    n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
+    _check(load().ppl_mlp_bind_workspace(mlp, _ptr(ws), n), "ppl_mlp_bind_workspace")
+
+
+def ppl_mlp_param_count(mlp) -> int:
+    return int(load().ppl_mlp_param_count(mlp))
+
+
+def ppl_mlp_init(mlp, seed=0):
+    _check(load().ppl_mlp_init(mlp, int(seed)), "ppl_mlp_init")
+
+
+def ppl_mlp_set_params(mlp, params):
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load().ppl_mlp_set_params(mlp, a.ctypes.data, a.size), "ppl_mlp_set_params")
+
+
+def ppl_mlp_get_params(mlp):
+    import numpy as np
+    a = np.empty(ppl_mlp_param_count(mlp), dtype=np.float32)
+    _check(load().ppl_mlp_get_params(mlp, a.ctypes.data, a.size), "ppl_mlp_get_params")
+    return a
+
+
+def ppl_mlp_grad(mlp, X, Y, n=None):
+    import numpy as np
+    n = Y.numel() if n is None else int(n)
+    g = np.empty(ppl_mlp_param_count(mlp), dtype=np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(load().ppl_mlp_grad(mlp, _ptr(X), _ptr(Y), n, g.ctypes.data, ctypes.byref(loss)), "ppl_mlp_grad")
+    return g, float(loss.value)
+
+
+def ppl_mlp_train_step(mlp, X, Y, lr, n=None, want_loss=False):
+    n = Y.numel() if n is None else int(n)
+    loss = ctypes.c_float(0.0)
+    _check(load().ppl_mlp_train_step(mlp, _ptr(X), _ptr(Y), n, float(lr),
+                                     ctypes.byref(loss) if want_loss else None), "ppl_mlp_train_step")
+    return float(loss.value) if want_loss else None
+
+
+def ppl_mlp_sigma(plan, t_mp2) -> float:
+    s = ctypes.c_double(0.0)
+    _check(load().ppl_mlp_sigma(plan, _ptr(t_mp2), ctypes.byref(s)), "ppl_mlp_sigma")
+    return float(s.value)
+
+
+def ppl_mlp_samples(plan, t_mp2, t_star, e_occ, e_vir, sigma, idx, X, Y=None):
+    _check(load().ppl_mlp_samples(plan, _ptr(t_mp2), _ptr(t_star), _ptr(e_occ), _ptr(e_vir), float(sigma),
+                                  _ptr(idx), idx.numel(), _ptr(X), _ptr(Y)), "ppl_mlp_samples")
+
+
+def ppl_mlp_guess(mlp, plan, t_mp2, e_occ, e_vir, sigma, t2_out):
+    _check(load().ppl_mlp_guess(mlp, plan, _ptr(t_mp2), _ptr(e_occ), _ptr(e_vir), float(sigma),
+                                _ptr(t2_out)), "ppl_mlp_guess")
+
+
+def ppl_mlp_destroy(mlp):
+    if mlp is not None:
+        load().ppl_mlp_destroy(mlp)
 
 
 def ppl_destroy(plan):

@@ -282,6 +282,21 @@ static int refresh_operands(ppl_plan_t p, OperandSet& s) {
   return PPL_OK;
 }
 
+// V = (ia|jb) from the occupied-virtual block of L, packed into VS / VA
+static int setup_ov_integrals(ppl_plan_t p, const double* L) {
+  hipStream_t st = p->stream;
+  ProfScope ps(p, PPL_PROF_OTHER, 0.0);
+  PPL_TRY(stage_ov(st, L, p->o, p->v, p->naux, p->ldx, at<double>(p, p->xov)));
+  const int64_t ov = (int64_t)p->o * p->v;
+  double* vfull = at<double>(p, p->g);
+  PPL_TRY(gemm_store_f64(st, ov, ov, p->ldx, at<double>(p, p->xov), p->ldx, at<double>(p, p->xov), p->ldx,
+                         vfull, ov));
+  PPL_TRY(pack_pm(st, p->o, p->v, vfull, (int64_t)p->v * ov, p->v, ov, 1, 0.5, 0.5, 0.5,
+                  at<double>(p, p->vs), p->ldp, at<double>(p, p->va), p->ldm, at<int>(p, p->tab_op),
+                  at<int>(p, p->tab_om), at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+  return PPL_OK;
+}
+
 static int read_red(ppl_plan_t p, double out[4]) {
   const double* red_out = at<double>(p, p->red) + kReduceBlocks * 4;
   PPL_HIP_TRY(hipMemcpyAsync(out, red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
@@ -537,14 +552,7 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   double h[4];
 
   // integrals: V = (ia|jb) packed into VS / VA, then V+- of every operand set
-  PPL_TRY(stage_ov(st, L, p->o, p->v, p->naux, p->ldx, at<double>(p, p->xov)));
-  const int64_t ov = (int64_t)p->o * p->v;
-  double* vfull = at<double>(p, p->g);
-  PPL_TRY(gemm_store_f64(st, ov, ov, p->ldx, at<double>(p, p->xov), p->ldx, at<double>(p, p->xov), p->ldx,
-                         vfull, ov));
-  PPL_TRY(pack_pm(st, p->o, p->v, vfull, (int64_t)p->v * ov, p->v, ov, 1, 0.5, 0.5, 0.5,
-                  at<double>(p, p->vs), p->ldp, at<double>(p, p->va), p->ldm, at<int>(p, p->tab_op),
-                  at<int>(p, p->tab_om), at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+  PPL_TRY(setup_ov_integrals(p, L));
   PPL_TRY(ppl_build_batch(p, L, -1));
 
   const int* tabs[4] = {at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp),
@@ -757,10 +765,229 @@ int ppl_profile_read(ppl_plan_t p, ppl_profile_t* out) {
   return PPL_OK;
 }
 
+int ppl_mp2(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2_out,
+            double* e_mp2) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!L || !e_occ || !e_vir || !t2_out) return fail(PPL_E_ARG, "null device pointer");
+  hipStream_t st = p->stream;
+  double* partials = at<double>(p, p->red);
+  double* red_out = partials + kReduceBlocks * 4;
+  PPL_TRY(setup_ov_integrals(p, L));
+  double* s64 = at<double>(p, p->s64);
+  double* a64 = at<double>(p, p->a64);
+  PPL_TRY(mp2_start(st, p->o, p->v, e_occ, e_vir, at<double>(p, p->vs), at<double>(p, p->va), p->ldp, p->ldm,
+                    s64, a64, at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp),
+                    at<int>(p, p->tab_vm), partials, red_out));
+  PPL_TRY(unpack_t(st, p->o, p->v, s64, p->ldp, a64, p->ldm, t2_out));
+  if (e_mp2) {
+    double h[4];
+    PPL_TRY(read_red(p, h));
+    *e_mp2 = h[1];
+  }
+  return PPL_OK;
+}
+
+int ppl_mlp_sigma(ppl_plan_t p, const double* t_mp2, double* sigma) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!t_mp2 || !sigma) return fail(PPL_E_ARG, "null pointer");
+  double* partials = at<double>(p, p->red);
+  double* red_out = partials + kReduceBlocks * 4;
+  const int64_t n = (int64_t)p->o * p->o * p->v * p->v;
+  PPL_TRY(sumsq_launch(p->stream, t_mp2, n, partials, red_out));
+  double h[4];
+  PPL_TRY(read_red(p, h));
+  *sigma = sqrt(h[0] / (double)n);
+  return PPL_OK;
+}
+
+int ppl_mlp_samples(ppl_plan_t p, const double* t_mp2, const double* t_star, const double* e_occ,
+                    const double* e_vir, double sigma, const int64_t* idx, int64_t n, float* X, float* Y) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!t_mp2 || !e_occ || !e_vir || !idx || !X || n < 0) return fail(PPL_E_ARG, "bad argument");
+  if ((t_star == nullptr) != (Y == nullptr)) return fail(PPL_E_ARG, "t_star and Y go together");
+  if (!(sigma > 0.0)) return fail(PPL_E_ARG, "sigma must be > 0");
+  if (n == 0) return PPL_OK;
+  return mlp_samples_launch(p->stream, p->o, p->v, t_mp2, t_star, e_occ, e_vir, sigma, idx, n, X, Y);
+}
+
 int ppl_destroy(ppl_plan_t p) {
   if (!p) return PPL_OK;
   for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
   delete p;
+  return PPL_OK;
+}
+
+// ---------------------------------------------------------------- learned start
+}  // extern "C"
+
+struct ppl_mlp_s {
+  hipStream_t stream = nullptr;
+  int64_t max_batch = 0;
+  char* ws = nullptr;
+  uint64_t ws_bytes = 0, need = 0;
+  ppl::Region prm, m, v, grad, gpart, lpart, loss;
+  int step = 0;
+};
+
+namespace ppl {
+template <class T>
+inline T* mat(ppl_mlp_t q, const Region& r) {
+  return reinterpret_cast<T*>(q->ws + r.off);
+}
+static int mlp_check(ppl_mlp_t q) {
+  if (!q) return fail(PPL_E_ARG, "null mlp");
+  if (!q->ws) return fail(PPL_E_STATE, "no MLP workspace bound");
+  return PPL_OK;
+}
+// splitmix64: a small published counter-based generator for the host-side init
+static uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+}  // namespace ppl
+
+extern "C" {
+
+int ppl_mlp_create(int32_t width, int64_t max_batch, void* stream, ppl_mlp_t* out) {
+  g_err[0] = 0;
+  if (!out) return fail(PPL_E_ARG, "null out");
+  *out = nullptr;
+  if (width != 128) return fail(PPL_E_UNSUPPORTED, "only width 128 is built (got %d)", width);
+  if (max_batch < 1 || max_batch > (int64_t)1 << 26) return fail(PPL_E_ARG, "max_batch out of range");
+  ppl_mlp_t q = new (std::nothrow) ppl_mlp_s();
+  if (!q) return fail(PPL_E_NOMEM, "host allocation failed");
+  q->stream = (hipStream_t)stream;
+  q->max_batch = max_batch;
+  const uint64_t P = (uint64_t)mlp_param_count();
+  const uint64_t nwg = (uint64_t)((max_batch + mlp_train_rows() - 1) / mlp_train_rows());
+  Layout L;
+  q->prm = L.take(P * 4);
+  q->m = L.take(P * 4);
+  q->v = L.take(P * 4);
+  q->grad = L.take(P * 4);
+  q->gpart = L.take(nwg * P * 4);
+  q->lpart = L.take(nwg * 4);
+  q->loss = L.take(16);
+  q->need = L.cur;
+  *out = q;
+  return PPL_OK;
+}
+
+int ppl_mlp_workspace_bytes(ppl_mlp_t q, uint64_t* bytes) {
+  if (!q || !bytes) return fail(PPL_E_ARG, "null argument");
+  *bytes = q->need;
+  return PPL_OK;
+}
+
+int ppl_mlp_param_count(ppl_mlp_t q) {
+  (void)q;
+  return mlp_param_count();
+}
+
+int ppl_mlp_bind_workspace(ppl_mlp_t q, void* dptr, uint64_t bytes) {
+  g_err[0] = 0;
+  if (!q || !dptr) return fail(PPL_E_ARG, "null argument");
+  if (((uintptr_t)dptr) % 256 != 0) return fail(PPL_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < q->need) return fail(PPL_E_NOMEM, "MLP workspace needs %llu bytes", (unsigned long long)q->need);
+  q->ws = (char*)dptr;
+  q->ws_bytes = bytes;
+  PPL_TRY(zero_bytes(q->stream, q->ws, q->need));
+  q->step = 0;
+  return PPL_OK;
+}
+
+int ppl_mlp_set_params(ppl_mlp_t q, const float* host, int64_t n) {
+  g_err[0] = 0;
+  PPL_TRY(mlp_check(q));
+  if (!host || n != mlp_param_count()) return fail(PPL_E_ARG, "expected %d parameters", mlp_param_count());
+  PPL_HIP_TRY(hipMemcpyAsync(mat<float>(q, q->prm), host, (size_t)n * 4, hipMemcpyHostToDevice, q->stream));
+  PPL_TRY(zero_bytes(q->stream, q->ws + q->m.off, q->m.bytes));
+  PPL_TRY(zero_bytes(q->stream, q->ws + q->v.off, q->v.bytes));
+  PPL_HIP_TRY(hipStreamSynchronize(q->stream));
+  q->step = 0;
+  return PPL_OK;
+}
+
+int ppl_mlp_get_params(ppl_mlp_t q, float* host, int64_t n) {
+  g_err[0] = 0;
+  PPL_TRY(mlp_check(q));
+  if (!host || n != mlp_param_count()) return fail(PPL_E_ARG, "expected %d parameters", mlp_param_count());
+  PPL_HIP_TRY(hipMemcpyAsync(host, mat<float>(q, q->prm), (size_t)n * 4, hipMemcpyDeviceToHost, q->stream));
+  PPL_HIP_TRY(hipStreamSynchronize(q->stream));
+  return PPL_OK;
+}
+
+int ppl_mlp_init(ppl_mlp_t q, uint64_t seed) {
+  g_err[0] = 0;
+  PPL_TRY(mlp_check(q));
+  const int P = mlp_param_count(), H = 128;
+  std::vector<float> w(P);
+  uint64_t st = seed;
+  auto uni = [&](double bound) {
+    const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
+    return (float)((2.0 * u - 1.0) * bound);
+  };
+  int o = 0;
+  for (int k = 0; k < H * 4; ++k) w[o++] = uni(1.0 / sqrt(4.0));     // W1
+  for (int k = 0; k < H; ++k) w[o++] = uni(1.0 / sqrt(4.0));         // b1
+  for (int k = 0; k < H * H; ++k) w[o++] = uni(1.0 / sqrt((double)H));  // W2
+  for (int k = 0; k < H; ++k) w[o++] = uni(1.0 / sqrt((double)H));     // b2
+  for (int k = 0; k < H; ++k) w[o++] = uni(1.0 / sqrt((double)H));     // W3
+  w[o++] = uni(1.0 / sqrt((double)H));                                  // b3
+  return ppl_mlp_set_params(q, w.data(), P);
+}
+
+int ppl_mlp_grad(ppl_mlp_t q, const float* X, const float* Y, int64_t n, float* host_grad, float* host_loss) {
+  g_err[0] = 0;
+  PPL_TRY(mlp_check(q));
+  if (!X || !Y || n < 1 || n > q->max_batch) return fail(PPL_E_ARG, "bad batch (n = %lld)", (long long)n);
+  PPL_TRY(mlp_train_launch(q->stream, mat<float>(q, q->prm), X, Y, n, mat<float>(q, q->gpart),
+                           mat<float>(q, q->lpart), mat<float>(q, q->grad), mat<float>(q, q->loss)));
+  if (host_grad)
+    PPL_HIP_TRY(hipMemcpyAsync(host_grad, mat<float>(q, q->grad), (size_t)mlp_param_count() * 4,
+                               hipMemcpyDeviceToHost, q->stream));
+  if (host_loss)
+    PPL_HIP_TRY(hipMemcpyAsync(host_loss, mat<float>(q, q->loss), 4, hipMemcpyDeviceToHost, q->stream));
+  PPL_HIP_TRY(hipStreamSynchronize(q->stream));
+  return PPL_OK;
+}
+
+int ppl_mlp_train_step(ppl_mlp_t q, const float* X, const float* Y, int64_t n, float lr, float* host_loss) {
+  g_err[0] = 0;
+  PPL_TRY(mlp_check(q));
+  if (!X || !Y || n < 1 || n > q->max_batch) return fail(PPL_E_ARG, "bad batch (n = %lld)", (long long)n);
+  if (!(lr > 0.0f)) return fail(PPL_E_ARG, "lr must be > 0");
+  PPL_TRY(mlp_train_launch(q->stream, mat<float>(q, q->prm), X, Y, n, mat<float>(q, q->gpart),
+                           mat<float>(q, q->lpart), mat<float>(q, q->grad), mat<float>(q, q->loss)));
+  q->step += 1;
+  PPL_TRY(mlp_adam_launch(q->stream, mat<float>(q, q->prm), mat<float>(q, q->grad), mat<float>(q, q->m),
+                          mat<float>(q, q->v), lr, q->step, 0.9f, 0.999f, 1e-8f));
+  if (host_loss) {
+    PPL_HIP_TRY(hipMemcpyAsync(host_loss, mat<float>(q, q->loss), 4, hipMemcpyDeviceToHost, q->stream));
+    PPL_HIP_TRY(hipStreamSynchronize(q->stream));
+  }
+  return PPL_OK;
+}
+
+int ppl_mlp_guess(ppl_mlp_t q, ppl_plan_t p, const double* t_mp2, const double* e_occ, const double* e_vir,
+                  double sigma, double* t2_out) {
+  g_err[0] = 0;
+  PPL_TRY(mlp_check(q));
+  PPL_TRY(check_bound(p));
+  if (!t_mp2 || !e_occ || !e_vir || !t2_out) return fail(PPL_E_ARG, "null device pointer");
+  if ((const void*)t_mp2 == (const void*)t2_out) return fail(PPL_E_ARG, "t2_out may not alias t_mp2");
+  if (!(sigma > 0.0)) return fail(PPL_E_ARG, "sigma must be > 0");
+  return mlp_infer_launch(p->stream, mat<float>(q, q->prm), p->o, p->v, t_mp2, e_occ, e_vir, sigma,
+                          at<int>(p, p->tab_om), at<int>(p, p->tab_vp), t2_out);
+}
+
+int ppl_mlp_destroy(ppl_mlp_t q) {
+  delete q;
   return PPL_OK;
 }
 

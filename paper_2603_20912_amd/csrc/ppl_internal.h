@@ -209,6 +209,19 @@ int zero_bytes(hipStream_t s, void* p, uint64_t bytes);
 // count non-finite values of an FP64 array (red_out[2])
 int count_nonfinite(hipStream_t s, const double* x, int64_t n, double* partials, double* red_out);
 
+// learned start
+int mlp_param_count();
+int mlp_train_rows();
+int mlp_train_launch(hipStream_t s, const float* prm, const float* X, const float* Y, int64_t n,
+                     float* gpart, float* lpart, float* grad, float* loss);
+int mlp_adam_launch(hipStream_t s, float* prm, const float* grad, float* m, float* v, float lr, int step,
+                    float beta1, float beta2, float eps);
+int mlp_samples_launch(hipStream_t s, int o, int v, const double* tm, const double* ts, const double* e_occ,
+                       const double* e_vir, double sigma, const int64_t* idx, int64_t n, float* X, float* Y);
+int mlp_infer_launch(hipStream_t s, const float* prm, int o, int v, const double* tm, const double* e_occ,
+                     const double* e_vir, double sigma, const int* tab_om, const int* tab_vp, double* tout);
+int sumsq_launch(hipStream_t s, const double* x, int64_t n, double* partials, double* red_out);
+
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 
