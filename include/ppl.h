@@ -66,6 +66,7 @@ typedef struct {
   int32_t  tile_contract; /* contraction tile id, -1 = planner's choice (see ppl_tile_count) */
   uint64_t hbm_budget;  /* bytes the workspace may use; 0 = 90% of the device's free memory */
   void*    stream;      /* hipStream_t every call of this plan enqueues on (NULL = null stream) */
+  uint64_t build_scratch; /* bytes of integral-build scratch (0 = up to 4 GiB); larger = fewer build steps */
 } ppl_desc_t;
 
 /* What the planner decided (output of ppl_plan_query). */
@@ -242,6 +243,33 @@ int ppl_set_contract_config(ppl_plan_t plan, int32_t tile_plus, int32_t splits_p
  * best_ms (optional, 2 doubles) receives the winning average times.
  */
 int ppl_autotune(ppl_plan_t plan, int32_t reps, double* best_ms);
+
+/* ------------------------------------------------ batched instances (one persistent launch) */
+/*
+ * Many independent, uneven (o, v, naux) instances of the ladder term share one
+ * workspace; their contractions run as one persistent grouped launch whose
+ * workgroups pull (instance, R+/R-, tile) items from a queue sorted
+ * longest-first, each instance with its own tile shape. The contraction
+ * sequence (packing, grouped launch, unpacking) can be captured once in a
+ * hipGraph and replayed. All instances use one precision (FP64 or FP32) and
+ * the stream of descs[0]; graph capture needs a non-default stream.
+ */
+typedef struct ppl_batch_s* ppl_batch_t;
+
+int ppl_batch_plan(int32_t n, const ppl_desc_t* descs, ppl_batch_t* out);
+/* workspace bytes and the current number of queue items (after build / autotune) */
+int ppl_batch_query(ppl_batch_t batch, uint64_t* workspace_bytes, int32_t* n_items);
+int ppl_batch_bind_workspace(ppl_batch_t batch, void* dptr, uint64_t bytes);
+/* L: host array of n device pointers, one Cholesky tensor per instance */
+int ppl_batch_build(ppl_batch_t batch, const double* const* L);
+/* per-instance tile choice of the grouped launch by timing each candidate (synchronous) */
+int ppl_batch_autotune(ppl_batch_t batch, int32_t reps);
+/* t2, R: host arrays of n device pointers; R_k = PPL_k(t2_k) */
+int ppl_batch_contract(ppl_batch_t batch, const double* const* t2, double* const* R);
+/* record ppl_batch_contract on these pointers into a graph (replaces a previous one) */
+int ppl_batch_graph_capture(ppl_batch_t batch, const double* const* t2, double* const* R);
+int ppl_batch_graph_launch(ppl_batch_t batch);
+int ppl_batch_destroy(ppl_batch_t batch);
 
 /* ------------------------------------------------ kernel timing (HIP events) */
 #define PPL_PROF_BUILD_GEMM     0  /* integral-build GEMM launches */

@@ -11,6 +11,9 @@ import ctypes
 import torch
 
 from . import _lib
+from ._lib import (ppl_batch_plan, ppl_batch_query, ppl_batch_bind_workspace, ppl_batch_build,
+                   ppl_batch_autotune, ppl_batch_contract, ppl_batch_graph_capture, ppl_batch_graph_launch,
+                   ppl_batch_destroy)
 from ._lib import (ppl_mp2, ppl_mlp_create, ppl_mlp_workspace_bytes, ppl_mlp_bind_workspace,
                    ppl_mlp_param_count, ppl_mlp_init, ppl_mlp_set_params, ppl_mlp_get_params, ppl_mlp_grad,
                    ppl_mlp_train_step, ppl_mlp_sigma, ppl_mlp_samples, ppl_mlp_guess, ppl_mlp_destroy,
@@ -25,7 +28,10 @@ __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace"
            "ppl_set_contract_config", "ppl_autotune", "ppl_mp2", "MLP", "ppl_mlp_create",
            "ppl_mlp_workspace_bytes", "ppl_mlp_bind_workspace", "ppl_mlp_param_count", "ppl_mlp_init",
            "ppl_mlp_set_params", "ppl_mlp_get_params", "ppl_mlp_grad", "ppl_mlp_train_step",
-           "ppl_mlp_sigma", "ppl_mlp_samples", "ppl_mlp_guess", "ppl_mlp_destroy"]
+           "ppl_mlp_sigma", "ppl_mlp_samples", "ppl_mlp_guess", "ppl_mlp_destroy", "Batch",
+           "ppl_batch_plan", "ppl_batch_query", "ppl_batch_bind_workspace", "ppl_batch_build",
+           "ppl_batch_autotune", "ppl_batch_contract", "ppl_batch_graph_capture", "ppl_batch_graph_launch",
+           "ppl_batch_destroy"]
 
 
 class PPL:
@@ -149,6 +155,50 @@ class MLP:
     def close(self):
         if getattr(self, "h", None) is not None:
             ppl_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many uneven instances contracted by one persistent grouped launch (optionally a hipGraph)."""
+
+    def __init__(self, shapes, prec="fp64", stream=None, device="cuda"):
+        self.shapes = list(shapes)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = ppl_batch_plan(self.shapes, prec, self.stream)
+        nbytes, _ = ppl_batch_query(self.h)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        ppl_batch_bind_workspace(self.h, self.workspace)
+
+    @property
+    def n_items(self):
+        return ppl_batch_query(self.h)[1]
+
+    def build(self, Ls):
+        self._L = list(Ls)          # the library keeps raw pointers
+        ppl_batch_build(self.h, self._L)
+
+    def autotune(self, reps=2):
+        ppl_batch_autotune(self.h, reps)
+
+    def contract(self, t2s, Rs):
+        ppl_batch_contract(self.h, t2s, Rs)
+
+    def capture(self, t2s, Rs):
+        self._graph_args = (list(t2s), list(Rs))
+        ppl_batch_graph_capture(self.h, t2s, Rs)
+
+    def replay(self):
+        ppl_batch_graph_launch(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ppl_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

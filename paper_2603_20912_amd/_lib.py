@@ -36,7 +36,7 @@ class ppl_desc_t(ctypes.Structure):
     _fields_ = [("o", ctypes.c_int32), ("v", ctypes.c_int32), ("naux", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("keep_fp64", ctypes.c_int32),
                 ("tile_contract", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("build_scratch", ctypes.c_uint64)]
 
 
 class ppl_plan_info_t(ctypes.Structure):
@@ -99,6 +99,15 @@ SIGNATURES = {
     "ppl_mlp_samples": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, ctypes.c_int64, _P, _P]),
     "ppl_mlp_guess": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P]),
     "ppl_mlp_destroy": (ctypes.c_int, [_P]),
+    "ppl_batch_plan": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ppl_desc_t), ctypes.POINTER(_P)]),
+    "ppl_batch_query": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32)]),
+    "ppl_batch_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "ppl_batch_build": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "ppl_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ppl_batch_contract": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "ppl_batch_graph_capture": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "ppl_batch_graph_launch": (ctypes.c_int, [_P]),
+    "ppl_batch_destroy": (ctypes.c_int, [_P]),
     "ppl_set_contract_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32]),
     "ppl_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
@@ -159,10 +168,11 @@ def _stream_handle(stream):
 
 
 # ---------------------------------------------------------------- same names as the C ABI
-def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None, tile_contract=-1):
+def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None, tile_contract=-1,
+             build_scratch=0):
     d = ppl_desc_t(o, v, naux, PREC[prec] if isinstance(prec, str) else int(prec), int(bool(keep_fp64)),
                    int(tile_contract), int(hbm_budget),
-                   _stream_handle(stream) if stream is not False else None)
+                   _stream_handle(stream) if stream is not False else None, int(build_scratch))
     h = ctypes.c_void_p()
     _check(load().ppl_plan(ctypes.byref(d), ctypes.byref(h)), "ppl_plan")
     return h
@@ -308,6 +318,61 @@ def ppl_mlp_guess(mlp, plan, t_mp2, e_occ, e_vir, sigma, t2_out):
 def ppl_mlp_destroy(mlp):
     if mlp is not None:
         load().ppl_mlp_destroy(mlp)
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t)
+    return arr
+
+
+def ppl_batch_plan(shapes, prec="fp64", stream=None):
+    n = len(shapes)
+    descs = (ppl_desc_t * n)()
+    sh = _stream_handle(stream)
+    for k, (o, v, naux) in enumerate(shapes):
+        descs[k] = ppl_desc_t(o, v, naux, PREC[prec], 0, -1, 0, sh, 0)
+    h = ctypes.c_void_p()
+    _check(load().ppl_batch_plan(n, descs, ctypes.byref(h)), "ppl_batch_plan")
+    return h
+
+
+def ppl_batch_query(batch):
+    b = ctypes.c_uint64(0)
+    n = ctypes.c_int32(0)
+    _check(load().ppl_batch_query(batch, ctypes.byref(b), ctypes.byref(n)), "ppl_batch_query")
+    return int(b.value), int(n.value)
+
+
+def ppl_batch_bind_workspace(batch, ws, nbytes=None):
+    n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
+    _check(load().ppl_batch_bind_workspace(batch, _ptr(ws), n), "ppl_batch_bind_workspace")
+
+
+def ppl_batch_build(batch, Ls):
+    _check(load().ppl_batch_build(batch, _ptr_array(Ls)), "ppl_batch_build")
+
+
+def ppl_batch_autotune(batch, reps=2):
+    _check(load().ppl_batch_autotune(batch, int(reps)), "ppl_batch_autotune")
+
+
+def ppl_batch_contract(batch, t2s, Rs):
+    _check(load().ppl_batch_contract(batch, _ptr_array(t2s), _ptr_array(Rs)), "ppl_batch_contract")
+
+
+def ppl_batch_graph_capture(batch, t2s, Rs):
+    _check(load().ppl_batch_graph_capture(batch, _ptr_array(t2s), _ptr_array(Rs)), "ppl_batch_graph_capture")
+
+
+def ppl_batch_graph_launch(batch):
+    _check(load().ppl_batch_graph_launch(batch), "ppl_batch_graph_launch")
+
+
+def ppl_batch_destroy(batch):
+    if batch is not None:
+        load().ppl_batch_destroy(batch)
 
 
 def ppl_destroy(plan):

@@ -145,6 +145,8 @@ static void make_tile_tables(ppl_plan_t p) {
   }
 }
 
+int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms, bool grouped_only);
+
 static int check_plan(ppl_plan_t p) {
   if (!p) return fail(PPL_E_ARG, "null plan");
   return PPL_OK;
@@ -395,9 +397,10 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   }
   p->budget = budget;
 
-  // G cap: at most 4 GiB of scratch, at least one full row a = 0 (v pairs)
+  // G cap: at most build_scratch (default 4 GiB) of scratch, at least one full row a = 0 (v pairs)
   const uint64_t per_pair_g = (uint64_t)p->v * p->v * acc_bytes(p->prec);
-  int64_t gcap = (int64_t)std::max<uint64_t>((uint64_t)p->v, (4ull << 30) / per_pair_g);
+  const uint64_t gbytes_cap = d->build_scratch ? d->build_scratch : (4ull << 30);
+  int64_t gcap = (int64_t)std::max<uint64_t>((uint64_t)p->v, gbytes_cap / per_pair_g);
   gcap = std::min<int64_t>(gcap, p->Pp);
   // try resident
   make_batches(p->v, gcap, p->batches);
@@ -676,7 +679,12 @@ int ppl_set_contract_config(ppl_plan_t p, int32_t tp, int32_t sp, int32_t tm, in
   return PPL_OK;
 }
 
-int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) {
+int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) { return autotune_impl(p, reps, best_ms, false); }
+
+}  // extern "C"
+
+namespace ppl {
+int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms, bool grouped_only) {
   g_err[0] = 0;
   PPL_TRY(check_bound(p));
   if (reps < 1) return fail(PPL_E_ARG, "reps must be >= 1");
@@ -701,7 +709,8 @@ int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) {
     const void* V_lo = (plus ? s.vp_lo : s.vm_lo).bytes ? at<void>(p, plus ? s.vp_lo : s.vm_lo) : nullptr;
     void* C = at<void>(p, plus ? p->rp : p->rm);
     for (int t = 0; t < nt && rc == PPL_OK; ++t) {
-      for (int sp = 1; sp <= kMaxSplits && rc == PPL_OK; ++sp) {
+      if (grouped_only && !grouped_tile_ok(t)) continue;
+      for (int sp = 1; sp <= (grouped_only ? 1 : kMaxSplits) && rc == PPL_OK; ++sp) {
         if (sp > 1 && contract_jobs(t, s.prec, Nr, Pr, ld, sp) == contract_jobs(t, s.prec, Nr, Pr, ld, sp - 1))
           continue;   // same effective split count as a smaller request
         rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld);
@@ -738,6 +747,9 @@ int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) {
   }
   return PPL_OK;
 }
+}  // namespace ppl
+
+extern "C" {
 
 int ppl_profile_enable(ppl_plan_t p, int on) {
   PPL_TRY(check_plan(p));
@@ -988,6 +1000,270 @@ int ppl_mlp_guess(ppl_mlp_t q, ppl_plan_t p, const double* t_mp2, const double* 
 
 int ppl_mlp_destroy(ppl_mlp_t q) {
   delete q;
+  return PPL_OK;
+}
+
+// ---------------------------------------------------------------- batched instances
+}  // extern "C"
+
+struct ppl_batch_s {
+  int n = 0, prec = PPL_FP64;
+  hipStream_t stream = nullptr;
+  std::vector<ppl_plan_t> plans;
+  std::vector<uint64_t> offs;
+  uint64_t need = 0;
+  ppl::Region groups_r, items_r, counter_r;
+  int64_t max_items = 0;
+  char* ws = nullptr;
+  std::vector<ppl::GroupDesc> groups;
+  std::vector<int4> items;
+  bool built = false, prepared = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace ppl {
+static int batch_check(ppl_batch_t b) {
+  if (!b) return fail(PPL_E_ARG, "null batch");
+  if (!b->ws) return fail(PPL_E_STATE, "no batch workspace bound");
+  return PPL_OK;
+}
+
+// model choice among the grouped tiles: least padding of the occupied-pair rows, then the larger tile
+static int grouped_default_tile(int64_t rows) {
+  int best = 5;
+  double best_eff = -1.0;
+  for (int t = 0; t < contract_tile_count(); ++t) {
+    if (!grouped_tile_ok(t)) continue;
+    int bm, bn;
+    grouped_tile_dims(t, &bm, &bn);
+    const double eff = (double)rows / (double)((rows + bm - 1) / bm * bm) + 1e-6 * bm;
+    if (eff > best_eff) {
+      best_eff = eff;
+      best = t;
+    }
+  }
+  return best;
+}
+
+static int batch_prepare(ppl_batch_t b) {
+  b->groups.clear();
+  b->items.clear();
+  const int KC = b->prec == PPL_FP64 ? 16 : 32;
+  struct Item { int4 w; double work; };
+  std::vector<Item> its;
+  for (int k = 0; k < b->n; ++k) {
+    ppl_plan_t p = b->plans[k];
+    OperandSet& s = p->ops[0];
+    for (int which = 0; which < 2; ++which) {
+      const bool plus = which == 0;
+      const int64_t M = plus ? p->Np : p->Nm, N = plus ? p->Pp : p->Pm, ld = plus ? p->ldp : p->ldm;
+      if (M <= 0 || N <= 0) continue;
+      int tile = plus ? p->tile_contract : p->tile_m;
+      if (!grouped_tile_ok(tile)) tile = grouped_default_tile(M);
+      GroupDesc g;
+      g.A = at<void>(p, plus ? s.sp : s.am);
+      g.B = at<void>(p, plus ? s.vp : s.vm);
+      g.C = at<void>(p, plus ? p->rp : p->rm);
+      g.M = M;
+      g.N = N;
+      g.nk = ld / KC;
+      g.lda = g.ldb = g.ldc = ld;
+      g.cfg = tile;
+      g.pad = 0;
+      const int gi = (int)b->groups.size();
+      b->groups.push_back(g);
+      int bm, bn;
+      grouped_tile_dims(tile, &bm, &bn);
+      for (int64_t mt = 0; mt * bm < M; ++mt)
+        for (int64_t nt = 0; nt * bn < N; ++nt)
+          its.push_back({int4{gi, (int)(mt * bm), (int)(nt * bn), 0}, (double)bm * bn * g.nk});
+    }
+  }
+  if ((int64_t)its.size() > b->max_items) return fail(PPL_E_ARG, "too many batch items");
+  std::stable_sort(its.begin(), its.end(), [](const Item& x, const Item& y) { return x.work > y.work; });
+  for (const Item& it : its) b->items.push_back(it.w);
+  if (!b->groups.empty())
+    PPL_HIP_TRY(hipMemcpyAsync(b->ws + b->groups_r.off, b->groups.data(), b->groups.size() * sizeof(GroupDesc),
+                               hipMemcpyHostToDevice, b->stream));
+  if (!b->items.empty())
+    PPL_HIP_TRY(hipMemcpyAsync(b->ws + b->items_r.off, b->items.data(), b->items.size() * sizeof(int4),
+                               hipMemcpyHostToDevice, b->stream));
+  PPL_HIP_TRY(hipStreamSynchronize(b->stream));
+  b->prepared = true;
+  return PPL_OK;
+}
+
+static int batch_enqueue(ppl_batch_t b, const double* const* t2, double* const* R) {
+  for (int k = 0; k < b->n; ++k) {
+    ppl_plan_t p = b->plans[k];
+    const int64_t o = p->o, v = p->v;
+    if (!t2[k] || !R[k]) return fail(PPL_E_ARG, "null t2 or R for instance %d", k);
+    PPL_TRY(pack_pm(b->stream, p->o, p->v, t2[k], o * v * v, v * v, v, 1, 1.0, 0.5, 1.0, at<double>(p, p->s64),
+                    p->ldp, at<double>(p, p->a64), p->ldm, at<int>(p, p->tab_op), at<int>(p, p->tab_om),
+                    at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+    PPL_TRY(refresh_operands(p, p->ops[0]));
+  }
+  const int n_items = (int)b->items.size();
+  const int grid = n_items < 512 ? n_items : 512;
+  PPL_TRY(gemm_grouped(b->stream, b->prec, reinterpret_cast<const GroupDesc*>(b->ws + b->groups_r.off),
+                       reinterpret_cast<const int4*>(b->ws + b->items_r.off), n_items,
+                       reinterpret_cast<int*>(b->ws + b->counter_r.off), grid));
+  for (int k = 0; k < b->n; ++k) {
+    ppl_plan_t p = b->plans[k];
+    PPL_TRY(unpack_r(b->stream, b->prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, at<void>(p, p->rp),
+                     p->ldp, at<void>(p, p->rm), p->ldm, R[k], 1.0, 0.0));
+  }
+  return PPL_OK;
+}
+
+static void batch_drop_graph(ppl_batch_t b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+}  // namespace ppl
+
+extern "C" {
+
+int ppl_batch_plan(int32_t n, const ppl_desc_t* descs, ppl_batch_t* out) {
+  g_err[0] = 0;
+  if (!out || !descs || n < 1) return fail(PPL_E_ARG, "bad batch arguments");
+  *out = nullptr;
+  const int prec = descs[0].prec;
+  if (prec != PPL_FP64 && prec != PPL_FP32) return fail(PPL_E_UNSUPPORTED, "batched instances run in FP64 or FP32");
+  ppl_batch_t b = new (std::nothrow) ppl_batch_s();
+  if (!b) return fail(PPL_E_NOMEM, "host allocation failed");
+  b->n = n;
+  b->prec = prec;
+  b->stream = (hipStream_t)descs[0].stream;
+  uint64_t off = 0;
+  int64_t max_items = 0;
+  for (int k = 0; k < n; ++k) {
+    ppl_desc_t d = descs[k];
+    if (d.prec != prec || d.stream != descs[0].stream) {
+      ppl_batch_destroy(b);
+      return fail(PPL_E_ARG, "all instances need the same precision and stream");
+    }
+    d.keep_fp64 = 0;
+    if (d.hbm_budget == 0) d.hbm_budget = (uint64_t)1 << 62;
+    if (d.build_scratch == 0) d.build_scratch = (uint64_t)256 << 20;   // builds run one instance at a time
+    ppl_plan_t p = nullptr;
+    const int rc = ppl_plan(&d, &p);
+    if (rc != PPL_OK) {
+      ppl_batch_destroy(b);
+      return rc;
+    }
+    b->plans.push_back(p);
+    if (!p->resident) {
+      ppl_batch_destroy(b);
+      return fail(PPL_E_UNSUPPORTED, "instance %d does not fit its budget resident", k);
+    }
+    b->offs.push_back(off);
+    off += align256(p->ws_bytes_needed);
+    // upper bound of items: the smallest grouped tiles (32 rows, 64 columns)
+    max_items += ((p->Np + 31) / 32) * ((p->Pp + 63) / 64) + ((p->Nm + 31) / 32) * ((p->Pm + 63) / 64);
+  }
+  Layout L;
+  L.cur = off;
+  b->groups_r = L.take((uint64_t)2 * n * sizeof(GroupDesc));
+  b->items_r = L.take((uint64_t)max_items * sizeof(int4));
+  b->counter_r = L.take(256);
+  b->max_items = max_items;
+  b->need = L.cur;
+  *out = b;
+  return PPL_OK;
+}
+
+int ppl_batch_query(ppl_batch_t b, uint64_t* bytes, int32_t* n_items) {
+  if (!b) return fail(PPL_E_ARG, "null batch");
+  if (bytes) *bytes = b->need;
+  if (n_items) *n_items = (int32_t)b->items.size();
+  return PPL_OK;
+}
+
+int ppl_batch_bind_workspace(ppl_batch_t b, void* dptr, uint64_t bytes) {
+  g_err[0] = 0;
+  if (!b || !dptr) return fail(PPL_E_ARG, "null argument");
+  if (((uintptr_t)dptr) % 256 != 0) return fail(PPL_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < b->need) return fail(PPL_E_NOMEM, "batch workspace needs %llu bytes", (unsigned long long)b->need);
+  for (int k = 0; k < b->n; ++k)
+    PPL_TRY(ppl_bind_workspace(b->plans[k], (char*)dptr + b->offs[k], b->plans[k]->ws_bytes_needed));
+  b->ws = (char*)dptr;
+  b->built = b->prepared = false;
+  batch_drop_graph(b);
+  return PPL_OK;
+}
+
+int ppl_batch_build(ppl_batch_t b, const double* const* L) {
+  g_err[0] = 0;
+  PPL_TRY(batch_check(b));
+  if (!L) return fail(PPL_E_ARG, "null L array");
+  for (int k = 0; k < b->n; ++k) {
+    if (!L[k]) return fail(PPL_E_ARG, "null L for instance %d", k);
+    PPL_TRY(ppl_build_batch(b->plans[k], L[k], -1));
+  }
+  b->built = true;
+  return batch_prepare(b);
+}
+
+int ppl_batch_autotune(ppl_batch_t b, int32_t reps) {
+  g_err[0] = 0;
+  PPL_TRY(batch_check(b));
+  if (!b->built) return fail(PPL_E_STATE, "build the batch before autotuning");
+  for (int k = 0; k < b->n; ++k) PPL_TRY(autotune_impl(b->plans[k], reps, nullptr, true));
+  batch_drop_graph(b);
+  return batch_prepare(b);
+}
+
+int ppl_batch_contract(ppl_batch_t b, const double* const* t2, double* const* R) {
+  g_err[0] = 0;
+  PPL_TRY(batch_check(b));
+  if (!t2 || !R) return fail(PPL_E_ARG, "null pointer array");
+  if (!b->built || !b->prepared) return fail(PPL_E_STATE, "batch not built");
+  return batch_enqueue(b, t2, R);
+}
+
+int ppl_batch_graph_capture(ppl_batch_t b, const double* const* t2, double* const* R) {
+  g_err[0] = 0;
+  PPL_TRY(batch_check(b));
+  if (!t2 || !R) return fail(PPL_E_ARG, "null pointer array");
+  if (!b->built || !b->prepared) return fail(PPL_E_STATE, "batch not built");
+  if (b->stream == nullptr) return fail(PPL_E_ARG, "graph capture needs a non-default stream");
+  batch_drop_graph(b);
+  for (int k = 0; k < b->n; ++k) b->plans[k]->prof_on = false;
+  PPL_HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  const int rc = batch_enqueue(b, t2, R);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc != PPL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PPL_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  b->graph = g;
+  const hipError_t e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    batch_drop_graph(b);
+    return fail(PPL_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
+  }
+  return PPL_OK;
+}
+
+int ppl_batch_graph_launch(ppl_batch_t b) {
+  g_err[0] = 0;
+  PPL_TRY(batch_check(b));
+  if (!b->exec) return fail(PPL_E_STATE, "no captured graph");
+  PPL_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  return PPL_OK;
+}
+
+int ppl_batch_destroy(ppl_batch_t b) {
+  if (!b) return PPL_OK;
+  batch_drop_graph(b);
+  for (ppl_plan_t p : b->plans) ppl_destroy(p);
+  delete b;
   return PPL_OK;
 }
 

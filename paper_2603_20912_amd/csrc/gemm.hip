@@ -164,10 +164,21 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
 };
 
 // ------------------------------------------------------------------ the kernel (FP64 / FP32)
-template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
-__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(2)))
-gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int64_t lda,
-               const T* __restrict__ B, int64_t ldb, Epi epi, Map map) {
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+struct TileGeom {
+  static constexpr int NT = 64 * WAVES_M * WAVES_N;
+  static constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  static constexpr int LDSR = KC + 16 / (int)sizeof(T);
+  static constexpr int LDS_A = 2 * BM * LDSR, LDS_B = 2 * BN * LDSR;   // elements, two buffers each
+  static constexpr int LDS_BYTES = (LDS_A + LDS_B) * (int)sizeof(T);
+};
+
+// One BM x BN tile of C over the K chunks [job.kc0, job.kc1); sA0 / sB0 hold
+// two LDS buffers of BM (BN) rows each.
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
+__device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t N, const T* __restrict__ A,
+                                          int64_t lda, const T* __restrict__ B, int64_t ldb, const Epi& epi,
+                                          T* __restrict__ sA0, T* __restrict__ sB0) {
   using accv = typename AccOf<T>::vec;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
@@ -178,11 +189,6 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
   constexpr int NLA = (BM * VPR + NT - 1) / NT;
   constexpr int NLB = (BN * VPR + NT - 1) / NT;
   static_assert(KC % 4 == 0 && KC % VEC == 0, "bad KC");
-  __shared__ __attribute__((aligned(16))) T sA[2][BM * LDSR];
-  __shared__ __attribute__((aligned(16))) T sB[2][BN * LDSR];
-
-  TileJob job;
-  if (!map(blockIdx.x, job)) return;
   const int64_t m0 = job.m0, n0 = job.n0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
@@ -230,9 +236,9 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
 #pragma unroll
     for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i]);
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA[0][oa[i]]) = ra[i];
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA0[oa[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB[0][ob[i]]) = rb[i];
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB0[ob[i]]) = rb[i];
   }
   __syncthreads();
 
@@ -245,8 +251,8 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
     for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i] + k1);
 #pragma unroll
     for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i] + k1);
-    const T* As = sA[buf];
-    const T* Bs = sB[buf];
+    const T* As = sA0 + buf * (BM * LDSR);
+    const T* Bs = sB0 + buf * (BN * LDSR);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T a[WM], b[WN];
@@ -260,15 +266,15 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
         for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
     }
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA[buf ^ 1][oa[i]]) = ra[i];
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA0[(buf ^ 1) * (BM * LDSR) + oa[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB[buf ^ 1][ob[i]]) = rb[i];
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB0[(buf ^ 1) * (BN * LDSR) + ob[i]]) = rb[i];
     __syncthreads();
   }
   {  // last chunk
     const int buf = (int)((nk - 1) & 1);
-    const T* As = sA[buf];
-    const T* Bs = sB[buf];
+    const T* As = sA0 + buf * (BM * LDSR);
+    const T* Bs = sB0 + buf * (BN * LDSR);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T a[WM], b[WN];
@@ -298,6 +304,19 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
       }
     }
   }
+}
+
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int64_t lda,
+               const T* __restrict__ B, int64_t ldb, Epi epi, Map map) {
+  using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
+  __shared__ __attribute__((aligned(16))) T sA[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) T sB[G::LDS_B];
+  (void)Kpad;
+  TileJob job;
+  if (!map(blockIdx.x, job)) return;
+  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA, sB);
 }
 
 // ------------------------------------------------------------------ the kernel (BF16 x 3)
@@ -454,6 +473,9 @@ static const TileCfg kContract[] = {
     {2, 4, 1, 4},   // 3:  32 x 256
     {3, 4, 1, 4},   // 4:  48 x 256
     {6, 2, 1, 4},   // 5:  96 x 128
+    {2, 2, 1, 4},   // 6:  32 x 128
+    {3, 2, 1, 4},   // 7:  48 x 128
+    {4, 2, 1, 4},   // 8:  64 x 128
 };
 static const int kNumContract = sizeof(kContract) / sizeof(kContract[0]);
 static const TileCfg kBuild = {4, 4, 2, 2};   // 128 x 128
@@ -609,6 +631,9 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
     PPL_CFG(3, 2, 4, 1, 4)
     PPL_CFG(4, 3, 4, 1, 4)
     PPL_CFG(5, 6, 2, 1, 4)
+    PPL_CFG(6, 2, 2, 1, 4)
+    PPL_CFG(7, 3, 2, 1, 4)
+    PPL_CFG(8, 4, 2, 1, 4)
     default:
       return fail(PPL_E_ARG, "unknown contraction tile %d", tile);
   }
@@ -695,6 +720,85 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
   EpiStore<double> epi{C, ldc, 0, M, N, 1.0, 0.0, 0};
   return launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, map.n_mt * map.n_nt, M, N, Kpad, A, lda, B,
                                                       ldb, epi, map);
+}
+
+// ------------------------------------------------------------------ grouped persistent contraction
+// Many independent contraction GEMMs (instances x {R+, R-}) in one launch: a
+// fixed grid of workgroups pulls (group, row tile, column tile) items from a
+// queue sorted longest-first; each group carries its own tile shape. Every
+// workgroup leaves the loop once the queue counter passes the item count.
+bool grouped_tile_ok(int tile) { return tile == 1 || tile == 2 || tile >= 5; }
+
+template <class T>
+struct GroupedLds {
+  static constexpr int bytes = TileGeom<T, 13, 1, 1, 4, (sizeof(T) == 8 ? 16 : 32)>::LDS_BYTES;  // largest allowed tile
+};
+
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, char* smem) {
+  using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
+  static_assert(G::LDS_BYTES <= GroupedLds<T>::bytes, "tile does not fit the grouped LDS buffer");
+  static_assert(G::NT == 256, "grouped tiles use 256 threads");
+  TileJob job{m0, n0, 0, g.nk, 0};
+  EpiStore<T> epi{(T*)g.C, g.ldc, 0, g.M, g.N, 1.0, 0.0, 0};
+  T* sA = reinterpret_cast<T*>(smem);
+  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, g.M, g.N, (const T*)g.A, g.lda, (const T*)g.B, g.ldb, epi,
+                                             sA, sA + G::LDS_A);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict__ items, int n_items,
+                    int* counter) {
+  constexpr int KC = sizeof(T) == 8 ? 16 : 32;
+  __shared__ __attribute__((aligned(16))) char smem[GroupedLds<T>::bytes];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int4 w = items[it];
+    const GroupDesc g = groups[w.x];
+    switch (g.cfg) {
+      case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, smem); break;
+      case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(int* c) { *c = 0; }
+
+// tile sizes a grouped item of `tile` covers (must match grouped_tile above)
+void grouped_tile_dims(int tile, int* bm, int* bn) {
+  switch (tile) {
+    case 1: *bm = 128; *bn = 128; break;
+    case 2: *bm = 208; *bn = 64; break;
+    case 5: *bm = 96; *bn = 128; break;
+    case 6: *bm = 32; *bn = 128; break;
+    case 7: *bm = 48; *bn = 128; break;
+    default: *bm = 64; *bn = 128; break;
+  }
+}
+
+int gemm_grouped(hipStream_t s, int prec, const GroupDesc* groups, const int4* items, int n_items, int* counter,
+                 int grid) {
+  if (n_items <= 0) return PPL_OK;
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  PPL_HIP_TRY(hipGetLastError());
+  if (prec == PPL_FP64)
+    hipLaunchKernelGGL(gemm_grouped_kernel<double>, dim3(grid), dim3(256), 0, s, groups, items, n_items, counter);
+  else if (prec == PPL_FP32)
+    hipLaunchKernelGGL(gemm_grouped_kernel<float>, dim3(grid), dim3(256), 0, s, groups, items, n_items, counter);
+  else
+    return fail(PPL_E_UNSUPPORTED, "grouped contraction supports FP64 and FP32");
+  PPL_HIP_TRY(hipGetLastError());
+  return PPL_OK;
 }
 
 }  // namespace ppl

@@ -150,6 +150,19 @@ void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int m
                      int* splits_out);
 constexpr int kMaxSplits = 4;
 
+// grouped persistent contraction (batched instances)
+struct GroupDesc {
+  const void* A;         // S' or A' rows [M][lda]
+  const void* B;         // V+ or V- rows [N][ldb]
+  void* C;               // R+ or R- [M][ldc]
+  int64_t M, N, nk, lda, ldb, ldc;
+  int cfg, pad;
+};
+bool grouped_tile_ok(int tile);
+void grouped_tile_dims(int tile, int* bm, int* bn);
+int gemm_grouped(hipStream_t s, int prec, const GroupDesc* groups, const int4* items, int n_items, int* counter,
+                 int grid);
+
 // Integral build G[pair(a,b) - pair(a0,a0)][c][d] = sum_P Xt[(a,c)][P] Xt[(b,d)][P]
 // for a in [a0, a1), b in [a, v).
 int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,

@@ -1,0 +1,122 @@
+"""GPU tests of the batched persistent launch: per-instance parity of the
+grouped contraction against the oracle, FP32 at its bound, bitwise equality of
+hipGraph replays with the eager launch, and the full uneven 32-instance list
+at sampled entries."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import ppl_synth as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2603_20912_amd as P
+    return P
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+SMALL = [(3, 17, 51), (8, 40, 120), (2, 9, 27), (12, 33, 99), (5, 64, 30), (1, 5, 15)]
+
+
+def make(shapes, seed0):
+    systems, amps = [], []
+    for k, (o, v, naux) in enumerate(shapes):
+        systems.append(S.make_system(o, v, naux, seed0 + k))
+        amps.append(S.make_amplitudes(o, v, seed0 + 100 + k))
+    return systems, amps
+
+
+@pytest.mark.parametrize("prec,bound,tune", [("fp64", 1e-12, False), ("fp64", 1e-12, True), ("fp32", 2e-6, True)])
+def test_grouped_contraction_matches_oracle(P, prec, bound, tune):
+    say(f"batched {prec} autotune={tune} shapes={SMALL}")
+    systems, amps = make(SMALL, 500)
+    b = P.Batch(SMALL, prec=prec)
+    Ls = [torch.from_numpy(s["L"]).cuda() for s in systems]
+    ts = [torch.from_numpy(t).cuda() for t in amps]
+    Rs = [torch.empty_like(t) for t in ts]
+    b.build(Ls)
+    if tune:
+        b.autotune(reps=1)
+    assert b.n_items > 0
+    b.contract(ts, Rs)
+    torch.cuda.synchronize()
+    for k, (s, t) in enumerate(zip(systems, amps)):
+        err = rel(Rs[k].cpu().numpy(), O.ppl(s["L"], s["o"], t))
+        assert err < bound, (k, err)
+    b.close()
+
+
+def test_graph_replay_is_bitwise_equal_to_eager(P):
+    say("batched fp64 hipGraph replays")
+    systems, amps = make(SMALL, 700)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = P.Batch(SMALL, prec="fp64", stream=stream)
+        Ls = [torch.from_numpy(s["L"]).cuda() for s in systems]
+        ts = [torch.from_numpy(t).cuda() for t in amps]
+        Rg = [torch.empty_like(t) for t in ts]
+        Re = [torch.empty_like(t) for t in ts]
+        b.build(Ls)
+        b.autotune(reps=1)
+        b.capture(ts, Rg)
+        for rep in range(3):
+            for t in ts:                     # new amplitudes in place between replays
+                t.mul_(1.0 + 0.25 * rep)
+            stream.synchronize()
+            b.replay()
+            stream.synchronize()
+            b.contract(ts, Re)               # eager work between the replays
+            stream.synchronize()
+            for k in range(len(ts)):
+                assert torch.equal(Rg[k], Re[k]), (rep, k)
+        for k, s in enumerate(systems):
+            ref = O.ppl(s["L"], s["o"], ts[k].cpu().numpy())
+            assert rel(Rg[k].cpu().numpy(), ref) < 1e-12
+        b.close()
+
+
+def test_full_uneven_list_sampled(P):
+    shapes = S.batched_shapes(32, seed=4)
+    say(f"batched fp64, 32 uneven instances: {[(d['o'], d['v']) for d in shapes]}")
+    sh = [(d["o"], d["v"], d["naux"]) for d in shapes]
+    b = P.Batch(sh, prec="fp64")
+    Ls, ts, Rs, systems, amps = [], [], [], [], []
+    for d in shapes:
+        s = S.make_system(d["o"], d["v"], d["naux"], d["seed"])
+        t = S.make_amplitudes(d["o"], d["v"], d["seed"] + 5000)
+        systems.append(s)
+        amps.append(t)
+        Ls.append(torch.from_numpy(s["L"]).cuda())
+        ts.append(torch.from_numpy(t).cuda())
+        Rs.append(torch.empty_like(ts[-1]))
+        s["L_host"] = s.pop("L")
+    b.build(Ls)
+    b.autotune(reps=1)
+    b.contract(ts, Rs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    for k, (s, t) in enumerate(zip(systems, amps)):
+        o, v = s["o"], s["v"]
+        idx = [tuple(int(x) for x in (rng.integers(o), rng.integers(o), rng.integers(v), rng.integers(v)))
+               for _ in range(20)]
+        ref = O.ppl_sampled(s["L_host"], o, t, idx)
+        R = Rs[k].cpu().numpy()
+        got = np.array([R[i] for i in idx])
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max(), k
+    b.close()
