@@ -78,6 +78,65 @@ def measured_traffic(config):
     return rec["traffic_bytes_per_launch"]
 
 
+def study_c3(args):
+    """Time to an amplitude residual of 1e-7 at (40, 400, 1200), contractive generator
+    seed 2: FP64, BF16x3 / FP32 sweeps refined in FP64, and the same from the learned
+    start; plus single-evaluation errors of the low-precision GEMMs."""
+    import numpy as np
+    import torch
+
+    import paper_2603_20912_amd as P
+    from paper_2603_20912_amd import learned as Lr
+    import ppl_synth
+
+    o, v, naux = 40, 400, 1200
+    sysd = ppl_synth.make_system(o, v, naux, 2, "contractive")
+    mlp = None
+    if args.weights and os.path.exists(args.weights):
+        mlp = P.MLP(max_batch=1024)
+        mlp.set_params(np.fromfile(args.weights, dtype="<f4"))
+    # warm-up of every code path on a small instance
+    small = ppl_synth.make_system(4, 24, 72, 99, "contractive")
+    for start, prec, keep in (("mp2", "fp64", False), ("mp2", "bf16x3", True), ("mp2", "fp32", True)):
+        Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep)
+    if mlp is not None:
+        Lr.time_to_tol(small, "learned", mlp=mlp, prec="bf16x3", keep_fp64=True)
+    runs = [("fp64", "mp2", "fp64", False), ("bf16x3+fp64", "mp2", "bf16x3", True),
+            ("fp32+fp64", "mp2", "fp32", True)]
+    if mlp is not None:
+        runs += [("bf16x3+fp64 learned", "learned", "bf16x3", True), ("fp64 learned", "learned", "fp64", False)]
+    out = {"config": {"o": o, "v": v, "naux": naux, "generator": "contractive", "seed": 2, "tol": 1e-7}}
+    ref_t, ref_E = None, None
+    for label, start, prec, keep in runs:
+        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep)
+        row = {"seconds": round(rep["seconds"], 3), "sweeps_lp": rep["sweeps_lp"], "sweeps_fp64": rep["sweeps_fp64"],
+               "residual": rep["residual"], "energy": rep["energy"], "status": rep["status"]}
+        if ref_t is None:
+            ref_t, ref_E = t.clone(), rep["energy"]
+        else:
+            row["rel_err_t_vs_fp64"] = (torch.linalg.norm(t - ref_t) / torch.linalg.norm(ref_t)).item()
+            row["abs_err_E_vs_fp64"] = abs(rep["energy"] - ref_E)
+        out[label] = row
+        print(json.dumps({label: row}), file=sys.stderr, flush=True)
+        del t
+        torch.cuda.empty_cache()
+    # single-evaluation errors of R (MP2 amplitudes) against the FP64 path
+    d = Lr.upload_system(sysd)
+    Rs = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        eng = P.PPL(o, v, naux, prec=prec)
+        tm, _ = eng.mp2(d["L"], d["e_occ"], d["e_vir"])
+        eng.build(d["L"])
+        Rs[prec] = eng.contract(tm)
+        eng.close()
+        del eng
+        torch.cuda.empty_cache()
+    for prec in ("fp32", "bf16x3"):
+        out[f"single_R_rel_err_{prec}"] = (torch.linalg.norm(Rs[prec] - Rs["fp64"]) /
+                                           torch.linalg.norm(Rs["fp64"])).item()
+    print(json.dumps({"study": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +147,11 @@ def main():
                     help="tile_plus,splits_plus,tile_minus,splits_minus instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--study", default="", help="c3: time-to-1e-7 study at (40, 400, 1200)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2603_20912_amd", "weights", "mlp_start.f32"))
     args = ap.parse_args()
+    if args.study == "c3":
+        return study_c3(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(every box has a single MI355X); run with --gpus 1", file=sys.stderr)

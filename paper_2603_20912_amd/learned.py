@@ -94,3 +94,103 @@ def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, m
     rep["sweeps"] = rep["sweeps_lp"] + rep["sweeps_fp64"]
     eng.close()
     return rep, t
+
+
+# ---------------------------------------------------------------- command line
+def _train_main(args):
+    import json
+    import ppl_synth as S
+    shapes = S.training_shapes(args.n_inst, seed=args.shape_seed)
+    gen = torch.Generator().manual_seed(args.seed)
+    Xs, Ys, meta = [], [], []
+    t0 = time.perf_counter()
+    for k, sh in enumerate(shapes):
+        sysd = S.make_system(sh["o"], sh["v"], sh["naux"], sh["seed"], "contractive")
+        inst = converge(sysd, tol=args.tol)
+        X, Y = sample(inst, args.samples, gen)
+        Xs.append(X)
+        Ys.append(Y)
+        rep = inst["report"]
+        meta.append({"o": sh["o"], "v": sh["v"], "seed": sh["seed"], "sweeps": rep["sweeps_fp64"],
+                     "residual": rep["residual"]})
+        inst["eng"].close()
+        del inst
+        torch.cuda.empty_cache()
+        print(f"[train-data] {k + 1}/{len(shapes)} o={sh['o']} v={sh['v']} sweeps={rep['sweeps_fp64']} "
+              f"r={rep['residual']:.1e} t={time.perf_counter() - t0:.0f}s", flush=True)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    del Xs, Ys
+    mlp = MLP(max_batch=args.batch, seed=args.seed)
+    t1 = time.perf_counter()
+    hist = train(mlp, X, Y, steps=args.steps, batch=args.batch, lr=args.lr, seed=args.seed,
+                 log_every=max(args.steps // 20, 1))
+    torch.cuda.synchronize()
+    for it, loss in hist:
+        print(f"[train] step {it} loss {loss:.4e}", flush=True)
+    params = mlp.get_params()
+    params.astype("<f4").tofile(args.out)
+    info = {"instances": len(shapes), "samples": int(Y.numel()), "steps": args.steps, "batch": args.batch,
+            "lr": args.lr, "data_seconds": t1 - t0, "train_seconds": time.perf_counter() - t1,
+            "loss_first": hist[0][1], "loss_last": hist[-1][1], "weights": args.out}
+    print(json.dumps(info), flush=True)
+
+
+def _eval_main(args):
+    import json
+    import ppl_synth as S
+    mlp = MLP(max_batch=1024)
+    mlp.set_params(np.fromfile(args.weights, dtype="<f4"))
+    # warm every code path once so that no timed run pays first-launch costs
+    small = S.make_system(4, 24, 72, 99, "contractive")
+    for start, prec, keep in (("mp2", "fp64", False), ("checked", "fp64", False), ("learned", args.lp, True)):
+        time_to_tol(small, start, mlp=mlp, tol=args.tol, prec=prec, keep_fp64=keep)
+    out = []
+    for k in range(args.held_out):
+        sysd = S.make_system(args.o, args.v, args.naux, args.seed0 + k, "contractive")
+        row = {"seed": args.seed0 + k}
+        for label, start, prec, keep in (("fp64_mp2", "mp2", "fp64", False),
+                                         ("fp64_learned", "learned", "fp64", False),
+                                         ("fp64_checked", "checked", "fp64", False),
+                                         ("mixed_mp2", "mp2", args.lp, True),
+                                         ("mixed_learned", "learned", args.lp, True)):
+            rep, _ = time_to_tol(sysd, start, mlp=mlp, tol=args.tol, prec=prec, keep_fp64=keep)
+            row[label] = {"seconds": round(rep["seconds"], 4), "sweeps": rep["sweeps"],
+                          "sweeps_lp": rep["sweeps_lp"], "residual": rep["residual"], "energy": rep["energy"],
+                          "status": rep["status"], "restarted_mp2": rep["restarted_mp2"]}
+            torch.cuda.empty_cache()
+        print(json.dumps(row), flush=True)
+        out.append(row)
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description=__doc__)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train", help="converge instances, sample, train the network, save its weights")
+    t.add_argument("--n-inst", type=int, default=200)
+    t.add_argument("--shape-seed", type=int, default=5)
+    t.add_argument("--samples", type=int, default=65536)
+    t.add_argument("--tol", type=float, default=1e-9)
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--batch", type=int, default=8192)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--out", required=True)
+    e = sub.add_parser("eval", help="time to residual tol from MP2 and learned starts on held-out instances")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--o", type=int, default=30)
+    e.add_argument("--v", type=int, default=300)
+    e.add_argument("--naux", type=int, default=900)
+    e.add_argument("--held-out", type=int, default=5)
+    e.add_argument("--seed0", type=int, default=3000)
+    e.add_argument("--tol", type=float, default=1e-7)
+    e.add_argument("--lp", default="bf16x3")
+    a = ap.parse_args(argv)
+    if a.cmd == "train":
+        _train_main(a)
+    else:
+        _eval_main(a)
+
+
+if __name__ == "__main__":
+    main()
