@@ -138,7 +138,7 @@ typedef struct {
   int32_t max_sweeps;       /* hard cap on sweeps (all precisions), >= 1 */
   int32_t start;            /* PPL_START_* */
   double  tol;              /* stop when the FP64 residual ||t_new - t||_F < tol (0 = never) */
-  double  switch_tol;       /* mixed: go to FP64 sweeps when the residual < switch_tol */
+  double  switch_tol;       /* mixed: go to FP64 sweeps when the residual < switch_tol (0 = 1e-6 for BF16X3, 1e-7 for FP32) */
   double  stagnation;       /* mixed: go to FP64 sweeps when r_n / r_{n-1} > stagnation */
   int32_t min_fp64_sweeps;  /* mixed: at least this many FP64 sweeps after the switch */
   int32_t fail_on_noconv;   /* 1: return PPL_E_NOCONV when max_sweeps is reached (else OK) */
@@ -157,7 +157,7 @@ typedef struct {
   double  first_residual;   /* residual of the first sweep */
 } ppl_iter_report_t;
 
-/* Fill *opts with the defaults: 100 sweeps, MP2 start, tol 1e-7, switch_tol 1e-5,
+/* Fill *opts with the defaults: 100 sweeps, MP2 start, tol 1e-7, switch_tol 0 (automatic),
  * stagnation 0.95, min_fp64_sweeps 2, fail_on_noconv 1, diverge_factor 1e3. */
 void ppl_iter_opts_default(ppl_iter_opts_t* opts);
 

@@ -58,7 +58,7 @@ class PPL:
         ppl_contract(self.plan, t2, R, alpha, beta)
         return R
 
-    def iterate(self, L, e_occ, e_vir, t2, max_sweeps=100, tol=1e-7, start="mp2", switch_tol=1e-5,
+    def iterate(self, L, e_occ, e_vir, t2, max_sweeps=100, tol=1e-7, start="mp2", switch_tol=0.0,
                 stagnation=0.95, min_fp64_sweeps=2, diverge_factor=1e3, fail_on_noconv=True,
                 history=True, raise_on_status=True):
         opts = ppl_iter_opts_default()

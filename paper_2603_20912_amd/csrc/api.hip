@@ -324,7 +324,7 @@ void ppl_iter_opts_default(ppl_iter_opts_t* o) {
   o->max_sweeps = 100;
   o->start = PPL_START_MP2;
   o->tol = 1e-7;
-  o->switch_tol = 1e-5;
+  o->switch_tol = 0.0;
   o->stagnation = 0.95;
   o->min_fp64_sweeps = 2;
   o->fail_on_noconv = 1;
@@ -584,6 +584,9 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
 
   // which operand set a sweep uses
   const bool mixed = p->ops[0].prec != PPL_FP64;
+  // automatic switch point: a few times above the rounding floor of the low-precision GEMMs
+  // (relative single-evaluation errors ~3e-6 for BF16x3 and ~2e-7 for FP32)
+  if (o.switch_tol <= 0.0) o.switch_tol = p->ops[0].prec == PPL_FP32 ? 1e-7 : 1e-6;
   const int fp64_set = mixed ? (p->ops[1].present ? 1 : -1) : 0;
   bool lp_phase = mixed;
   int fp64_sweeps = 0;

@@ -63,7 +63,7 @@ def train(mlp: MLP, X, Y, steps=2000, batch=4096, lr=1e-3, seed=0, log_every=0):
 
 
 def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, max_sweeps=300,
-                device="cuda", switch_tol=1e-5):
+                device="cuda", switch_tol=0.0):
     """Wall time and sweeps from inputs in HBM to a converged residual below tol.
 
     start: 'mp2' (plain), 'learned' (network guess, unchecked) or 'checked'

@@ -121,7 +121,7 @@ def test_calls_out_of_order_are_state_errors(P):
 def test_iteration_defaults(P):
     o = P.ppl_iter_opts_default()
     assert o.max_sweeps == 100 and o.tol == 1e-7 and o.min_fp64_sweeps == 2
-    assert o.start == 0 and abs(o.stagnation - 0.95) < 1e-15
+    assert o.start == 0 and abs(o.stagnation - 0.95) < 1e-15 and o.switch_tol == 0.0
 
 
 def test_product_does_not_import_the_oracle():
@@ -132,3 +132,50 @@ def test_product_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "ppl_oracle" not in txt, f
+
+
+def test_batch_plan_accounting(P):
+    import ppl_synth as S
+    shapes = [(d["o"], d["v"], d["naux"]) for d in S.batched_shapes(32, seed=4)]
+    h = P.ppl_batch_plan(shapes, "fp64", stream=0)
+    try:
+        total, n_items = P.ppl_batch_query(h)
+    finally:
+        P.ppl_batch_destroy(h)
+    # every instance's resident V+- is inside the batch workspace
+    vpm = 0
+    for o, v, naux in shapes:
+        i = plan_info(P, o, v, naux, hbm_budget=1 << 60, build_scratch=256 << 20)
+        assert i["resident"] == 1
+        vpm += i["vpm_bytes"]
+    assert total > vpm and total < 288e9
+    assert n_items == 0          # items are laid out after the build
+    with pytest.raises(P.PPLError):
+        P.ppl_batch_plan(shapes[:2], "bf16x3", stream=0)
+
+
+def test_mlp_handle_without_device(P):
+    from paper_2603_20912_amd import _lib
+    lib = _lib.load()
+    h = P.ppl_mlp_create(128, 4096, stream=0)
+    try:
+        assert P.ppl_mlp_param_count(h) == 128 * 4 + 128 + 128 * 128 + 128 + 128 + 1
+        nbytes = P.ppl_mlp_workspace_bytes(h)
+        assert nbytes >= 4 * 4 * P.ppl_mlp_param_count(h)
+        # unbound workspace: state error, no device access
+        assert lib.ppl_mlp_init(h, 0) == -7
+    finally:
+        P.ppl_mlp_destroy(h)
+    bad = ctypes.c_void_p()
+    assert lib.ppl_mlp_create(64, 1024, None, ctypes.byref(bad)) == -8
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2603_20912_amd import _lib
+    saved = _lib._lib
+    _lib._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="no CPU fallback"):
+            _lib.load(str(tmp_path / "missing.so"))
+    finally:
+        _lib._lib = saved
