@@ -85,6 +85,8 @@ typedef struct {
   int32_t  splits_contract;   /* split-K slices of the R+ contraction GEMM (1 = none) */
   int32_t  tile_contract_minus;   /* tile id of the R- contraction GEMM */
   int32_t  splits_contract_minus; /* split-K slices of the R- contraction GEMM */
+  uint64_t build_scratch_bytes;   /* bytes of the integral-build scratch */
+  int64_t  max_step_pairs;        /* largest number of (a<=b) pairs one build step holds */
   double   flops_build;       /* useful flops of one integral build: 2 naux v^2 P+ */
   double   flops_contract;    /* useful flops of one contraction: 2 (P+^2 N+ + P-^2 N-) */
 } ppl_plan_info_t;

@@ -46,7 +46,8 @@ class ppl_plan_info_t(ctypes.Structure):
                 ("tile_contract", ctypes.c_int32), ("n_plus", ctypes.c_int32),
                 ("n_minus", ctypes.c_int32), ("p_plus", ctypes.c_int32), ("p_minus", ctypes.c_int32),
                 ("splits_contract", ctypes.c_int32), ("tile_contract_minus", ctypes.c_int32),
-                ("splits_contract_minus", ctypes.c_int32), ("flops_build", ctypes.c_double),
+                ("splits_contract_minus", ctypes.c_int32), ("build_scratch_bytes", ctypes.c_uint64),
+                ("max_step_pairs", ctypes.c_int64), ("flops_build", ctypes.c_double),
                 ("flops_contract", ctypes.c_double)]
 
 

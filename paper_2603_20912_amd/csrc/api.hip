@@ -78,6 +78,15 @@ static void make_batches(int v, int64_t cap, std::vector<Batch>& out) {
   }
 }
 
+// Bytes per element of the build scratch G: the widest accumulator among the
+// operand sets the plan builds (a mixed plan with an FP64 copy needs 8).
+static int g_acc_bytes(ppl_plan_t p) {
+  int w = 0;
+  for (int k = 0; k < 2; ++k)
+    if (p->ops[k].present) w = std::max(w, acc_bytes(p->ops[k].prec));
+  return w;
+}
+
 // Assign every workspace region for a given G cap and residency; returns total bytes.
 static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t max_batch_pairs) {
   Layout L;
@@ -105,7 +114,7 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     }
   }
   // build scratch G (accumulator precision) doubles as the (ia|jb) scratch
-  const uint64_t gbytes = std::max<uint64_t>((uint64_t)gcap * v * v * acc_bytes(p->ops[0].prec),
+  const uint64_t gbytes = std::max<uint64_t>((uint64_t)gcap * v * v * g_acc_bytes(p),
                                              (uint64_t)(o * v) * (o * v) * 8);
   p->g = L.take(gbytes);
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
@@ -197,6 +206,18 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
   build_tile_table(p->tile_build, p->v, b.a0, b.a1, pre, nmt, nnt);
   const int* dpre = at<int>(p, p->tiles) + p->tiles_off[bi];
   const int64_t nvalid = pre.back();
+  // every write of this step must stay inside its region
+  const uint64_t g_need = (uint64_t)(b.p1 - b.p0) * p->v * p->v * acc_bytes(s.prec);
+  if (g_need > p->g.bytes)
+    return fail(PPL_E_STATE, "build step %d needs %llu B of scratch, plan has %llu B", bi,
+                (unsigned long long)g_need, (unsigned long long)p->g.bytes);
+  {
+    const int64_t r0p = p->resident ? b.p0 : 0, r0m = p->resident ? b.q0 : 0;
+    const uint64_t w = (uint64_t)elem_bytes(s.prec);
+    if ((uint64_t)(r0p + (b.p1 - b.p0)) * p->ldp * w > s.vp.bytes ||
+        (uint64_t)(r0m + (b.q1 - b.q0)) * p->ldm * w > s.vm.bytes)
+      return fail(PPL_E_STATE, "build step %d exceeds the V+- rows of the plan", bi);
+  }
   {
     ProfScope ps(p, PPL_PROF_BUILD_GEMM, 2.0 * p->naux * (double)p->v * p->v * (double)(b.p1 - b.p0));
     PPL_TRY(gemm_build(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
@@ -229,6 +250,10 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
   const void* am_lo = s.am_lo.bytes ? at<void>(p, s.am_lo) : nullptr;
   const int tile = p->tile_contract, tile_m = p->tile_m;
   void* part = p->part.bytes ? at<void>(p, p->part) : nullptr;
+  if (std::max(p->split_p, p->split_m) > kMaxSplits ||
+      (uint64_t)std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8 > p->part.bytes ||
+      (uint64_t)p->Np * p->ldp * 8 > p->rp.bytes)
+    return fail(PPL_E_STATE, "contraction buffers smaller than the plan requires");
   const double fp = 2.0 * (double)p->Np * p->Pp, fm = 2.0 * (double)p->Nm * p->Pm;
   if (p->resident) {
     if (!s.built) return fail(PPL_E_STATE, "V+- not built (call ppl_build_batch first)");
@@ -398,7 +423,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   p->budget = budget;
 
   // G cap: at most build_scratch (default 4 GiB) of scratch, at least one full row a = 0 (v pairs)
-  const uint64_t per_pair_g = (uint64_t)p->v * p->v * acc_bytes(p->prec);
+  const uint64_t per_pair_g = (uint64_t)p->v * p->v * g_acc_bytes(p);
   const uint64_t gbytes_cap = d->build_scratch ? d->build_scratch : (4ull << 30);
   int64_t gcap = (int64_t)std::max<uint64_t>((uint64_t)p->v, gbytes_cap / per_pair_g);
   gcap = std::min<int64_t>(gcap, p->Pp);
@@ -460,6 +485,12 @@ int ppl_plan_query(ppl_plan_t p, ppl_plan_info_t* info) {
   info->p_plus = (int32_t)p->Pp;
   info->p_minus = (int32_t)p->Pm;
   info->splits_contract = p->split_p;
+  info->build_scratch_bytes = p->g.bytes;
+  {
+    int64_t mp = 0;
+    for (const Batch& b : p->batches) mp = std::max<int64_t>(mp, b.p1 - b.p0);
+    info->max_step_pairs = mp;
+  }
   info->tile_contract_minus = p->tile_m;
   info->splits_contract_minus = p->split_m;
   const double v = p->v, na = p->naux;

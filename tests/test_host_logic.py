@@ -179,3 +179,14 @@ def test_binding_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
     finally:
         _lib._lib = saved
+
+
+@pytest.mark.parametrize("o,v,naux,prec,keep", [(10, 100, 300, "bf16x3", True), (10, 100, 300, "fp32", True),
+                                                (6, 40, 120, "bf16x3", False), (40, 400, 1200, "bf16x3", True),
+                                                (20, 200, 600, "fp64", False)])
+def test_build_scratch_holds_the_widest_accumulator(P, o, v, naux, prec, keep):
+    # a mixed plan builds an FP64 copy too: its scratch must hold 8-byte integrals
+    i = plan_info(P, o, v, naux, prec=prec, keep_fp64=keep, hbm_budget=280 << 30)
+    acc = 8 if (prec == "fp64" or keep) else 4
+    assert i["build_scratch_bytes"] >= i["max_step_pairs"] * v * v * acc
+    assert i["build_scratch_bytes"] >= (o * v) ** 2 * 8
