@@ -20,14 +20,15 @@ def upload_system(sysd, device="cuda"):
     return {k: torch.from_numpy(np.ascontiguousarray(sysd[k])).to(device) for k in ("L", "e_occ", "e_vir")}
 
 
-def converge(sysd, tol=1e-9, max_sweeps=300, device="cuda"):
-    """FP64 Jacobi from MP2 to `tol`; returns device tensors and the report."""
+def converge(sysd, tol=1e-9, max_sweeps=500, device="cuda"):
+    """FP64 Jacobi from MP2 to `tol` (or max_sweeps); returns device tensors and the report."""
     o, v, naux = sysd["o"], sysd["v"], sysd["naux"]
     d = upload_system(sysd, device)
     eng = PPL(o, v, naux, prec="fp64")
     t_mp2, e_mp2 = eng.mp2(d["L"], d["e_occ"], d["e_vir"])
     t_star = torch.empty_like(t_mp2)
-    rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t_star, max_sweeps=max_sweeps, tol=tol)
+    rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t_star, max_sweeps=max_sweeps, tol=tol,
+                      raise_on_status=False)
     sigma = ppl_mlp_sigma(eng.plan, t_mp2)
     return {"eng": eng, "d": d, "t_mp2": t_mp2, "t_star": t_star, "sigma": sigma, "report": rep,
             "e_mp2": e_mp2, "o": o, "v": v}

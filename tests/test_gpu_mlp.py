@@ -167,7 +167,8 @@ def test_learned_start_gain_small(P):
     Xs, Ys = [], []
     for sh in shapes:
         sysd = S.make_system(sh["o"], sh["v"], sh["naux"], sh["seed"], "contractive")
-        inst = Lr.converge(sysd, tol=1e-10)
+        inst = Lr.converge(sysd, tol=1e-9)
+        say(f"  train instance {sh}: sweeps {inst['report']['sweeps_fp64']} r {inst['report']['residual']:.1e}")
         X, Y = Lr.sample(inst, 20000, gen)
         Xs.append(X)
         Ys.append(Y)
@@ -180,7 +181,7 @@ def test_learned_start_gain_small(P):
     ratios, sw = [], []
     for k in range(3):
         sysd = S.make_system(8, 32, 96, 3000 + k, "contractive")
-        inst = Lr.converge(sysd, tol=1e-11)
+        inst = Lr.converge(sysd, tol=1e-11, max_sweeps=1000)
         tg = mlp.guess(inst["eng"], inst["t_mp2"], inst["d"]["e_occ"], inst["d"]["e_vir"], inst["sigma"])
         e_l = torch.linalg.norm(tg - inst["t_star"]).item()
         e_m = torch.linalg.norm(inst["t_mp2"] - inst["t_star"]).item()
