@@ -651,8 +651,18 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
   return ((Nrows + c.bm() - 1) / c.bm()) * ((Prows + c.bn() - 1) / c.bn()) * splits;
 }
 
+// Relative per-tile throughput on large problems, measured with HIP events on
+// gfx950 (contraction at (40, 400, 1200) and (30, 300, 900); 1.0 = best tile of
+// the precision). Tiles 6-8 were not in that measurement and carry estimates
+// that grow with their row count.
+static const double kTileEff[3][9] = {
+    /* FP64   */ {0.87, 0.73, 0.65, 0.59, 0.67, 1.00, 0.55, 0.65, 0.75},
+    /* FP32   */ {0.97, 0.97, 0.90, 0.67, 0.72, 1.00, 0.60, 0.70, 0.85},
+    /* BF16x3 */ {1.00, 0.83, 0.66, 0.50, 0.60, 0.97, 0.50, 0.60, 0.75}};
+
 // Model choice of (tile, splits): useful work over the work of the padded tiles,
-// times the fill of the last round of workgroups over 256 CUs.
+// times the fill of the last round of workgroups over 256 CUs, times the
+// measured relative throughput of the tile.
 void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
                      int* splits_out) {
   double best = -1.0;
@@ -667,8 +677,9 @@ void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int m
       const int64_t jobs = contract_jobs(t, prec, Nrows, Prows, Kpad, sp);
       const double rounds = (double)jobs / 256.0;
       const double fill = rounds / std::ceil(rounds);
-      // small penalty per extra slice (partial traffic, reduction launch) and for tiny tiles
-      const double score = pad * fill * (1.0 - 0.01 * (sp - 1)) * (c.bm() * c.bn() >= 8192 ? 1.0 : 0.9);
+      // small penalty per extra slice (partial traffic, reduction launch)
+      const int pi = prec == PPL_FP64 ? 0 : (prec == PPL_FP32 ? 1 : 2);
+      const double score = pad * fill * (1.0 - 0.01 * (sp - 1)) * kTileEff[pi][t];
       if (score > best + 1e-9) {
         best = score;
         bt = t;
