@@ -231,7 +231,7 @@ int ppl_mlp_destroy(ppl_mlp_t mlp);
 /* ------------------------------------------------ contraction tile configuration */
 /*
  * ppl_set_contract_config: choose the tile id (0 .. ppl_tile_count()-1) and the
- * split-K slice count (1 .. 4) of the R+ and R- contraction GEMMs. Split-K
+ * split-K slice count (1 .. 8) of the R+ and R- contraction GEMMs. Split-K
  * slices are summed in slice order, so a fixed configuration gives bitwise
  * reproducible results. PPL_E_ARG for out-of-range values.
  */

@@ -1083,7 +1083,7 @@ static int grouped_default_tile(int64_t rows) {
 static int batch_prepare(ppl_batch_t b) {
   b->groups.clear();
   b->items.clear();
-  const int KC = b->prec == PPL_FP64 ? 16 : 32;
+  const int KC = kc_of_prec(b->prec);
   struct Item { int4 w; double work; };
   std::vector<Item> its;
   for (int k = 0; k < b->n; ++k) {

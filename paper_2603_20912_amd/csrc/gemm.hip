@@ -164,14 +164,78 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
 };
 
 // ------------------------------------------------------------------ the kernel (FP64 / FP32)
+// LDS layout of a staged K chunk (BM or BN rows of KC elements, moved as 16-byte vectors):
+//   0: each row padded by 16 bytes;
+//   1: unpadded rows, vector kv of row r stored at vector slot kv ^ (r % (KC / VEC)).
+// Fragment reads (PPL_FRAG_VEC):
+//   0: one element per lane per MFMA (lane l holds k = l / 16 of the 4-wide step);
+//   1: one 16-byte vector per lane covering VEC consecutive MFMA steps: in step e
+//      lane l holds k = VEC * (l / 16) + e of the 4 * VEC-wide group. A and B use
+//      the same assignment, so every k is paired exactly once.
+#ifndef PPL_LDS_LAYOUT
+#define PPL_LDS_LAYOUT 1
+#endif
+#ifndef PPL_FRAG_VEC
+#define PPL_FRAG_VEC 1
+#endif
+constexpr int kLdsLayout = PPL_LDS_LAYOUT;
+constexpr int kFragVec = PPL_FRAG_VEC;
+
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
 struct TileGeom {
   static constexpr int NT = 64 * WAVES_M * WAVES_N;
   static constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  static constexpr int LDSR = KC + 16 / (int)sizeof(T);
+  static constexpr int LDSR = kLdsLayout == 0 ? KC + 16 / (int)sizeof(T) : KC;
   static constexpr int LDS_A = 2 * BM * LDSR, LDS_B = 2 * BN * LDSR;   // elements, two buffers each
   static constexpr int LDS_BYTES = (LDS_A + LDS_B) * (int)sizeof(T);
 };
+
+// element offset of 16-byte vector kv of staged row r
+template <int VEC, int VPR, int LDSR>
+__device__ __forceinline__ int lds_vec_off(int r, int kv) {
+  if constexpr (kLdsLayout == 0) return r * LDSR + kv * VEC;
+  else return r * LDSR + ((kv ^ (r % VPR)) * VEC);
+}
+
+// Multiply one staged chunk (As: A rows, Bs: B rows, LDSR elements apart) into acc.
+template <class T, int WM, int WN, int KC, int LDSR>
+__device__ __forceinline__ void consume_chunk(typename AccOf<T>::vec (&acc)[WM][WN], const T* __restrict__ As,
+                                              const T* __restrict__ Bs, int arow, int brow, int fq, int key) {
+  constexpr int VEC = 16 / sizeof(T);
+  if constexpr (kFragVec) {
+#pragma unroll
+    for (int kg = 0; kg < KC / (4 * VEC); ++kg) {
+      const int col = ((kg * 4 + fq) ^ key) * VEC;
+      union U { uint4 u; T e[VEC]; };
+      U a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i].u = *reinterpret_cast<const uint4*>(&As[arow + i * 16 * LDSR + col]);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j].u = *reinterpret_cast<const uint4*>(&Bs[brow + j * 16 * LDSR + col]);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i].e[e], b[j].e[e], acc[i][j]);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int c = kk + fq;
+      const int col = ((c / VEC) ^ key) * VEC + c % VEC;
+      T a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i] = As[arow + i * 16 * LDSR + col];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j] = Bs[brow + j * 16 * LDSR + col];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+    }
+  }
+}
 
 // One BM x BN tile of C over the K chunks [job.kc0, job.kc1); sA0 / sB0 hold
 // two LDS buffers of BM (BN) rows each.
@@ -182,13 +246,13 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
   using accv = typename AccOf<T>::vec;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  constexpr int VEC = 16 / sizeof(T);             // elements per 16-byte load
-  constexpr int PAD = 16 / sizeof(T);             // keeps 16-byte alignment and spreads banks
-  constexpr int LDSR = KC + PAD;
+  constexpr int VEC = 16 / sizeof(T);             // elements per 16-byte vector
+  constexpr int LDSR = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>::LDSR;
   constexpr int VPR = KC / VEC;                   // 16-byte vectors per staged row
   constexpr int NLA = (BM * VPR + NT - 1) / NT;
   constexpr int NLB = (BN * VPR + NT - 1) / NT;
-  static_assert(KC % 4 == 0 && KC % VEC == 0, "bad KC");
+  static_assert(KC % (4 * VEC) == 0, "bad KC");
+  static_assert(16 % VPR == 0, "swizzle period must divide the 16-row fragment blocks");
   const int64_t m0 = job.m0, n0 = job.n0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
@@ -205,7 +269,7 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
     int64_t gr = m0 + r;
     if (gr > M - 1) gr = M - 1;
     pa[i] = A + gr * lda + kv * VEC + job.kc0 * KC;
-    oa[i] = r * LDSR + kv * VEC;
+    oa[i] = lds_vec_off<VEC, VPR, LDSR>(r, kv);
   }
 #pragma unroll
   for (int i = 0; i < NLB; ++i) {
@@ -215,7 +279,7 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
     int64_t gr = n0 + r;
     if (gr > N - 1) gr = N - 1;
     pb[i] = B + gr * ldb + kv * VEC + job.kc0 * KC;
-    ob[i] = r * LDSR + kv * VEC;
+    ob[i] = lds_vec_off<VEC, VPR, LDSR>(r, kv);
   }
 
   accv acc[WM][WN];
@@ -224,8 +288,12 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = accv{0, 0, 0, 0};
 
-  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR + (lane >> 4);
-  const int brow = (wn * WN * 16 + (lane & 15)) * LDSR + (lane >> 4);
+  // fragment rows: row (lane & 15) of each 16-row block; a block start is a
+  // multiple of 16, so the swizzle key of the row is (lane & 15) % VPR
+  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR;
+  const int brow = (wn * WN * 16 + (lane & 15)) * LDSR;
+  const int fq = lane >> 4;
+  const int key = kLdsLayout == 0 ? 0 : (lane & 15) % VPR;
   const int64_t nk = job.kc1 - job.kc0;
 
   // chunk 0 straight into LDS buffer 0
@@ -251,20 +319,7 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
     for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i] + k1);
 #pragma unroll
     for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i] + k1);
-    const T* As = sA0 + buf * (BM * LDSR);
-    const T* Bs = sB0 + buf * (BN * LDSR);
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      T a[WM], b[WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) a[i] = As[arow + i * 16 * LDSR + kk];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) b[j] = Bs[brow + j * 16 * LDSR + kk];
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
-    }
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0 + buf * (BM * LDSR), sB0 + buf * (BN * LDSR), arow, brow, fq, key);
 #pragma unroll
     for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA0[(buf ^ 1) * (BM * LDSR) + oa[i]]) = ra[i];
 #pragma unroll
@@ -273,20 +328,7 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
   }
   {  // last chunk
     const int buf = (int)((nk - 1) & 1);
-    const T* As = sA0 + buf * (BM * LDSR);
-    const T* Bs = sB0 + buf * (BN * LDSR);
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      T a[WM], b[WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) a[i] = As[arow + i * 16 * LDSR + kk];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) b[j] = Bs[brow + j * 16 * LDSR + kk];
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
-    }
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0 + buf * (BM * LDSR), sB0 + buf * (BN * LDSR), arow, brow, fq, key);
   }
 
 #pragma unroll
@@ -570,7 +612,7 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
                         const void* V_lo, int64_t ldv, void* C, int64_t ldc, int64_t c_col0,
                         int splits, void* partial, int64_t partial_ld) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  const int KC = prec == PPL_FP64 ? 16 : 32;
+  const int KC = kc_of_prec(prec);
   const int64_t nk = Kpad / KC;
   if (splits < 1) splits = 1;
   if (splits > nk) splits = (int)nk;
@@ -585,17 +627,17 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
   if (prec == PPL_FP64) {
     EpiStore<double> epi = direct ? EpiStore<double>{(double*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
                                   : EpiStore<double>{(double*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
-    rc = launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, grid, Nrows, Prows, Kpad, (const double*)S, lds_,
+    rc = launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, grid, Nrows, Prows, Kpad, (const double*)S, lds_,
                                                       (const double*)V, ldv, epi, map);
   } else if (prec == PPL_FP32) {
     EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
                                  : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
-    rc = launch<float, WM, WN, WAVES_M, WAVES_N, 32>(s, grid, Nrows, Prows, Kpad, (const float*)S, lds_,
+    rc = launch<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(s, grid, Nrows, Prows, Kpad, (const float*)S, lds_,
                                                      (const float*)V, ldv, epi, map);
   } else if (prec == PPL_BF16X3) {
     EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
                                  : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
-    rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, 32>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
+    rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
                                                   (const __bf16*)S_lo, lds_, (const __bf16*)V,
                                                   (const __bf16*)V_lo, ldv, epi, map);
   } else {
@@ -643,7 +685,7 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
 // Workgroups of one contraction launch for a (tile, splits) choice.
 int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits) {
   const TileCfg& c = kContract[tile];
-  const int KC = prec == PPL_FP64 ? 16 : 32;
+  const int KC = kc_of_prec(prec);
   const int64_t nk = Kpad / KC;
   if (splits > nk) splits = (int)nk;
   const int64_t kps = (nk + splits - 1) / splits;
@@ -652,13 +694,12 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 }
 
 // Relative per-tile throughput on large problems, measured with HIP events on
-// gfx950 (contraction at (40, 400, 1200) and (30, 300, 900); 1.0 = best tile of
-// the precision). Tiles 6-8 were not in that measurement and carry estimates
-// that grow with their row count.
+// gfx950: best over 1, 2 and 4 K slices, averaged over R+ and R- at (30, 300, 900)
+// and (40, 400, 1200); 1.0 = best tile of the precision.
 static const double kTileEff[3][9] = {
-    /* FP64   */ {0.87, 0.73, 0.65, 0.59, 0.67, 1.00, 0.55, 0.65, 0.75},
-    /* FP32   */ {0.97, 0.97, 0.90, 0.67, 0.72, 1.00, 0.60, 0.70, 0.85},
-    /* BF16x3 */ {1.00, 0.83, 0.66, 0.50, 0.60, 0.97, 0.50, 0.60, 0.75}};
+    /* FP64   */ {0.99, 0.97, 0.82, 0.90, 0.95, 1.00, 0.93, 0.95, 0.99},
+    /* FP32   */ {0.96, 0.94, 0.87, 0.92, 0.94, 0.97, 0.94, 0.96, 1.00},
+    /* BF16x3 */ {1.00, 0.77, 0.56, 0.48, 0.57, 0.94, 0.58, 0.80, 0.89}};
 
 // Model choice of (tile, splits): useful work over the work of the padded tiles,
 // times the fill of the last round of workgroups over 256 CUs, times the
@@ -700,24 +741,24 @@ int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
   MapBuild map{tile_prefix, n_mtiles, n_valid_tiles, v, BM, BN, 0};
-  map.nk = Kpad / (prec == PPL_FP64 ? 16 : 32);
+  map.nk = Kpad / kc_of_prec(prec);
   if (prec == PPL_FP64) {
     const double* X = (const double*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<double> epi{(double*)G, M, N, v, a0};
-    return launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, n_valid_tiles, M, N, Kpad, X, ldx, X, ldx,
+    return launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, n_valid_tiles, M, N, Kpad, X, ldx, X, ldx,
                                                         epi, map);
   }
   if (prec == PPL_FP32) {
     const float* X = (const float*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<float> epi{(float*)G, M, N, v, a0};
-    return launch<float, WM, WN, WAVES_M, WAVES_N, 32>(s, n_valid_tiles, M, N, Kpad, X, ldx, X, ldx,
+    return launch<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, X, ldx, X, ldx,
                                                        epi, map);
   }
   if (prec == PPL_BF16X3) {
     const __bf16* Xh = (const __bf16*)Xt + (int64_t)a0 * v * ldx;
     const __bf16* Xl = (const __bf16*)Xt_lo + (int64_t)a0 * v * ldx;
     EpiBuild<float> epi{(float*)G, M, N, v, a0};
-    return launch_bf3<WM, WN, WAVES_M, WAVES_N, 32>(s, n_valid_tiles, M, N, Kpad, Xh, Xl, ldx, Xh,
+    return launch_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, Xh, Xl, ldx, Xh,
                                                     Xl, ldx, epi, map);
   }
   return fail(PPL_E_ARG, "unknown precision %d", prec);
@@ -727,9 +768,9 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
                    const double* B, int64_t ldb, double* C, int64_t ldc) {
   constexpr int WM = 4, WN = 4, WAVES_M = 2, WAVES_N = 2;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  MapGrid map{(M + BM - 1) / BM, (N + BN - 1) / BN, BM, BN, 1, Kpad / 16, Kpad / 16};
+  MapGrid map{(M + BM - 1) / BM, (N + BN - 1) / BN, BM, BN, 1, Kpad / kKcF64, Kpad / kKcF64};
   EpiStore<double> epi{C, ldc, 0, M, N, 1.0, 0.0, 0};
-  return launch<double, WM, WN, WAVES_M, WAVES_N, 16>(s, map.n_mt * map.n_nt, M, N, Kpad, A, lda, B,
+  return launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, map.n_mt * map.n_nt, M, N, Kpad, A, lda, B,
                                                       ldb, epi, map);
 }
 
@@ -742,7 +783,7 @@ bool grouped_tile_ok(int tile) { return tile == 1 || tile == 2 || tile >= 5; }
 
 template <class T>
 struct GroupedLds {
-  static constexpr int bytes = TileGeom<T, 13, 1, 1, 4, (sizeof(T) == 8 ? 16 : 32)>::LDS_BYTES;  // largest allowed tile
+  static constexpr int bytes = TileGeom<T, 13, 1, 1, 4, (sizeof(T) == 8 ? kKcF64 : kKcF32)>::LDS_BYTES;  // largest allowed tile
 };
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
@@ -761,7 +802,7 @@ template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict__ items, int n_items,
                     int* counter) {
-  constexpr int KC = sizeof(T) == 8 ? 16 : 32;
+  constexpr int KC = sizeof(T) == 8 ? kKcF64 : kKcF32;
   __shared__ __attribute__((aligned(16))) char smem[GroupedLds<T>::bytes];
   __shared__ int s_item;
   for (;;) {

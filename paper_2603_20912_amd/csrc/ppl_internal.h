@@ -30,6 +30,16 @@ __host__ __device__ inline int pair_second(int packed) { return packed & 0xffff;
 
 // leading dimension of every packed operand row: a multiple of 64 elements,
 // so the GEMM K loop never needs a bounds check (the padding is kept zero)
+// K elements staged per LDS chunk by the GEMM tiles (FP64 / FP32 and BF16 operands);
+// leading dimensions (pad_ld) are multiples of both.
+#ifndef PPL_KC64
+#define PPL_KC64 16
+#endif
+constexpr int kKcF64 = PPL_KC64;
+constexpr int kKcF32 = 32;
+__host__ __device__ constexpr int kc_of_prec(int prec) { return prec == PPL_FP64 ? kKcF64 : kKcF32; }
+static_assert(64 % kKcF64 == 0 && 64 % kKcF32 == 0, "K chunk must divide the leading-dimension padding");
+
 __host__ __device__ inline int64_t pad_ld(int64_t k) { return (k + 63) / 64 * 64; }
 
 // ------------------------------------------------------------------ errors
@@ -148,7 +158,7 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 // *tile_out >= 0 on entry fixes the tile and only chooses the split count
 void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
                      int* splits_out);
-constexpr int kMaxSplits = 4;
+constexpr int kMaxSplits = 8;
 
 // grouped persistent contraction (batched instances)
 struct GroupDesc {

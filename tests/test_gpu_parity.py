@@ -94,15 +94,16 @@ def test_alpha_beta_accumulate(P):
 
 
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
-@pytest.mark.parametrize("tile", range(6))
+@pytest.mark.parametrize("tile", range(9))
 def test_every_contraction_tile_and_split(P, tile, prec, bound):
-    say(f"contract {prec} tile {tile} splits 1..4 (7,37,50)")
-    s = S.make_system(7, 37, 50, 20 + tile)
+    say(f"contract {prec} tile {tile} splits 1..8 (7,37,130)")
+    # K padded to 192: 12 FP64 / 6 FP32 chunks, so 8 slices are clamped to 6 for FP32 and BF16x3
+    s = S.make_system(7, 37, 130, 20 + tile)
     t = S.make_amplitudes(7, 37, 30 + tile)
     Rref = O.ppl(s["L"], 7, t)
     first = None
-    for sp in (1, 2, 3, 4):
-        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 6, 5 - sp))
+    for sp in (1, 2, 3, 4, 6, 8):
+        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 9, 9 - sp))
         assert info["tile_contract"] == tile and info["splits_contract"] == sp
         assert rel(R, Rref) < bound
         if prec == "fp64":
