@@ -82,9 +82,9 @@ typedef struct {
   int32_t  n_minus;           /* N- = o(o-1)/2 occupied pairs i<j */
   int32_t  p_plus;            /* P+ = v(v+1)/2 virtual pairs a<=b */
   int32_t  p_minus;           /* P- = v(v-1)/2 virtual pairs a<b */
-  int32_t  splits_contract;   /* split-K slices of the R+ contraction GEMM (1 = none) */
+  int32_t  splits_contract;   /* split-K slices of the R+ contraction GEMM (1 = none, 0 = stream-K) */
   int32_t  tile_contract_minus;   /* tile id of the R- contraction GEMM */
-  int32_t  splits_contract_minus; /* split-K slices of the R- contraction GEMM */
+  int32_t  splits_contract_minus; /* split-K slices of the R- contraction GEMM (0 = stream-K) */
   uint64_t build_scratch_bytes;   /* bytes of the integral-build scratch */
   int64_t  max_step_pairs;        /* largest number of (a<=b) pairs one build step holds */
   double   flops_build;       /* useful flops of one integral build: 2 naux v^2 P+ */
@@ -231,9 +231,12 @@ int ppl_mlp_destroy(ppl_mlp_t mlp);
 /* ------------------------------------------------ contraction tile configuration */
 /*
  * ppl_set_contract_config: choose the tile id (0 .. ppl_tile_count()-1) and the
- * split-K slice count (1 .. 8) of the R+ and R- contraction GEMMs. Split-K
- * slices are summed in slice order, so a fixed configuration gives bitwise
- * reproducible results. PPL_E_ARG for out-of-range values.
+ * K decomposition of the R+ and R- contraction GEMMs: 1 .. 8 = that many split-K
+ * slices, 0 = stream-K (the (tile, K chunk) iterations cut into equal ranges, one
+ * per workgroup the device holds at once; tiles shared by several workgroups are
+ * summed afterwards in workgroup order). Split-K slices are summed in slice order,
+ * so a fixed configuration on a given device gives bitwise reproducible results.
+ * PPL_E_ARG for out-of-range values.
  */
 int ppl_set_contract_config(ppl_plan_t plan, int32_t tile_plus, int32_t splits_plus,
                             int32_t tile_minus, int32_t splits_minus);

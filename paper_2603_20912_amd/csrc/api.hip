@@ -119,8 +119,15 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   p->g = L.take(gbytes);
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
   p->rm = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
-  // split-K slices for up to kMaxSplits (autotuning may pick any count), sized for FP64
-  p->part = L.take(std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8);
+  // split-K slices for up to kMaxSplits (autotuning may pick any count), sized for FP64,
+  // or the stream-K partial slots of the largest tile, whichever is larger
+  uint64_t part_bytes = std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8;
+  for (int t = 0; t < contract_tile_count(); ++t) {
+    part_bytes = std::max(part_bytes, streamk_part_bytes(t, PPL_FP64, p->Np, resident ? p->Pp : max_batch_pairs, p->ldp));
+    if (p->Nm > 0)
+      part_bytes = std::max(part_bytes, streamk_part_bytes(t, PPL_FP64, p->Nm, resident ? p->Pm : max_batch_pairs, p->ldm));
+  }
+  p->part = L.take(part_bytes);
   if (p->ops[0].prec != PPL_FP64) {   // FP64 master amplitudes
     p->s64 = L.take((uint64_t)p->Np * p->ldp * 8);
     p->a64 = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
@@ -261,13 +268,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, fp * p->Pp);
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, p->Pp, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, 0, p->split_p, part, p->ldp));
+                            at<void>(p, p->rp), p->ldp, 0, p->split_p, part, p->ldp, p->part.bytes));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, fm * p->Pm);
     if (p->Nm > 0 && p->Pm > 0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, p->Pm, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, 0, p->split_m, part, p->ldm));
+                            at<void>(p, p->rm), p->ldm, 0, p->split_m, part, p->ldm, p->part.bytes));
     return PPL_OK;
   }
   if (!p->L_last) return fail(PPL_E_STATE, "streaming plan has no Cholesky vectors (call ppl_build_batch)");
@@ -278,13 +285,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, 2.0 * (double)p->Np * p->Pp * (double)(b.p1 - b.p0));
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, b.p1 - b.p0, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, b.p0, p->split_p, part, p->ldp));
+                            at<void>(p, p->rp), p->ldp, b.p0, p->split_p, part, p->ldp, p->part.bytes));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, 2.0 * (double)p->Nm * p->Pm * (double)(b.q1 - b.q0));
     if (p->Nm > 0 && b.q1 > b.q0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, b.q1 - b.q0, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, b.q0, p->split_m, part, p->ldm));
+                            at<void>(p, p->rm), p->ldm, b.q0, p->split_m, part, p->ldm, p->part.bytes));
   }
   return PPL_OK;
 }
@@ -704,8 +711,8 @@ int ppl_set_contract_config(ppl_plan_t p, int32_t tp, int32_t sp, int32_t tm, in
   PPL_TRY(check_plan(p));
   const int nt = contract_tile_count();
   if (tp < 0 || tp >= nt || tm < 0 || tm >= nt) return fail(PPL_E_ARG, "tile id out of range [0, %d)", nt);
-  if (sp < 1 || sp > kMaxSplits || sm < 1 || sm > kMaxSplits)
-    return fail(PPL_E_ARG, "split count out of range [1, %d]", kMaxSplits);
+  if (sp < 0 || sp > kMaxSplits || sm < 0 || sm > kMaxSplits)
+    return fail(PPL_E_ARG, "split count out of range [0, %d] (0 = stream-K)", kMaxSplits);
   p->tile_contract = tp;
   p->split_p = sp;
   p->tile_m = tm;
@@ -744,14 +751,18 @@ int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms, bool grouped_only
     void* C = at<void>(p, plus ? p->rp : p->rm);
     for (int t = 0; t < nt && rc == PPL_OK; ++t) {
       if (grouped_only && !grouped_tile_ok(t)) continue;
-      for (int sp = 1; sp <= (grouped_only ? 1 : kMaxSplits) && rc == PPL_OK; ++sp) {
+      // split counts 1 .. kMaxSplits, then stream-K (0)
+      for (int k = 1; k <= (grouped_only ? 1 : kMaxSplits + 1) && rc == PPL_OK; ++k) {
+        const int sp = k <= kMaxSplits ? k : 0;
         if (sp > 1 && contract_jobs(t, s.prec, Nr, Pr, ld, sp) == contract_jobs(t, s.prec, Nr, Pr, ld, sp - 1))
           continue;   // same effective split count as a smaller request
-        rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld);
+        rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld,
+                           p->part.bytes);
         if (rc != PPL_OK) break;
         if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PPL_E_HIP, "event record failed"); break; }
         for (int r = 0; r < reps && rc == PPL_OK; ++r)
-          rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld);
+          rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld,
+                             p->part.bytes);
         if (rc != PPL_OK) break;
         float ms = 0.f;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -140,6 +140,29 @@ struct EpiStore {        // C[split][m][c_col0 + n] = alpha * acc + beta * C (be
   }
 };
 
+template <class Tc>
+struct EpiSK {           // stream-K: whole tiles go to C, shared tiles to a dense BM x BN partial slot
+  Tc* C;
+  int64_t ldc, c_col0, M, N;
+  Tc* P;                 // partial slot of this tile (to_part) or unused
+  int64_t m0, n0;
+  int ldp;               // = BN
+  bool to_part;
+  __device__ void row(int, int64_t m, int64_t& base, bool& ok) const {
+    if (to_part) {
+      ok = true;
+      base = (m - m0) * ldp - n0;
+    } else {
+      ok = m < M;
+      base = m * ldc + c_col0;
+    }
+  }
+  __device__ void put(int64_t base, bool ok, int64_t n, typename AccOf<Tc>::type x) const {
+    if (to_part) P[base + n] = (Tc)x;
+    else if (ok && n < N) C[base + n] = (Tc)x;
+  }
+};
+
 template <class Tg>
 struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
   Tg* G;
@@ -178,16 +201,25 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
 #ifndef PPL_FRAG_VEC
 #define PPL_FRAG_VEC 1
 #endif
+#ifndef PPL_SCHED_FENCE
+#define PPL_SCHED_FENCE 0
+#endif
+#ifndef PPL_DIRECT_LDS
+#define PPL_DIRECT_LDS 0
+#endif
 constexpr int kLdsLayout = PPL_LDS_LAYOUT;
 constexpr int kFragVec = PPL_FRAG_VEC;
+constexpr int kSchedFence = PPL_SCHED_FENCE;
+constexpr int kDirectLds = PPL_DIRECT_LDS;   // 1: chunks go global -> LDS without registers (layout 1 only)
+static_assert(!kDirectLds || kLdsLayout == 1, "direct LDS loads need the unpadded swizzled layout");
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
 struct TileGeom {
   static constexpr int NT = 64 * WAVES_M * WAVES_N;
   static constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   static constexpr int LDSR = kLdsLayout == 0 ? KC + 16 / (int)sizeof(T) : KC;
-  static constexpr int LDS_A = 2 * BM * LDSR, LDS_B = 2 * BN * LDSR;   // elements, two buffers each
-  static constexpr int LDS_BYTES = (LDS_A + LDS_B) * (int)sizeof(T);
+  static constexpr int BUF_A = BM * LDSR, BUF_B = BN * LDSR;   // elements of one buffer
+  static constexpr int LDS_BYTES = 2 * (BUF_A + BUF_B) * (int)sizeof(T);
 };
 
 // element offset of 16-byte vector kv of staged row r
@@ -237,12 +269,139 @@ __device__ __forceinline__ void consume_chunk(typename AccOf<T>::vec (&acc)[WM][
   }
 }
 
-// One BM x BN tile of C over the K chunks [job.kc0, job.kc1); sA0 / sB0 hold
-// two LDS buffers of BM (BN) rows each.
+// Write the accumulators of one wave (16-row blocks i, 16-column blocks j) through the epilogue.
+template <class T, int WM, int WN, class Epi>
+__device__ __forceinline__ void store_acc(typename AccOf<T>::vec (&acc)[WM][WN], const TileJob& job, const Epi& epi,
+                                          int wm, int wn, int lane) {
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = job.m0 + wm * WM * 16 + i * 16 + AccOf<T>::row(lane, r);
+      int64_t base;
+      bool ok;
+      epi.row(job.split, m, base, ok);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int64_t n = job.n0 + wn * WN * 16 + j * 16 + (lane & 15);
+        epi.put(base, ok, n, acc[i][j][r]);
+      }
+    }
+  }
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void global_cvoid_t;
+
+// The tile with chunks moved straight from global memory into LDS: one wave
+// instruction fills 64 / VPR whole staged rows (1 KB, one 16-byte vector per lane),
+// lane l taking the global vector that the swizzled layout keeps at its slot.
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
+__device__ __forceinline__ void tile_body_direct(const TileJob& job, int64_t M, int64_t N, const T* __restrict__ A,
+                                                 int64_t lda, const T* __restrict__ B, int64_t ldb, const Epi& epi,
+                                                 T* __restrict__ a0, T* __restrict__ a1, T* __restrict__ b0,
+                                                 T* __restrict__ b1) {
+  using accv = typename AccOf<T>::vec;
+  constexpr int NW = WAVES_M * WAVES_N;
+  constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int LDSR = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>::LDSR;
+  constexpr int VPR = KC / VEC;
+  constexpr int RPI = 64 / VPR;                   // staged rows per wave instruction
+  constexpr int GA = BM / RPI, GB = BN / RPI;     // wave instructions per chunk
+  constexpr int IA = (GA + NW - 1) / NW, IB = (GB + NW - 1) / NW;
+  static_assert(LDSR == KC && 64 % VPR == 0 && BM % RPI == 0 && BN % RPI == 0, "direct LDS geometry");
+  static_assert(KC % (4 * VEC) == 0 && 16 % VPR == 0, "bad KC");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const int lr = lane / VPR, slot = lane % VPR;
+
+  const T* pa[IA];
+  const T* pb[IB];
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const int g = wave + i * NW, r = g * RPI + lr;
+    int64_t gr = job.m0 + r;
+    if (gr > M - 1) gr = M - 1;
+    pa[i] = A + gr * lda + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
+  }
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const int g = wave + i * NW, r = g * RPI + lr;
+    int64_t gr = job.n0 + r;
+    if (gr > N - 1) gr = N - 1;
+    pb[i] = B + gr * ldb + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
+  }
+  // chunk c (relative to job.kc0) into LDS buffer `buf`
+  auto issue = [&](int64_t c, int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int g = wave + i * NW;
+      if (g < GA)
+        __builtin_amdgcn_global_load_lds((global_cvoid_t*)(pa[i] + c * KC),
+                                         (lds_void_t*)((buf ? a1 : a0) + g * RPI * LDSR), 16, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int g = wave + i * NW;
+      if (g < GB)
+        __builtin_amdgcn_global_load_lds((global_cvoid_t*)(pb[i] + c * KC),
+                                         (lds_void_t*)((buf ? b1 : b0) + g * RPI * LDSR), 16, 0, 0);
+    }
+  };
+
+  accv acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = accv{0, 0, 0, 0};
+  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR;
+  const int brow = (wn * WN * 16 + (lane & 15)) * LDSR;
+  const int fq = lane >> 4;
+  const int key = (lane & 15) % VPR;
+  const int64_t nk = job.kc1 - job.kc0;
+
+  // two steps per loop trip so that every LDS access names its buffer (four distinct
+  // objects: the compiler then needs no wait on the DMA into one buffer before
+  // reading the other)
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  int64_t kt = 0;
+  for (; kt + 2 < nk; kt += 2) {
+    issue(kt + 1, 1);
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, a0, b0, arow, brow, fq, key);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's part of chunk kt+1 is in LDS
+    __syncthreads();
+    issue(kt + 2, 0);
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, a1, b1, arow, brow, fq, key);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+  if (kt + 1 < nk) {   // chunks kt (buffer 0) and kt + 1 (buffer 1) remain
+    issue(kt + 1, 1);
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, a0, b0, arow, brow, fq, key);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, a1, b1, arow, brow, fq, key);
+  } else {             // chunk kt (buffer 0) remains
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, a0, b0, arow, brow, fq, key);
+  }
+  store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
+}
+
+// One BM x BN tile of C over the K chunks [job.kc0, job.kc1); sA0 / sA1 (sB0 / sB1)
+// are the two LDS buffers of BM (BN) staged rows.
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
 __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t N, const T* __restrict__ A,
                                           int64_t lda, const T* __restrict__ B, int64_t ldb, const Epi& epi,
-                                          T* __restrict__ sA0, T* __restrict__ sB0) {
+                                          T* __restrict__ sA0, T* __restrict__ sA1, T* __restrict__ sB0,
+                                          T* __restrict__ sB1) {
+  if constexpr (kDirectLds) {
+    tile_body_direct<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA0, sA1, sB0, sB1);
+    return;
+  }
   using accv = typename AccOf<T>::vec;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
@@ -319,33 +478,37 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
     for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i] + k1);
 #pragma unroll
     for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i] + k1);
-    consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0 + buf * (BM * LDSR), sB0 + buf * (BN * LDSR), arow, brow, fq, key);
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, buf ? sA1 : sA0, buf ? sB1 : sB0, arow, brow, fq, key);
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA0[(buf ^ 1) * (BM * LDSR) + oa[i]]) = ra[i];
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&(buf ? sA0 : sA1)[oa[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB0[(buf ^ 1) * (BN * LDSR) + ob[i]]) = rb[i];
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&(buf ? sB0 : sB1)[ob[i]]) = rb[i];
+    if constexpr (kSchedFence) {
+      // order of this block: the global loads of the next chunk, then the LDS reads and
+      // MFMAs of this chunk group by group, then the LDS stores (whose waits on the
+      // global loads thereby come after every MFMA of the chunk)
+      constexpr int NG = KC / (4 * VEC), MG = WM * WN * VEC;
+      constexpr int EARLY = kSchedFence == 2 ? (MG < 4 ? MG : 4) : MG;
+      __builtin_amdgcn_sched_group_barrier(0x020, NLA + NLB, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, WM + WN, 0);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        // with kSchedFence == 2 the fragments of group g+1 are read after the first
+        // few MFMAs of group g
+        __builtin_amdgcn_sched_group_barrier(0x008, EARLY, 0);
+        if (g + 1 < NG) __builtin_amdgcn_sched_group_barrier(0x100, WM + WN, 0);
+        if (MG > EARLY) __builtin_amdgcn_sched_group_barrier(0x008, MG - EARLY, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x200, NLA + NLB, 0);
+    }
     __syncthreads();
   }
   {  // last chunk
     const int buf = (int)((nk - 1) & 1);
-    consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0 + buf * (BM * LDSR), sB0 + buf * (BN * LDSR), arow, brow, fq, key);
+    consume_chunk<T, WM, WN, KC, LDSR>(acc, buf ? sA1 : sA0, buf ? sB1 : sB0, arow, brow, fq, key);
   }
 
-#pragma unroll
-  for (int i = 0; i < WM; ++i) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t m = m0 + wm * WM * 16 + i * 16 + AccOf<T>::row(lane, r);
-      int64_t base;
-      bool ok;
-      epi.row(job.split, m, base, ok);
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int64_t n = n0 + wn * WN * 16 + j * 16 + (lane & 15);
-        epi.put(base, ok, n, acc[i][j][r]);
-      }
-    }
-  }
+  store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
 }
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
@@ -353,38 +516,45 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_
 gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int64_t lda,
                const T* __restrict__ B, int64_t ldb, Epi epi, Map map) {
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
-  __shared__ __attribute__((aligned(16))) T sA[G::LDS_A];
-  __shared__ __attribute__((aligned(16))) T sB[G::LDS_B];
+  __shared__ __attribute__((aligned(16))) T sA0[G::BUF_A];
+  __shared__ __attribute__((aligned(16))) T sA1[G::BUF_A];
+  __shared__ __attribute__((aligned(16))) T sB0[G::BUF_B];
+  __shared__ __attribute__((aligned(16))) T sB1[G::BUF_B];
   (void)Kpad;
   TileJob job;
   if (!map(blockIdx.x, job)) return;
-  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA, sB);
+  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA0, sA1, sB0, sB1);
 }
 
 // ------------------------------------------------------------------ the kernel (BF16 x 3)
 // x = hi + lo with hi = bf16(x), lo = bf16(x - hi); x*y ~ hi*hi + hi*lo + lo*hi,
 // the two small cross products accumulated in their own FP32 register set and
 // added to the hi*hi set once at the end.
-template <int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
-__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
-gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restrict__ Ah,
-                      const __bf16* __restrict__ Al, int64_t lda, const __bf16* __restrict__ Bh,
-                      const __bf16* __restrict__ Bl, int64_t ldb, Epi epi, Map map) {
+template <int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+struct Bf3Geom {
+  static constexpr int NT = 64 * WAVES_M * WAVES_N;
+  static constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  static constexpr int LDSR = KC + 8;              // rows padded by 16 bytes
+  static constexpr int LDS_A = 2 * BM * LDSR, LDS_B = 2 * BN * LDSR;   // per plane, two buffers
+};
+
+// One BM x BN tile over the K chunks [job.kc0, job.kc1); the s* arrays hold two LDS
+// buffers each of the hi and lo planes.
+template <int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
+__device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int64_t N, const __bf16* __restrict__ Ah,
+                                              const __bf16* __restrict__ Al, int64_t lda,
+                                              const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl,
+                                              int64_t ldb, const Epi& epi, __bf16* __restrict__ sAh,
+                                              __bf16* __restrict__ sAl, __bf16* __restrict__ sBh,
+                                              __bf16* __restrict__ sBl) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   constexpr int VEC = 8;                           // bf16 per 16-byte load
-  constexpr int LDSR = KC + 8;
+  constexpr int LDSR = Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>::LDSR;
   constexpr int VPR = KC / VEC;
   constexpr int NLA = (BM * VPR + NT - 1) / NT;
   constexpr int NLB = (BN * VPR + NT - 1) / NT;
   static_assert(KC % 32 == 0, "bad KC");
-  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BM * LDSR];
-  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BM * LDSR];
-  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][BN * LDSR];
-  __shared__ __attribute__((aligned(16))) __bf16 sBl[2][BN * LDSR];
-
-  TileJob job;
-  if (!map(blockIdx.x, job)) return;
   const int64_t m0 = job.m0, n0 = job.n0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
@@ -435,23 +605,23 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
   }
 #define PPL_BF3_STORE(buf)                                                   \
   _Pragma("unroll") for (int i = 0; i < NLA; ++i) {                          \
-    *reinterpret_cast<uint4*>(&sAh[buf][oa[i]]) = rah[i];                    \
-    *reinterpret_cast<uint4*>(&sAl[buf][oa[i]]) = ral[i];                    \
+    *reinterpret_cast<uint4*>(&sAh[(buf) * (BM * LDSR) + oa[i]]) = rah[i];                    \
+    *reinterpret_cast<uint4*>(&sAl[(buf) * (BM * LDSR) + oa[i]]) = ral[i];                    \
   }                                                                          \
   _Pragma("unroll") for (int i = 0; i < NLB; ++i) {                          \
-    *reinterpret_cast<uint4*>(&sBh[buf][ob[i]]) = rbh[i];                    \
-    *reinterpret_cast<uint4*>(&sBl[buf][ob[i]]) = rbl[i];                    \
+    *reinterpret_cast<uint4*>(&sBh[(buf) * (BN * LDSR) + ob[i]]) = rbh[i];                    \
+    *reinterpret_cast<uint4*>(&sBl[(buf) * (BN * LDSR) + ob[i]]) = rbl[i];                    \
   }
 #define PPL_BF3_COMPUTE(buf)                                                                   \
   _Pragma("unroll") for (int kk = 0; kk < KC; kk += 32) {                                      \
     bf8 ah[WM], al[WM], bh[WN], bl[WN];                                                        \
     _Pragma("unroll") for (int i = 0; i < WM; ++i) {                                           \
-      ah[i] = *reinterpret_cast<const bf8*>(&sAh[buf][arow + i * 16 * LDSR + kk]);             \
-      al[i] = *reinterpret_cast<const bf8*>(&sAl[buf][arow + i * 16 * LDSR + kk]);             \
+      ah[i] = *reinterpret_cast<const bf8*>(&sAh[(buf) * (BM * LDSR) + arow + i * 16 * LDSR + kk]);             \
+      al[i] = *reinterpret_cast<const bf8*>(&sAl[(buf) * (BM * LDSR) + arow + i * 16 * LDSR + kk]);             \
     }                                                                                          \
     _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                           \
-      bh[j] = *reinterpret_cast<const bf8*>(&sBh[buf][brow + j * 16 * LDSR + kk]);             \
-      bl[j] = *reinterpret_cast<const bf8*>(&sBl[buf][brow + j * 16 * LDSR + kk]);             \
+      bh[j] = *reinterpret_cast<const bf8*>(&sBh[(buf) * (BN * LDSR) + brow + j * 16 * LDSR + kk]);             \
+      bl[j] = *reinterpret_cast<const bf8*>(&sBl[(buf) * (BN * LDSR) + brow + j * 16 * LDSR + kk]);             \
     }                                                                                          \
     _Pragma("unroll") for (int i = 0; i < WM; ++i)                                             \
     _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                           \
@@ -498,6 +668,22 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
       }
     }
   }
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
+gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restrict__ Ah,
+                      const __bf16* __restrict__ Al, int64_t lda, const __bf16* __restrict__ Bh,
+                      const __bf16* __restrict__ Bl, int64_t ldb, Epi epi, Map map) {
+  using G = Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>;
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[G::LDS_B];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[G::LDS_B];
+  (void)Kpad;
+  TileJob job;
+  if (!map(blockIdx.x, job)) return;
+  bf3_tile_body<WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, Ah, Al, lda, Bh, Bl, ldb, epi, sAh, sAl, sBh, sBl);
 }
 
 // ------------------------------------------------------------------ tile configurations
@@ -605,13 +791,214 @@ __global__ void splitk_reduce_kernel(const Tc* __restrict__ P, int splits, int64
   }
 }
 
+// ------------------------------------------------------------------ stream-K
+// The (tile, K chunk) iterations of one GEMM, tiles in row-tile-fastest order, are cut
+// into G contiguous ranges of equal length, one per workgroup, with G the number of
+// workgroups the device holds at once: the launch is one full wave of workgroups with
+// no tail. A workgroup stores a tile that lies wholly inside its range straight into C.
+// A tile shared by several workgroups is written by each into its own partial slot
+// (slot 0: the first tile of its range, slot 1: the last one) and summed in workgroup
+// order by streamk_fixup_kernel, so a given G gives bitwise reproducible results.
+struct StreamK {
+  int64_t n_mt, nk, iters, G;
+  __host__ __device__ int64_t start(int64_t w) const { return w * iters / G; }
+};
+
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_streamk_kernel(int64_t M, int64_t N, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                    int64_t ldb, T* C, int64_t ldc, int64_t c_col0, T* part, StreamK sk) {
+  using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
+  __shared__ __attribute__((aligned(16))) T sA0[G::BUF_A];
+  __shared__ __attribute__((aligned(16))) T sA1[G::BUF_A];
+  __shared__ __attribute__((aligned(16))) T sB0[G::BUF_B];
+  __shared__ __attribute__((aligned(16))) T sB1[G::BUF_B];
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t begin = sk.start(w), end = sk.start(w + 1);
+  const int64_t first_tile = begin / sk.nk;
+  for (int64_t it = begin; it < end;) {
+    const int64_t tile = it / sk.nk, t0 = tile * sk.nk;
+    const int64_t k0 = it - t0, k1 = end - t0 < sk.nk ? end - t0 : sk.nk;
+    TileJob job{(tile % sk.n_mt) * G::BM, (tile / sk.n_mt) * G::BN, k0, k1, 0};
+    const bool whole = k0 == 0 && k1 == sk.nk;
+    EpiSK<T> epi{C, ldc, c_col0, M, N,
+                 part + (w * 2 + (tile == first_tile ? 0 : 1)) * (int64_t)(G::BM * G::BN),
+                 job.m0, job.n0, G::BN, !whole};
+    tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA0, sA1, sB0, sB1);
+    it = t0 + k1;
+    __syncthreads();   // the next tile refills the LDS buffers
+  }
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
+gemm_streamk_bf16x3_kernel(int64_t M, int64_t N, const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al,
+                           int64_t lda, const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int64_t ldb,
+                           float* C, int64_t ldc, int64_t c_col0, float* part, StreamK sk) {
+  using G = Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>;
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[G::LDS_B];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[G::LDS_B];
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t begin = sk.start(w), end = sk.start(w + 1);
+  const int64_t first_tile = begin / sk.nk;
+  for (int64_t it = begin; it < end;) {
+    const int64_t tile = it / sk.nk, t0 = tile * sk.nk;
+    const int64_t k0 = it - t0, k1 = end - t0 < sk.nk ? end - t0 : sk.nk;
+    TileJob job{(tile % sk.n_mt) * G::BM, (tile / sk.n_mt) * G::BN, k0, k1, 0};
+    const bool whole = k0 == 0 && k1 == sk.nk;
+    EpiSK<float> epi{C, ldc, c_col0, M, N,
+                     part + (w * 2 + (tile == first_tile ? 0 : 1)) * (int64_t)(G::BM * G::BN),
+                     job.m0, job.n0, G::BN, !whole};
+    bf3_tile_body<WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, Ah, Al, lda, Bh, Bl, ldb, epi, sAh, sAl, sBh, sBl);
+    it = t0 + k1;
+    __syncthreads();   // the next tile refills the LDS buffers
+  }
+}
+
+// C tile `blockIdx.x` = sum of the partial slots of the workgroups that shared it
+template <class T>
+__global__ void __launch_bounds__(256)
+streamk_fixup_kernel(const T* __restrict__ part, T* C, int64_t ldc, int64_t c_col0, int64_t M, int64_t N,
+                     int bm, int bn, StreamK sk) {
+  const int64_t tile = blockIdx.x;
+  const int64_t a = tile * sk.nk, b = a + sk.nk;
+  int64_t wlo = a * sk.G / sk.iters;          // start(wlo) <= a; step up to the last such
+  while (wlo + 1 < sk.G && sk.start(wlo + 1) <= a) ++wlo;
+  int64_t whi = (b - 1) * sk.G / sk.iters;
+  while (whi + 1 < sk.G && sk.start(whi + 1) <= b - 1) ++whi;
+  if (wlo == whi) return;                    // one workgroup held the whole tile
+  const int64_t m0 = (tile % sk.n_mt) * bm, n0 = (tile / sk.n_mt) * bn;
+  const int64_t slot_elems = (int64_t)bm * bn;
+  for (int e = threadIdx.x; e < bm * bn; e += blockDim.x) {
+    const int r = e / bn, c = e - r * bn;
+    if (m0 + r >= M || n0 + c >= N) continue;
+    T acc = 0;
+    bool first = true;
+    for (int64_t w = wlo; w <= whi; ++w) {
+      const int64_t s0 = sk.start(w);
+      if (sk.start(w + 1) <= s0) continue;    // empty range
+      const T x = part[(w * 2 + (s0 / sk.nk == tile ? 0 : 1)) * slot_elems + e];
+      acc = first ? x : acc + x;
+      first = false;
+    }
+    C[(m0 + r) * ldc + c_col0 + n0 + c] = acc;
+  }
+}
+
+// workgroups of `kernel` resident on the current device at once (cached per device)
+template <class K>
+static int64_t resident_workgroups(K kernel, int threads) {
+  static int64_t cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int cus = 0, nb = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess) return 0;
+    cache[dev] = (int64_t)cus * (nb > 0 ? nb : 1);
+  }
+  return cache[dev];
+}
+
+// workgroups of a stream-K launch: all resident ones, at most kStreamKMaxGrid, and
+// few enough that each gets at least kStreamKMinChunks K chunks
+static int64_t streamk_grid(int64_t resident, int64_t iters) {
+  int64_t g = resident < kStreamKMaxGrid ? resident : kStreamKMaxGrid;
+  const int64_t cap = iters / kStreamKMinChunks;
+  if (g > cap) g = cap;
+  return g > 1 ? g : 1;
+}
+
+uint64_t streamk_part_bytes(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad) {
+  const TileCfg& c = kContract[tile];
+  const int64_t iters = ((Nrows + c.bm() - 1) / c.bm()) * ((Prows + c.bn() - 1) / c.bn()) * (Kpad / kc_of_prec(prec));
+  return (uint64_t)streamk_grid(kStreamKMaxGrid, iters) * 2 * c.bm() * c.bn() * (prec == PPL_FP64 ? 8 : 4);
+}
+
+// grid of a stream-K launch: G workgroups over the (tile, chunk) iterations, with a
+// check that the partial buffer holds G x 2 slots of BM x BN elements
+static int streamk_setup(int64_t resident, int64_t M, int64_t N, int64_t nk, int bm, int bn, size_t elem,
+                         const void* part, uint64_t part_bytes, StreamK& sk, int64_t& n_tiles) {
+  if (resident <= 0) return fail(PPL_E_HIP, "occupancy query for the stream-K kernel failed");
+  sk = StreamK{(M + bm - 1) / bm, nk, 0, 0};
+  n_tiles = sk.n_mt * ((N + bn - 1) / bn);
+  sk.iters = n_tiles * nk;
+  if (sk.iters <= 0) return PPL_OK;
+  sk.G = streamk_grid(resident, sk.iters);
+  const uint64_t need = (uint64_t)sk.G * 2 * bm * bn * elem;
+  if (!part || need > part_bytes)
+    return fail(PPL_E_STATE, "stream-K partial buffer holds %llu bytes, needs %llu",
+                (unsigned long long)part_bytes, (unsigned long long)need);
+  if (n_tiles > 0x7fffffffLL) return fail(PPL_E_ARG, "GEMM grid too large (%lld tiles)", (long long)n_tiles);
+  return PPL_OK;
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+static int launch_streamk_bf3(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const __bf16* Ah,
+                              const __bf16* Al, int64_t lda, const __bf16* Bh, const __bf16* Bl, int64_t ldb,
+                              float* C, int64_t ldc, int64_t c_col0, void* part, uint64_t part_bytes) {
+  using G = Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>;
+  if (Kpad % KC != 0) return fail(PPL_E_ARG, "K padding %lld not a multiple of %d", (long long)Kpad, KC);
+  auto kern = gemm_streamk_bf16x3_kernel<WM, WN, WAVES_M, WAVES_N, KC>;
+  StreamK sk;
+  int64_t n_tiles = 0;
+  PPL_TRY(streamk_setup(resident_workgroups(kern, G::NT), M, N, Kpad / KC, G::BM, G::BN, sizeof(float), part,
+                        part_bytes, sk, n_tiles));
+  if (sk.iters <= 0) return PPL_OK;
+  hipLaunchKernelGGL(kern, dim3((unsigned)sk.G), dim3(G::NT), 0, s, M, N, Ah, Al, lda, Bh, Bl, ldb, C, ldc,
+                     c_col0, (float*)part, sk);
+  PPL_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(streamk_fixup_kernel<float>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const float*)part,
+                     C, ldc, c_col0, M, N, G::BM, G::BN, sk);
+  PPL_HIP_TRY(hipGetLastError());
+  return PPL_OK;
+}
+
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+static int launch_streamk(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const T* A, int64_t lda,
+                          const T* B, int64_t ldb, T* C, int64_t ldc, int64_t c_col0, void* part,
+                          uint64_t part_bytes) {
+  using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
+  if (Kpad % KC != 0) return fail(PPL_E_ARG, "K padding %lld not a multiple of %d", (long long)Kpad, KC);
+  auto kern = gemm_streamk_kernel<T, WM, WN, WAVES_M, WAVES_N, KC>;
+  StreamK sk;
+  int64_t n_tiles = 0;
+  PPL_TRY(streamk_setup(resident_workgroups(kern, G::NT), M, N, Kpad / KC, G::BM, G::BN, sizeof(T), part,
+                        part_bytes, sk, n_tiles));
+  if (sk.iters <= 0) return PPL_OK;
+  hipLaunchKernelGGL(kern, dim3((unsigned)sk.G), dim3(G::NT), 0, s, M, N, A, lda, B, ldb, C, ldc, c_col0,
+                     (T*)part, sk);
+  PPL_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(streamk_fixup_kernel<T>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const T*)part, C, ldc,
+                     c_col0, M, N, G::BM, G::BN, sk);
+  PPL_HIP_TRY(hipGetLastError());
+  return PPL_OK;
+}
+
 // dispatch of one precision over the contraction tiles
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad,
                         const void* S, const void* S_lo, int64_t lds_, const void* V,
                         const void* V_lo, int64_t ldv, void* C, int64_t ldc, int64_t c_col0,
-                        int splits, void* partial, int64_t partial_ld) {
+                        int splits, void* partial, int64_t partial_ld, uint64_t partial_bytes) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  if (splits == 0) {   // stream-K
+    if (prec == PPL_FP64)
+      return launch_streamk<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(
+          s, Nrows, Prows, Kpad, (const double*)S, lds_, (const double*)V, ldv, (double*)C, ldc, c_col0, partial,
+          partial_bytes);
+    if (prec == PPL_FP32)
+      return launch_streamk<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(
+          s, Nrows, Prows, Kpad, (const float*)S, lds_, (const float*)V, ldv, (float*)C, ldc, c_col0, partial,
+          partial_bytes);
+    if (prec == PPL_BF16X3)
+      return launch_streamk_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(
+          s, Nrows, Prows, Kpad, (const __bf16*)S, (const __bf16*)S_lo, lds_, (const __bf16*)V,
+          (const __bf16*)V_lo, ldv, (float*)C, ldc, c_col0, partial, partial_bytes);
+    return fail(PPL_E_ARG, "unknown precision %d", prec);
+  }
   const int KC = kc_of_prec(prec);
   const int64_t nk = Kpad / KC;
   if (splits < 1) splits = 1;
@@ -619,7 +1006,8 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
   const int64_t kps = (nk + splits - 1) / splits;
   splits = (int)((nk + kps - 1) / kps);                 // no empty slice
   const bool direct = splits == 1;
-  if (!direct && !partial) return fail(PPL_E_ARG, "split-K needs a partial buffer");
+  if (!direct && (!partial || (uint64_t)splits * Nrows * partial_ld * (prec == PPL_FP64 ? 8 : 4) > partial_bytes))
+    return fail(PPL_E_STATE, "split-K partial buffer too small for %d slices", splits);
   MapGrid map{(Nrows + BM - 1) / BM, (Prows + BN - 1) / BN, BM, BN, splits, nk, kps};
   const int64_t grid = map.n_mt * map.n_nt * splits;
   const int64_t pstride = Nrows * partial_ld;
@@ -660,12 +1048,12 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
 int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
                   const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
                   int64_t ldv, void* C, int64_t ldc, int64_t c_col0, int splits, void* partial,
-                  int64_t partial_ld) {
+                  int64_t partial_ld, uint64_t partial_bytes) {
   if (Nrows <= 0 || Prows <= 0) return PPL_OK;
 #define PPL_CFG(id, a, b, c, d)                                                                  \
   case id:                                                                                       \
     return contract_cfg<a, b, c, d>(s, prec, Nrows, Prows, Kpad, S, S_lo, lds_, V, V_lo, ldv, C,  \
-                                    ldc, c_col0, splits, partial, partial_ld);
+                                    ldc, c_col0, splits, partial, partial_ld, partial_bytes);
   switch (tile) {
     PPL_CFG(0, 7, 2, 1, 4)
     PPL_CFG(1, 4, 4, 2, 2)
@@ -782,28 +1170,34 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 bool grouped_tile_ok(int tile) { return tile == 1 || tile == 2 || tile >= 5; }
 
 template <class T>
-struct GroupedLds {
-  static constexpr int bytes = TileGeom<T, 13, 1, 1, 4, (sizeof(T) == 8 ? kKcF64 : kKcF32)>::LDS_BYTES;  // largest allowed tile
+struct GroupedLds {       // one LDS buffer of the largest allowed tile (A: 208 rows, B: 128 rows)
+  static constexpr int KC = sizeof(T) == 8 ? kKcF64 : kKcF32;
+  static constexpr int LDSR = TileGeom<T, 13, 1, 1, 4, KC>::LDSR;
+  static constexpr int A = 208 * LDSR, B = 128 * LDSR;
 };
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
-__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, char* smem) {
+__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, T* __restrict__ a0, T* __restrict__ a1,
+                                          T* __restrict__ b0, T* __restrict__ b1) {
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
-  static_assert(G::LDS_BYTES <= GroupedLds<T>::bytes, "tile does not fit the grouped LDS buffer");
+  static_assert(G::BUF_A <= GroupedLds<T>::A && G::BUF_B <= GroupedLds<T>::B,
+                "tile does not fit the grouped LDS buffers");
   static_assert(G::NT == 256, "grouped tiles use 256 threads");
   TileJob job{m0, n0, 0, g.nk, 0};
   EpiStore<T> epi{(T*)g.C, g.ldc, 0, g.M, g.N, 1.0, 0.0, 0};
-  T* sA = reinterpret_cast<T*>(smem);
   tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, g.M, g.N, (const T*)g.A, g.lda, (const T*)g.B, g.ldb, epi,
-                                             sA, sA + G::LDS_A);
+                                             a0, a1, b0, b1);
 }
 
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict__ items, int n_items,
                     int* counter) {
-  constexpr int KC = sizeof(T) == 8 ? kKcF64 : kKcF32;
-  __shared__ __attribute__((aligned(16))) char smem[GroupedLds<T>::bytes];
+  constexpr int KC = GroupedLds<T>::KC;
+  __shared__ __attribute__((aligned(16))) T sA0[GroupedLds<T>::A];
+  __shared__ __attribute__((aligned(16))) T sA1[GroupedLds<T>::A];
+  __shared__ __attribute__((aligned(16))) T sB0[GroupedLds<T>::B];
+  __shared__ __attribute__((aligned(16))) T sB1[GroupedLds<T>::B];
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -814,12 +1208,12 @@ gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict
     const int4 w = items[it];
     const GroupDesc g = groups[w.x];
     switch (g.cfg) {
-      case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, smem); break;
-      case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, smem); break;
-      case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
-      case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
-      case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
-      default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
+      case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
+      case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
+      case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
+      case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
+      default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
     }
   }
 }

@@ -153,12 +153,16 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
                   const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
                   int64_t ldv, void* C, int64_t ldc, int64_t c_col0, int splits, void* partial,
-                  int64_t partial_ld);
+                  int64_t partial_ld, uint64_t partial_bytes);
+// bytes of partial slots a stream-K contraction (splits == 0) with this tile needs at most
+uint64_t streamk_part_bytes(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad);
 int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits);
 // *tile_out >= 0 on entry fixes the tile and only chooses the split count
 void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
                      int* splits_out);
-constexpr int kMaxSplits = 8;
+constexpr int kMaxSplits = 8;          // split-K slices 1 .. kMaxSplits; 0 selects stream-K
+constexpr int64_t kStreamKMaxGrid = 1024;   // stream-K workgroups at most (partial slots: 2 each)
+constexpr int64_t kStreamKMinChunks = 8;    // and at least this many K chunks per workgroup
 
 // grouped persistent contraction (batched instances)
 struct GroupDesc {

@@ -96,14 +96,15 @@ def test_alpha_beta_accumulate(P):
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
 @pytest.mark.parametrize("tile", range(9))
 def test_every_contraction_tile_and_split(P, tile, prec, bound):
-    say(f"contract {prec} tile {tile} splits 1..8 (7,37,130)")
+    say(f"contract {prec} tile {tile} splits 1..8 and stream-K (7,37,130)")
     # K padded to 192: 12 FP64 / 6 FP32 chunks, so 8 slices are clamped to 6 for FP32 and BF16x3
     s = S.make_system(7, 37, 130, 20 + tile)
     t = S.make_amplitudes(7, 37, 30 + tile)
     Rref = O.ppl(s["L"], 7, t)
     first = None
-    for sp in (1, 2, 3, 4, 6, 8):
-        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 9, 9 - sp))
+    for sp in (1, 2, 3, 4, 6, 8, 0):
+        # 0 = stream-K on the R+ GEMM; the R- GEMM takes another tile and K decomposition
+        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 9, (9 - sp) % 9))
         assert info["tile_contract"] == tile and info["splits_contract"] == sp
         assert rel(R, Rref) < bound
         if prec == "fp64":
@@ -122,14 +123,30 @@ def test_autotuned_contraction_matches(P):
 
 
 def test_streaming_batches_are_bitwise_equal_to_resident(P):
-    say("contract fp64 streaming vs resident (6,60,50)")
+    say("contract fp64 streaming vs resident (6,60,50), split-K")
     s = S.make_system(6, 60, 50, 40)
     t = S.make_amplitudes(6, 60, 41)
-    R_res, i_res = gpu_contract(P, s, t)
-    R_str, i_str = gpu_contract(P, s, t, budget=i_res["workspace_bytes"] // 3)
+    # split-K sums every column over the same K slices whatever the column batch
+    R_res, i_res = gpu_contract(P, s, t, config=(5, 2, 0, 3))
+    R_str, i_str = gpu_contract(P, s, t, budget=i_res["workspace_bytes"] // 3, config=(5, 2, 0, 3))
     assert i_res["resident"] == 1 and i_str["resident"] == 0 and i_str["n_batches"] > 1
     assert np.array_equal(R_res, R_str)
     assert rel(R_res, O.ppl(s["L"], 6, t)) < 1e-12
+
+
+def test_streaming_batches_stream_k(P):
+    say("contract fp64 streaming vs resident (6,60,50), stream-K")
+    s = S.make_system(6, 60, 50, 40)
+    t = S.make_amplitudes(6, 60, 41)
+    R_res, i_res = gpu_contract(P, s, t, config=(0, 0, 5, 0))
+    R_str, i_str = gpu_contract(P, s, t, budget=i_res["workspace_bytes"] // 3, config=(0, 0, 5, 0))
+    assert i_res["resident"] == 1 and i_str["resident"] == 0 and i_str["n_batches"] > 1
+    # the K ranges of shared tiles follow each launch's partition: equal up to rounding
+    assert rel(R_str, R_res) < 1e-14
+    assert rel(R_res, O.ppl(s["L"], 6, t)) < 1e-12
+    # a repeated launch gives the same bits
+    R_again, _ = gpu_contract(P, s, t, config=(0, 0, 5, 0))
+    assert np.array_equal(R_res, R_again)
 
 
 @pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("bf16x3", 4e-5)])
