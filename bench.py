@@ -65,7 +65,8 @@ def cpu_baseline(s, o):
 
 def measured_traffic(config):
     """HBM bytes per R+ launch from the committed hardware-counter summary, or None
-    when the kernel source or the contraction configuration differs from the one measured."""
+    when the kernel source differs from the one measured or its R+ configuration
+    (tile, split-K count) was not measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "contract_fp64_o20_v200_naux600_traffic.json")
     try:
@@ -73,9 +74,9 @@ def measured_traffic(config):
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_16"] or list(config) != rec["contract_config"]:
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("sha256_16"):
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec.get("bytes_per_launch", {}).get(f"{config[0]},{config[1]}")
 
 
 def study_c3(args):

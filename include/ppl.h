@@ -310,6 +310,14 @@ const char* ppl_last_error(void);
 /* Number of contraction tile configurations compiled into the library. */
 int ppl_tile_count(void);
 
+/*
+ * ppl_tile_dims: rows (bm, of the occupied-pair operand) and columns (bn, of the
+ * virtual-pair operand) of the C tile of contraction tile `tile`, and the threads
+ * per workgroup of its kernels. Host only. PPL_E_ARG for an unknown tile id or a
+ * NULL output.
+ */
+int ppl_tile_dims(int32_t tile, int32_t* bm, int32_t* bn, int32_t* threads);
+
 /* Library version string. */
 const char* ppl_version(void);
 

@@ -117,6 +117,8 @@ SIGNATURES = {
     "ppl_destroy": (ctypes.c_int, [_P]),
     "ppl_last_error": (ctypes.c_char_p, []),
     "ppl_tile_count": (ctypes.c_int, []),
+    "ppl_tile_dims": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "ppl_version": (ctypes.c_char_p, []),
 }
 
@@ -387,6 +389,13 @@ def ppl_last_error() -> str:
 
 def ppl_tile_count() -> int:
     return load().ppl_tile_count()
+
+
+def ppl_tile_dims(tile: int):
+    """(bm, bn, threads) of contraction tile `tile`."""
+    bm, bn, th = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().ppl_tile_dims(int(tile), ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(th)), "ppl_tile_dims")
+    return bm.value, bn.value, th.value
 
 
 def ppl_version() -> str:

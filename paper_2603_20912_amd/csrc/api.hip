@@ -152,12 +152,14 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
 static void make_tile_tables(ppl_plan_t p) {
   p->tiles_host.clear();
   p->tiles_off.clear();
+  p->tiles_n.clear();
   for (const Batch& b : p->batches) {
-    std::vector<int> pre;
+    std::vector<int> list;
     int nmt, nnt;
-    build_tile_table(p->tile_build, p->v, b.a0, b.a1, pre, nmt, nnt);
+    build_tile_table(p->tile_build, p->v, b.a0, b.a1, list, nmt, nnt);
     p->tiles_off.push_back((int64_t)p->tiles_host.size());
-    p->tiles_host.insert(p->tiles_host.end(), pre.begin(), pre.end());
+    p->tiles_n.push_back((int64_t)list.size() / 2);
+    p->tiles_host.insert(p->tiles_host.end(), list.begin(), list.end());
   }
 }
 
@@ -208,11 +210,8 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
     PPL_TRY(stage_vv(st, s.prec, L, p->o, p->v, p->naux, p->ldx, at<void>(p, s.xt),
                      s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr));
   }
-  std::vector<int> pre;
-  int nmt, nnt;
-  build_tile_table(p->tile_build, p->v, b.a0, b.a1, pre, nmt, nnt);
-  const int* dpre = at<int>(p, p->tiles) + p->tiles_off[bi];
-  const int64_t nvalid = pre.back();
+  const int* dtiles = at<int>(p, p->tiles) + p->tiles_off[bi];
+  const int64_t nvalid = p->tiles_n[bi];
   // every write of this step must stay inside its region
   const uint64_t g_need = (uint64_t)(b.p1 - b.p0) * p->v * p->v * acc_bytes(s.prec);
   if (g_need > p->g.bytes)
@@ -228,8 +227,8 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
   {
     ProfScope ps(p, PPL_PROF_BUILD_GEMM, 2.0 * p->naux * (double)p->v * p->v * (double)(b.p1 - b.p0));
     PPL_TRY(gemm_build(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
-                       s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dpre,
-                       nmt, nnt, nvalid));
+                       s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dtiles,
+                       nvalid));
   }
   const int64_t row0p = p->resident ? 0 : b.p0;
   const int64_t row0m = p->resident ? 0 : b.q0;
@@ -350,6 +349,14 @@ const char* ppl_version(void) { return "ppl-mi355x 0.1 (gfx950)"; }
 
 int ppl_tile_count(void) { return contract_tile_count(); }
 
+int ppl_tile_dims(int32_t tile, int32_t* bm, int32_t* bn, int32_t* threads) {
+  g_err[0] = 0;
+  if (!bm || !bn || !threads) return fail(PPL_E_ARG, "NULL output");
+  if (tile < 0 || tile >= contract_tile_count()) return fail(PPL_E_ARG, "tile id out of range [0, %d)", contract_tile_count());
+  contract_tile_dims(tile, bm, bn, threads);
+  return PPL_OK;
+}
+
 void ppl_iter_opts_default(ppl_iter_opts_t* o) {
   if (!o) return;
   memset(o, 0, sizeof(*o));
@@ -404,7 +411,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   p->ops[0].present = true;
   p->ops[1].prec = PPL_FP64;
   p->ops[1].present = p->keep_fp64 != 0;
-  p->tile_build = 0;
+  p->tile_build = build_tile_for_prec(p->prec);
   {
     int t = d->tile_contract, sp = 1;
     contract_choose(p->prec, p->Np, p->Pp, p->ldp, kMaxSplits, &t, &sp);

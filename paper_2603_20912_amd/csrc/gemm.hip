@@ -97,23 +97,14 @@ struct MapGrid {
 };
 
 struct MapBuild {        // block-upper-triangle of the (a,c) x (b,d) grid: only tiles with some b >= a
-  const int* prefix;     // prefix[mt] = valid tiles in row tiles < mt (n_mt + 1 entries)
-  int n_mt;
+  const int* tiles;      // (row tile, column tile) of each job, in launch order
   int64_t total;
-  int v, bm, bn;
+  int bm, bn;
   int64_t nk;
   __device__ bool operator()(int64_t bid, TileJob& j) const {
     const int64_t t = xcd_remap(bid, total);
-    int lo = 0, hi = n_mt - 1;              // largest mt with prefix[mt] <= t
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    const int mt = lo;
-    const int64_t arel = (int64_t)mt * bm / v;          // first a of the row tile, relative to a0
-    const int64_t nt_min = arel * v / bn;
-    j.m0 = (int64_t)mt * bm;
-    j.n0 = (nt_min + (t - prefix[mt])) * bn;
+    j.m0 = (int64_t)tiles[2 * t] * bm;
+    j.n0 = (int64_t)tiles[2 * t + 1] * bn;
     j.kc0 = 0;
     j.kc1 = nk;
     j.split = 0;
@@ -704,11 +695,19 @@ static const TileCfg kContract[] = {
     {2, 2, 1, 4},   // 6:  32 x 128
     {3, 2, 1, 4},   // 7:  48 x 128
     {4, 2, 1, 4},   // 8:  64 x 128
+    {7, 2, 2, 4},   // 9: 224 x 128, eight waves (one row tile covers up to 224 occupied pairs)
+    {7, 1, 2, 4},   // 10: 224 x 64, eight waves
 };
 static const int kNumContract = sizeof(kContract) / sizeof(kContract[0]);
-static const TileCfg kBuild = {4, 4, 2, 2};   // 128 x 128
 
 int contract_tile_count() { return kNumContract; }
+
+void contract_tile_dims(int tile, int* bm, int* bn, int* threads) {
+  const TileCfg& c = kContract[tile];
+  *bm = c.bm();
+  *bn = c.bn();
+  *threads = 64 * c.waves_m * c.waves_n;
+}
 
 int contract_tile_default(int prec, int64_t Nrows) {
   (void)prec;
@@ -727,25 +726,40 @@ int contract_tile_default(int prec, int64_t Nrows) {
   return best;
 }
 
+// The integral build runs on one of these contraction tiles (ids as in kContract).
+bool build_tile_ok(int tile) { return tile == 0 || tile == 1 || tile == 5 || tile == 8; }
+
 int build_tile_dims(int tile, int* bm, int* bn) {
-  (void)tile;
-  *bm = kBuild.bm();
-  *bn = kBuild.bn();
+  if (!build_tile_ok(tile)) return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
+  *bm = kContract[tile].bm();
+  *bn = kContract[tile].bn();
   return PPL_OK;
 }
 
-void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& prefix, int& n_mt,
-                      int& n_nt) {
+// Valid (row tile, column tile) pairs of one build step in launch order: row tiles
+// in groups of kBuildGroup, each group walked column tile by column tile with its row
+// tiles innermost, so that workgroups running together on one XCD share operand rows
+// in L2 (a column tile is re-read once per group instead of once per row tile).
+// A row tile starting at a (relative to a0) needs the column tiles from the one
+// holding b = a on; the earlier ones lie wholly below the diagonal b >= a.
+void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mt, int& n_nt) {
+  constexpr int kBuildGroup = 8;
   int bm, bn;
   build_tile_dims(tile, &bm, &bn);
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
   n_mt = (int)((M + bm - 1) / bm);
   n_nt = (int)((N + bn - 1) / bn);
-  prefix.assign(n_mt + 1, 0);
-  for (int mt = 0; mt < n_mt; ++mt) {
-    const int64_t arel = (int64_t)mt * bm / v;
-    const int64_t nt_min = arel * v / bn;
-    prefix[mt + 1] = prefix[mt] + (int)(n_nt - nt_min);
+  tiles.clear();
+  for (int g0 = 0; g0 < n_mt; g0 += kBuildGroup) {
+    const int g1 = g0 + kBuildGroup < n_mt ? g0 + kBuildGroup : n_mt;
+    const int nt_first = (int)(((int64_t)g0 * bm / v) * v / bn);
+    for (int nt = nt_first; nt < n_nt; ++nt)
+      for (int mt = g0; mt < g1; ++mt) {
+        const int64_t arel = (int64_t)mt * bm / v;
+        if (nt < arel * v / bn) break;   // nt_min grows with mt
+        tiles.push_back(mt);
+        tiles.push_back(nt);
+      }
   }
 }
 
@@ -1064,6 +1078,8 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
     PPL_CFG(6, 2, 2, 1, 4)
     PPL_CFG(7, 3, 2, 1, 4)
     PPL_CFG(8, 4, 2, 1, 4)
+    PPL_CFG(9, 7, 2, 2, 4)
+    PPL_CFG(10, 7, 1, 2, 4)
     default:
       return fail(PPL_E_ARG, "unknown contraction tile %d", tile);
   }
@@ -1083,11 +1099,12 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 
 // Relative per-tile throughput on large problems, measured with HIP events on
 // gfx950: best over 1, 2 and 4 K slices, averaged over R+ and R- at (30, 300, 900)
-// and (40, 400, 1200); 1.0 = best tile of the precision.
-static const double kTileEff[3][9] = {
-    /* FP64   */ {0.99, 0.97, 0.82, 0.90, 0.95, 1.00, 0.93, 0.95, 0.99},
-    /* FP32   */ {0.96, 0.94, 0.87, 0.92, 0.94, 0.97, 0.94, 0.96, 1.00},
-    /* BF16x3 */ {1.00, 0.77, 0.56, 0.48, 0.57, 0.94, 0.58, 0.80, 0.89}};
+// and (40, 400, 1200) (FP32 at the first only); 1.0 = best tile of the precision.
+static const double kTileEff[3][11] = {
+    /* FP64   */ {1.00, 0.97, 0.87, 0.91, 0.99, 0.99, 0.95, 0.97, 1.00, 0.87, 0.83},
+    /* FP32   */ {0.93, 0.92, 0.74, 0.90, 0.93, 0.96, 0.96, 0.97, 1.00, 0.81, 0.87},
+    /* BF16x3 */ {0.93, 0.73, 0.53, 0.51, 0.56, 0.92, 0.59, 0.76, 0.82, 1.00, 0.66}};
+static_assert(sizeof(kTileEff[0]) / sizeof(double) == kNumContract, "one efficiency per tile");
 
 // Model choice of (tile, splits): useful work over the work of the padded tiles,
 // times the fill of the last round of workgroups over 256 CUs, times the
@@ -1120,36 +1137,45 @@ void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int m
   *splits_out = bs;
 }
 
-int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,
-               const void* Xt, const void* Xt_lo, int64_t ldx, void* G, const int* tile_prefix,
-               int n_mtiles, int n_ntiles, int64_t n_valid_tiles) {
-  (void)tile;
-  (void)n_ntiles;
-  constexpr int WM = 4, WN = 4, WAVES_M = 2, WAVES_N = 2;
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                     const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
-  MapBuild map{tile_prefix, n_mtiles, n_valid_tiles, v, BM, BN, 0};
+  MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
   map.nk = Kpad / kc_of_prec(prec);
   if (prec == PPL_FP64) {
     const double* X = (const double*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<double> epi{(double*)G, M, N, v, a0};
     return launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, n_valid_tiles, M, N, Kpad, X, ldx, X, ldx,
-                                                        epi, map);
+                                                            epi, map);
   }
   if (prec == PPL_FP32) {
     const float* X = (const float*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<float> epi{(float*)G, M, N, v, a0};
     return launch<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, X, ldx, X, ldx,
-                                                       epi, map);
+                                                           epi, map);
   }
   if (prec == PPL_BF16X3) {
     const __bf16* Xh = (const __bf16*)Xt + (int64_t)a0 * v * ldx;
     const __bf16* Xl = (const __bf16*)Xt_lo + (int64_t)a0 * v * ldx;
     EpiBuild<float> epi{(float*)G, M, N, v, a0};
     return launch_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, Xh, Xl, ldx, Xh,
-                                                    Xl, ldx, epi, map);
+                                                        Xl, ldx, epi, map);
   }
   return fail(PPL_E_ARG, "unknown precision %d", prec);
+}
+
+int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,
+               const void* Xt, const void* Xt_lo, int64_t ldx, void* G, const int* tile_list,
+               int64_t n_valid_tiles) {
+  switch (tile) {
+    case 0: return build_cfg<7, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
+    case 1: return build_cfg<4, 4, 2, 2>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
+    case 5: return build_cfg<6, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
+    case 8: return build_cfg<4, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
+    default: return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
+  }
 }
 
 int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const double* A, int64_t lda,
@@ -1167,26 +1193,24 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 // fixed grid of workgroups pulls (group, row tile, column tile) items from a
 // queue sorted longest-first; each group carries its own tile shape. Every
 // workgroup leaves the loop once the queue counter passes the item count.
-bool grouped_tile_ok(int tile) { return tile == 1 || tile == 2 || tile >= 5; }
+bool grouped_tile_ok(int tile) { return tile == 1 || tile == 2 || (tile >= 5 && tile <= 8); }
 
 template <class T>
-struct GroupedLds {       // one LDS buffer of the largest allowed tile (A: 208 rows, B: 128 rows)
+struct GroupedLds {       // LDS of the largest allowed tile (208 x 64 rows staged, 272 in all)
   static constexpr int KC = sizeof(T) == 8 ? kKcF64 : kKcF32;
-  static constexpr int LDSR = TileGeom<T, 13, 1, 1, 4, KC>::LDSR;
-  static constexpr int A = 208 * LDSR, B = 128 * LDSR;
+  static constexpr int bytes = TileGeom<T, 13, 1, 1, 4, KC>::LDS_BYTES;
 };
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
-__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, T* __restrict__ a0, T* __restrict__ a1,
-                                          T* __restrict__ b0, T* __restrict__ b1) {
+__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, char* smem) {
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
-  static_assert(G::BUF_A <= GroupedLds<T>::A && G::BUF_B <= GroupedLds<T>::B,
-                "tile does not fit the grouped LDS buffers");
+  static_assert(G::LDS_BYTES <= GroupedLds<T>::bytes, "tile does not fit the grouped LDS buffer");
   static_assert(G::NT == 256, "grouped tiles use 256 threads");
   TileJob job{m0, n0, 0, g.nk, 0};
   EpiStore<T> epi{(T*)g.C, g.ldc, 0, g.M, g.N, 1.0, 0.0, 0};
+  T* s = reinterpret_cast<T*>(smem);
   tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, g.M, g.N, (const T*)g.A, g.lda, (const T*)g.B, g.ldb, epi,
-                                             a0, a1, b0, b1);
+                                             s, s + G::BUF_A, s + 2 * G::BUF_A, s + 2 * G::BUF_A + G::BUF_B);
 }
 
 template <class T>
@@ -1194,10 +1218,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict__ items, int n_items,
                     int* counter) {
   constexpr int KC = GroupedLds<T>::KC;
-  __shared__ __attribute__((aligned(16))) T sA0[GroupedLds<T>::A];
-  __shared__ __attribute__((aligned(16))) T sA1[GroupedLds<T>::A];
-  __shared__ __attribute__((aligned(16))) T sB0[GroupedLds<T>::B];
-  __shared__ __attribute__((aligned(16))) T sB1[GroupedLds<T>::B];
+  __shared__ __attribute__((aligned(16))) char smem[GroupedLds<T>::bytes];
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -1208,12 +1229,12 @@ gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict
     const int4 w = items[it];
     const GroupDesc g = groups[w.x];
     switch (g.cfg) {
-      case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
-      case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
-      case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
-      case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
-      case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
-      default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, sA0, sA1, sB0, sB1); break;
+      case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, smem); break;
+      case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+      default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
     }
   }
 }

@@ -114,9 +114,10 @@ struct ppl_plan_s {
   ppl::Region xov;                     // staged occupied-virtual block [(i,a)][ldx] (FP64)
   ppl::Region tab_vp, tab_vm, tab_op, tab_om;  // pair tables (int32)
   ppl::Region red;                     // reduction partials
-  ppl::Region tiles;                   // per-batch tile prefix tables of the build GEMM (int32)
+  ppl::Region tiles;                   // per-batch (row tile, column tile) lists of the build GEMM (int32 pairs)
   std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
-  std::vector<int64_t> tiles_off;      // element offset of each batch's table in `tiles`
+  std::vector<int64_t> tiles_off;      // element offset of each batch's list in `tiles`
+  std::vector<int64_t> tiles_n;        // tiles in each batch's list
   const double* L_last = nullptr;
   bool setup_done = false;
   // kernel timing
@@ -160,6 +161,9 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 // *tile_out >= 0 on entry fixes the tile and only chooses the split count
 void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
                      int* splits_out);
+// contraction tile the integral build GEMM of a plan runs on (measured at (20, 200, 600)
+// and (30, 300, 900): 128 x 128 for FP64 and FP32 operands, 96 x 128 for BF16x3)
+inline int build_tile_for_prec(int prec) { return prec == PPL_BF16X3 ? 5 : 1; }
 constexpr int kMaxSplits = 8;          // split-K slices 1 .. kMaxSplits; 0 selects stream-K
 constexpr int64_t kStreamKMaxGrid = 1024;   // stream-K workgroups at most (partial slots: 2 each)
 constexpr int64_t kStreamKMinChunks = 8;    // and at least this many K chunks per workgroup
@@ -180,12 +184,14 @@ int gemm_grouped(hipStream_t s, int prec, const GroupDesc* groups, const int4* i
 // Integral build G[pair(a,b) - pair(a0,a0)][c][d] = sum_P Xt[(a,c)][P] Xt[(b,d)][P]
 // for a in [a0, a1), b in [a, v).
 int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,
-               const void* Xt, const void* Xt_lo, int64_t ldx, void* G, const int* tile_prefix,
-               int n_mtiles, int n_ntiles, int64_t n_valid_tiles);
-// host helper: number of valid tiles and per-row-tile prefix of a build step
-void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& prefix, int& n_mtiles,
+               const void* Xt, const void* Xt_lo, int64_t ldx, void* G, const int* tile_list,
+               int64_t n_valid_tiles);
+// host helper: the valid (row tile, column tile) pairs of a build step in launch order
+// (two ints per tile)
+void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mtiles,
                       int& n_ntiles);
 int build_tile_dims(int tile, int* bm, int* bn);
+void contract_tile_dims(int tile, int* bm, int* bn, int* threads);
 int contract_tile_count();
 int contract_tile_default(int prec, int64_t Nrows);
 

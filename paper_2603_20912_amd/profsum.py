@@ -1,0 +1,169 @@
+"""Summaries of rocprofv3 runs of bench.py for the profiles/ folder.
+
+    python -m paper_2603_20912_amd.profsum --trace-stats TRACE_kernel_stats.csv \
+        --counters 0,4,8,6 FETCH_counter_collection.csv WRITE_counter_collection.csv [--counters ...] \
+        --command "rocprofv3 ..." [--command ...] --md OUT.md --json OUT.json
+
+Inputs are the CSV files of one `--kernel-trace --stats` run and, per contraction
+configuration, one FETCH_SIZE and one WRITE_SIZE counter run of
+`bench.py --steps 1 --warmup 0 --contract-config CFG --copy-calibration`.
+
+Calibration: the counter runs begin with one plain 1 GiB device-to-device copy.
+The copy dispatch whose WRITE_SIZE is closest to 1 GiB scales both counters
+(bytes moved / counter reading), so the traffic of the other kernels is stated
+in bytes.
+
+The R+ contraction launches are the GEMM dispatches whose grid matches the R+
+grid of the configuration (tile shape from ppl_tile_dims, split-K count after the
+library's clamping); each is counted together with the split-K reduction that
+follows it, which is what the bench times as one R+ launch. The JSON gives the
+bytes per R+ launch keyed by "tile,splits", with the sha256 of the GEMM source,
+so that the bench reports traffic only for the kernel code that was measured.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GEMM_SRC = "paper_2603_20912_amd/csrc/gemm.hip"
+GIB_KIB = 1024.0 * 1024.0
+
+
+def pairs_plus(n):
+    return n * (n + 1) // 2
+
+
+def pad64(k):
+    return (k + 63) // 64 * 64
+
+
+def short_name(k):
+    k = k.replace("void ", "").replace("ppl::", "")
+    return k.split("(")[0] if "<" not in k else k[: k.index(">") + 1]
+
+
+def rplus_grid(tile, splits, o, v, kc=16):
+    """Threads of the R+ GEMM launch of (tile, splits) (split-K configurations only)."""
+    from . import ppl_tile_dims
+    bm, bn, th = ppl_tile_dims(tile)
+    M, N, K = pairs_plus(o), pairs_plus(v), pad64(pairs_plus(v))
+    nk = K // kc
+    s = max(1, min(splits, nk))
+    kps = (nk + s - 1) // s
+    s = (nk + kps - 1) // kps
+    return -(-M // bm) * -(-N // bn) * s * th
+
+
+def read_counters(path):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def calibration_dispatch(write_rows):
+    """Dispatch id of the 1 GiB calibration copy: the copy whose WRITE_SIZE is closest to 1 GiB."""
+    copies = [r for r in write_rows if "copy" in r["Kernel_Name"].lower()]
+    best = min(copies, key=lambda r: abs(float(r["Counter_Value"]) - GIB_KIB))
+    if abs(float(best["Counter_Value"]) - GIB_KIB) > 0.02 * GIB_KIB:
+        raise SystemExit("no 1 GiB calibration copy in the WRITE_SIZE run (bench.py --copy-calibration)")
+    return int(best["Dispatch_Id"])
+
+
+def per_launch(fetch_rows, write_rows, fscale, wscale, grid):
+    """Scaled bytes of each R+ GEMM dispatch plus the reduction dispatch right after it."""
+    w = {int(r["Dispatch_Id"]): r for r in write_rows}
+    out = []
+    for i, r in enumerate(fetch_rows):
+        if "gemm_nt_kernel<double" not in r["Kernel_Name"] or "MapGrid" not in r["Kernel_Name"]:
+            continue
+        if int(r["Grid_Size"]) != grid:
+            continue
+        ids = [int(r["Dispatch_Id"])]
+        if i + 1 < len(fetch_rows) and "splitk_reduce" in fetch_rows[i + 1]["Kernel_Name"]:
+            ids.append(int(fetch_rows[i + 1]["Dispatch_Id"]))
+        fb = sum(float(next(x for x in fetch_rows if int(x["Dispatch_Id"]) == d)["Counter_Value"]) for d in ids)
+        wb = sum(float(w[d]["Counter_Value"]) for d in ids)
+        out.append((fb * fscale + wb * wscale) * 1024.0)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--trace-stats", required=True)
+    ap.add_argument("--counters", nargs=3, action="append", metavar=("CFG", "FETCH_CSV", "WRITE_CSV"), default=[])
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--o", type=int, default=20)
+    ap.add_argument("--v", type=int, default=200)
+    ap.add_argument("--naux", type=int, default=600)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--json", required=True)
+    a = ap.parse_args(argv)
+
+    sha = hashlib.sha256(open(os.path.join(ROOT, GEMM_SRC), "rb").read()).hexdigest()[:16]
+    stats = list(csv.DictReader(open(a.trace_stats)))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# FP64 contraction and build kernels, PPL step at (o, v, naux) = ({a.o}, {a.v}, {a.naux})", "",
+             "Commands (run from the repository root on one MI355X, ROCm 7.2, `export TMPDIR=/tmp`):", "", "```"]
+    lines += a.command + ["```", "",
+                          f"Kernel source: `{GEMM_SRC}` sha256[:16] = `{sha}`.", "",
+                          "## Kernel trace summary (`--kernel-trace --stats`)", "",
+                          "| calls | avg ms | % time | kernel |", "|---:|---:|---:|---|"]
+    for r in stats[:12]:
+        lines.append(f"| {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} | "
+                     f"`{short_name(r['Name'])}` |")
+    rec = {"kernel": "R+ contraction GEMM with its split-K reduction", "source": GEMM_SRC, "sha256_16": sha,
+           "workload": f"fp64 ({a.o},{a.v},{a.naux})", "bytes_per_launch": {}, "calibration": {}}
+    algo = {}
+    M, N, K = pairs_plus(a.o), pairs_plus(a.v), pad64(pairs_plus(a.v))
+    for cfg, fpath, wpath in a.counters:
+        c = [int(x) for x in cfg.split(",")]
+        fr, wr = read_counters(fpath), read_counters(wpath)
+        cal = calibration_dispatch(wr)
+        fc = next(r for r in fr if int(r["Dispatch_Id"]) == cal)
+        wc = next(r for r in wr if int(r["Dispatch_Id"]) == cal)
+        if fc["Kernel_Name"] != wc["Kernel_Name"]:
+            raise SystemExit("the FETCH_SIZE and WRITE_SIZE runs dispatched different kernels")
+        fscale = GIB_KIB / float(fc["Counter_Value"])   # the copy read 1 GiB
+        wscale = GIB_KIB / float(wc["Counter_Value"])   # and wrote 1 GiB
+        launches = per_launch(fr, wr, fscale, wscale, rplus_grid(c[0], c[1], a.o, a.v))
+        if not launches:
+            raise SystemExit(f"no R+ launch of config {cfg} found in {fpath}")
+        key = f"{c[0]},{c[1]}"
+        rec["bytes_per_launch"][key] = sum(launches) / len(launches)
+        rec["calibration"][key] = {"fetch_scale": fscale, "write_scale": wscale}
+        s_eff = rplus_grid(c[0], c[1], a.o, a.v) // rplus_grid(c[0], 1, a.o, a.v)
+        # V+ and S' read once, R+ written once, split-K slices written once and read once
+        algo[key] = 8.0 * (N * K + M * K + M * K + (2 * s_eff * M * K if s_eff > 1 else 0))
+        # per-kernel table for this configuration
+        kf, kw, kn = defaultdict(float), defaultdict(float), defaultdict(int)
+        wmap = {int(r["Dispatch_Id"]): r for r in wr}
+        for r in fr:
+            d = int(r["Dispatch_Id"])
+            if d not in wmap:
+                continue
+            k = short_name(r["Kernel_Name"])
+            kf[k] += float(r["Counter_Value"]) * fscale
+            kw[k] += float(wmap[d]["Counter_Value"]) * wscale
+            kn[k] += 1
+        lines += ["", f"## Hardware byte counters, contraction config {cfg} (KiB per dispatch, calibrated)", "",
+                  f"Calibration: FETCH_SIZE x {fscale:.4f}, WRITE_SIZE x {wscale:.4f} (one 1 GiB device copy).", "",
+                  "| kernel | dispatches | FETCH KiB | WRITE KiB | GB / dispatch |", "|---|---:|---:|---:|---:|"]
+        for k in sorted(kf, key=lambda k: -(kf[k] + kw[k]) / kn[k])[:10]:
+            lines.append(f"| `{k}` | {kn[k]} | {kf[k] / kn[k]:.0f} | {kw[k] / kn[k]:.0f} | "
+                         f"{(kf[k] + kw[k]) / kn[k] * 1024 / 1e9:.3f} |")
+        lines += ["", f"R+ launch (GEMM + reduction) of config {cfg}: {rec['bytes_per_launch'][key] / 1e9:.3f} GB "
+                  f"measured over {len(launches)} launches; algorithmic {algo[key] / 1e9:.3f} GB "
+                  f"(V+ {N} x {K}, S' {M} x {K}, the split-K slices written and read once, R+ {M} x {K}, 8 B each)."]
+    os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
+    open(a.md, "w").write("\n".join(lines) + "\n")
+    json.dump(rec, open(a.json, "w"), indent=1)
+    print(f"wrote {a.md} and {a.json}")
+
+
+if __name__ == "__main__":
+    main()

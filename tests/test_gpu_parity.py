@@ -94,7 +94,7 @@ def test_alpha_beta_accumulate(P):
 
 
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
-@pytest.mark.parametrize("tile", range(9))
+@pytest.mark.parametrize("tile", range(11))
 def test_every_contraction_tile_and_split(P, tile, prec, bound):
     say(f"contract {prec} tile {tile} splits 1..8 and stream-K (7,37,130)")
     # K padded to 192: 12 FP64 / 6 FP32 chunks, so 8 slices are clamped to 6 for FP32 and BF16x3
@@ -104,7 +104,7 @@ def test_every_contraction_tile_and_split(P, tile, prec, bound):
     first = None
     for sp in (1, 2, 3, 4, 6, 8, 0):
         # 0 = stream-K on the R+ GEMM; the R- GEMM takes another tile and K decomposition
-        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 9, (9 - sp) % 9))
+        R, info = gpu_contract(P, s, t, prec=prec, config=(tile, sp, (tile + 1) % 11, (9 - sp) % 9))
         assert info["tile_contract"] == tile and info["splits_contract"] == sp
         assert rel(R, Rref) < bound
         if prec == "fp64":

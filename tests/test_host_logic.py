@@ -190,3 +190,28 @@ def test_build_scratch_holds_the_widest_accumulator(P, o, v, naux, prec, keep):
     acc = 8 if (prec == "fp64" or keep) else 4
     assert i["build_scratch_bytes"] >= i["max_step_pairs"] * v * v * acc
     assert i["build_scratch_bytes"] >= (o * v) ** 2 * 8
+
+
+def test_tile_dims_and_contract_config_range(P):
+    from paper_2603_20912_amd import _lib
+    n = P.ppl_tile_count()
+    assert n == 11   # the GPU tests walk tiles 0 .. 10
+    dims = [P.ppl_tile_dims(t) for t in range(n)]
+    # MFMA blocks are 16 x 16 and contraction workgroups have four or eight waves
+    assert all(bm % 16 == 0 and bn % 16 == 0 and th in (256, 512) for bm, bn, th in dims)
+    for bad in (-1, n):
+        with pytest.raises(_lib.PPLError) as e:
+            P.ppl_tile_dims(bad)
+        assert e.value.code == _lib.PPL_E_ARG
+    plan = _lib.ppl_plan(5, 20, 60, hbm_budget=1 << 30, stream=False)
+    try:
+        for sp in (0, 1, 8):   # 0 = stream-K
+            _lib.ppl_set_contract_config(plan, 0, sp, 1, sp)
+            info = _lib.ppl_plan_query(plan)
+            assert info["splits_contract"] == sp and info["splits_contract_minus"] == sp
+        for sp in (-1, 9):
+            with pytest.raises(_lib.PPLError) as e:
+                _lib.ppl_set_contract_config(plan, 0, sp, 0, 1)
+            assert e.value.code == _lib.PPL_E_ARG
+    finally:
+        _lib.ppl_destroy(plan)
