@@ -138,6 +138,88 @@ def study_c3(args):
     print(json.dumps({"study": out}), flush=True)
 
 
+def study_batched(args):
+    """The 32 uneven instances of the batched configuration (o in [8, 24], v in [80, 240],
+    naux = 3v): contraction of all instances by one grouped persistent launch replayed
+    from a hipGraph, against one autotuned plan per instance launched one after another."""
+    import torch
+
+    import paper_2603_20912_amd as P
+    import ppl_synth
+
+    shapes = ppl_synth.batched_shapes(32, seed=4)
+    tup = [(d["o"], d["v"], d["naux"]) for d in shapes]
+    flops = sum(nominal(*t)["contract"] for t in tup)
+    out = {"instances": len(tup), "shapes": tup, "useful_contract_flops": flops}
+    stream = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    with torch.cuda.stream(stream):
+        for prec in ("fp64", "fp32"):
+            seq_ms = 0.0
+            for d, (o, v, naux) in zip(shapes, tup):
+                sysd = ppl_synth.make_system(o, v, naux, d["seed"])
+                L = torch.from_numpy(sysd["L"]).cuda()
+                t = torch.from_numpy(ppl_synth.make_amplitudes(o, v, d["seed"] + 5000)).cuda()
+                eng = P.PPL(o, v, naux, prec=prec, stream=stream)
+                eng.build(L)
+                eng.autotune(reps=2)
+                R = eng.contract(t)
+                e0.record(stream)
+                for _ in range(reps):
+                    eng.contract(t, R)
+                e1.record(stream)
+                e1.synchronize()
+                seq_ms += e0.elapsed_time(e1) / reps
+                eng.close()
+                del L, t, R, eng
+            torch.cuda.empty_cache()
+            b = P.Batch(tup, prec=prec, stream=stream)
+            Ls, ts = [], []
+            for d, (o, v, naux) in zip(shapes, tup):
+                Ls.append(torch.from_numpy(ppl_synth.make_system(o, v, naux, d["seed"])["L"]).cuda())
+                ts.append(torch.from_numpy(ppl_synth.make_amplitudes(o, v, d["seed"] + 5000)).cuda())
+            Rs = [torch.empty_like(t) for t in ts]
+            stream.synchronize()
+            t0 = time.perf_counter()
+            b.build(Ls)
+            stream.synchronize()
+            build_s = time.perf_counter() - t0
+            b.contract(ts, Rs)
+            e0.record(stream)
+            for _ in range(reps):
+                b.contract(ts, Rs)
+            e1.record(stream)
+            e1.synchronize()
+            model_ms = e0.elapsed_time(e1) / reps
+            b.autotune(reps=2)
+            b.contract(ts, Rs)
+            e0.record(stream)
+            for _ in range(reps):
+                b.contract(ts, Rs)
+            e1.record(stream)
+            e1.synchronize()
+            eager_ms = e0.elapsed_time(e1) / reps
+            b.capture(ts, Rs)
+            b.replay()
+            e0.record(stream)
+            for _ in range(reps):
+                b.replay()
+            e1.record(stream)
+            e1.synchronize()
+            graph_ms = e0.elapsed_time(e1) / reps
+            out[prec] = {"graph_ms": round(graph_ms, 3), "eager_grouped_ms": round(eager_ms, 3),
+                         "eager_grouped_model_tiles_ms": round(model_ms, 3),
+                         "sequential_ms": round(seq_ms, 3), "graph_tflops": round(flops / graph_ms / 1e9, 2),
+                         "sequential_tflops": round(flops / seq_ms / 1e9, 2),
+                         "speedup_vs_sequential": round(seq_ms / graph_ms, 3), "build_s": round(build_s, 3)}
+            print(json.dumps({prec: out[prec]}), file=sys.stderr, flush=True)
+            b.close()
+            del b, Ls, ts, Rs
+            torch.cuda.empty_cache()
+    print(json.dumps({"study": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,11 +230,14 @@ def main():
                     help="tile_plus,splits_plus,tile_minus,splits_minus instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
-    ap.add_argument("--study", default="", help="c3: time-to-1e-7 study at (40, 400, 1200)")
+    ap.add_argument("--study", default="", help="c3: time-to-1e-7 study at (40, 400, 1200); "
+                    "batched: the 32 uneven instances, grouped graph launch vs one plan each")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2603_20912_amd", "weights", "mlp_start.f32"))
     args = ap.parse_args()
     if args.study == "c3":
         return study_c3(args)
+    if args.study == "batched":
+        return study_batched(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(every box has a single MI355X); run with --gpus 1", file=sys.stderr)

@@ -267,7 +267,13 @@ int ppl_batch_query(ppl_batch_t batch, uint64_t* workspace_bytes, int32_t* n_ite
 int ppl_batch_bind_workspace(ppl_batch_t batch, void* dptr, uint64_t bytes);
 /* L: host array of n device pointers, one Cholesky tensor per instance */
 int ppl_batch_build(ppl_batch_t batch, const double* const* L);
-/* per-instance tile choice of the grouped launch by timing each candidate (synchronous) */
+/*
+ * Tile choice of the grouped launch, timed on the launch itself with HIP events
+ * (synchronous; operand values do not matter). Candidates: the model's tile for
+ * every instance GEMM (the default before autotuning: least row padding times the
+ * tile's measured throughput), and for each grouped tile t, t for every GEMM whose
+ * occupied-pair rows it pads by at most a quarter. The fastest assignment is kept.
+ */
 int ppl_batch_autotune(ppl_batch_t batch, int32_t reps);
 /* t2, R: host arrays of n device pointers; R_k = PPL_k(t2_k) */
 int ppl_batch_contract(ppl_batch_t batch, const double* const* t2, double* const* R);

@@ -1064,11 +1064,13 @@ struct ppl_batch_s {
   std::vector<ppl_plan_t> plans;
   std::vector<uint64_t> offs;
   uint64_t need = 0;
-  ppl::Region groups_r, items_r, counter_r;
+  ppl::Region groups_r, items_r, counter_r;   // counter_r: queue counters, then the queue starts
+  std::vector<int> q_begin;                   // host copy of the queue starts (kept for the async copy)
   int64_t max_items = 0;
   char* ws = nullptr;
   std::vector<ppl::GroupDesc> groups;
   std::vector<int4> items;
+  std::vector<int> gtile;                     // grouped tile per instance GEMM (2k: R+, 2k+1: R-), -1 = model
   bool built = false, prepared = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1081,29 +1083,21 @@ static int batch_check(ppl_batch_t b) {
   return PPL_OK;
 }
 
-// model choice among the grouped tiles: least padding of the occupied-pair rows, then the larger tile
-static int grouped_default_tile(int64_t rows) {
-  int best = 5;
-  double best_eff = -1.0;
-  for (int t = 0; t < contract_tile_count(); ++t) {
-    if (!grouped_tile_ok(t)) continue;
-    int bm, bn;
-    grouped_tile_dims(t, &bm, &bn);
-    const double eff = (double)rows / (double)((rows + bm - 1) / bm * bm) + 1e-6 * bm;
-    if (eff > best_eff) {
-      best_eff = eff;
-      best = t;
-    }
-  }
-  return best;
-}
+
+// byte offset of the queue start table inside the batch's counter region
+constexpr uint64_t kQueueBeginOffset = 64;
+static_assert(kGroupedQueues * sizeof(int) <= kQueueBeginOffset &&
+              kQueueBeginOffset + (kGroupedQueues + 1) * sizeof(int) <= 256, "counter region layout");
 
 static int batch_prepare(ppl_batch_t b) {
   b->groups.clear();
   b->items.clear();
   const int KC = kc_of_prec(b->prec);
-  struct Item { int4 w; double work; };
-  std::vector<Item> its;
+  // a column group: every row tile of one column tile of one instance GEMM (they read
+  // the same V rows, so they go to one XCD queue and are handed out back to back)
+  struct Col { int gi; int n0, bm; int64_t M; double work; };
+  std::vector<Col> cols;
+  int64_t n_items = 0;
   for (int k = 0; k < b->n; ++k) {
     ppl_plan_t p = b->plans[k];
     OperandSet& s = p->ops[0];
@@ -1111,12 +1105,12 @@ static int batch_prepare(ppl_batch_t b) {
       const bool plus = which == 0;
       const int64_t M = plus ? p->Np : p->Nm, N = plus ? p->Pp : p->Pm, ld = plus ? p->ldp : p->ldm;
       if (M <= 0 || N <= 0) continue;
-      int tile = plus ? p->tile_contract : p->tile_m;
-      if (!grouped_tile_ok(tile)) tile = grouped_default_tile(M);
+      const int forced = (int)b->gtile.size() > 2 * k + which ? b->gtile[2 * k + which] : -1;
+      const int tile = forced >= 0 ? forced : grouped_choose_tile(b->prec, M);
       GroupDesc g;
-      g.A = at<void>(p, plus ? s.sp : s.am);
-      g.B = at<void>(p, plus ? s.vp : s.vm);
-      g.C = at<void>(p, plus ? p->rp : p->rm);
+      g.a_off = at<char>(p, plus ? s.sp : s.am) - b->ws;
+      g.b_off = at<char>(p, plus ? s.vp : s.vm) - b->ws;
+      g.c_off = at<char>(p, plus ? p->rp : p->rm) - b->ws;
       g.M = M;
       g.N = N;
       g.nk = ld / KC;
@@ -1127,20 +1121,39 @@ static int batch_prepare(ppl_batch_t b) {
       b->groups.push_back(g);
       int bm, bn;
       grouped_tile_dims(tile, &bm, &bn);
-      for (int64_t mt = 0; mt * bm < M; ++mt)
-        for (int64_t nt = 0; nt * bn < N; ++nt)
-          its.push_back({int4{gi, (int)(mt * bm), (int)(nt * bn), 0}, (double)bm * bn * g.nk});
+      const int64_t n_mt = (M + bm - 1) / bm;
+      for (int64_t nt = 0; nt * bn < N; ++nt) {
+        cols.push_back({gi, (int)(nt * bn), bm, M, (double)n_mt * bm * bn * g.nk});
+        n_items += n_mt;
+      }
     }
   }
-  if ((int64_t)its.size() > b->max_items) return fail(PPL_E_ARG, "too many batch items");
-  std::stable_sort(its.begin(), its.end(), [](const Item& x, const Item& y) { return x.work > y.work; });
-  for (const Item& it : its) b->items.push_back(it.w);
+  if (n_items > b->max_items) return fail(PPL_E_ARG, "too many batch items");
+  // longest column groups first, each to the least loaded queue; a queue runs its
+  // groups in that order
+  std::stable_sort(cols.begin(), cols.end(), [](const Col& x, const Col& y) { return x.work > y.work; });
+  std::vector<std::vector<int4>> q(kGroupedQueues);
+  double load[kGroupedQueues] = {0};
+  for (const Col& c : cols) {
+    int qi = 0;
+    for (int j = 1; j < kGroupedQueues; ++j)
+      if (load[j] < load[qi]) qi = j;
+    for (int64_t m0 = 0; m0 < c.M; m0 += c.bm) q[qi].push_back(int4{c.gi, (int)m0, c.n0, 0});
+    load[qi] += c.work;
+  }
+  b->q_begin.assign(1, 0);
+  for (int j = 0; j < kGroupedQueues; ++j) {
+    b->items.insert(b->items.end(), q[j].begin(), q[j].end());
+    b->q_begin.push_back((int)b->items.size());
+  }
   if (!b->groups.empty())
     PPL_HIP_TRY(hipMemcpyAsync(b->ws + b->groups_r.off, b->groups.data(), b->groups.size() * sizeof(GroupDesc),
                                hipMemcpyHostToDevice, b->stream));
   if (!b->items.empty())
     PPL_HIP_TRY(hipMemcpyAsync(b->ws + b->items_r.off, b->items.data(), b->items.size() * sizeof(int4),
                                hipMemcpyHostToDevice, b->stream));
+  PPL_HIP_TRY(hipMemcpyAsync(b->ws + b->counter_r.off + kQueueBeginOffset, b->q_begin.data(),
+                             b->q_begin.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
   PPL_HIP_TRY(hipStreamSynchronize(b->stream));
   b->prepared = true;
   return PPL_OK;
@@ -1158,8 +1171,9 @@ static int batch_enqueue(ppl_batch_t b, const double* const* t2, double* const* 
   }
   const int n_items = (int)b->items.size();
   const int grid = n_items < 512 ? n_items : 512;
-  PPL_TRY(gemm_grouped(b->stream, b->prec, reinterpret_cast<const GroupDesc*>(b->ws + b->groups_r.off),
+  PPL_TRY(gemm_grouped(b->stream, b->prec, b->ws, reinterpret_cast<const GroupDesc*>(b->ws + b->groups_r.off),
                        reinterpret_cast<const int4*>(b->ws + b->items_r.off), n_items,
+                       reinterpret_cast<const int*>(b->ws + b->counter_r.off + kQueueBeginOffset),
                        reinterpret_cast<int*>(b->ws + b->counter_r.off), grid));
   for (int k = 0; k < b->n; ++k) {
     ppl_plan_t p = b->plans[k];
@@ -1264,9 +1278,58 @@ int ppl_batch_autotune(ppl_batch_t b, int32_t reps) {
   g_err[0] = 0;
   PPL_TRY(batch_check(b));
   if (!b->built) return fail(PPL_E_STATE, "build the batch before autotuning");
-  for (int k = 0; k < b->n; ++k) PPL_TRY(autotune_impl(b->plans[k], reps, nullptr, true));
+  if (reps < 1) return fail(PPL_E_ARG, "reps must be >= 1");
   batch_drop_graph(b);
-  return batch_prepare(b);
+  // Policies timed on the real grouped launch (operand values do not matter): the
+  // model's tile for every GEMM, and for each grouped tile t, t wherever it pads the
+  // occupied-pair rows by at most a quarter (the model's tile elsewhere).
+  const int nt = contract_tile_count();
+  std::vector<int> best_tiles(2 * b->n, -1);
+  double best_ms = 1e300;
+  hipEvent_t e0, e1;
+  PPL_HIP_TRY(hipEventCreate(&e0));
+  PPL_HIP_TRY(hipEventCreate(&e1));
+  int rc = PPL_OK;
+  for (int pol = -1; pol < nt && rc == PPL_OK; ++pol) {
+    if (pol >= 0 && !grouped_tile_ok(pol)) continue;
+    b->gtile.assign(2 * b->n, -1);
+    if (pol >= 0) {
+      int bm, bn;
+      grouped_tile_dims(pol, &bm, &bn);
+      for (int k = 0; k < b->n; ++k)
+        for (int which = 0; which < 2; ++which) {
+          const int64_t M = which == 0 ? b->plans[k]->Np : b->plans[k]->Nm;
+          if (M > 0 && (double)M / (double)((M + bm - 1) / bm * bm) >= 0.75) b->gtile[2 * k + which] = pol;
+        }
+    }
+    if ((rc = batch_prepare(b)) != PPL_OK) break;
+    auto launch = [&]() {
+      const int n_items = (int)b->items.size();
+      return gemm_grouped(b->stream, b->prec, b->ws, reinterpret_cast<const GroupDesc*>(b->ws + b->groups_r.off),
+                          reinterpret_cast<const int4*>(b->ws + b->items_r.off), n_items,
+                          reinterpret_cast<const int*>(b->ws + b->counter_r.off + kQueueBeginOffset),
+                          reinterpret_cast<int*>(b->ws + b->counter_r.off), n_items < 512 ? n_items : 512);
+    };
+    if ((rc = launch()) != PPL_OK) break;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = fail(PPL_E_HIP, "event record failed"); break; }
+    for (int r = 0; r < reps && rc == PPL_OK; ++r) rc = launch();
+    if (rc != PPL_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = fail(PPL_E_HIP, "event timing failed");
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_tiles = b->gtile;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->gtile = best_tiles;
+  const int rc2 = batch_prepare(b);
+  return rc != PPL_OK ? rc : rc2;
 }
 
 int ppl_batch_contract(ppl_batch_t b, const double* const* t2, double* const* R) {

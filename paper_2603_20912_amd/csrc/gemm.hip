@@ -1193,7 +1193,27 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 // fixed grid of workgroups pulls (group, row tile, column tile) items from a
 // queue sorted longest-first; each group carries its own tile shape. Every
 // workgroup leaves the loop once the queue counter passes the item count.
-bool grouped_tile_ok(int tile) { return tile == 1 || tile == 2 || (tile >= 5 && tile <= 8); }
+bool grouped_tile_ok(int tile) { return (tile >= 0 && tile <= 2) || (tile >= 5 && tile <= 8); }
+
+// the model's choice among the grouped tiles: the batch fills the device, so only the
+// padding of the occupied-pair rows and the measured per-tile throughput count
+int grouped_choose_tile(int prec, int64_t rows) {
+  const int pi = prec == PPL_FP64 ? 0 : (prec == PPL_FP32 ? 1 : 2);
+  int best = 5;
+  double best_score = -1.0;
+  for (int t = 0; t < kNumContract; ++t) {
+    if (!grouped_tile_ok(t)) continue;
+    const int bm = kContract[t].bm();
+    const double score = (double)rows / (double)((rows + bm - 1) / bm * bm) * kTileEff[pi][t];
+    if (score > best_score + 1e-9) {
+      best_score = score;
+      best = t;
+    }
+  }
+  return best;
+}
+
+typedef __attribute__((address_space(1))) char global_char_t;
 
 template <class T>
 struct GroupedLds {       // LDS of the largest allowed tile (208 x 64 rows staged, 272 in all)
@@ -1202,48 +1222,65 @@ struct GroupedLds {       // LDS of the largest allowed tile (208 x 64 rows stag
 };
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
-__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, char* smem) {
+__device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, char* smem, global_char_t* base) {
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
   static_assert(G::LDS_BYTES <= GroupedLds<T>::bytes, "tile does not fit the grouped LDS buffer");
   static_assert(G::NT == 256, "grouped tiles use 256 threads");
   TileJob job{m0, n0, 0, g.nk, 0};
-  EpiStore<T> epi{(T*)g.C, g.ldc, 0, g.M, g.N, 1.0, 0.0, 0};
+  // operands addressed from a base pointer typed as global memory: generic pointers
+  // (loaded from memory, or passed to a function that is not inlined) give flat loads,
+  // which also count against the LDS wait counter and serialize the chunk pipeline
+  const T* A = (const T*)(base + g.a_off);
+  const T* B = (const T*)(base + g.b_off);
+  EpiStore<T> epi{(T*)(base + g.c_off), g.ldc, 0, g.M, g.N, 1.0, 0.0, 0};
   T* s = reinterpret_cast<T*>(smem);
-  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, g.M, g.N, (const T*)g.A, g.lda, (const T*)g.B, g.ldb, epi,
+  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, g.M, g.N, A, g.lda, B, g.ldb, epi,
                                              s, s + G::BUF_A, s + 2 * G::BUF_A, s + 2 * G::BUF_A + G::BUF_B);
 }
 
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-gemm_grouped_kernel(const GroupDesc* __restrict__ groups, const int4* __restrict__ items, int n_items,
-                    int* counter) {
+gemm_grouped_kernel(char* base, const GroupDesc* __restrict__ groups, const int4* __restrict__ items,
+                    const int* __restrict__ q_begin, int* counters) {
   constexpr int KC = GroupedLds<T>::KC;
   __shared__ __attribute__((aligned(16))) char smem[GroupedLds<T>::bytes];
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it >= n_items) break;
-    const int4 w = items[it];
-    const GroupDesc g = groups[w.x];
-    switch (g.cfg) {
-      case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, smem); break;
-      case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, smem); break;
-      case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
-      case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
-      case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
-      default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, smem); break;
+  global_char_t* const gbase = (global_char_t*)base;
+  // queue q holds items [q_begin[q], q_begin[q + 1]); a workgroup drains the queue of
+  // its own XCD first, then helps the others in turn, and leaves once all are empty
+  const int x0 = (int)(blockIdx.x % kGroupedQueues);
+  for (int qi = 0; qi < kGroupedQueues; ++qi) {
+    const int q = (x0 + qi) % kGroupedQueues;
+    const int b = q_begin[q], e = q_begin[q + 1];
+    for (;;) {
+      if (threadIdx.x == 0) s_item = b + atomicAdd(&counters[q], 1);
+      __syncthreads();
+      const int it = s_item;
+      __syncthreads();
+      if (it >= e) break;
+      const int4 w = items[it];
+      const GroupDesc g = groups[w.x];
+      switch (g.cfg) {
+        case 0: grouped_tile<T, 7, 2, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
+        case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, smem, gbase); break;
+        case 2: grouped_tile<T, 13, 1, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
+        case 5: grouped_tile<T, 6, 2, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
+        case 6: grouped_tile<T, 2, 2, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
+        case 7: grouped_tile<T, 3, 2, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
+        default: grouped_tile<T, 4, 2, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
+      }
     }
   }
 }
 
-__global__ void reset_counter_kernel(int* c) { *c = 0; }
+__global__ void reset_counters_kernel(int* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
 
 // tile sizes a grouped item of `tile` covers (must match grouped_tile above)
 void grouped_tile_dims(int tile, int* bm, int* bn) {
   switch (tile) {
+    case 0: *bm = 112; *bn = 128; break;
     case 1: *bm = 128; *bn = 128; break;
     case 2: *bm = 208; *bn = 64; break;
     case 5: *bm = 96; *bn = 128; break;
@@ -1253,15 +1290,17 @@ void grouped_tile_dims(int tile, int* bm, int* bn) {
   }
 }
 
-int gemm_grouped(hipStream_t s, int prec, const GroupDesc* groups, const int4* items, int n_items, int* counter,
-                 int grid) {
+int gemm_grouped(hipStream_t s, int prec, char* base, const GroupDesc* groups, const int4* items, int n_items,
+                 const int* q_begin, int* counters, int grid) {
   if (n_items <= 0) return PPL_OK;
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, counters, kGroupedQueues);
   PPL_HIP_TRY(hipGetLastError());
   if (prec == PPL_FP64)
-    hipLaunchKernelGGL(gemm_grouped_kernel<double>, dim3(grid), dim3(256), 0, s, groups, items, n_items, counter);
+    hipLaunchKernelGGL(gemm_grouped_kernel<double>, dim3(grid), dim3(256), 0, s, base, groups, items, q_begin,
+                       counters);
   else if (prec == PPL_FP32)
-    hipLaunchKernelGGL(gemm_grouped_kernel<float>, dim3(grid), dim3(256), 0, s, groups, items, n_items, counter);
+    hipLaunchKernelGGL(gemm_grouped_kernel<float>, dim3(grid), dim3(256), 0, s, base, groups, items, q_begin,
+                       counters);
   else
     return fail(PPL_E_UNSUPPORTED, "grouped contraction supports FP64 and FP32");
   PPL_HIP_TRY(hipGetLastError());

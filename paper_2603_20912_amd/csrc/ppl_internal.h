@@ -169,17 +169,20 @@ constexpr int64_t kStreamKMaxGrid = 1024;   // stream-K workgroups at most (part
 constexpr int64_t kStreamKMinChunks = 8;    // and at least this many K chunks per workgroup
 
 // grouped persistent contraction (batched instances)
-struct GroupDesc {
-  const void* A;         // S' or A' rows [M][lda]
-  const void* B;         // V+ or V- rows [N][ldb]
-  void* C;               // R+ or R- [M][ldc]
+struct GroupDesc {       // byte offsets from the launch's base pointer (the batch workspace)
+  int64_t a_off;         // S' or A' rows [M][lda]
+  int64_t b_off;         // V+ or V- rows [N][ldb]
+  int64_t c_off;         // R+ or R- [M][ldc]
   int64_t M, N, nk, lda, ldb, ldc;
   int cfg, pad;
 };
 bool grouped_tile_ok(int tile);
+int grouped_choose_tile(int prec, int64_t rows);
 void grouped_tile_dims(int tile, int* bm, int* bn);
-int gemm_grouped(hipStream_t s, int prec, const GroupDesc* groups, const int4* items, int n_items, int* counter,
-                 int grid);
+// one work queue per XCD (workgroups are dealt to the XCDs round robin)
+constexpr int kGroupedQueues = 8;
+int gemm_grouped(hipStream_t s, int prec, char* base, const GroupDesc* groups, const int4* items, int n_items,
+                 const int* q_begin, int* counters, int grid);
 
 // Integral build G[pair(a,b) - pair(a0,a0)][c][d] = sum_P Xt[(a,c)][P] Xt[(b,d)][P]
 // for a in [a0, a1), b in [a, v).
