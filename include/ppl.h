@@ -242,10 +242,15 @@ int ppl_set_contract_config(ppl_plan_t plan, int32_t tile_plus, int32_t splits_p
                             int32_t tile_minus, int32_t splits_minus);
 
 /*
- * ppl_autotune: time every (tile, split-K) candidate of both contraction GEMMs
- * `reps` times on the bound workspace with HIP events (V+- must be built;
- * operand values do not matter) and keep the fastest of each. Synchronous.
- * best_ms (optional, 2 doubles) receives the winning average times.
+ * ppl_autotune: time every (tile, K decomposition) candidate of both contraction
+ * GEMMs `reps` times on the bound workspace with HIP events (V+- must be built;
+ * operand values do not matter), after a few untimed launches that bring the
+ * device to its steady clock; the four fastest are timed again over three
+ * interleaved rounds and the fastest on average is kept. The operands are the
+ * ones in the workspace (the last packed amplitudes): the matrix-core rate depends
+ * on operand values through the power draw, so tune after a contraction of
+ * representative amplitudes. Synchronous. best_ms (optional, 2 doubles)
+ * receives the winning average times.
  */
 int ppl_autotune(ppl_plan_t plan, int32_t reps, double* best_ms);
 

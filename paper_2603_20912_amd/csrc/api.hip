@@ -163,7 +163,7 @@ static void make_tile_tables(ppl_plan_t p) {
   }
 }
 
-int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms, bool grouped_only);
+int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms);
 
 static int check_plan(ppl_plan_t p) {
   if (!p) return fail(PPL_E_ARG, "null plan");
@@ -727,12 +727,12 @@ int ppl_set_contract_config(ppl_plan_t p, int32_t tp, int32_t sp, int32_t tm, in
   return PPL_OK;
 }
 
-int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) { return autotune_impl(p, reps, best_ms, false); }
+int ppl_autotune(ppl_plan_t p, int32_t reps, double* best_ms) { return autotune_impl(p, reps, best_ms); }
 
 }  // extern "C"
 
 namespace ppl {
-int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms, bool grouped_only) {
+int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms) {
   g_err[0] = 0;
   PPL_TRY(check_bound(p));
   if (reps < 1) return fail(PPL_E_ARG, "reps must be >= 1");
@@ -756,35 +756,54 @@ int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms, bool grouped_only
     const void* V = at<void>(p, plus ? s.vp : s.vm);
     const void* V_lo = (plus ? s.vp_lo : s.vm_lo).bytes ? at<void>(p, plus ? s.vp_lo : s.vm_lo) : nullptr;
     void* C = at<void>(p, plus ? p->rp : p->rm);
-    for (int t = 0; t < nt && rc == PPL_OK; ++t) {
-      if (grouped_only && !grouped_tile_ok(t)) continue;
-      // split counts 1 .. kMaxSplits, then stream-K (0)
-      for (int k = 1; k <= (grouped_only ? 1 : kMaxSplits + 1) && rc == PPL_OK; ++k) {
+    auto run = [&](int t, int sp) {
+      return gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld, p->part.bytes);
+    };
+    // average over n launches after one untimed launch
+    auto timed = [&](int t, int sp, int n, double& ms_out) {
+      PPL_TRY(run(t, sp));
+      PPL_HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < n; ++r) PPL_TRY(run(t, sp));
+      float ms = 0.f;
+      PPL_HIP_TRY(hipEventRecord(e1, st));
+      PPL_HIP_TRY(hipEventSynchronize(e1));
+      PPL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      ms_out = ms / n;
+      return PPL_OK;
+    };
+    // bring the device to its steady clock before the first candidate is timed
+    for (int r = 0; r < 8 && rc == PPL_OK; ++r) rc = run(plus ? p->tile_contract : p->tile_m, 1);
+    // every (tile, K decomposition): split counts 1 .. kMaxSplits, then stream-K (0)
+    struct Cand { double ms; int t, sp; };
+    std::vector<Cand> cands;
+    for (int t = 0; t < nt && rc == PPL_OK; ++t)
+      for (int k = 1; k <= kMaxSplits + 1 && rc == PPL_OK; ++k) {
         const int sp = k <= kMaxSplits ? k : 0;
         if (sp > 1 && contract_jobs(t, s.prec, Nr, Pr, ld, sp) == contract_jobs(t, s.prec, Nr, Pr, ld, sp - 1))
           continue;   // same effective split count as a smaller request
-        rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld,
-                           p->part.bytes);
-        if (rc != PPL_OK) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PPL_E_HIP, "event record failed"); break; }
-        for (int r = 0; r < reps && rc == PPL_OK; ++r)
-          rc = gemm_contract(st, s.prec, t, Nr, Pr, ld, A, A_lo, ld, V, V_lo, ld, C, ld, 0, sp, part, ld,
-                             p->part.bytes);
-        if (rc != PPL_OK) break;
-        float ms = 0.f;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          rc = fail(PPL_E_HIP, "event timing failed");
-          break;
-        }
-        const double avg = ms / reps;
-        if (avg < best[which]) {
-          best[which] = avg;
-          bt[which] = t;
-          bs[which] = sp;
-        }
+        double ms = 0.0;
+        rc = timed(t, sp, reps, ms);
+        cands.push_back({ms, t, sp});
       }
-    }
+    if (rc != PPL_OK) break;
+    // the four fastest again, interleaved over three rounds, so that a slow or fast
+    // moment of the device does not decide alone
+    std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    const size_t nf = std::min<size_t>(4, cands.size());
+    std::vector<double> tot(nf, 0.0);
+    for (int round = 0; round < 3 && rc == PPL_OK; ++round)
+      for (size_t c = 0; c < nf && rc == PPL_OK; ++c) {
+        double ms = 0.0;
+        rc = timed(cands[c].t, cands[c].sp, reps, ms);
+        tot[c] += ms;
+      }
+    if (rc != PPL_OK) break;
+    for (size_t c = 0; c < nf; ++c)
+      if (tot[c] / 3.0 < best[which]) {
+        best[which] = tot[c] / 3.0;
+        bt[which] = cands[c].t;
+        bs[which] = cands[c].sp;
+      }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -33,6 +33,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// 16 bytes as a native vector (register staging of K chunks; HIP's uint4 is a struct
+// with a union, which keeps loop-carried arrays of it in scratch memory)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ inline d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -198,10 +202,14 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
 #ifndef PPL_DIRECT_LDS
 #define PPL_DIRECT_LDS 0
 #endif
+#ifndef PPL_PREFETCH
+#define PPL_PREFETCH 0
+#endif
 constexpr int kLdsLayout = PPL_LDS_LAYOUT;
 constexpr int kFragVec = PPL_FRAG_VEC;
 constexpr int kSchedFence = PPL_SCHED_FENCE;
 constexpr int kDirectLds = PPL_DIRECT_LDS;   // 1: chunks go global -> LDS without registers (layout 1 only)
+constexpr int kPrefetch = PPL_PREFETCH;      // chunks in flight in registers: 1, 2, or 0 = per tile (below)
 static_assert(!kDirectLds || kLdsLayout == 1, "direct LDS loads need the unpadded swizzled layout");
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
@@ -382,6 +390,26 @@ __device__ __forceinline__ void tile_body_direct(const TileJob& job, int64_t M, 
   store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
 }
 
+// Fetch chunk c (relative to the job's first chunk) of the staged rows into registers,
+// and store such registers into one LDS buffer.
+template <class T, int NLA, int NLB, int KC>
+__device__ __forceinline__ void chunk_load(u32x4 (&ra)[NLA], u32x4 (&rb)[NLB], const T* const (&pa)[NLA],
+                                           const T* const (&pb)[NLB], int64_t c) {
+#pragma unroll
+  for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(pa[i] + c * KC);
+#pragma unroll
+  for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(pb[i] + c * KC);
+}
+
+template <class T, int NLA, int NLB>
+__device__ __forceinline__ void chunk_store(const u32x4 (&ra)[NLA], const u32x4 (&rb)[NLB], T* sA, T* sB,
+                                            const int (&oa)[NLA], const int (&ob)[NLB]) {
+#pragma unroll
+  for (int i = 0; i < NLA; ++i) *reinterpret_cast<u32x4*>(&sA[oa[i]]) = ra[i];
+#pragma unroll
+  for (int i = 0; i < NLB; ++i) *reinterpret_cast<u32x4*>(&sB[ob[i]]) = rb[i];
+}
+
 // One BM x BN tile of C over the K chunks [job.kc0, job.kc1); sA0 / sA1 (sB0 / sB1)
 // are the two LDS buffers of BM (BN) staged rows.
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
@@ -446,17 +474,54 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
   const int key = kLdsLayout == 0 ? 0 : (lane & 15) % VPR;
   const int64_t nk = job.kc1 - job.kc0;
 
+  // Two chunks in flight where the registers allow: every FP32 tile, and the FP64
+  // tiles whose accumulators, two register sets and fragments come to at most 150
+  // VGPRs by this count (the larger FP64 tiles spill with two sets; measured on gfx950).
+  constexpr int kRegEst = WM * WN * 8 + 2 * (NLA + NLB) * 4 + (WM + WN) * 4;
+  constexpr int kDepth = kPrefetch != 0 ? kPrefetch : ((sizeof(T) == 4 || kRegEst <= 150) ? 2 : 1);
+  if constexpr (kDepth == 2) {
+    // two register sets: at the top of step kt, LDS buffer kt & 1 holds chunk kt and
+    // register set (kt + 1) & 1 holds chunk kt + 1, loaded one step earlier
+    u32x4 ra0[NLA], rb0[NLB], ra1[NLA], rb1[NLB];
+    chunk_load<T, NLA, NLB, KC>(ra0, rb0, pa, pb, 0);
+    chunk_store<T, NLA, NLB>(ra0, rb0, sA0, sB0, oa, ob);
+    // (loads past the last chunk re-read the last one: always in bounds, never stored)
+    chunk_load<T, NLA, NLB, KC>(ra1, rb1, pa, pb, nk > 1 ? 1 : 0);
+    __syncthreads();
+    int64_t kt = 0;
+    for (; kt + 2 < nk; kt += 2) {
+      chunk_load<T, NLA, NLB, KC>(ra0, rb0, pa, pb, kt + 2);
+      consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0, sB0, arow, brow, fq, key);
+      chunk_store<T, NLA, NLB>(ra1, rb1, sA1, sB1, oa, ob);
+      __syncthreads();
+      chunk_load<T, NLA, NLB, KC>(ra1, rb1, pa, pb, kt + 3 < nk ? kt + 3 : nk - 1);
+      consume_chunk<T, WM, WN, KC, LDSR>(acc, sA1, sB1, arow, brow, fq, key);
+      chunk_store<T, NLA, NLB>(ra0, rb0, sA0, sB0, oa, ob);
+      __syncthreads();
+    }
+    if (kt + 1 < nk) {   // chunks kt (LDS buffer 0) and kt + 1 (register set 1) remain
+      consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0, sB0, arow, brow, fq, key);
+      chunk_store<T, NLA, NLB>(ra1, rb1, sA1, sB1, oa, ob);
+      __syncthreads();
+      consume_chunk<T, WM, WN, KC, LDSR>(acc, sA1, sB1, arow, brow, fq, key);
+    } else {
+      consume_chunk<T, WM, WN, KC, LDSR>(acc, sA0, sB0, arow, brow, fq, key);
+    }
+    store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
+    return;
+  }
+
   // chunk 0 straight into LDS buffer 0
   {
-    uint4 ra[NLA], rb[NLB];
+    u32x4 ra[NLA], rb[NLB];
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i]);
+    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(pa[i]);
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i]);
+    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(pb[i]);
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&sA0[oa[i]]) = ra[i];
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<u32x4*>(&sA0[oa[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&sB0[ob[i]]) = rb[i];
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<u32x4*>(&sB0[ob[i]]) = rb[i];
   }
   __syncthreads();
 
@@ -464,16 +529,16 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
   for (int64_t kt = 0; kt + 1 < nk; ++kt) {
     const int buf = (int)(kt & 1);
     const int64_t k1 = (kt + 1) * KC;
-    uint4 ra[NLA], rb[NLB];
+    u32x4 ra[NLA], rb[NLB];
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const uint4*>(pa[i] + k1);
+    for (int i = 0; i < NLA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(pa[i] + k1);
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const uint4*>(pb[i] + k1);
+    for (int i = 0; i < NLB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(pb[i] + k1);
     consume_chunk<T, WM, WN, KC, LDSR>(acc, buf ? sA1 : sA0, buf ? sB1 : sB0, arow, brow, fq, key);
 #pragma unroll
-    for (int i = 0; i < NLA; ++i) *reinterpret_cast<uint4*>(&(buf ? sA0 : sA1)[oa[i]]) = ra[i];
+    for (int i = 0; i < NLA; ++i) *reinterpret_cast<u32x4*>(&(buf ? sA0 : sA1)[oa[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < NLB; ++i) *reinterpret_cast<uint4*>(&(buf ? sB0 : sB1)[ob[i]]) = rb[i];
+    for (int i = 0; i < NLB; ++i) *reinterpret_cast<u32x4*>(&(buf ? sB0 : sB1)[ob[i]]) = rb[i];
     if constexpr (kSchedFence) {
       // order of this block: the global loads of the next chunk, then the LDS reads and
       // MFMAs of this chunk group by group, then the LDS stores (whose waits on the
