@@ -590,7 +590,13 @@ template <int WM, int WN, int WAVES_M, int WAVES_N, int KC>
 struct Bf3Geom {
   static constexpr int NT = 64 * WAVES_M * WAVES_N;
   static constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  static constexpr int LDSR = KC + 8;              // rows padded by 16 bytes
+  // unpadded rows; 16-byte vector kv of row r at slot kv ^ key(r), with key(r) =
+  // (r / 2) mod 4 for 64-byte rows and r mod 8 for rows of 128 bytes and more, so that
+  // the eight lanes of a 16-byte access phase (rows r .. r+7, one vector each) hit
+  // eight different 16-byte bank groups
+  static constexpr int LDSR = KC;
+  static constexpr int VPR = KC / 8;
+  __host__ __device__ static constexpr int key(int r) { return VPR >= 8 ? (r & 7) : ((r >> 1) & 3); }
   static constexpr int LDS_A = 2 * BM * LDSR, LDS_B = 2 * BN * LDSR;   // per plane, two buffers
 };
 
@@ -625,7 +631,7 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
     int64_t gr = m0 + r;
     if (gr > M - 1) gr = M - 1;
     ga[i] = gr * lda + kv * VEC + job.kc0 * KC;
-    oa[i] = r * LDSR + kv * VEC;
+    oa[i] = r * LDSR + (kv ^ Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>::key(r)) * VEC;
   }
 #pragma unroll
   for (int i = 0; i < NLB; ++i) {
@@ -635,7 +641,7 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
     int64_t gr = n0 + r;
     if (gr > N - 1) gr = N - 1;
     gb[i] = gr * ldb + kv * VEC + job.kc0 * KC;
-    ob[i] = r * LDSR + kv * VEC;
+    ob[i] = r * LDSR + (kv ^ Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>::key(r)) * VEC;
   }
   f4 acc[WM][WN], accx[WM][WN];
 #pragma unroll
@@ -646,10 +652,15 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
       accx[i][j] = f4{0, 0, 0, 0};
     }
 
-  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR + 8 * (lane >> 4);
-  const int brow = (wn * WN * 16 + (lane & 15)) * LDSR + 8 * (lane >> 4);
+  // fragment rows start at multiples of 16, so a row's swizzle key is that of lane & 15
+  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR;
+  const int brow = (wn * WN * 16 + (lane & 15)) * LDSR;
+  const int fsw = Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>::key(lane & 15);
+  static_assert(KC == 32 || KC % 64 == 0, "the swizzle permutes aligned groups of 4 (or 8) 16-byte vectors");
   const int64_t nk = job.kc1 - job.kc0;
 
+// element offset of this lane's 8-element fragment vector at K offset kk of a staged row
+#define PPL_BF3_COL(kk) (((((kk) >> 3) + (lane >> 4)) ^ fsw) * 8)
 #define PPL_BF3_LOAD(k0)                                                     \
   _Pragma("unroll") for (int i = 0; i < NLA; ++i) {                          \
     rah[i] = *reinterpret_cast<const uint4*>(Ah + ga[i] + (k0));             \
@@ -672,12 +683,12 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
   _Pragma("unroll") for (int kk = 0; kk < KC; kk += 32) {                                      \
     bf8 ah[WM], al[WM], bh[WN], bl[WN];                                                        \
     _Pragma("unroll") for (int i = 0; i < WM; ++i) {                                           \
-      ah[i] = *reinterpret_cast<const bf8*>(&sAh[(buf) * (BM * LDSR) + arow + i * 16 * LDSR + kk]);             \
-      al[i] = *reinterpret_cast<const bf8*>(&sAl[(buf) * (BM * LDSR) + arow + i * 16 * LDSR + kk]);             \
+      ah[i] = *reinterpret_cast<const bf8*>(&sAh[(buf) * (BM * LDSR) + arow + i * 16 * LDSR + PPL_BF3_COL(kk)]); \
+      al[i] = *reinterpret_cast<const bf8*>(&sAl[(buf) * (BM * LDSR) + arow + i * 16 * LDSR + PPL_BF3_COL(kk)]); \
     }                                                                                          \
     _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                           \
-      bh[j] = *reinterpret_cast<const bf8*>(&sBh[(buf) * (BN * LDSR) + brow + j * 16 * LDSR + kk]);             \
-      bl[j] = *reinterpret_cast<const bf8*>(&sBl[(buf) * (BN * LDSR) + brow + j * 16 * LDSR + kk]);             \
+      bh[j] = *reinterpret_cast<const bf8*>(&sBh[(buf) * (BN * LDSR) + brow + j * 16 * LDSR + PPL_BF3_COL(kk)]); \
+      bl[j] = *reinterpret_cast<const bf8*>(&sBl[(buf) * (BN * LDSR) + brow + j * 16 * LDSR + PPL_BF3_COL(kk)]); \
     }                                                                                          \
     _Pragma("unroll") for (int i = 0; i < WM; ++i)                                             \
     _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                           \
@@ -708,6 +719,7 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
 #undef PPL_BF3_LOAD
 #undef PPL_BF3_STORE
 #undef PPL_BF3_COMPUTE
+#undef PPL_BF3_COL
 
 #pragma unroll
   for (int i = 0; i < WM; ++i) {
@@ -992,7 +1004,8 @@ static int64_t streamk_grid(int64_t resident, int64_t iters) {
 
 uint64_t streamk_part_bytes(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad) {
   const TileCfg& c = kContract[tile];
-  const int64_t iters = ((Nrows + c.bm() - 1) / c.bm()) * ((Prows + c.bn() - 1) / c.bn()) * (Kpad / kc_of_prec(prec));
+  const int KC = prec == PPL_BF16X3 ? bf3_kc(c.bm(), c.bn()) : kc_of_prec(prec);
+  const int64_t iters = ((Nrows + c.bm() - 1) / c.bm()) * ((Prows + c.bn() - 1) / c.bn()) * (Kpad / KC);
   return (uint64_t)streamk_grid(kStreamKMaxGrid, iters) * 2 * c.bm() * c.bn() * (prec == PPL_FP64 ? 8 : 4);
 }
 
@@ -1073,12 +1086,12 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
           s, Nrows, Prows, Kpad, (const float*)S, lds_, (const float*)V, ldv, (float*)C, ldc, c_col0, partial,
           partial_bytes);
     if (prec == PPL_BF16X3)
-      return launch_streamk_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(
+      return launch_streamk_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(
           s, Nrows, Prows, Kpad, (const __bf16*)S, (const __bf16*)S_lo, lds_, (const __bf16*)V,
           (const __bf16*)V_lo, ldv, (float*)C, ldc, c_col0, partial, partial_bytes);
     return fail(PPL_E_ARG, "unknown precision %d", prec);
   }
-  const int KC = kc_of_prec(prec);
+  const int KC = prec == PPL_BF16X3 ? bf3_kc(BM, BN) : kc_of_prec(prec);
   const int64_t nk = Kpad / KC;
   if (splits < 1) splits = 1;
   if (splits > nk) splits = (int)nk;
@@ -1104,7 +1117,7 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
   } else if (prec == PPL_BF16X3) {
     EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
                                  : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
-    rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
+    rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
                                                   (const __bf16*)S_lo, lds_, (const __bf16*)V,
                                                   (const __bf16*)V_lo, ldv, epi, map);
   } else {
@@ -1154,7 +1167,7 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
 // Workgroups of one contraction launch for a (tile, splits) choice.
 int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits) {
   const TileCfg& c = kContract[tile];
-  const int KC = kc_of_prec(prec);
+  const int KC = prec == PPL_BF16X3 ? bf3_kc(c.bm(), c.bn()) : kc_of_prec(prec);
   const int64_t nk = Kpad / KC;
   if (splits > nk) splits = (int)nk;
   const int64_t kps = (nk + splits - 1) / splits;
@@ -1208,7 +1221,7 @@ static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpa
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
   MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
-  map.nk = Kpad / kc_of_prec(prec);
+  map.nk = Kpad / (prec == PPL_BF16X3 ? bf3_kc(BM, BN) : kc_of_prec(prec));
   if (prec == PPL_FP64) {
     const double* X = (const double*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<double> epi{(double*)G, M, N, v, a0};
@@ -1225,7 +1238,7 @@ static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpa
     const __bf16* Xh = (const __bf16*)Xt + (int64_t)a0 * v * ldx;
     const __bf16* Xl = (const __bf16*)Xt_lo + (int64_t)a0 * v * ldx;
     EpiBuild<float> epi{(float*)G, M, N, v, a0};
-    return launch_bf3<WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, Xh, Xl, ldx, Xh,
+    return launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, n_valid_tiles, M, N, Kpad, Xh, Xl, ldx, Xh,
                                                         Xl, ldx, epi, map);
   }
   return fail(PPL_E_ARG, "unknown precision %d", prec);

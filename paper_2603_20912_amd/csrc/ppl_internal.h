@@ -38,7 +38,13 @@ __host__ __device__ inline int pair_second(int packed) { return packed & 0xffff;
 constexpr int kKcF64 = PPL_KC64;
 constexpr int kKcF32 = 32;
 __host__ __device__ constexpr int kc_of_prec(int prec) { return prec == PPL_FP64 ? kKcF64 : kKcF32; }
-static_assert(64 % kKcF64 == 0 && 64 % kKcF32 == 0, "K chunk must divide the leading-dimension padding");
+// BF16x3 tiles stage 64 K elements per chunk (two MFMA k-steps between barriers) when
+// two workgroups still fit in the 160 KB of LDS (two buffers of both bf16 planes: 512
+// bytes per staged row), 32 otherwise: measured on gfx950, one workgroup per CU with
+// the longer chunk is slower than two with the shorter one
+__host__ __device__ constexpr int bf3_kc(int bm, int bn) { return 2 * (bm + bn) * 512 <= 160 * 1024 ? 64 : 32; }
+static_assert(64 % kKcF64 == 0 && 64 % kKcF32 == 0 && 64 % bf3_kc(0, 0) == 0,
+              "K chunk must divide the leading-dimension padding");
 
 __host__ __device__ inline int64_t pad_ld(int64_t k) { return (k + 63) / 64 * 64; }
 
