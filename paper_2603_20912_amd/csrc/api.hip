@@ -254,9 +254,11 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
   const void* sp_lo = s.sp_lo.bytes ? at<void>(p, s.sp_lo) : nullptr;
   const void* am = at<void>(p, s.am);
   const void* am_lo = s.am_lo.bytes ? at<void>(p, s.am_lo) : nullptr;
-  const int tile = p->tile_contract, tile_m = p->tile_m;
+  const bool primary = &s == &p->ops[0];
+  const int tile = primary ? p->tile_contract : s.tile_p, tile_m = primary ? p->tile_m : s.tile_m;
+  const int split_p = primary ? p->split_p : s.split_p, split_m = primary ? p->split_m : s.split_m;
   void* part = p->part.bytes ? at<void>(p, p->part) : nullptr;
-  if (std::max(p->split_p, p->split_m) > kMaxSplits ||
+  if (std::max(split_p, split_m) > kMaxSplits ||
       (uint64_t)std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8 > p->part.bytes ||
       (uint64_t)p->Np * p->ldp * 8 > p->rp.bytes)
     return fail(PPL_E_STATE, "contraction buffers smaller than the plan requires");
@@ -267,13 +269,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, fp * p->Pp);
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, p->Pp, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, 0, p->split_p, part, p->ldp, p->part.bytes));
+                            at<void>(p, p->rp), p->ldp, 0, split_p, part, p->ldp, p->part.bytes));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, fm * p->Pm);
     if (p->Nm > 0 && p->Pm > 0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, p->Pm, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, 0, p->split_m, part, p->ldm, p->part.bytes));
+                            at<void>(p, p->rm), p->ldm, 0, split_m, part, p->ldm, p->part.bytes));
     return PPL_OK;
   }
   if (!p->L_last) return fail(PPL_E_STATE, "streaming plan has no Cholesky vectors (call ppl_build_batch)");
@@ -284,13 +286,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, 2.0 * (double)p->Np * p->Pp * (double)(b.p1 - b.p0));
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, b.p1 - b.p0, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, b.p0, p->split_p, part, p->ldp, p->part.bytes));
+                            at<void>(p, p->rp), p->ldp, b.p0, split_p, part, p->ldp, p->part.bytes));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, 2.0 * (double)p->Nm * p->Pm * (double)(b.q1 - b.q0));
     if (p->Nm > 0 && b.q1 > b.q0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, b.q1 - b.q0, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, b.q0, p->split_m, part, p->ldm, p->part.bytes));
+                            at<void>(p, p->rm), p->ldm, b.q0, split_m, part, p->ldm, p->part.bytes));
   }
   return PPL_OK;
 }
@@ -422,6 +424,19 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
     if (p->Nm > 0) contract_choose(p->prec, p->Nm, p->Pm, p->ldm, kMaxSplits, &t, &sp);
     p->tile_m = t < 0 ? 0 : t;
     p->split_m = sp;
+    if (p->ops[1].present) {   // the FP64 copy gets the model's choice for FP64 operands
+      OperandSet& f = p->ops[1];
+      t = -1;
+      sp = 1;
+      contract_choose(PPL_FP64, p->Np, p->Pp, p->ldp, kMaxSplits, &t, &sp);
+      f.tile_p = t;
+      f.split_p = sp;
+      t = -1;
+      sp = 1;
+      if (p->Nm > 0) contract_choose(PPL_FP64, p->Nm, p->Pm, p->ldm, kMaxSplits, &t, &sp);
+      f.tile_m = t < 0 ? 0 : t;
+      f.split_m = sp;
+    }
   }
 
   uint64_t budget = d->hbm_budget;

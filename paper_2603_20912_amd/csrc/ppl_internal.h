@@ -79,6 +79,9 @@ struct OperandSet {
   Region sp, sp_lo;        // S' [N+][ldp]
   Region am, am_lo;        // A' [N-][ldm]
   bool built = false;      // resident V+- complete
+  // contraction tiles and K decompositions of the FP64 copy of a mixed plan (the
+  // primary set uses the plan's, which the autotuner and ppl_set_contract_config set)
+  int tile_p = 0, split_p = 1, tile_m = 0, split_m = 1;
 };
 
 struct Batch {
