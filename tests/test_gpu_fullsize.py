@@ -1,0 +1,96 @@
+"""GPU parity at the full sizes of the precision and learned-start configurations,
+(40, 400, 1200) and (30, 300, 900), on entries the oracle computes one by one
+(each from its own (ac|bd) slab), plus properties that hold at any size.
+
+Bounds: FP64 1e-12 of the largest sampled |R|. FP32 and BF16x3 accumulate over
+K = v(v+1)/2 = 80200 terms in FP32 (unit roundoff 6e-8; a random-walk growth of
+sqrt(K) ~ 283 gives ~2e-5), so they are held to 1e-4 of the largest |R|, which
+still fails any wrong index or dropped term by orders of magnitude.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import ppl_synth as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2603_20912_amd as P
+    return P
+
+
+def sample_idx(o, v, n, seed):
+    rng = np.random.default_rng(seed)
+    idx = [tuple(int(x) for x in (rng.integers(o), rng.integers(o), rng.integers(v), rng.integers(v)))
+           for _ in range(n)]
+    return idx + [(0, 0, 0, 0), (o - 1, o - 1, v - 1, v - 1), (0, o - 1, v - 1, 0), (1, 0, 2, 2)]
+
+
+@pytest.fixture(scope="module")
+def c3():
+    o, v, naux = 40, 400, 1200
+    s = S.make_system(o, v, naux, 2, "contractive")
+    t = S.make_amplitudes(o, v, 3)
+    idx = sample_idx(o, v, 40, 11)
+    ref = O.ppl_sampled(s["L"], o, t, idx)
+    return s, t, idx, ref
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 1e-4), ("bf16x3", 1e-4)])
+def test_c3_sampled_entries(P, c3, prec, bound):
+    s, t, idx, ref = c3
+    o, v, naux = s["o"], s["v"], s["naux"]
+    say(f"contract {prec} (40,400,1200) sampled, planner's configuration")
+    eng = P.PPL(o, v, naux, prec=prec)
+    assert eng.info["resident"] == 1
+    L = torch.from_numpy(s["L"]).cuda()
+    eng.build(L)
+    td = torch.from_numpy(t).cuda()
+    R = eng.contract(td)
+    torch.cuda.synchronize()
+    got = np.array([R[k].item() for k in idx])
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale
+    say(f"  max |R_gpu - R_oracle| / max |R| = {err:.2e}")
+    assert err < bound
+    # pair symmetry R_ij^ab = R_ji^ba (both come from one packed entry)
+    Rt = R.permute(1, 0, 3, 2)
+    assert (torch.linalg.norm(R - Rt) / torch.linalg.norm(R)).item() < 1e-14
+    eng.close()
+    del L, td, R, Rt
+    torch.cuda.empty_cache()
+
+
+def test_learned_config_size_sampled(P):
+    o, v, naux = 30, 300, 900
+    say("contract fp64 (30,300,900) sampled, MP2 amplitudes")
+    s = S.make_system(o, v, naux, 3000, "contractive")
+    L = torch.from_numpy(s["L"]).cuda()
+    eng = P.PPL(o, v, naux)
+    tm, _ = eng.mp2(L, torch.from_numpy(s["e_occ"]).cuda(), torch.from_numpy(s["e_vir"]).cuda())
+    eng.build(L)
+    R = eng.contract(tm)
+    torch.cuda.synchronize()
+    idx = sample_idx(o, v, 40, 12)
+    t_host = tm.cpu().numpy()
+    ref = O.ppl_sampled(s["L"], o, t_host, idx)
+    got = np.array([R[k].item() for k in idx])
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    # the MP2 amplitudes themselves against the oracle's definition at the same entries
+    V, D = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
+    tref = np.array([V[k] / D[k] for k in idx])
+    assert np.abs(np.array([t_host[k] for k in idx]) - tref).max() < 1e-12 * np.abs(tref).max()
+    eng.close()
