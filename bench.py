@@ -220,6 +220,80 @@ def study_batched(args):
     print(json.dumps({"study": out}), flush=True)
 
 
+def study_paper(args):
+    """One FP64 PPL evaluation at the largest shape of the paper's contraction benchmark
+    (Tab. xc-split: N = 800, nocc = 100, nvec = 5N = 4000, nvir = 700), on one GPU.
+
+    V+- would take about 960 GB, so the plan streams: each row batch is built from the
+    Cholesky vectors and contracted at once, with t, R and L resident in HBM. Inputs are
+    drawn on the device (same recipe as the small configurations, contractive amplitude).
+    Timed: whole ppl_contract calls (staging, every batch's build and contraction,
+    packing and unpacking), after one untimed call."""
+    import torch
+
+    import paper_2603_20912_amd as P
+    import ppl_synth
+
+    o, v, naux = 100, 700, 4000
+    f = nominal(o, v, naux)
+    dense = {"build": 2.0 * naux * v ** 4, "contract": 2.0 * o * o * v ** 4}
+    out = {"shape": {"N": o + v, "nocc": o, "nvir": v, "nvec": naux}, "precision": "fp64",
+           "useful_flops": f["build"] + f["contract"], "dense_flops": dense["build"] + dense["contract"],
+           "paper_seconds_C_split": {"CuPy GH200": 306.6, "PyTorch GH200": 355.9, "CuPy H100": 461.5,
+                                     "PyTorch H100": 330.5}}
+    t0 = time.perf_counter()
+    sysd = ppl_synth.make_system_device(o, v, naux, 21)
+    t = ppl_synth.make_amplitudes_device(o, v, 22)
+    R = torch.empty_like(t)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps({"inputs_s": round(time.perf_counter() - t0, 2),
+                      "free_GB": torch.cuda.mem_get_info()[0] / 1e9}), file=sys.stderr, flush=True)
+    eng = P.PPL(o, v, naux, prec="fp64", build_scratch=64 << 30)
+    info = eng.info
+    out["plan"] = {k: info[k] for k in ("resident", "n_batches", "max_step_pairs", "workspace_bytes",
+                                        "tile_build", "tile_contract", "splits_contract",
+                                        "tile_contract_minus", "splits_contract_minus")}
+    print(json.dumps({"plan": out["plan"]}), file=sys.stderr, flush=True)
+    eng.build(sysd["L"])
+    times = []
+    for k in range(1 + args.steps):
+        if k == 1:
+            eng.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.contract(t, R)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print(json.dumps({"evaluation": k, "seconds": round(times[-1], 3), "timed": k > 0}),
+              file=sys.stderr, flush=True)
+    prof = eng.profile_read()
+    eng.profile(False)
+    eng.close()
+    del eng
+    torch.cuda.empty_cache()
+    sec = sum(times[1:]) / len(times[1:])
+    # pair symmetry R_ij^ab = R_ji^ba, one occupied row at a time (R is 39 GB)
+    num = den = 0.0
+    for i in range(o):
+        d = R[i] - R[:, i].transpose(1, 2)
+        num += (d * d).sum().item()
+        den += (R[i] * R[i]).sum().item()
+    sym = (num / den) ** 0.5
+    out.update({"seconds": round(sec, 3), "seconds_each": [round(x, 3) for x in times[1:]],
+                "untimed_first_s": round(times[0], 3),
+                "useful_tflops": round(out["useful_flops"] / sec / 1e12, 2),
+                "pct_fp64_mfma_peak": round(100.0 * out["useful_flops"] / sec / 1e12 / PEAK_FP64_TFLOPS, 2),
+                "dense_equivalent_tflops": round(out["dense_flops"] / sec / 1e12, 2),
+                "speedup_vs_best_paper_time": round(306.6 / sec, 2),
+                "pair_symmetry_rel": sym, "finite": bool(torch.isfinite(R).all().item())})
+    n = args.steps
+    out["kernels"] = {k: {"launches": d["launches"] // n, "s": round(d["ms"] / n / 1e3, 3),
+                          "tflops": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 2) if d["ms"] > 0 and d["flops"] > 0
+                          else None} for k, d in prof.items() if d["launches"]}
+    print(json.dumps({"study": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,13 +305,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--study", default="", help="c3: time-to-1e-7 study at (40, 400, 1200); "
-                    "batched: the 32 uneven instances, grouped graph launch vs one plan each")
+                    "batched: the 32 uneven instances, grouped graph launch vs one plan each; "
+                    "paper: one streamed FP64 evaluation at (nocc, nvir, nvec) = (100, 700, 4000)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2603_20912_amd", "weights", "mlp_start.f32"))
     args = ap.parse_args()
     if args.study == "c3":
         return study_c3(args)
     if args.study == "batched":
         return study_batched(args)
+    if args.study == "paper":
+        return study_paper(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(every box has a single MI355X); run with --gpus 1", file=sys.stderr)

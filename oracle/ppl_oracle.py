@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
-    "ppl_sampled", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
+    "ppl_sampled", "ppl_entry", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
     "jacobi", "fixed_point", "spectral_radius", "nominal_flops",
 ]
 
@@ -119,17 +119,23 @@ def ppl_factored(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
     return R
 
 
+def ppl_entry(La: np.ndarray, Lb: np.ndarray, tij: np.ndarray) -> float:
+    """One R_ij^ab from the slices it depends on: La[P, c] = L^P_ac and Lb[P, d] = L^P_bd
+    (virtual c, d), tij[c, d] = t_ij^cd. G[c, d] = (ac|bd) = sum_P L^P_ac L^P_bd, then
+    R = sum_cd G[c, d] t_ij^cd. Lets full-size results be checked from O(naux v) data."""
+    G = np.asarray(La, dtype=np.float64).T @ np.asarray(Lb, dtype=np.float64)   # [c][d]
+    return float(np.sum(G * np.asarray(tij, dtype=np.float64)))
+
+
 def ppl_sampled(L: np.ndarray, o: int, t: np.ndarray, idx) -> np.ndarray:
     """R_ij^ab at a list of (i, j, a, b) samples, each from its own (ac|bd) slab.
 
-    For one sample, G[c, d] = (ac|bd) = sum_P L^P_ac L^P_bd and R = sum_cd G[c,d] t_ij^cd.
     Cost per sample is O(naux v^2), so full-size results can be spot-checked.
     """
     Lvv = vv_block(np.asarray(L, dtype=np.float64), o)
     out = np.empty(len(idx))
     for k, (i, j, a, b) in enumerate(idx):
-        G = Lvv[:, a, :].T @ Lvv[:, b, :]          # [c][d]
-        out[k] = float(np.sum(G * t[i, j]))
+        out[k] = ppl_entry(Lvv[:, a, :], Lvv[:, b, :], t[i, j])
     return out
 
 

@@ -120,8 +120,10 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
   p->rm = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
   // split-K slices for up to kMaxSplits (autotuning may pick any count), sized for FP64,
-  // or the stream-K partial slots of the largest tile, whichever is larger
-  uint64_t part_bytes = std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8;
+  // or the stream-K partial slots of the largest tile, whichever is larger. A resident
+  // plan's slices span all columns; a streaming plan's span the widest batch only.
+  p->ld_part = resident ? std::max(p->ldp, p->ldm) : pad_ld(std::max<int64_t>(max_batch_pairs, 1));
+  uint64_t part_bytes = (uint64_t)std::max(p->Np, p->Nm) * p->ld_part * kMaxSplits * 8;
   for (int t = 0; t < contract_tile_count(); ++t) {
     part_bytes = std::max(part_bytes, streamk_part_bytes(t, PPL_FP64, p->Np, resident ? p->Pp : max_batch_pairs, p->ldp));
     if (p->Nm > 0)
@@ -259,7 +261,7 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
   const int split_p = primary ? p->split_p : s.split_p, split_m = primary ? p->split_m : s.split_m;
   void* part = p->part.bytes ? at<void>(p, p->part) : nullptr;
   if (std::max(split_p, split_m) > kMaxSplits ||
-      (uint64_t)std::max((uint64_t)p->Np * p->ldp, (uint64_t)p->Nm * p->ldm) * kMaxSplits * 8 > p->part.bytes ||
+      (uint64_t)std::max(p->Np, p->Nm) * p->ld_part * kMaxSplits * 8 > p->part.bytes ||
       (uint64_t)p->Np * p->ldp * 8 > p->rp.bytes)
     return fail(PPL_E_STATE, "contraction buffers smaller than the plan requires");
   const double fp = 2.0 * (double)p->Np * p->Pp, fm = 2.0 * (double)p->Nm * p->Pm;
@@ -269,13 +271,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, fp * p->Pp);
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, p->Pp, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, 0, split_p, part, p->ldp, p->part.bytes));
+                            at<void>(p, p->rp), p->ldp, 0, split_p, part, p->ld_part, p->part.bytes));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, fm * p->Pm);
     if (p->Nm > 0 && p->Pm > 0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, p->Pm, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, 0, split_m, part, p->ldm, p->part.bytes));
+                            at<void>(p, p->rm), p->ldm, 0, split_m, part, p->ld_part, p->part.bytes));
     return PPL_OK;
   }
   if (!p->L_last) return fail(PPL_E_STATE, "streaming plan has no Cholesky vectors (call ppl_build_batch)");
@@ -286,13 +288,13 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
       ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, 2.0 * (double)p->Np * p->Pp * (double)(b.p1 - b.p0));
       PPL_TRY(gemm_contract(st, s.prec, tile, p->Np, b.p1 - b.p0, p->ldp, sp, sp_lo, p->ldp,
                             at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp,
-                            at<void>(p, p->rp), p->ldp, b.p0, split_p, part, p->ldp, p->part.bytes));
+                            at<void>(p, p->rp), p->ldp, b.p0, split_p, part, p->ld_part, p->part.bytes));
     }
     ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, 2.0 * (double)p->Nm * p->Pm * (double)(b.q1 - b.q0));
     if (p->Nm > 0 && b.q1 > b.q0)
       PPL_TRY(gemm_contract(st, s.prec, tile_m, p->Nm, b.q1 - b.q0, p->ldm, am, am_lo, p->ldm,
                             at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm,
-                            at<void>(p, p->rm), p->ldm, b.q0, split_m, part, p->ldm, p->part.bytes));
+                            at<void>(p, p->rm), p->ldm, b.q0, split_m, part, p->ld_part, p->part.bytes));
   }
   return PPL_OK;
 }
@@ -463,28 +465,35 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   if (need <= budget) {
     p->resident = true;
   } else {
-    // streaming: V+- rows of one build step at a time; shrink the step until it fits
+    // streaming: V+- rows of one build step at a time; the largest step that fits
+    // (the need grows with the step's pair count, so a bisection over it suffices)
     p->resident = false;
-    bool ok = false;
-    for (int64_t cap = gcap; cap >= p->v; cap = cap / 2) {
+    auto need_for = [&](int64_t cap) {
       make_batches(p->v, cap, p->batches);
       make_tile_tables(p);
       int64_t maxp = 0;
       for (const Batch& b : p->batches) maxp = std::max<int64_t>(maxp, b.p1 - b.p0);
-      need = assign_layout(p, cap, false, maxp);
-      if (need <= budget) {
-        ok = true;
-        gcap = cap;
-        break;
-      }
-      if (cap == p->v) break;
-    }
-    if (!ok) {
+      return assign_layout(p, cap, false, maxp);
+    };
+    int64_t lo = std::min<int64_t>(p->v, gcap), hi = gcap;
+    need = need_for(lo);
+    if (need > budget) {
       const uint64_t n2 = need;
       delete p;
       return fail(PPL_E_NOMEM, "budget %llu B cannot hold one V+- row batch (needs %llu B)",
                   (unsigned long long)budget, (unsigned long long)n2);
     }
+    if (hi > lo && need_for(hi) <= budget) {
+      lo = hi;
+    } else {
+      while (hi - lo > std::max<int64_t>(1, lo / 32)) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (need_for(mid) <= budget) lo = mid;
+        else hi = mid;
+      }
+    }
+    need = need_for(lo);
+    gcap = lo;
   }
   p->g_pairs_cap = gcap;
   p->a_per_batch = p->batches.empty() ? 0 : p->batches[0].a1 - p->batches[0].a0;

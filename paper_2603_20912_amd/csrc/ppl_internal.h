@@ -106,6 +106,7 @@ struct ppl_plan_s {
   std::vector<ppl::Batch> batches;
   int a_per_batch = 0;
   int64_t g_pairs_cap = 0;             // pairs (a<=b) one build step may hold in G
+  int64_t ld_part = 0;                 // row length of split-K partial slices (streaming: one batch wide)
   // tiles
   int tile_build = 0, tile_contract = 0;
   int split_p = 1, tile_m = 0, split_m = 1;   // split-K of the R+ GEMM; tile and split-K of the R- GEMM

@@ -27,6 +27,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["make_system", "make_amplitudes", "batched_shapes", "training_shapes",
+           "make_system_device", "make_amplitudes_device",
            "amplitude_scale", "MAX_ELEMS_GEN"]
 
 # guard against accidentally asking for multi-100-GB host arrays
@@ -96,3 +97,52 @@ def training_shapes(n_inst: int = 200, seed: int = 5, o_range=(10, 30), v_range=
         v = int(rng.integers(v_range[0], v_range[1] + 1))
         out.append({"o": o, "v": v, "naux": 3 * v, "seed": 2000 + k})
     return out
+
+
+# ---------------------------------------------------------------- device-side draws
+# The same recipe drawn directly in device memory with torch's device generator
+# (Philox), for shapes whose host arrays would be tens of GB (the largest shape of
+# the contraction benchmark, Tab. xc-split: L is 20 GB, t 39 GB). The numbers
+# differ from the numpy draws of the same seed; only the distribution is shared.
+
+def make_system_device(o: int, v: int, naux: int, seed: int, variant: str = "contractive",
+                       device="cuda", chunk: int = 128) -> dict:
+    """L [naux][n][n] float64 on `device` with the module's recipe (symmetrized standard
+    normals scaled by amp * exp(-P / (naux / 3))), drawn `chunk` vectors at a time;
+    e_occ, e_vir as in make_system."""
+    import torch
+    n = o + v
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    amp = amplitude_scale(v, naux, variant)
+    L = torch.empty((naux, n, n), dtype=torch.float64, device=device)
+    decay = naux / 3.0
+    for p0 in range(0, naux, chunk):
+        p1 = min(naux, p0 + chunk)
+        A = torch.randn((p1 - p0, n, n), generator=g, dtype=torch.float64, device=device)
+        s = amp * torch.exp(-torch.arange(p0, p1, dtype=torch.float64, device=device) / decay)
+        L[p0:p1] = (A + A.transpose(1, 2)) * (0.5 * s)[:, None, None]
+        del A
+    e_occ = torch.sort(torch.rand(o, generator=g, dtype=torch.float64, device=device) * 1.5 - 2.0).values
+    e_vir = torch.sort(torch.rand(v, generator=g, dtype=torch.float64, device=device) * 4.8 + 0.2).values
+    return {"o": o, "v": v, "naux": naux, "seed": seed, "variant": variant, "L": L,
+            "e_occ": e_occ, "e_vir": e_vir}
+
+
+def make_amplitudes_device(o: int, v: int, seed: int, device="cuda"):
+    """Pair-symmetric t[i][j][a][b] = (X + X^pair) / 2 with X ~ N(0, 1), drawn in place on
+    `device`; the symmetrization runs one occupied row i at a time (temporary memory
+    of (i+1) v^2 values)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    t = torch.empty((o, o, v, v), dtype=torch.float64, device=device)
+    t.normal_(generator=g)
+    for i in range(o):
+        X = t[i, : i + 1]                          # t[i][j] for j <= i
+        Y = t[: i + 1, i].transpose(1, 2)          # t[j][i]^T for j <= i
+        S = (X + Y) * 0.5
+        t[i, : i + 1] = S
+        t[: i + 1, i] = S.transpose(1, 2)
+        del X, Y, S
+    return t

@@ -94,3 +94,36 @@ def test_learned_config_size_sampled(P):
     tref = np.array([V[k] / D[k] for k in idx])
     assert np.abs(np.array([t_host[k] for k in idx]) - tref).max() < 1e-12 * np.abs(tref).max()
     eng.close()
+
+
+def test_benchmark_shape_streaming_sampled(P):
+    """The largest shape of the contraction benchmark (Tab. xc-split): N = 800, nocc = 100,
+    nvec = 5N = 4000, nvir = 700. V+- (about 960 GB in FP64) streams through HBM in row
+    batches; sampled entries against the oracle, each from the O(naux v) slices it needs."""
+    o, v, naux = 100, 700, 4000
+    torch.cuda.empty_cache()
+    say("contract fp64 (100,700,4000) streaming, inputs drawn on the device")
+    sysd = S.make_system_device(o, v, naux, 31)
+    L = sysd["L"]
+    t = S.make_amplitudes_device(o, v, 32)
+    R = torch.empty_like(t)      # before the plan, which takes 90% of the free memory
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    eng = P.PPL(o, v, naux, build_scratch=64 << 30)
+    assert eng.info["resident"] == 0 and eng.info["n_batches"] > 1
+    say(f"  {eng.info['n_batches']} row batches of up to {eng.info['max_step_pairs']} pairs")
+    eng.build(L)
+    eng.contract(t, R)
+    torch.cuda.synchronize()
+    # the first and last pair rows of the first and last batch, the diagonal, random entries
+    idx = sample_idx(o, v, 6, 14) + [(o - 1, 0, 0, v - 1), (3, 7, v - 2, v - 1)]
+    ref = np.array([O.ppl_entry(L[:, o + a, o:].cpu().numpy(), L[:, o + b, o:].cpu().numpy(),
+                                t[i, j].cpu().numpy()) for (i, j, a, b) in idx])
+    got = np.array([R[k].item() for k in idx])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"  max |R_gpu - R_oracle| / max |R| = {err:.2e}")
+    assert err < 1e-12
+    assert torch.isfinite(R).all().item()
+    eng.close()
+    del L, t, R, sysd
+    torch.cuda.empty_cache()

@@ -74,6 +74,24 @@ def test_budget_forces_streaming_batches(P):
     assert i["workspace_bytes"] <= 1 << 30
 
 
+def test_streaming_plan_of_the_largest_benchmark_shape(P):
+    # (nocc, nvir, nvec) = (100, 700, 4000) of the contraction benchmark (Tab. xc-split):
+    # V+- would take about 960 GB in FP64, so the plan streams row batches; the split-K
+    # slices span one batch (all columns would need 79 GB more than the budget holds)
+    bud = 170 << 30
+    i = plan_info(P, 100, 700, 4000, hbm_budget=bud, build_scratch=64 << 30)
+    assert i["resident"] == 0 and i["n_batches"] > 1
+    assert i["workspace_bytes"] <= bud
+    # the planner takes (nearly) the largest build step that fits: one more virtual row
+    # per step (at most v pairs, V+- rows plus G scratch) would exceed the budget
+    v, ldp = 700, (700 * 701 // 2 + 63) // 64 * 64
+    row = v * (2 * ldp * 8 + v * v * 8)
+    assert i["workspace_bytes"] > bud - 3 * row
+    # a smaller budget streams in smaller steps
+    j = plan_info(P, 100, 700, 4000, hbm_budget=150 << 30, build_scratch=64 << 30)
+    assert j["max_step_pairs"] < i["max_step_pairs"] and j["n_batches"] > i["n_batches"]
+
+
 def test_budget_too_small_is_nomem(P):
     with pytest.raises(P.PPLError) as e:
         plan_info(P, 20, 200, 600, hbm_budget=1 << 20)
