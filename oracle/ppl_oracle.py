@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
     "ppl_sampled", "ppl_entry", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
-    "jacobi", "fixed_point", "spectral_radius", "nominal_flops",
+    "jacobi", "jacobi_diis", "fixed_point", "spectral_radius", "nominal_flops",
 ]
 
 
@@ -189,6 +189,55 @@ def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7
         hist.append(r)
         if not np.isfinite(r) or r < tol:
             break
+    return t, hist, energy(V, t)
+
+
+def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, tol: float = 1e-7):
+    """Jacobi iteration accelerated by direct inversion in the iterative subspace
+    (DIIS; P. Pulay, Chem. Phys. Lett. 73, 393 (1980)).
+
+    Sweep k maps its input t_k to t'_k = (V + PPL(t_k)) / D with error e_k = t'_k - t_k;
+    r_k = ||e_k||_F is the same residual the plain iteration reports. Unless r_k < tol,
+    the next input is t_{k+1} = sum_i c_i t'_i over the last m sweeps, where c minimizes
+    ||sum_i c_i e_i||_F subject to sum_i c_i = 1, i.e. solves
+        [ B   -1 ] [c     ]   [ 0 ]
+        [ -1^T 0 ] [lambda] = [-1 ],   B_ij = <e_i, e_j>_F.
+    A singular system drops the oldest sweep and is solved again. With m = 1 this is
+    the plain iteration. Returns (t, residual_history, E(t)), t = t'_k of the last sweep.
+    """
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    t = V / D if t0 is None else np.array(t0, dtype=np.float64)
+    Ts, Es, hist = [], [], []
+    for _ in range(max_sweeps):
+        t_new = (V + ppl(L, o, t)) / D
+        e = t_new - t
+        r = float(np.linalg.norm(e))
+        hist.append(r)
+        if not np.isfinite(r) or r < tol:
+            t = t_new
+            break
+        Ts.append(t_new)
+        Es.append(e)
+        if len(Ts) > m:
+            Ts.pop(0)
+            Es.pop(0)
+        while True:
+            n = len(Es)
+            A = np.zeros((n + 1, n + 1))
+            for i in range(n):
+                for j in range(n):
+                    A[i, j] = float(np.sum(Es[i] * Es[j]))
+            A[:n, n] = -1.0
+            A[n, :n] = -1.0
+            rhs = np.zeros(n + 1)
+            rhs[n] = -1.0
+            try:
+                c = np.linalg.solve(A, rhs)[:n]
+                break
+            except np.linalg.LinAlgError:
+                Ts.pop(0)
+                Es.pop(0)
+        t = sum(ci * Ti for ci, Ti in zip(c, Ts))
     return t, hist, energy(V, t)
 
 

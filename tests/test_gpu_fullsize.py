@@ -123,7 +123,9 @@ def test_benchmark_shape_streaming_sampled(P):
     err = np.abs(got - ref).max() / np.abs(ref).max()
     say(f"  max |R_gpu - R_oracle| / max |R| = {err:.2e}")
     assert err < 1e-12
-    assert torch.isfinite(R).all().item()
     eng.close()
+    del eng
+    torch.cuda.empty_cache()
+    assert all(torch.isfinite(R[i]).all().item() for i in range(o))
     del L, t, R, sysd
     torch.cuda.empty_cache()

@@ -176,6 +176,56 @@ def test_jacobi_reaches_the_exact_fixed_point():
     assert abs(E - O.energy(V, tstar)) < 1e-9
 
 
+def test_diis_with_one_vector_is_the_plain_iteration():
+    o, v, naux = 3, 12, 36
+    s = S.make_system(o, v, naux, 7, "contractive")
+    args = (s["L"], o, s["e_occ"], s["e_vir"])
+    t1, h1, E1 = O.jacobi(*args, max_sweeps=15, tol=0.0)
+    t2, h2, E2 = O.jacobi_diis(*args, m=1, max_sweeps=15, tol=0.0)
+    assert h1 == h2 and np.array_equal(t1, t2) and E1 == E2
+
+
+def test_diis_terminates_on_the_affine_map():
+    # The Jacobi map is affine; with the whole history DIIS minimizes the residual over a
+    # growing Krylov space (it is GMRES on (I - M) t = D^-1 V), so it reaches the exact
+    # fixed point once the space is exhausted: o = 1, v = 3 leaves 6 pair-symmetric
+    # unknowns, hence at most 6 extrapolations after the first sweep (8 sweeps in all).
+    o, v, naux = 1, 3, 4
+    s = S.make_system(o, v, naux, 7, "contractive")
+    args = (s["L"], o, s["e_occ"], s["e_vir"])
+    tstar = O.fixed_point(*args)
+    t, hist, _ = O.jacobi_diis(*args, m=8, max_sweeps=30, tol=1e-13)
+    assert len(hist) <= 8 and hist[-1] < 1e-13
+    assert rel(t, tstar) < 1e-13
+    # the plain iteration (spectral radius near 0.97) is still far away after as many sweeps
+    _, hj, _ = O.jacobi(*args, max_sweeps=len(hist), tol=0.0)
+    assert hj[-1] > 1e-5
+
+
+def test_diis_reaches_the_same_fixed_point_in_fewer_sweeps():
+    o, v, naux = 4, 24, 72
+    s = S.make_system(o, v, naux, 7, "contractive")
+    args = (s["L"], o, s["e_occ"], s["e_vir"])
+    tstar = O.fixed_point(*args)
+    tj, hj, _ = O.jacobi(*args, max_sweeps=200, tol=1e-10)
+    td, hd, Ed = O.jacobi_diis(*args, m=8, max_sweeps=200, tol=1e-10)
+    assert hd[-1] < 1e-10 and rel(td, tstar) < 1e-9 and rel(tj, tstar) < 1e-9
+    assert 2 * len(hd) < len(hj)
+    V, _ = O.mp2_parts(*args)
+    assert abs(Ed - O.energy(V, tstar)) < 1e-9
+
+
+def test_diis_converges_where_jacobi_diverges():
+    o, v, naux = 3, 16, 48
+    s = S.make_system(o, v, naux, 2, "literal")
+    args = (s["L"], o, s["e_occ"], s["e_vir"])
+    assert O.spectral_radius(*args, iters=150) > 1.3
+    _, hj, _ = O.jacobi(*args, max_sweeps=30, tol=0.0)
+    assert hj[-1] > 10 * hj[0]
+    t, hd, _ = O.jacobi_diis(*args, m=8, max_sweeps=60, tol=1e-10)
+    assert hd[-1] < 1e-10 and rel(t, O.fixed_point(*args)) < 1e-9
+
+
 def test_generator_variants_rho():
     o, v, naux = 5, 20, 60
     lit = S.make_system(o, v, naux, 0, "literal")
@@ -229,3 +279,38 @@ def test_planted_mistakes_are_caught(mutant):
     s = S.make_system(o, v, naux, 0)
     t = general_t(o, v, 10)
     assert rel(mutant(s["L"], o, t), O.ppl_loops(s["L"], o, t)) > 1e-3
+
+
+def _diis_variant(L, o, e_occ, e_vir, mistake, m=8, max_sweeps=30, tol=1e-13):
+    """The DIIS iteration with one planted mistake, to show that the DIIS pins catch it."""
+    V, D = O.mp2_parts(L, o, e_occ, e_vir)
+    t = V / D
+    Ts, Es, hist = [], [], []
+    for _ in range(max_sweeps):
+        t_new = (V + O.ppl(L, o, t)) / D
+        e = t_new - t
+        hist.append(float(np.linalg.norm(e)))
+        if hist[-1] < tol:
+            return t_new, hist
+        Ts.append(t if mistake == "extrapolate_inputs" else t_new)
+        Es.append(t_new if mistake == "errors_are_iterates" else e)
+        Ts, Es = Ts[-m:], Es[-m:]
+        n = len(Es)
+        A = np.zeros((n + 1, n + 1))
+        A[:n, :n] = [[float(np.sum(x * y)) for y in Es] for x in Es]
+        A[:n, n] = A[n, :n] = -1.0
+        rhs = np.zeros(n + 1)
+        rhs[n] = 1.0 if mistake == "constraint_sign" else -1.0
+        c = np.linalg.lstsq(A, rhs, rcond=None)[0][:n]
+        t = sum(ci * Ti for ci, Ti in zip(c, Ts))
+    return t, hist
+
+
+@pytest.mark.parametrize("mistake", ["extrapolate_inputs", "errors_are_iterates", "constraint_sign"])
+def test_planted_diis_mistakes_are_caught(mistake):
+    o, v, naux = 1, 3, 4
+    s = S.make_system(o, v, naux, 7, "contractive")
+    args = (s["L"], o, s["e_occ"], s["e_vir"])
+    t, hist = _diis_variant(*args, mistake)
+    # the affine-termination pin: exact fixed point within 8 sweeps
+    assert not (len(hist) <= 8 and hist[-1] < 1e-13 and rel(t, O.fixed_point(*args)) < 1e-13)
