@@ -67,6 +67,8 @@ typedef struct {
   uint64_t hbm_budget;  /* bytes the workspace may use; 0 = 90% of the device's free memory */
   void*    stream;      /* hipStream_t every call of this plan enqueues on (NULL = null stream) */
   uint64_t build_scratch; /* bytes of integral-build scratch (0 = up to 4 GiB); larger = fewer build steps */
+  int32_t  diis_max;    /* DIIS subspace capacity kept in the workspace, 0 .. PPL_DIIS_MAX (0 = none);
+                           costs 2 * diis_max packed FP64 amplitude vectors */
 } ppl_desc_t;
 
 /* What the planner decided (output of ppl_plan_query). */
@@ -135,6 +137,7 @@ int ppl_contract(ppl_plan_t plan, const double* t2, double* R, double alpha, dou
 #define PPL_START_MP2   0  /* start from t = V / D */
 #define PPL_START_GIVEN 1  /* start from the t2 passed in */
 #define PPL_START_GIVEN_CHECKED 2  /* start from t2, but restart from MP2 if its first residual is larger */
+#define PPL_DIIS_MAX 16            /* largest DIIS subspace */
 
 typedef struct {
   int32_t max_sweeps;       /* hard cap on sweeps (all precisions), >= 1 */
@@ -146,6 +149,7 @@ typedef struct {
   int32_t fail_on_noconv;   /* 1: return PPL_E_NOCONV when max_sweeps is reached (else OK) */
   double  diverge_factor;   /* PPL_E_DIVERGED when r > diverge_factor * r_first (0 = off) */
   double* history;          /* optional host array of max_sweeps residuals (NULL = none) */
+  int32_t diis;             /* DIIS subspace size (<= the plan's diis_max); 0 or 1 = plain Jacobi */
 } ppl_iter_opts_t;
 
 typedef struct {
@@ -157,10 +161,11 @@ typedef struct {
   double  energy;           /* E = sum V (2 t_ij^ab - t_ij^ba) of the final t */
   double  energy_start;     /* the same energy of the starting amplitudes */
   double  first_residual;   /* residual of the first sweep */
+  int32_t diis_dropped;     /* sweeps dropped from the DIIS subspace because its system was singular */
 } ppl_iter_report_t;
 
 /* Fill *opts with the defaults: 100 sweeps, MP2 start, tol 1e-7, switch_tol 0 (automatic),
- * stagnation 0.95, min_fp64_sweeps 2, fail_on_noconv 1, diverge_factor 1e3. */
+ * stagnation 0.95, min_fp64_sweeps 2, fail_on_noconv 1, diverge_factor 1e3, diis 0. */
 void ppl_iter_opts_default(ppl_iter_opts_t* opts);
 
 /*
@@ -171,6 +176,16 @@ void ppl_iter_opts_default(ppl_iter_opts_t* opts);
  * FP64 sweeps to tol. L, e_occ [o], e_vir [v] and t2 are device FP64; t2
  * holds the start (PPL_START_GIVEN*) on entry and the last iterate on return.
  * Synchronous: it reads two scalars back per sweep. Builds V+- itself.
+ *
+ * With opts->diis = m >= 2 the sweeps are accelerated by direct inversion in the
+ * iterative subspace (DIIS; P. Pulay, Chem. Phys. Lett. 73, 393 (1980)): sweep k
+ * maps t_k to t'_k = (V + PPL(t_k)) / D with error e_k = t'_k - t_k (its norm is the
+ * residual above); unless converged, the next input is sum_i c_i t'_i over the last m
+ * sweeps, c minimizing ||sum_i c_i e_i||_F subject to sum_i c_i = 1 (inner products
+ * over the full tensors, in FP64). A singular subspace system drops its oldest sweep.
+ * The subspace restarts when a mixed run switches to FP64 sweeps; the sweeps of a
+ * checked start are plain. The returned t2 is t'_k of the last sweep, as without DIIS.
+ * PPL_E_ARG when m exceeds the plan's diis_max.
  */
 int ppl_iterate(ppl_plan_t plan, const double* L, const double* e_occ, const double* e_vir,
                 double* t2, const ppl_iter_opts_t* opts, ppl_iter_report_t* report);

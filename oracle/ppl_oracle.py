@@ -204,7 +204,11 @@ def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, 
         [ -1^T 0 ] [lambda] = [-1 ],   B_ij = <e_i, e_j>_F.
     A singular system drops the oldest sweep and is solved again. With m = 1 this is
     the plain iteration. Returns (t, residual_history, E(t)), t = t'_k of the last sweep.
+
+    Singular is read numerically: the system, with B divided by its largest diagonal
+    entry, has an LU pivot (partial pivoting) below 1e-14.
     """
+    import scipy.linalg
     V, D = mp2_parts(L, o, e_occ, e_vir)
     t = V / D if t0 is None else np.array(t0, dtype=np.float64)
     Ts, Es, hist = [], [], []
@@ -227,16 +231,20 @@ def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, 
             for i in range(n):
                 for j in range(n):
                     A[i, j] = float(np.sum(Es[i] * Es[j]))
+            A[:n, :n] /= max(abs(A[i, i]) for i in range(n))
             A[:n, n] = -1.0
             A[n, :n] = -1.0
             rhs = np.zeros(n + 1)
             rhs[n] = -1.0
-            try:
-                c = np.linalg.solve(A, rhs)[:n]
+            lu, piv = scipy.linalg.lu_factor(A, check_finite=False)
+            if np.min(np.abs(np.diag(lu))) >= 1e-14:
+                c = scipy.linalg.lu_solve((lu, piv), rhs)[:n]
                 break
-            except np.linalg.LinAlgError:
-                Ts.pop(0)
-                Es.pop(0)
+            if n == 1:                 # a zero error vector: the sweep's own amplitudes
+                c = np.ones(1)
+                break
+            Ts.pop(0)
+            Es.pop(0)
         t = sum(ci * Ti for ci, Ti in zip(c, Ts))
     return t, hist, energy(V, t)
 

@@ -36,7 +36,7 @@ class ppl_desc_t(ctypes.Structure):
     _fields_ = [("o", ctypes.c_int32), ("v", ctypes.c_int32), ("naux", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("keep_fp64", ctypes.c_int32),
                 ("tile_contract", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p), ("build_scratch", ctypes.c_uint64)]
+                ("stream", ctypes.c_void_p), ("build_scratch", ctypes.c_uint64), ("diis_max", ctypes.c_int32)]
 
 
 class ppl_plan_info_t(ctypes.Structure):
@@ -55,14 +55,16 @@ class ppl_iter_opts_t(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("start", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("switch_tol", ctypes.c_double), ("stagnation", ctypes.c_double),
                 ("min_fp64_sweeps", ctypes.c_int32), ("fail_on_noconv", ctypes.c_int32),
-                ("diverge_factor", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double))]
+                ("diverge_factor", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("diis", ctypes.c_int32)]
 
 
 class ppl_iter_report_t(ctypes.Structure):
     _fields_ = [("sweeps_lp", ctypes.c_int32), ("sweeps_fp64", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("restarted_mp2", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("energy", ctypes.c_double),
-                ("energy_start", ctypes.c_double), ("first_residual", ctypes.c_double)]
+                ("energy_start", ctypes.c_double), ("first_residual", ctypes.c_double),
+                ("diis_dropped", ctypes.c_int32)]
 
 
 PPL_PROF_KINDS = 6
@@ -172,10 +174,10 @@ def _stream_handle(stream):
 
 # ---------------------------------------------------------------- same names as the C ABI
 def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None, tile_contract=-1,
-             build_scratch=0):
+             build_scratch=0, diis_max=0):
     d = ppl_desc_t(o, v, naux, PREC[prec] if isinstance(prec, str) else int(prec), int(bool(keep_fp64)),
                    int(tile_contract), int(hbm_budget),
-                   _stream_handle(stream) if stream is not False else None, int(build_scratch))
+                   _stream_handle(stream) if stream is not False else None, int(build_scratch), int(diis_max))
     h = ctypes.c_void_p()
     _check(load().ppl_plan(ctypes.byref(d), ctypes.byref(h)), "ppl_plan")
     return h

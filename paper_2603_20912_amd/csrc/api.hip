@@ -147,6 +147,14 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   p->tab_op = L.take((uint64_t)p->Np * 4);
   p->tab_om = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * 4);
   p->red = L.take((uint64_t)(kReduceBlocks * 4 + 8) * 8);
+  p->diis_slot_n = p->Np * p->ldp + std::max<int64_t>(p->Nm, 1) * p->ldm;
+  if (p->diis_max > 0) {
+    p->diis_t = L.take((uint64_t)p->diis_max * p->diis_slot_n * 8);
+    p->diis_e = L.take((uint64_t)p->diis_max * p->diis_slot_n * 8);
+    p->diis_red = L.take((uint64_t)(kReduceBlocks + 1) * kDiisMax * 8);
+  } else {
+    p->diis_t = p->diis_e = p->diis_red = Region{};
+  }
   p->tiles = L.take((uint64_t)p->tiles_host.size() * 4);
   return L.cur;
 }
@@ -341,6 +349,49 @@ static int read_red(ppl_plan_t p, double out[4]) {
   return PPL_OK;
 }
 
+// DIIS coefficients of the subspace `ids` (oldest first) from the inner products B:
+// the system [B -1; -1^T 0][c; lambda] = [0; -1], with B scaled by its largest
+// diagonal entry, by Gaussian elimination with partial pivoting. Singular (false)
+// when a pivot falls below 1e-14 or the result is not finite.
+static bool diis_solve(const double (&B)[kDiisMax][kDiisMax], const std::vector<int>& ids, double* c) {
+  const int n = (int)ids.size(), N = n + 1;
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, fabs(B[ids[i]][ids[i]]));
+  if (!(scale > 0.0) || !isfinite(scale)) return false;
+  double A[kDiisMax + 1][kDiisMax + 2];
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) A[i][j] = B[ids[i]][ids[j]] / scale;
+    A[i][n] = -1.0;
+    A[n][i] = -1.0;
+    A[i][N] = 0.0;
+  }
+  A[n][n] = 0.0;
+  A[n][N] = -1.0;
+  for (int col = 0; col < N; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < N; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (!(fabs(A[piv][col]) >= 1e-14)) return false;
+    if (piv != col)
+      for (int k = 0; k <= N; ++k) std::swap(A[piv][k], A[col][k]);
+    for (int r = col + 1; r < N; ++r) {
+      const double f = A[r][col] / A[col][col];
+      for (int k = col; k <= N; ++k) A[r][k] -= f * A[col][k];
+    }
+  }
+  double x[kDiisMax + 1];
+  for (int r = N - 1; r >= 0; --r) {
+    double acc = A[r][N];
+    for (int k = r + 1; k < N; ++k) acc -= A[r][k] * x[k];
+    x[r] = acc / A[r][r];
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!isfinite(x[i])) return false;
+    c[i] = x[i];
+  }
+  return true;
+}
+
 }  // namespace ppl
 
 using namespace ppl;
@@ -373,6 +424,7 @@ void ppl_iter_opts_default(ppl_iter_opts_t* o) {
   o->fail_on_noconv = 1;
   o->diverge_factor = 1e3;
   o->history = nullptr;
+  o->diis = 0;
 }
 
 int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
@@ -387,6 +439,8 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
     return fail(PPL_E_ARG, "unknown precision %d", d->prec);
   if (d->tile_contract < -1 || d->tile_contract >= contract_tile_count())
     return fail(PPL_E_ARG, "tile_contract %d out of range", d->tile_contract);
+  if (d->diis_max < 0 || d->diis_max > PPL_DIIS_MAX)
+    return fail(PPL_E_ARG, "diis_max %d out of range [0, %d]", d->diis_max, PPL_DIIS_MAX);
   // 64-bit size sanity: the largest products used anywhere
   {
     uint64_t x;
@@ -403,6 +457,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   p->naux = d->naux;
   p->prec = d->prec;
   p->keep_fp64 = (d->prec != PPL_FP64) && d->keep_fp64;
+  p->diis_max = d->diis_max;
   p->stream = (hipStream_t)d->stream;
   p->Pp = npairs_plus(p->v);
   p->Pm = npairs_minus(p->v);
@@ -616,6 +671,9 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   if (opts) o = *opts; else ppl_iter_opts_default(&o);
   if (o.max_sweeps < 1) return fail(PPL_E_ARG, "max_sweeps must be >= 1");
   if (o.start < PPL_START_MP2 || o.start > PPL_START_GIVEN_CHECKED) return fail(PPL_E_ARG, "bad start");
+  if (o.diis < 0 || o.diis > p->diis_max)
+    return fail(PPL_E_ARG, "diis %d exceeds the plan's subspace capacity %d (ppl_desc_t.diis_max)", o.diis,
+                p->diis_max);
   ppl_iter_report_t r;
   memset(&r, 0, sizeof(r));
   hipStream_t st = p->stream;
@@ -663,14 +721,67 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   int status = PPL_E_NOCONV;
   int sweeps = 0;
 
+  // DIIS state: slot ids of the subspace (oldest first), their inner products, and the
+  // slot the current sweep writes (-1: a plain sweep)
+  const bool diis_on = o.diis >= 2;
+  std::vector<int> sub;
+  double B[kDiisMax][kDiisMax] = {};
+  int slot = -1;
+  double* const dT = diis_on ? at<double>(p, p->diis_t) : nullptr;
+  double* const dE = diis_on ? at<double>(p, p->diis_e) : nullptr;
+  double* const dred = diis_on ? at<double>(p, p->diis_red) : nullptr;
+
   auto sweep_once = [&](OperandSet& s) -> int {
     PPL_TRY(refresh_operands(p, s));
     PPL_TRY(contract_packed(p, s));
     ProfScope ps(p, PPL_PROF_UPDATE, 0.0);
+    double* ts = slot >= 0 ? dT + slot * p->diis_slot_n : nullptr;
+    double* es = slot >= 0 ? dE + slot * p->diis_slot_n : nullptr;
     PPL_TRY(update_sweep(st, s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, e_occ, e_vir,
                          at<double>(p, p->vs), at<double>(p, p->va), at<void>(p, p->rp), at<void>(p, p->rm),
-                         p->ldp, p->ldm, s64, a64, tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out));
+                         p->ldp, p->ldm, s64, a64, tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out,
+                         ts, es));
     return read_red(p, h);
+  };
+  // before a DIIS sweep: the slot it writes (the oldest vector's once the subspace is full)
+  auto diis_pick_slot = [&]() {
+    if ((int)sub.size() == o.diis) sub.erase(sub.begin());
+    for (int k = 0; k < o.diis; ++k)
+      if (std::find(sub.begin(), sub.end(), k) == sub.end()) {
+        slot = k;
+        return;
+      }
+  };
+  // after it: add the new vector, extrapolate the next input into S'/A'
+  auto diis_step = [&]() -> int {
+    ProfScope ps(p, PPL_PROF_UPDATE, 0.0);
+    sub.push_back(slot);
+    DiisSet set{};
+    set.n = (int)sub.size();
+    for (int i = 0; i < set.n; ++i) set.id[i] = sub[i];
+    PPL_TRY(diis_dots(st, p->o, p->v, p->ldp, p->ldm, tabs[0], tabs[1], tabs[2], tabs[3], dE, p->diis_slot_n,
+                      set, slot, dred, dred + kReduceBlocks * kDiisMax));
+    double dots[kDiisMax];
+    PPL_HIP_TRY(hipMemcpyAsync(dots, dred + kReduceBlocks * kDiisMax, set.n * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+    PPL_HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < set.n; ++i) B[slot][sub[i]] = B[sub[i]][slot] = dots[i];
+    double c[kDiisMax];
+    while (!diis_solve(B, sub, c)) {
+      if (sub.size() == 1) {   // a zero error vector: the sweep's own amplitudes
+        c[0] = 1.0;
+        break;
+      }
+      sub.erase(sub.begin());
+      ++r.diis_dropped;
+    }
+    set.n = (int)sub.size();
+    for (int i = 0; i < set.n; ++i) {
+      set.id[i] = sub[i];
+      set.c[i] = c[i];
+    }
+    slot = -1;
+    return diis_combine(st, p->o, p->v, p->ldp, p->ldm, dT, p->diis_slot_n, set, s64, a64);
   };
   auto count_sweep = [&](const OperandSet& s, double rr) {
     if (o.history && sweeps < o.max_sweeps) o.history[sweeps] = rr;
@@ -710,21 +821,34 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
 
   while (sweeps < o.max_sweeps) {
     OperandSet& s = (lp_phase || fp64_set < 0) ? p->ops[0] : p->ops[fp64_set];
+    if (diis_on) diis_pick_slot();
     PPL_TRY(sweep_once(s));
     const double rr = sqrt(fabs(h[0]));
     count_sweep(s, rr);
     if (r_first < 0) r_first = rr;
     if (h[2] != 0.0 || !isfinite(rr) || !isfinite(h[1])) { status = PPL_E_NONFINITE; break; }
     if (o.diverge_factor > 0 && rr > o.diverge_factor * r_first) { status = PPL_E_DIVERGED; break; }
+    bool restart = false;
     if (lp_phase) {
       const bool stagnant = r_prev > 0 && rr / r_prev > o.stagnation;
-      if (fp64_set >= 0 && (rr < o.switch_tol || stagnant)) lp_phase = false;
+      if (fp64_set >= 0 && (rr < o.switch_tol || stagnant)) {
+        lp_phase = false;
+        restart = true;
+      }
       else if (fp64_set < 0 && o.tol > 0 && rr < o.tol) { status = PPL_OK; break; }
     } else {
       const int need = mixed ? o.min_fp64_sweeps : 0;
       if (o.tol > 0 && rr < o.tol && fp64_sweeps >= need) { status = PPL_OK; break; }
     }
     r_prev = rr;
+    if (diis_on && sweeps < o.max_sweeps) {
+      if (restart) {     // FP64 sweeps start a new subspace from this sweep's amplitudes
+        sub.clear();
+        slot = -1;
+      } else {
+        PPL_TRY(diis_step());
+      }
+    }
   }
   if (o.tol <= 0 && status == PPL_E_NOCONV) status = PPL_OK;   // fixed sweep count requested
   PPL_TRY(unpack_t(st, p->o, p->v, s64, p->ldp, a64, p->ldm, t2));
@@ -1256,6 +1380,7 @@ int ppl_batch_plan(int32_t n, const ppl_desc_t* descs, ppl_batch_t* out) {
       return fail(PPL_E_ARG, "all instances need the same precision and stream");
     }
     d.keep_fp64 = 0;
+    d.diis_max = 0;                      // batched instances are contracted, not iterated
     if (d.hbm_budget == 0) d.hbm_budget = (uint64_t)1 << 62;
     if (d.build_scratch == 0) d.build_scratch = (uint64_t)256 << 20;   // builds run one instance at a time
     ppl_plan_t p = nullptr;

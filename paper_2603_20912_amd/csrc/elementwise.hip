@@ -415,11 +415,15 @@ __device__ inline double denom(const double* e_occ, const double* e_vir, int ij,
 // mode 0: MP2 start   S' = (2-d_ab) VS / D, A' = 2 VA / D, energy of the result
 // mode 1: Jacobi update from R+- (type Tr); residual^2, energy, non-finite count
 // mode 2: energy of the current S'/A' only
-template <int MODE, class Tr>
+// SAVE (mode 1 only): also write the new amplitudes and the error (new - old), both
+// in the packed S'/A' scaling, to one DIIS slot each (plus part, then minus part at
+// offset Np * ldp); padding columns of the slots are not written.
+template <int MODE, class Tr, bool SAVE = false>
 __global__ void __launch_bounds__(kReduceThreads)
 sweep_kernel(PairGeom g, const double* __restrict__ e_occ, const double* __restrict__ e_vir,
              const double* __restrict__ vs, const double* __restrict__ va, const Tr* __restrict__ rp,
-             const Tr* __restrict__ rm, double* sp, double* am, double* partials) {
+             const Tr* __restrict__ rm, double* sp, double* am, double* partials,
+             double* __restrict__ tslot = nullptr, double* __restrict__ eslot = nullptr) {
   double r2 = 0.0, en = 0.0, bad = 0.0;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -443,6 +447,10 @@ sweep_kernel(PairGeom g, const double* __restrict__ e_occ, const double* __restr
       const double ds = snew - sold;
       r2 += w * ds * ds;
       sp[x] = wab * snew;
+      if (SAVE) {
+        tslot[x] = wab * snew;
+        eslot[x] = wab * ds;
+      }
     } else {
       snew = sp[x] / wab;
     }
@@ -465,6 +473,10 @@ sweep_kernel(PairGeom g, const double* __restrict__ e_occ, const double* __restr
       const double da = anew - 0.5 * am[x];
       r2 += 4.0 * da * da;
       am[x] = 2.0 * anew;
+      if (SAVE) {
+        tslot[totp + x] = 2.0 * anew;
+        eslot[totp + x] = 2.0 * da;
+      }
     } else {
       anew = 0.5 * am[x];
     }
@@ -505,11 +517,139 @@ int mp2_start(hipStream_t s, int o, int v, const double* e_occ, const double* e_
 int update_sweep(hipStream_t s, int acc_prec, int o, int v, const double* e_occ, const double* e_vir,
                  const double* vs, const double* va, const void* rp, const void* rm, int64_t ldp,
                  int64_t ldm, double* sp, double* am, const int* tab_op, const int* tab_om,
-                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out) {
+                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out,
+                 double* tslot, double* eslot) {
   PairGeom g = geom(o, v, ldp, ldm, tab_op, tab_om, tab_vp, tab_vm);
+  if (tslot && eslot) {
+    if (acc_prec == PPL_FP64)
+      hipLaunchKernelGGL((sweep_kernel<1, double, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, g,
+                         e_occ, e_vir, vs, va, (const double*)rp, (const double*)rm, sp, am, partials, tslot,
+                         eslot);
+    else
+      hipLaunchKernelGGL((sweep_kernel<1, float, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, g,
+                         e_occ, e_vir, vs, va, (const float*)rp, (const float*)rm, sp, am, partials, tslot,
+                         eslot);
+    PPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, kReduceBlocks,
+                       red_out);
+    PPL_LAUNCH_CHECK();
+    return PPL_OK;
+  }
   if (acc_prec == PPL_FP64)
     return sweep_launch<1, double>(s, g, e_occ, e_vir, vs, va, rp, rm, sp, am, partials, red_out);
   return sweep_launch<1, float>(s, g, e_occ, e_vir, vs, va, rp, rm, sp, am, partials, red_out);
+}
+
+// ------------------------------------------------------------------ DIIS subspace
+// Inner products <e_new, e_i> over the full o x o x v x v tensors, from the packed
+// slots: a "+" entry of S' scaling carries weight (2 - d_ij) / (2 - d_ab) (its
+// full-tensor multiplicity over the square of its packing factor), a "-" entry of A'
+// scaling weight 1 (four entries, each half of A').
+__global__ void __launch_bounds__(kReduceThreads)
+diis_dots_kernel(PairGeom g, const double* __restrict__ E, int64_t slot_n, DiisSet set, int knew,
+                 double* partials) {
+  double acc[kDiisMax];
+#pragma unroll
+  for (int i = 0; i < kDiisMax; ++i) acc[i] = 0.0;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const double* en = E + knew * slot_n;
+  const int64_t totp = g.Np * g.ldp;
+  for (int64_t x = tid0; x < totp; x += st) {
+    const int64_t q = x / g.ldp, p = x - q * g.ldp;
+    if (p >= g.Pp) continue;
+    const int ij = g.tab_op[q], ab = g.tab_vp[p];
+    const double w = (pair_first(ij) == pair_second(ij) ? 1.0 : 2.0) /
+                     (pair_first(ab) == pair_second(ab) ? 1.0 : 2.0);
+    const double a = w * en[x];
+#pragma unroll
+    for (int i = 0; i < kDiisMax; ++i)
+      if (i < set.n) acc[i] += a * E[set.id[i] * slot_n + x];
+  }
+  const int64_t totm = g.Nm * g.ldm;
+  for (int64_t x = tid0; x < totm; x += st) {
+    const int64_t p = x % g.ldm;
+    if (p >= g.Pm) continue;
+    const double a = en[totp + x];
+#pragma unroll
+    for (int i = 0; i < kDiisMax; ++i)
+      if (i < set.n) acc[i] += a * E[set.id[i] * slot_n + totp + x];
+  }
+  __shared__ double sh[kDiisMax][kReduceThreads];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kDiisMax; ++i) sh[i][tid] = acc[i];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int i = 0; i < kDiisMax; ++i) sh[i][tid] += sh[i][tid + w];
+    __syncthreads();
+  }
+  if (tid < kDiisMax) partials[blockIdx.x * kDiisMax + tid] = sh[tid][0];
+}
+
+__global__ void diis_final_kernel(const double* __restrict__ partials, int nblocks, double* out) {
+  __shared__ double sh[kDiisMax][kReduceThreads];
+  const int tid = threadIdx.x;
+  double acc[kDiisMax];
+  for (int i = 0; i < kDiisMax; ++i) acc[i] = 0.0;
+  for (int b = tid; b < nblocks; b += kReduceThreads)
+    for (int i = 0; i < kDiisMax; ++i) acc[i] += partials[b * kDiisMax + i];
+  for (int i = 0; i < kDiisMax; ++i) sh[i][tid] = acc[i];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int i = 0; i < kDiisMax; ++i) sh[i][tid] += sh[i][tid + w];
+    __syncthreads();
+  }
+  if (tid < kDiisMax) out[tid] = sh[tid][0];
+}
+
+int diis_dots(hipStream_t s, int o, int v, int64_t ldp, int64_t ldm, const int* tab_op, const int* tab_om,
+              const int* tab_vp, const int* tab_vm, const double* E, int64_t slot_n, const DiisSet& set,
+              int knew, double* partials, double* out) {
+  if (set.n < 1 || set.n > kDiisMax) return fail(PPL_E_ARG, "DIIS set of %d vectors", set.n);
+  PairGeom g = geom(o, v, ldp, ldm, tab_op, tab_om, tab_vp, tab_vm);
+  hipLaunchKernelGGL(diis_dots_kernel, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, g, E, slot_n, set, knew,
+                     partials);
+  PPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(diis_final_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, kReduceBlocks, out);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// S'/A' = sum_i c_i T_i over the slots of the set; padding columns set to zero.
+__global__ void diis_combine_kernel(PairGeom g, const double* __restrict__ T, int64_t slot_n, DiisSet set,
+                                    double* sp, double* am) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t totp = g.Np * g.ldp;
+  for (int64_t x = tid0; x < totp; x += st) {
+    const int64_t p = x % g.ldp;
+    double y = 0.0;
+    if (p < g.Pp)
+      for (int i = 0; i < set.n; ++i) y += set.c[i] * T[set.id[i] * slot_n + x];
+    sp[x] = y;
+  }
+  const int64_t totm = g.Nm * g.ldm;
+  for (int64_t x = tid0; x < totm; x += st) {
+    const int64_t p = x % g.ldm;
+    double y = 0.0;
+    if (p < g.Pm)
+      for (int i = 0; i < set.n; ++i) y += set.c[i] * T[set.id[i] * slot_n + totp + x];
+    am[x] = y;
+  }
+}
+
+int diis_combine(hipStream_t s, int o, int v, int64_t ldp, int64_t ldm, const double* T, int64_t slot_n,
+                 const DiisSet& set, double* sp, double* am) {
+  if (set.n < 1 || set.n > kDiisMax) return fail(PPL_E_ARG, "DIIS set of %d vectors", set.n);
+  PairGeom g = geom(o, v, ldp, ldm, nullptr, nullptr, nullptr, nullptr);
+  const int64_t total = std::max(g.Np * ldp, g.Nm * ldm);
+  hipLaunchKernelGGL(diis_combine_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g, T, slot_n, set, sp, am);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
 }
 
 int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va, const double* sp,

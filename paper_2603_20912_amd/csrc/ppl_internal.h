@@ -124,6 +124,10 @@ struct ppl_plan_s {
   ppl::Region xov;                     // staged occupied-virtual block [(i,a)][ldx] (FP64)
   ppl::Region tab_vp, tab_vm, tab_op, tab_om;  // pair tables (int32)
   ppl::Region red;                     // reduction partials
+  int diis_max = 0;                    // DIIS subspace capacity
+  int64_t diis_slot_n = 0;             // doubles per DIIS slot: S' rows [N+][ldp], then A' rows [N-][ldm]
+  ppl::Region diis_t, diis_e;          // diis_max slots of amplitudes t' and of errors t' - t (S'/A' scaling)
+  ppl::Region diis_red;                // DIIS inner-product partials and results
   ppl::Region tiles;                   // per-batch (row tile, column tile) lists of the build GEMM (int32 pairs)
   std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
   std::vector<int64_t> tiles_off;      // element offset of each batch's list in `tiles`
@@ -242,10 +246,28 @@ int mp2_start(hipStream_t s, int o, int v, const double* e_occ, const double* e_
               double* red_out);
 // Jacobi update in packed space with FP64 residual^2 / energy partial sums
 // (red_out[0] = r^2, red_out[1] = E, red_out[2] = non-finite count)
+// tslot / eslot (both or neither): DIIS slots that also receive the new amplitudes and
+// the error new - old in the packed scaling (padding columns untouched)
 int update_sweep(hipStream_t s, int acc_prec, int o, int v, const double* e_occ, const double* e_vir,
                  const double* vs, const double* va, const void* rp, const void* rm, int64_t ldp,
                  int64_t ldm, double* sp, double* am, const int* tab_op, const int* tab_om,
-                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out);
+                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out,
+                 double* tslot = nullptr, double* eslot = nullptr);
+// DIIS: the vectors of a subspace (slot ids) and their extrapolation coefficients
+constexpr int kDiisMax = 16;
+static_assert(kDiisMax == PPL_DIIS_MAX, "one DIIS capacity limit");
+struct DiisSet {
+  int n;
+  int id[kDiisMax];
+  double c[kDiisMax];
+};
+// out[i] = <E_knew, E_id[i]> over the full tensors, i < set.n (partials: kReduceBlocks x kDiisMax)
+int diis_dots(hipStream_t s, int o, int v, int64_t ldp, int64_t ldm, const int* tab_op, const int* tab_om,
+              const int* tab_vp, const int* tab_vm, const double* E, int64_t slot_n, const DiisSet& set,
+              int knew, double* partials, double* out);
+// S'/A' = sum_i c_i T_id[i], zero padding
+int diis_combine(hipStream_t s, int o, int v, int64_t ldp, int64_t ldm, const double* T, int64_t slot_n,
+                 const DiisSet& set, double* sp, double* am);
 // energy of the current packed amplitudes (red_out[1] = E)
 int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va, const double* sp,
                 const double* am, int64_t ldp, int64_t ldm, const int* tab_op, const int* tab_om,

@@ -92,6 +92,20 @@ def test_streaming_plan_of_the_largest_benchmark_shape(P):
     assert j["max_step_pairs"] < i["max_step_pairs"] and j["n_batches"] > i["n_batches"]
 
 
+def test_diis_slots_in_the_workspace(P):
+    o, v, naux = 20, 200, 600
+    base = plan_info(P, o, v, naux, hbm_budget=64 << 30)
+    d8 = plan_info(P, o, v, naux, hbm_budget=64 << 30, diis_max=8)
+    ldp, ldm = (20100 + 63) // 64 * 64, (19900 + 63) // 64 * 64
+    slot = (210 * ldp + 190 * ldm) * 8            # one packed FP64 S'/A' vector
+    extra = d8["workspace_bytes"] - base["workspace_bytes"]
+    assert 2 * 8 * slot <= extra <= 2 * 8 * slot + (1024 + 1) * 16 * 8 + 3 * 256
+    for bad in (-1, 17):
+        with pytest.raises(P.PPLError) as e:
+            plan_info(P, o, v, naux, hbm_budget=64 << 30, diis_max=bad)
+        assert e.value.code == -1
+
+
 def test_budget_too_small_is_nomem(P):
     with pytest.raises(P.PPLError) as e:
         plan_info(P, 20, 200, 600, hbm_budget=1 << 20)
