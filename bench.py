@@ -82,7 +82,8 @@ def measured_traffic(config):
 def study_c3(args):
     """Time to an amplitude residual of 1e-7 at (40, 400, 1200), contractive generator
     seed 2: FP64, BF16x3 / FP32 sweeps refined in FP64, and the same from the learned
-    start; plus single-evaluation errors of the low-precision GEMMs."""
+    start, each also with DIIS (subspace 8); plus single-evaluation errors of the
+    low-precision GEMMs."""
     import numpy as np
     import torch
 
@@ -100,18 +101,28 @@ def study_c3(args):
     small = ppl_synth.make_system(4, 24, 72, 99, "contractive")
     for start, prec, keep in (("mp2", "fp64", False), ("mp2", "bf16x3", True), ("mp2", "fp32", True)):
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep)
+        Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=8)
     if mlp is not None:
         Lr.time_to_tol(small, "learned", mlp=mlp, prec="bf16x3", keep_fp64=True)
-    runs = [("fp64", "mp2", "fp64", False), ("bf16x3+fp64", "mp2", "bf16x3", True),
-            ("fp32+fp64", "mp2", "fp32", True)]
+    runs = [("fp64", "mp2", "fp64", False, 0), ("bf16x3+fp64", "mp2", "bf16x3", True, 0),
+            ("fp32+fp64", "mp2", "fp32", True, 0)]
     if mlp is not None:
-        runs += [("bf16x3+fp64 learned", "learned", "bf16x3", True), ("fp64 learned", "learned", "fp64", False)]
+        runs += [("bf16x3+fp64 learned", "learned", "bf16x3", True, 0), ("fp64 learned", "learned", "fp64", False, 0)]
+    # the same with DIIS (subspace of 8)
+    runs += [("fp64 diis", "mp2", "fp64", False, 8), ("bf16x3+fp64 diis", "mp2", "bf16x3", True, 8),
+             ("fp32+fp64 diis", "mp2", "fp32", True, 8)]
+    if mlp is not None:
+        runs += [("bf16x3+fp64 learned diis", "learned", "bf16x3", True, 8),
+                 ("fp64 learned diis", "learned", "fp64", False, 8)]
     out = {"config": {"o": o, "v": v, "naux": naux, "generator": "contractive", "seed": 2, "tol": 1e-7}}
     ref_t, ref_E = None, None
-    for label, start, prec, keep in runs:
-        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep)
+    for label, start, prec, keep, diis in runs:
+        torch.cuda.empty_cache()
+        free_gib = torch.cuda.mem_get_info()[0] / 2 ** 30
+        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep, diis=diis)
         row = {"seconds": round(rep["seconds"], 3), "sweeps_lp": rep["sweeps_lp"], "sweeps_fp64": rep["sweeps_fp64"],
-               "residual": rep["residual"], "energy": rep["energy"], "status": rep["status"]}
+               "residual": rep["residual"], "energy": rep["energy"], "status": rep["status"],
+               "resident": rep["resident"], "free_GiB_before": round(free_gib, 1), "kernel_ms": rep["kernel_ms"]}
         if ref_t is None:
             ref_t, ref_E = t.clone(), rep["energy"]
         else:

@@ -112,8 +112,15 @@ class PPL:
 
     def close(self):
         if getattr(self, "plan", None) is not None:
+            # the plan's enqueued work must end before its workspace goes back to torch
+            self.stream.synchronize()
             ppl_destroy(self.plan)
             self.plan = None
+        if getattr(self, "workspace", None) is not None:
+            # hand the (large) workspace back to the device at once: left in torch's cache,
+            # its segment could be split for a later small tensor and then never released
+            self.workspace = None
+            torch.cuda.empty_cache()
 
     def __del__(self):
         try:
@@ -160,8 +167,10 @@ class MLP:
 
     def close(self):
         if getattr(self, "h", None) is not None:
+            self.stream.synchronize()
             ppl_mlp_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -204,8 +213,12 @@ class Batch:
 
     def close(self):
         if getattr(self, "h", None) is not None:
+            self.stream.synchronize()
             ppl_batch_destroy(self.h)
             self.h = None
+        if getattr(self, "workspace", None) is not None:
+            self.workspace = None
+            torch.cuda.empty_cache()
 
     def __del__(self):
         try:

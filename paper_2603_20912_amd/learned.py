@@ -64,35 +64,40 @@ def train(mlp: MLP, X, Y, steps=2000, batch=4096, lr=1e-3, seed=0, log_every=0):
 
 
 def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, max_sweeps=300,
-                device="cuda", switch_tol=0.0):
+                device="cuda", switch_tol=0.0, diis=0):
     """Wall time and sweeps from inputs in HBM to a converged residual below tol.
 
     start: 'mp2' (plain), 'learned' (network guess, unchecked) or 'checked'
     (network guess, restarted from MP2 when its first residual is larger).
+    diis >= 2 accelerates the sweeps with a DIIS subspace of that size.
     The timed region covers the first-order amplitudes, the network guess, the
     integral builds and every sweep.
     """
     o, v, naux = sysd["o"], sysd["v"], sysd["naux"]
     d = upload_system(sysd, device)
-    eng = PPL(o, v, naux, prec=prec, keep_fp64=keep_fp64)
+    eng = PPL(o, v, naux, prec=prec, keep_fp64=keep_fp64, diis_max=diis)
     t = torch.empty((o, o, v, v), dtype=torch.float64, device=device)
     tm = torch.empty_like(t) if start != "mp2" else None
     torch.cuda.synchronize()
+    eng.profile(True)
     t0 = time.perf_counter()
     if start == "mp2":
         rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t, max_sweeps=max_sweeps, tol=tol, start="mp2",
-                          switch_tol=switch_tol, raise_on_status=False)
+                          switch_tol=switch_tol, raise_on_status=False, diis=diis)
     else:
         eng.mp2(d["L"], d["e_occ"], d["e_vir"], tm)
         mlp.guess(eng, tm, d["e_occ"], d["e_vir"], t2_out=t)
         rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t, max_sweeps=max_sweeps, tol=tol,
                           start="checked" if start == "checked" else "given", switch_tol=switch_tol,
-                          raise_on_status=False)
+                          raise_on_status=False, diis=diis)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rep = dict(rep)
     rep["seconds"] = dt
     rep["sweeps"] = rep["sweeps_lp"] + rep["sweeps_fp64"]
+    rep["resident"] = eng.info["resident"]
+    rep["kernel_ms"] = {k: round(x["ms"], 1) for k, x in eng.profile_read().items()}
+    eng.profile(False)
     eng.close()
     return rep, t
 
