@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
-    "ppl_sampled", "ppl_entry", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
+    "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
     "jacobi", "jacobi_diis", "fixed_point", "spectral_radius", "nominal_flops",
 ]
 
@@ -137,6 +137,39 @@ def ppl_sampled(L: np.ndarray, o: int, t: np.ndarray, idx) -> np.ndarray:
     for k, (i, j, a, b) in enumerate(idx):
         out[k] = ppl_entry(Lvv[:, a, :], Lvv[:, b, :], t[i, j])
     return out
+
+
+# ---------------------------------------------------------------------------
+# terms of the CCSD residual next to the ladder (not part of the paper's hot
+# path; standard closed-shell CCSD, written from the definitions)
+# ---------------------------------------------------------------------------
+def oo_block(L: np.ndarray, o: int) -> np.ndarray:
+    """Occupied-occupied block L[P, k, i] of the Cholesky vectors."""
+    return L[:, :o, :o]
+
+
+def tau(t2: np.ndarray, t1: np.ndarray) -> np.ndarray:
+    """tau_ij^ab = t_ij^ab + t_i^a t_j^b, the amplitudes that carry the singles into the
+    particle-particle ladder of CCSD (t1 is [i][a])."""
+    t1 = np.asarray(t1, dtype=np.float64)
+    return np.asarray(t2, dtype=np.float64) + t1[:, None, :, None] * t1[None, :, None, :]
+
+
+def ppl_tau(L: np.ndarray, o: int, t2: np.ndarray, t1: np.ndarray) -> np.ndarray:
+    """The ladder term of CCSD: R_ij^ab = sum_cd (ac|bd) tau_ij^cd."""
+    return ppl(L, o, tau(t2, t1))
+
+
+def hhl(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
+    """Hole-hole ladder R_ij^ab = sum_kl (ki|lj) t_kl^ab with (ki|lj) = sum_P L^P_ki L^P_lj."""
+    Loo = np.asarray(oo_block(np.asarray(L, dtype=np.float64), o))
+    naux = Loo.shape[0]
+    X = Loo.reshape(naux, o * o)                       # [P][(k,i)]
+    W = (X.T @ X).reshape(o, o, o, o)                  # W[k, i, l, j] = (ki|lj)
+    t = np.asarray(t, dtype=np.float64)
+    v = t.shape[2]
+    M = W.transpose(1, 3, 0, 2).reshape(o * o, o * o)  # [(i,j)][(k,l)]
+    return (M @ t.reshape(o * o, v * v)).reshape(o, o, v, v)
 
 
 # ---------------------------------------------------------------------------

@@ -314,3 +314,85 @@ def test_planted_diis_mistakes_are_caught(mistake):
     t, hist = _diis_variant(*args, mistake)
     # the affine-termination pin: exact fixed point within 8 sweeps
     assert not (len(hist) <= 8 and hist[-1] < 1e-13 and rel(t, O.fixed_point(*args)) < 1e-13)
+
+
+# ---------------------------------------------------------------- CCSD terms next to the ladder
+def test_hhl_matches_loops():
+    o, v, naux = 3, 2, 2
+    s = S.make_system(o, v, naux, 5)
+    L = s["L"]
+    t = general_t(o, v, 6)
+    R = np.zeros((o, o, v, v))
+    for i in range(o):
+        for j in range(o):
+            for a in range(v):
+                for b in range(v):
+                    for k in range(o):
+                        for l in range(o):
+                            for P in range(naux):
+                                R[i, j, a, b] += L[P, k, i] * L[P, l, j] * t[k, l, a, b]
+    assert rel(O.hhl(L, o, t), R) < 1e-14
+
+
+def test_hhl_special_cases():
+    # one Cholesky vector: R_ab = Loo^T T_ab Loo for every virtual pair (a, b)
+    o, v = 4, 3
+    s = S.make_system(o, v, 1, 8)
+    t = general_t(o, v, 9)
+    Loo = s["L"][0, :o, :o]
+    ref = np.einsum("ki,klab,lj->ijab", Loo, t, Loo)
+    assert rel(O.hhl(s["L"], o, t), ref) < 1e-14
+    # one occupied orbital: R_00^ab = (00|00) t_00^ab
+    s1 = S.make_system(1, 5, 6, 10)
+    t1 = general_t(1, 5, 11)
+    assert rel(O.hhl(s1["L"], 1, t1), np.sum(s1["L"][:, 0, 0] ** 2) * t1) < 1e-14
+    # only the occupied block of L enters
+    s2 = S.make_system(3, 5, 4, 12)
+    L2 = s2["L"].copy()
+    L2[:, 3:, :] *= -7.0
+    L2[:, :, 3:] += 1.0
+    t2 = general_t(3, 5, 13)
+    assert np.array_equal(O.hhl(s2["L"], 3, t2), O.hhl(L2, 3, t2))
+
+
+def test_hhl_keeps_pair_symmetry():
+    o, v, naux = 4, 5, 6
+    s = S.make_system(o, v, naux, 14)
+    t = S.make_amplitudes(o, v, 15)
+    R = O.hhl(s["L"], o, t)
+    assert rel(R, R.transpose(1, 0, 3, 2)) < 1e-14
+
+
+def test_ppl_tau_against_independent_association():
+    o, v, naux = 3, 6, 5
+    s = S.make_system(o, v, naux, 16)
+    t2 = S.make_amplitudes(o, v, 17)
+    t1 = np.random.default_rng(18).standard_normal((o, v))
+    # singles switched off: the plain ladder
+    assert np.array_equal(O.ppl_tau(s["L"], o, t2, np.zeros((o, v))), O.ppl(s["L"], o, t2))
+    # the singles part: sum_cd (ac|bd) t_i^c t_j^d = sum_P (L^P t1^T)_ai (L^P t1^T)_bj
+    Lvv = s["L"][:, o:, o:]
+    Y = Lvv @ t1.T                                   # [P][a][i]
+    quad = np.einsum("Pai,Pbj->ijab", Y, Y)
+    assert rel(O.ppl_tau(s["L"], o, t2, t1) - O.ppl(s["L"], o, t2), quad) < 1e-13
+    # tau keeps the pair symmetry of t2
+    tt = O.tau(t2, t1)
+    assert np.array_equal(tt, tt.transpose(1, 0, 3, 2))
+
+
+def _hhl_swapped_integral(L, o, t):
+    Loo = L[:, :o, :o]
+    W = np.einsum("Pkl,Pij->klij", Loo, Loo)          # (kl|ij) instead of (ki|lj)
+    return np.einsum("klij,klab->ijab", W, t)
+
+
+def _hhl_transposed_amplitudes(L, o, t):
+    return O.hhl(L, o, t.transpose(1, 0, 2, 3))
+
+
+@pytest.mark.parametrize("mutant", [_hhl_swapped_integral, _hhl_transposed_amplitudes])
+def test_planted_hhl_mistakes_are_caught(mutant):
+    o, v, naux = 3, 2, 2
+    s = S.make_system(o, v, naux, 5)
+    t = general_t(o, v, 6)
+    assert rel(mutant(s["L"], o, t), O.hhl(s["L"], o, t)) > 1e-3
