@@ -133,6 +133,28 @@ int ppl_build_batch(ppl_plan_t plan, const double* L, int32_t batch);
  */
 int ppl_contract(ppl_plan_t plan, const double* t2, double* R, double alpha, double beta);
 
+/*
+ * ppl_contract_tau: the ladder term of CCSD, R = beta * R + alpha * PPL(tau) with
+ * tau_ij^cd = t_ij^cd + t_i^c t_j^d (the standard closed-shell CCSD ladder; the paper
+ * treats the doubles part, eq. (vfunction-chol)). t1 is device FP64 [o][v]; tau is
+ * formed while packing, never stored. Same layouts, state and errors as ppl_contract;
+ * PPL_E_ARG for a null t1.
+ */
+int ppl_contract_tau(ppl_plan_t plan, const double* t2, const double* t1, double* R, double alpha,
+                     double beta);
+
+/*
+ * ppl_hhl: the hole-hole ladder of the doubles residual, R = beta * R + alpha * HHL(t2)
+ * with HHL_ij^ab = sum_kl (ki|lj) t_kl^ab and (ki|lj) = sum_P L^P_ki L^P_lj from the
+ * occupied block of L (eq. (cholesky) applied to occupied indices). In the pair space:
+ * W+-_{ij,kl} = ((ki|lj) +- (li|kj)) / 2, a K = N+ (N-) FP64 MFMA contraction against the
+ * packed amplitudes, unpacked with the same signs as ppl_contract. L is device FP64
+ * [naux][o+v][o+v], t2 and R device FP64 [o][o][v][v], t2 pair-symmetric, R not
+ * aliasing t2. Uses the plan's build scratch, so it must not run concurrently with
+ * another call of the same plan; V+- are not needed (any bound plan).
+ */
+int ppl_hhl(ppl_plan_t plan, const double* L, const double* t2, double* R, double alpha, double beta);
+
 /* ------------------------------------------------ linearized doubles iteration */
 #define PPL_START_MP2   0  /* start from t = V / D */
 #define PPL_START_GIVEN 1  /* start from the t2 passed in */

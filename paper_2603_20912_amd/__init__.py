@@ -17,13 +17,14 @@ from ._lib import (ppl_batch_plan, ppl_batch_query, ppl_batch_bind_workspace, pp
 from ._lib import (ppl_mp2, ppl_mlp_create, ppl_mlp_workspace_bytes, ppl_mlp_bind_workspace,
                    ppl_mlp_param_count, ppl_mlp_init, ppl_mlp_set_params, ppl_mlp_get_params, ppl_mlp_grad,
                    ppl_mlp_train_step, ppl_mlp_sigma, ppl_mlp_samples, ppl_mlp_guess, ppl_mlp_destroy,
-                   PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_destroy,
+                   PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_contract_tau, ppl_hhl,
+                   ppl_destroy,
                    ppl_iter_opts_default, ppl_iterate, ppl_last_error, ppl_plan, ppl_plan_query,
                    ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_tile_dims, ppl_version,
                    ppl_set_contract_config, ppl_autotune)
 
 __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace", "ppl_build_batch",
-           "ppl_contract", "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count", "ppl_tile_dims",
+           "ppl_contract", "ppl_contract_tau", "ppl_hhl", "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count", "ppl_tile_dims",
            "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read",
            "ppl_set_contract_config", "ppl_autotune", "ppl_mp2", "MLP", "ppl_mlp_create",
            "ppl_mlp_workspace_bytes", "ppl_mlp_bind_workspace", "ppl_mlp_param_count", "ppl_mlp_init",
@@ -57,10 +58,21 @@ class PPL:
     def build(self, L, batch=-1):
         ppl_build_batch(self.plan, L, batch)
 
-    def contract(self, t2, R=None, alpha=1.0, beta=0.0):
+    def contract(self, t2, R=None, alpha=1.0, beta=0.0, t1=None):
+        """R = beta R + alpha PPL(t2), or PPL(t2 + t1 t1) when singles t1 [o][v] are given."""
         if R is None:
             R = torch.empty_like(t2)
-        ppl_contract(self.plan, t2, R, alpha, beta)
+        if t1 is None:
+            ppl_contract(self.plan, t2, R, alpha, beta)
+        else:
+            ppl_contract_tau(self.plan, t2, t1, R, alpha, beta)
+        return R
+
+    def hhl(self, L, t2, R=None, alpha=1.0, beta=0.0):
+        """R = beta R + alpha sum_kl (ki|lj) t_kl^ab."""
+        if R is None:
+            R = torch.empty_like(t2)
+        ppl_hhl(self.plan, L, t2, R, alpha, beta)
         return R
 
     def iterate(self, L, e_occ, e_vir, t2, max_sweeps=100, tol=1e-7, start="mp2", switch_tol=0.0,

@@ -84,6 +84,8 @@ SIGNATURES = {
     "ppl_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
     "ppl_build_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "ppl_contract": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double]),
+    "ppl_contract_tau": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
+    "ppl_hhl": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "ppl_iter_opts_default": (None, [ctypes.POINTER(ppl_iter_opts_t)]),
     "ppl_iterate": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ppl_iter_opts_t),
                                    ctypes.POINTER(ppl_iter_report_t)]),
@@ -200,6 +202,15 @@ def ppl_build_batch(plan, L, batch=-1):
 
 def ppl_contract(plan, t2, R, alpha=1.0, beta=0.0):
     _check(load().ppl_contract(plan, _ptr(t2), _ptr(R), float(alpha), float(beta)), "ppl_contract")
+
+
+def ppl_contract_tau(plan, t2, t1, R, alpha=1.0, beta=0.0):
+    _check(load().ppl_contract_tau(plan, _ptr(t2), _ptr(t1), _ptr(R), float(alpha), float(beta)),
+           "ppl_contract_tau")
+
+
+def ppl_hhl(plan, L, t2, R, alpha=1.0, beta=0.0):
+    _check(load().ppl_hhl(plan, _ptr(L), _ptr(t2), _ptr(R), float(alpha), float(beta)), "ppl_hhl")
 
 
 def ppl_iter_opts_default() -> ppl_iter_opts_t:

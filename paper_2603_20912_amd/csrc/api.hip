@@ -87,6 +87,36 @@ static int g_acc_bytes(ppl_plan_t p) {
   return w;
 }
 
+// Scratch of the hole-hole ladder, carved from the build scratch G: staged occupied
+// block, (ki|lj), W+- [N+][ldq] / [N-][ldqm], the transposed packed amplitudes
+// [P+][ldq] / [P-][ldqm] and the transposed results of the same shapes.
+struct HhlScratch {
+  int64_t ldq, ldqm;
+  uint64_t xoo, woo, wp, wm, st, at, cp, cm, bytes;
+};
+static HhlScratch hhl_scratch(ppl_plan_t p) {
+  HhlScratch h{};
+  const int64_t o = p->o, Nmq = std::max<int64_t>(p->Nm, 1), Pmq = std::max<int64_t>(p->Pm, 1);
+  h.ldq = pad_ld(p->Np);
+  h.ldqm = pad_ld(Nmq);
+  uint64_t cur = 0;
+  auto take = [&](uint64_t b) {
+    const uint64_t at = cur;
+    cur = align256(cur + b);
+    return at;
+  };
+  h.xoo = take((uint64_t)o * o * p->ldx * 8);
+  h.woo = take((uint64_t)o * o * o * o * 8);
+  h.wp = take((uint64_t)p->Np * h.ldq * 8);
+  h.wm = take((uint64_t)Nmq * h.ldqm * 8);
+  h.st = take((uint64_t)p->Pp * h.ldq * 8);
+  h.at = take((uint64_t)Pmq * h.ldqm * 8);
+  h.cp = take((uint64_t)p->Pp * h.ldq * 8);
+  h.cm = take((uint64_t)Pmq * h.ldqm * 8);
+  h.bytes = cur;
+  return h;
+}
+
 // Assign every workspace region for a given G cap and residency; returns total bytes.
 static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t max_batch_pairs) {
   Layout L;
@@ -114,8 +144,9 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     }
   }
   // build scratch G (accumulator precision) doubles as the (ia|jb) scratch
-  const uint64_t gbytes = std::max<uint64_t>((uint64_t)gcap * v * v * g_acc_bytes(p),
-                                             (uint64_t)(o * v) * (o * v) * 8);
+  const uint64_t gbytes = std::max<uint64_t>(std::max<uint64_t>((uint64_t)gcap * v * v * g_acc_bytes(p),
+                                                               (uint64_t)(o * v) * (o * v) * 8),
+                                             hhl_scratch(p).bytes);
   p->g = L.take(gbytes);
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
   p->rm = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
@@ -644,22 +675,80 @@ int ppl_build_batch(ppl_plan_t p, const double* L, int32_t batch) {
   return PPL_OK;
 }
 
-int ppl_contract(ppl_plan_t p, const double* t2, double* R, double alpha, double beta) {
+}  // extern "C"
+
+namespace ppl {
+static int contract_impl(ppl_plan_t p, const double* t2, const double* t1, double* R, double alpha,
+                         double beta) {
   g_err[0] = 0;
   PPL_TRY(check_bound(p));
   if (!t2 || !R) return fail(PPL_E_ARG, "null t2 or R");
   if ((const void*)t2 == (const void*)R) return fail(PPL_E_ARG, "R may not alias t2");
   OperandSet& s = p->ops[0];
   const int64_t o = p->o, v = p->v;
-  // S' = (2 - d_cd)(t^cd + t^dc)/2, A' = t^cd - t^dc on the i<=j / i<j rows
+  // S' = (2 - d_cd)(t^cd + t^dc)/2, A' = t^cd - t^dc on the i<=j / i<j rows (t + t1 t1 with singles)
   PPL_TRY(pack_pm(p->stream, p->o, p->v, t2, o * v * v, v * v, v, 1, 1.0, 0.5, 1.0, at<double>(p, p->s64),
                   p->ldp, at<double>(p, p->a64), p->ldm, at<int>(p, p->tab_op), at<int>(p, p->tab_om),
-                  at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+                  at<int>(p, p->tab_vp), at<int>(p, p->tab_vm), t1));
   PPL_TRY(refresh_operands(p, s));
   PPL_TRY(contract_packed(p, s));
   PPL_TRY(unpack_r(p->stream, s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, at<void>(p, p->rp),
                    p->ldp, at<void>(p, p->rm), p->ldm, R, alpha, beta));
   return PPL_OK;
+}
+}  // namespace ppl
+
+extern "C" {
+
+int ppl_contract(ppl_plan_t p, const double* t2, double* R, double alpha, double beta) {
+  return contract_impl(p, t2, nullptr, R, alpha, beta);
+}
+
+int ppl_contract_tau(ppl_plan_t p, const double* t2, const double* t1, double* R, double alpha, double beta) {
+  if (!t1) return fail(PPL_E_ARG, "null t1");
+  return contract_impl(p, t2, t1, R, alpha, beta);
+}
+
+int ppl_hhl(ppl_plan_t p, const double* L, const double* t2, double* R, double alpha, double beta) {
+  g_err[0] = 0;
+  PPL_TRY(check_bound(p));
+  if (!L || !t2 || !R) return fail(PPL_E_ARG, "null device pointer");
+  if ((const void*)t2 == (const void*)R) return fail(PPL_E_ARG, "R may not alias t2");
+  const HhlScratch h = hhl_scratch(p);
+  if (h.bytes > p->g.bytes)
+    return fail(PPL_E_STATE, "hole-hole scratch needs %llu B, the plan has %llu B",
+                (unsigned long long)h.bytes, (unsigned long long)p->g.bytes);
+  hipStream_t st = p->stream;
+  char* g = at<char>(p, p->g);
+  double *xoo = (double*)(g + h.xoo), *woo = (double*)(g + h.woo), *wp = (double*)(g + h.wp),
+         *wm = (double*)(g + h.wm), *sT = (double*)(g + h.st), *aT = (double*)(g + h.at),
+         *cp = (double*)(g + h.cp), *cm = (double*)(g + h.cm);
+  const int64_t o = p->o, v = p->v, oo = o * o;
+  const int *tab_op = at<int>(p, p->tab_op), *tab_om = at<int>(p, p->tab_om), *tab_vp = at<int>(p, p->tab_vp),
+            *tab_vm = at<int>(p, p->tab_vm);
+  ProfScope ps(p, PPL_PROF_OTHER, 2.0 * (double)p->Pp * p->Np * p->Np + 2.0 * (double)p->Pm * p->Nm * p->Nm);
+  // (ki|lj) = sum_P L^P_ki L^P_lj as Woo[(k,i)][(l,j)]
+  PPL_TRY(stage_oo(st, L, p->o, p->v, p->naux, p->ldx, xoo));
+  PPL_TRY(gemm_store_f64(st, oo, oo, p->ldx, xoo, p->ldx, xoo, p->ldx, woo, oo));
+  // W+-_{ij,kl} = ((ki|lj) +- (li|kj)) / 2 on the i<=j (i<j) rows and k<=l (k<l) columns
+  PPL_TRY(pack_pm(st, p->o, p->o, woo, oo, 1, o * oo, o, 0.5, 0.5, 0.5, wp, h.ldq, wm, h.ldqm, tab_op, tab_om,
+                  tab_op, tab_om));
+  // transposed packed amplitudes: sT[(a<=b)][(k<=l)] = (2 - d_kl) s_kl^ab, aT[(a<b)][(k<l)] = 2 a_kl^ab
+  PPL_TRY(pack_pm(st, p->v, p->o, t2, v, 1, o * v * v, v * v, 1.0, 0.5, 1.0, sT, h.ldq, aT, h.ldqm, tab_vp, tab_vm,
+                  tab_op, tab_om));
+  // C+ = sT W+^T, C- = aT W-^T (K = occupied pairs)
+  int tile = -1, sp = 1;
+  contract_choose(PPL_FP64, p->Pp, p->Np, h.ldq, 1, &tile, &sp);
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, p->Pp, p->Np, h.ldq, sT, nullptr, h.ldq, wp, nullptr, h.ldq, cp, h.ldq,
+                        0, 1, nullptr, h.ldq, 0));
+  if (p->Nm > 0) {
+    tile = -1;
+    sp = 1;
+    contract_choose(PPL_FP64, p->Pm, p->Nm, h.ldqm, 1, &tile, &sp);
+    PPL_TRY(gemm_contract(st, PPL_FP64, tile, p->Pm, p->Nm, h.ldqm, aT, nullptr, h.ldqm, wm, nullptr, h.ldqm, cm,
+                          h.ldqm, 0, 1, nullptr, h.ldqm, 0));
+  }
+  return unpack_rt(st, p->o, p->v, cp, h.ldq, cm, h.ldqm, R, alpha, beta);
 }
 
 int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,

@@ -215,10 +215,11 @@ int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void
 }
 
 // ------------------------------------------------------------------ generic (i,j,a,b) -> +/- packing
+// With t1 ([i][a], row length v1) the packed tensor is X_ij^ab + t1_i^a t1_j^b.
 __global__ void pack_plus_kernel(const double* __restrict__ X, int64_t si, int64_t sj, int64_t sa,
                                  int64_t sb, double s_off, double s_diag, double* plus, int64_t Np,
                                  int64_t Pp, int64_t ldp, const int* __restrict__ tab_op,
-                                 const int* __restrict__ tab_vp) {
+                                 const int* __restrict__ tab_vp, const double* __restrict__ t1, int64_t v1) {
   const int64_t total = Np * ldp;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
@@ -228,7 +229,11 @@ __global__ void pack_plus_kernel(const double* __restrict__ X, int64_t si, int64
       const int ij = tab_op[q], ab = tab_vp[p];
       const int i = pair_first(ij), j = pair_second(ij), a = pair_first(ab), b = pair_second(ab);
       const int64_t base = i * si + j * sj;
-      const double xab = X[base + a * sa + b * sb], xba = X[base + b * sa + a * sb];
+      double xab = X[base + a * sa + b * sb], xba = X[base + b * sa + a * sb];
+      if (t1) {
+        xab += t1[i * v1 + a] * t1[j * v1 + b];
+        xba += t1[i * v1 + b] * t1[j * v1 + a];
+      }
       val = (a == b ? s_diag : s_off) * (xab + xba);
     }
     plus[x] = val;
@@ -238,7 +243,7 @@ __global__ void pack_plus_kernel(const double* __restrict__ X, int64_t si, int64
 __global__ void pack_minus_kernel(const double* __restrict__ X, int64_t si, int64_t sj, int64_t sa,
                                   int64_t sb, double am, double* minus, int64_t Nm, int64_t Pm,
                                   int64_t ldm, const int* __restrict__ tab_om,
-                                  const int* __restrict__ tab_vm) {
+                                  const int* __restrict__ tab_vm, const double* __restrict__ t1, int64_t v1) {
   const int64_t total = Nm * ldm;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
@@ -248,7 +253,12 @@ __global__ void pack_minus_kernel(const double* __restrict__ X, int64_t si, int6
       const int ij = tab_om[q], ab = tab_vm[p];
       const int i = pair_first(ij), j = pair_second(ij), a = pair_first(ab), b = pair_second(ab);
       const int64_t base = i * si + j * sj;
-      val = am * (X[base + a * sa + b * sb] - X[base + b * sa + a * sb]);
+      double xab = X[base + a * sa + b * sb], xba = X[base + b * sa + a * sb];
+      if (t1) {
+        xab += t1[i * v1 + a] * t1[j * v1 + b];
+        xba += t1[i * v1 + b] * t1[j * v1 + a];
+      }
+      val = am * (xab - xba);
     }
     minus[x] = val;
   }
@@ -257,17 +267,21 @@ __global__ void pack_minus_kernel(const double* __restrict__ X, int64_t si, int6
 int pack_pm(hipStream_t s, int o, int v, const double* X, int64_t si, int64_t sj, int64_t sa,
             int64_t sb, double sp_off, double sp_diag, double am, double* plus, int64_t ldp,
             double* minus, int64_t ldm, const int* tab_op, const int* tab_om, const int* tab_vp,
-            const int* tab_vm) {
+            const int* tab_vm, const double* t1) {
   const int64_t Np = npairs_plus(o), Nm = npairs_minus(o), Pp = npairs_plus(v), Pm = npairs_minus(v);
   hipLaunchKernelGGL(pack_plus_kernel, dim3(grid_for(Np * ldp, 256)), dim3(256), 0, s, X, si, sj, sa,
-                     sb, sp_off, sp_diag, plus, Np, Pp, ldp, tab_op, tab_vp);
+                     sb, sp_off, sp_diag, plus, Np, Pp, ldp, tab_op, tab_vp, t1, (int64_t)v);
   PPL_LAUNCH_CHECK();
-  if (Nm > 0) {
+  if (Nm > 0 && Pm > 0) {
     hipLaunchKernelGGL(pack_minus_kernel, dim3(grid_for(Nm * ldm, 256)), dim3(256), 0, s, X, si, sj,
-                       sa, sb, am, minus, Nm, Pm, ldm, tab_om, tab_vm);
+                       sa, sb, am, minus, Nm, Pm, ldm, tab_om, tab_vm, t1, (int64_t)v);
     PPL_LAUNCH_CHECK();
   }
   return PPL_OK;
+}
+
+int stage_oo(hipStream_t s, const double* L, int o, int v, int naux, int64_t ldx, double* xoo) {
+  return stage_launch<PPL_FP64>(s, L, o + v, naux, 0, 0, o, o, ldx, xoo, nullptr);
 }
 
 // ------------------------------------------------------------------ FP64 rows -> operand precision
@@ -328,6 +342,39 @@ int unpack_r(hipStream_t s, int acc_prec, int o, int v, const void* rp, int64_t 
   else
     hipLaunchKernelGGL(unpack_r_kernel<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v,
                        (const float*)rp, ldp, (const float*)rm, ldm, R, alpha, beta);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// R = beta R + alpha (C+ +- C-) from transposed packed results: C+[(a<=b)][(i<=j)] and
+// C-[(a<b)][(i<j)] (rows of ldcp / ldcm doubles).
+__global__ void unpack_rt_kernel(int o, int v, const double* __restrict__ cp, int64_t ldcp,
+                                 const double* __restrict__ cm, int64_t ldcm, double* R, double alpha,
+                                 double beta) {
+  const int64_t total = (int64_t)o * o * v * v;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int b = (int)(x % v);
+    const int64_t y = x / v;
+    const int a = (int)(y % v);
+    const int64_t z = y / v;
+    const int j = (int)(z % o), i = (int)(z / o);
+    const int i0 = i < j ? i : j, j0 = i < j ? j : i;
+    const int a0 = a < b ? a : b, b0 = a < b ? b : a;
+    double r = cp[pair_plus(a0, b0, v) * ldcp + pair_plus(i0, j0, o)];
+    if (i != j && a != b) {
+      const double m = cm[pair_minus(a0, b0, v) * ldcm + pair_minus(i0, j0, o)];
+      r += ((i < j) == (a < b)) ? m : -m;
+    }
+    R[x] = (beta == 0.0) ? alpha * r : alpha * r + beta * R[x];
+  }
+}
+
+int unpack_rt(hipStream_t s, int o, int v, const double* cp, int64_t ldcp, const double* cm, int64_t ldcm,
+              double* R, double alpha, double beta) {
+  const int64_t total = (int64_t)o * o * v * v;
+  hipLaunchKernelGGL(unpack_rt_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v, cp, ldcp, cm, ldcm, R,
+                     alpha, beta);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

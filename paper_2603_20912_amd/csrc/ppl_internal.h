@@ -226,10 +226,16 @@ int fill_tables(hipStream_t s, int o, int v, int* tab_vp, int* tab_vm, int* tab_
 // generic pack of an (i,j,a,b)-indexed FP64 tensor into + / - packed rows:
 //   plus [q(i<=j)][p(a<=b)] = (a<b ? sp_off : sp_diag) * (X^ab + X^ba)
 //   minus[q(i<j)][p(a<b)]   = am * (X^ab - X^ba)
+// where, with t1 ([i][a], row length v), X_ij^ab stands for X_ij^ab + t1_i^a t1_j^b
 int pack_pm(hipStream_t s, int o, int v, const double* X, int64_t si, int64_t sj, int64_t sa,
             int64_t sb, double sp_off, double sp_diag, double am, double* plus, int64_t ldp,
             double* minus, int64_t ldm, const int* tab_op, const int* tab_om, const int* tab_vp,
-            const int* tab_vm);
+            const int* tab_vm, const double* t1 = nullptr);
+// staging: Xoo[(k,i)][P] = L[P][k][i] (FP64)
+int stage_oo(hipStream_t s, const double* L, int o, int v, int naux, int64_t ldx, double* xoo);
+// R = beta R + alpha (C+ +- C-) from C+[(a<=b)][(i<=j)], C-[(a<b)][(i<j)]
+int unpack_rt(hipStream_t s, int o, int v, const double* cp, int64_t ldcp, const double* cm, int64_t ldcm,
+              double* R, double alpha, double beta);
 // convert FP64 packed rows to an operand precision (FP32 or BF16 hi/lo), zero padding kept
 int convert_rows(hipStream_t s, int prec, const double* src, int64_t rows, int64_t cols, int64_t ld,
                  void* dst, void* dst_lo);

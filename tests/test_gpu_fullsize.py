@@ -129,3 +129,31 @@ def test_benchmark_shape_streaming_sampled(P):
     assert all(torch.isfinite(R[i]).all().item() for i in range(o))
     del L, t, R, sysd
     torch.cuda.empty_cache()
+
+
+def test_c3_hhl_and_tau_sampled(P, c3):
+    s, t, idx, _ = c3
+    o, v, naux = s["o"], s["v"], s["naux"]
+    say("hhl and contract_tau fp64 (40,400,1200) sampled")
+    t1 = 0.05 * np.random.default_rng(19).standard_normal((o, v))
+    eng = P.PPL(o, v, naux)
+    L = torch.from_numpy(s["L"]).cuda()
+    td = torch.from_numpy(t).cuda()
+    H = eng.hhl(L, td)
+    eng.build(L)
+    Rt = eng.contract(td, t1=torch.from_numpy(t1).cuda())
+    torch.cuda.synchronize()
+    # the hole-hole ladder costs the oracle only O(o^4 v^2): compare every element
+    ref_h = O.hhl(s["L"], o, t)
+    Hh = H.cpu().numpy()
+    assert np.linalg.norm(Hh - ref_h) < 1e-12 * np.linalg.norm(ref_h)
+    assert np.abs(Hh - ref_h).max() < 1e-12 * np.abs(ref_h).max()
+    # the ladder with singles at the sampled entries, each from its own (ac|bd) slab
+    Lvv = s["L"][:, o:, o:]
+    ref_t = np.array([O.ppl_entry(Lvv[:, a, :], Lvv[:, b, :], t[i, j] + np.outer(t1[i], t1[j]))
+                      for (i, j, a, b) in idx])
+    got_t = np.array([Rt[k].item() for k in idx])
+    assert np.abs(got_t - ref_t).max() < 1e-12 * np.abs(ref_t).max()
+    eng.close()
+    del L, td, H, Rt
+    torch.cuda.empty_cache()

@@ -144,6 +144,9 @@ def test_calls_out_of_order_are_state_errors(P):
         assert lib.ppl_build_batch(h, ctypes.c_void_p(256), -1) == -7
         assert lib.ppl_contract(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1.0, 0.0) == -7
         assert "workspace" in P.ppl_last_error()
+        assert lib.ppl_contract_tau(h, ctypes.c_void_p(256), ctypes.c_void_p(768), ctypes.c_void_p(512),
+                                    1.0, 0.0) == -7
+        assert lib.ppl_hhl(h, ctypes.c_void_p(1024), ctypes.c_void_p(256), ctypes.c_void_p(512), 1.0, 0.0) == -7
         # misaligned workspace is an argument error
         assert lib.ppl_bind_workspace(h, ctypes.c_void_p(300), 1 << 30) == -1
     finally:
@@ -152,7 +155,7 @@ def test_calls_out_of_order_are_state_errors(P):
 
 def test_iteration_defaults(P):
     o = P.ppl_iter_opts_default()
-    assert o.max_sweeps == 100 and o.tol == 1e-7 and o.min_fp64_sweeps == 2
+    assert o.max_sweeps == 100 and o.tol == 1e-7 and o.min_fp64_sweeps == 2 and o.diis == 0
     assert o.start == 0 and abs(o.stagnation - 0.95) < 1e-15 and o.switch_tol == 0.0
 
 
