@@ -305,6 +305,43 @@ def study_paper(args):
     print(json.dumps({"study": out}), flush=True)
 
 
+def study_terms(args):
+    """Times of the CCSD terms next to the ladder at (40, 400, 1200), FP64, inputs in HBM:
+    the ladder PPL(t2), the ladder with singles PPL(t2 + t1 t1) and the hole-hole ladder
+    sum_kl (ki|lj) t_kl^ab (integrals from L included), each averaged over 5 calls."""
+    import numpy as np
+    import torch
+
+    import paper_2603_20912_amd as P
+    import ppl_synth
+
+    o, v, naux = 40, 400, 1200
+    sysd = ppl_synth.make_system(o, v, naux, 2, "contractive")
+    L = torch.from_numpy(sysd["L"]).cuda()
+    t2 = torch.from_numpy(ppl_synth.make_amplitudes(o, v, 3)).cuda()
+    t1 = torch.from_numpy(0.05 * np.random.default_rng(19).standard_normal((o, v))).cuda()
+    R = torch.empty_like(t2)
+    eng = P.PPL(o, v, naux)
+    eng.build(L)
+    Pp, Pm, Np, Nm = v * (v + 1) // 2, v * (v - 1) // 2, o * (o + 1) // 2, o * (o - 1) // 2
+    calls = {"ppl": lambda: eng.contract(t2, R), "ppl_tau": lambda: eng.contract(t2, R, t1=t1),
+             "hhl": lambda: eng.hhl(L, t2, R)}
+    flops = {"ppl": nominal(o, v, naux)["contract"], "ppl_tau": nominal(o, v, naux)["contract"],
+             "hhl": 2.0 * (Pp * Np * Np + Pm * Nm * Nm)}
+    out = {"config": {"o": o, "v": v, "naux": naux, "precision": "fp64"}}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 5
+        out[name] = {"ms": round(ms, 3), "useful_tflops": round(flops[name] / ms / 1e9, 2)}
+    eng.close()
+    print(json.dumps({"study": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,7 +354,8 @@ def main():
                     help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--study", default="", help="c3: time-to-1e-7 study at (40, 400, 1200); "
                     "batched: the 32 uneven instances, grouped graph launch vs one plan each; "
-                    "paper: one streamed FP64 evaluation at (nocc, nvir, nvec) = (100, 700, 4000)")
+                    "paper: one streamed FP64 evaluation at (nocc, nvir, nvec) = (100, 700, 4000); "
+                    "terms: ladder, ladder with singles and hole-hole ladder at (40, 400, 1200)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2603_20912_amd", "weights", "mlp_start.f32"))
     args = ap.parse_args()
     if args.study == "c3":
@@ -326,6 +364,8 @@ def main():
         return study_batched(args)
     if args.study == "paper":
         return study_paper(args)
+    if args.study == "terms":
+        return study_terms(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(every box has a single MI355X); run with --gpus 1", file=sys.stderr)
