@@ -9,8 +9,8 @@ literal input generator (seed 1), all inputs already resident in HBM:
     residual and energy each),
   * one more PPL evaluation R = PPL(t) of the final amplitudes, unpacked to
     the caller's [o][o][v][v] array.
-value = useful flops of the pair method (one build + 11 contractions) / step
-time. The dominant kernel is the R+ contraction GEMM; its roofline entry uses
+value = useful flops of the pair method (one build of the upper triangle of V+-,
+2 naux P+^2, + 11 contractions) / step time. The dominant kernel is the R+ contraction GEMM; its roofline entry uses
 HIP-event timings of its launches inside the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -32,10 +32,14 @@ O_, V_, NAUX_, SEED_ = 20, 200, 600, 1
 SWEEPS = 10
 
 
-def nominal(o, v, naux):
+def nominal(o, v, naux, resident=True):
+    """Useful flops of the pair method. A resident plan builds the upper triangle of V+-
+    (rows (a, c >= a), columns (b >= a, d >= a): 2 naux P+^2); a streaming plan builds
+    every row in full (2 naux v^2 P+)."""
     Pp, Pm = v * (v + 1) // 2, v * (v - 1) // 2
     Np, Nm = o * (o + 1) // 2, o * (o - 1) // 2
-    return {"build": 2.0 * naux * v * v * Pp, "contract": 2.0 * (Pp * Pp * Np + Pm * Pm * Nm),
+    build = 2.0 * naux * Pp * Pp if resident else 2.0 * naux * v * v * Pp
+    return {"build": build, "contract": 2.0 * (Pp * Pp * Np + Pm * Pm * Nm),
             "contract_plus": 2.0 * Pp * Pp * Np, "contract_minus": 2.0 * Pm * Pm * Nm}
 
 
@@ -246,7 +250,7 @@ def study_paper(args):
     import ppl_synth
 
     o, v, naux = 100, 700, 4000
-    f = nominal(o, v, naux)
+    f = nominal(o, v, naux, resident=False)
     dense = {"build": 2.0 * naux * v ** 4, "contract": 2.0 * o * o * v ** 4}
     out = {"shape": {"N": o + v, "nocc": o, "nvir": v, "nvec": naux}, "precision": "fp64",
            "useful_flops": f["build"] + f["contract"], "dense_flops": dense["build"] + dense["contract"],
@@ -388,7 +392,8 @@ def main():
     t = torch.zeros((O_, O_, V_, V_), dtype=torch.float64, device=dev)
     R = torch.empty_like(t)
     eng = P.PPL(O_, V_, NAUX_, prec="fp64")
-    f = nominal(O_, V_, NAUX_)
+    f = nominal(O_, V_, NAUX_, resident=bool(eng.info["resident"]))
+    assert f["build"] == eng.info["flops_build"] and f["contract"] == eng.info["flops_contract"]
     flops_step = f["build"] + (SWEEPS + 1) * f["contract"]
 
     def step():

@@ -187,6 +187,7 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     p->diis_t = p->diis_e = p->diis_red = Region{};
   }
   p->tiles = L.take((uint64_t)p->tiles_host.size() * 4);
+  p->cols = p->sym_build ? L.take((uint64_t)v * v * 4) : Region{};
   return L.cur;
 }
 
@@ -197,7 +198,8 @@ static void make_tile_tables(ppl_plan_t p) {
   for (const Batch& b : p->batches) {
     std::vector<int> list;
     int nmt, nnt;
-    build_tile_table(p->tile_build, p->v, b.a0, b.a1, list, nmt, nnt);
+    if (p->sym_build) build_tile_table_sym(p->tile_build, p->v, b.a0, b.a1, list, nmt, nnt);
+    else build_tile_table(p->tile_build, p->v, b.a0, b.a1, list, nmt, nnt);
     p->tiles_off.push_back((int64_t)p->tiles_host.size());
     p->tiles_n.push_back((int64_t)list.size() / 2);
     p->tiles_host.insert(p->tiles_host.end(), list.begin(), list.end());
@@ -243,6 +245,31 @@ struct ProfScope {
 
 
 // ------------------------------------------------------------------ build
+// Useful flops of building virtual rows a in [a0, a1): 2 naux v^2 per pair (a <= b) for full
+// rows; 2 naux (v - a)^3 per virtual a for the upper triangle (rows (a, c >= a), columns
+// (b >= a, d >= a)).
+static double build_flops(ppl_plan_t p, int a0, int a1) {
+  double f = 0.0;
+  for (int a = a0; a < a1; ++a) {
+    const double w = (double)(p->v - a);
+    f += p->sym_build ? w * w * w : (double)p->v * p->v * w;
+  }
+  return 2.0 * p->naux * f;
+}
+
+static int mirror_vpm(ppl_plan_t p, OperandSet& s) {
+  if (!p->sym_build) return PPL_OK;
+  ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
+  const int w = elem_bytes(s.prec);
+  PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vp), p->Pp, p->ldp));
+  if (s.vp_lo.bytes) PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vp_lo), p->Pp, p->ldp));
+  if (p->Pm > 0) {
+    PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vm), p->Pm, p->ldm));
+    if (s.vm_lo.bytes) PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vm_lo), p->Pm, p->ldm));
+  }
+  return PPL_OK;
+}
+
 static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool staged) {
   const Batch& b = p->batches[bi];
   hipStream_t st = p->stream;
@@ -265,8 +292,20 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
         (uint64_t)(r0m + (b.q1 - b.q0)) * p->ldm * w > s.vm.bytes)
       return fail(PPL_E_STATE, "build step %d exceeds the V+- rows of the plan", bi);
   }
+  if (p->sym_build) {
+    {
+      ProfScope ps(p, PPL_PROF_BUILD_GEMM, build_flops(p, b.a0, b.a1));
+      PPL_TRY(gemm_build_sym(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
+                             s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dtiles,
+                             nvalid, at<int>(p, p->tab_vp), at<int>(p, p->cols)));
+    }
+    ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
+    return pack_vpm_sym(st, s.prec, p->v, b.a0, b.a1, at<void>(p, p->g), at<void>(p, s.vp),
+                        s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp, at<void>(p, s.vm),
+                        s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm, at<int>(p, p->tab_vp));
+  }
   {
-    ProfScope ps(p, PPL_PROF_BUILD_GEMM, 2.0 * p->naux * (double)p->v * p->v * (double)(b.p1 - b.p0));
+    ProfScope ps(p, PPL_PROF_BUILD_GEMM, build_flops(p, b.a0, b.a1));
     PPL_TRY(gemm_build(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
                        s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dtiles,
                        nvalid));
@@ -283,6 +322,7 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
 
 static int build_all(ppl_plan_t p, OperandSet& s, const double* L) {
   for (int bi = 0; bi < (int)p->batches.size(); ++bi) PPL_TRY(build_one(p, s, L, bi, bi > 0));
+  PPL_TRY(mirror_vpm(p, s));
   s.built = true;
   return PPL_OK;
 }
@@ -544,13 +584,20 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   const uint64_t gbytes_cap = d->build_scratch ? d->build_scratch : (4ull << 30);
   int64_t gcap = (int64_t)std::max<uint64_t>((uint64_t)p->v, gbytes_cap / per_pair_g);
   gcap = std::min<int64_t>(gcap, p->Pp);
-  // try resident
+  // try resident (V+- symmetric: build the upper triangle, mirror the rest; PPL_SYM_BUILD=0
+  // builds every row in full instead)
+  {
+    const char* e = getenv("PPL_SYM_BUILD");
+    p->sym_build = !(e && e[0] == '0');
+  }
   make_batches(p->v, gcap, p->batches);
   make_tile_tables(p);
   uint64_t need = assign_layout(p, gcap, true, 0);
   if (need <= budget) {
     p->resident = true;
+    if (p->sym_build) build_column_order(p->v, p->cols_host);
   } else {
+    p->sym_build = false;
     // streaming: V+- rows of one build step at a time; the largest step that fits
     // (the need grows with the step's pair count, so a bisection over it suffices)
     p->resident = false;
@@ -617,8 +664,7 @@ int ppl_plan_query(ppl_plan_t p, ppl_plan_info_t* info) {
   }
   info->tile_contract_minus = p->tile_m;
   info->splits_contract_minus = p->split_m;
-  const double v = p->v, na = p->naux;
-  info->flops_build = 2.0 * na * v * v * (double)p->Pp;
+  info->flops_build = build_flops(p, 0, p->v);
   info->flops_contract =
       2.0 * ((double)p->Pp * p->Pp * p->Np + (double)p->Pm * p->Pm * p->Nm);
   return PPL_OK;
@@ -648,6 +694,9 @@ int ppl_bind_workspace(ppl_plan_t p, void* dptr, uint64_t bytes) {
   if (!p->tiles_host.empty())
     PPL_HIP_TRY(hipMemcpyAsync(at<int>(p, p->tiles), p->tiles_host.data(), p->tiles_host.size() * 4,
                                hipMemcpyHostToDevice, st));
+  if (p->sym_build)
+    PPL_HIP_TRY(hipMemcpyAsync(at<int>(p, p->cols), p->cols_host.data(), p->cols_host.size() * 4,
+                               hipMemcpyHostToDevice, st));
   PPL_HIP_TRY(hipStreamSynchronize(st));   // the host tile table must not be reused before the copy ends
   p->setup_done = true;
   return PPL_OK;
@@ -669,7 +718,10 @@ int ppl_build_batch(ppl_plan_t p, const double* L, int32_t batch) {
     } else {
       PPL_TRY(build_one(p, s, L, batch, false));
       // a resident plan counts as built once its last batch is built in order
-      if (batch == nb - 1) s.built = true;
+      if (batch == nb - 1) {
+        PPL_TRY(mirror_vpm(p, s));
+        s.built = true;
+      }
     }
   }
   return PPL_OK;

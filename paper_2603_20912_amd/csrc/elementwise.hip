@@ -214,6 +214,121 @@ int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void
   return PPL_OK;
 }
 
+// Upper triangle of V+- rows from an upper-triangle build step: G holds
+// G_ab[c - a0][d - a0] = (ac|bd) for c, d >= a (W x W per pair, pairs from pair0); the
+// block of pair (a, b) writes V+[ab][cd] and V-[ab][cd] for the columns (cd) >= (ab) in
+// packed order (c > a, or c == a and d >= b), which need only c, d >= a. The columns
+// before (ab) are the mirror image of earlier rows (mirror_lower) and are left alone.
+template <class Tg, int PREC>
+__global__ void __launch_bounds__(256)
+pack_vpm_sym_kernel(int v, int a0, int64_t pair0, const Tg* __restrict__ G, const int* __restrict__ tab_vp,
+                    void* vp, void* vp_lo, int64_t ldp, void* vm, void* vm_lo, int64_t ldm, int64_t Pp,
+                    int64_t Pm) {
+  __shared__ double t1[32][33], t2[32][33];
+  const int W = v - a0;
+  const int64_t pr = pair0 + blockIdx.x;
+  const int ab = tab_vp[pr];
+  const int a = pair_first(ab), b = pair_second(ab);
+  const Tg* g = G + (int64_t)blockIdx.x * W * W;
+  const bool has_minus = a < b;
+  const int64_t rowm = has_minus ? pair_minus(a, b, v) : 0;
+  const int tid = threadIdx.x;
+  const int nt = (v - a + 31) / 32;            // 32-wide tiles of c and d, starting at a
+  for (int ci = 0; ci < nt; ++ci) {
+    for (int di = ci; di < nt; ++di) {
+      const int cB = a + ci * 32, dB = a + di * 32;
+      for (int e = tid; e < 1024; e += 256) {
+        const int r = e >> 5, q = e & 31;
+        const int c1 = cB + r, d1 = dB + q;
+        t1[r][q] = (c1 < v && d1 < v) ? (double)g[(int64_t)(c1 - a0) * W + (d1 - a0)] : 0.0;
+        const int c2 = dB + r, d2 = cB + q;   // row d, col c
+        t2[q][r] = (c2 < v && d2 < v) ? (double)g[(int64_t)(c2 - a0) * W + (d2 - a0)] : 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 256) {
+        const int r = e >> 5, q = e & 31;
+        const int c = cB + r, d = dB + q;
+        if (c < v && d < v && c <= d && (c > a || d >= b)) {
+          const double gcd = t1[r][q], gdc = t2[r][q];
+          Store<PREC>::put(vp, vp_lo, pr * ldp + pair_plus(c, d, v), 0.5 * (gcd + gdc));
+          if (has_minus && c < d)
+            Store<PREC>::put(vm, vm_lo, rowm * ldm + pair_minus(c, d, v), 0.5 * (gcd - gdc));
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t k = Pp + tid; k < ldp; k += 256) Store<PREC>::put(vp, vp_lo, pr * ldp + k, 0.0);
+  if (has_minus)
+    for (int64_t k = Pm + tid; k < ldm; k += 256) Store<PREC>::put(vm, vm_lo, rowm * ldm + k, 0.0);
+}
+
+int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
+                 int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp) {
+  const int64_t p0 = pair_plus(a0, a0, v);
+  const int64_t p1 = (a1 >= v) ? npairs_plus(v) : pair_plus(a1, a1, v);
+  const int64_t npairs = p1 - p0;
+  if (npairs <= 0) return PPL_OK;
+  const int64_t Pp = npairs_plus(v), Pm = npairs_minus(v);
+  dim3 grid((unsigned)npairs);
+  if (prec == PPL_FP64)
+    hipLaunchKernelGGL((pack_vpm_sym_kernel<double, PPL_FP64>), grid, dim3(256), 0, s, v, a0, p0, (const double*)G,
+                       tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else if (prec == PPL_FP32)
+    hipLaunchKernelGGL((pack_vpm_sym_kernel<float, PPL_FP32>), grid, dim3(256), 0, s, v, a0, p0, (const float*)G,
+                       tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else if (prec == PPL_BF16X3)
+    hipLaunchKernelGGL((pack_vpm_sym_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, a0, p0,
+                       (const float*)G, tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else
+    return fail(PPL_E_ARG, "pack_vpm_sym: unknown precision %d", prec);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// Strictly lower triangle of an n x n symmetric matrix (row length ld) from its upper
+// triangle: V[r][q] = V[q][r] for q < r, as a bit copy of elements of type E. One 64 x 64
+// block pair per workgroup: block (I, J), I >= J, reads rows J and columns I (upper) through
+// LDS and writes rows I and columns J (lower), both along contiguous rows.
+template <class E>
+__global__ void __launch_bounds__(256) mirror_lower_kernel(E* V, int64_t n, int64_t ld) {
+  __shared__ E sh[64][65];
+  const int64_t t = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int64_t J = t - I * (I + 1) / 2;
+  const int tid = threadIdx.x;
+  const int64_t r0 = I * 64, q0 = J * 64;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int ql = e >> 6, rl = e & 63;                  // read row q0 + ql, column r0 + rl
+    const int64_t q = q0 + ql, r = r0 + rl;
+    if (q < n && r < n && q < r) sh[ql][rl] = V[q * ld + r];
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int rl = e >> 6, ql = e & 63;                  // write row r0 + rl, column q0 + ql
+    const int64_t r = r0 + rl, q = q0 + ql;
+    if (q < n && r < n && q < r) V[r * ld + q] = sh[ql][rl];
+  }
+}
+
+int mirror_lower(hipStream_t s, int elem_bytes, void* V, int64_t n, int64_t ld) {
+  if (n <= 1) return PPL_OK;
+  const int64_t T = (n + 63) / 64, blocks = T * (T + 1) / 2;
+  if (blocks > 0x7fffffffLL) return fail(PPL_E_ARG, "mirror of %lld rows too large", (long long)n);
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(mirror_lower_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t*)V, n, ld);
+  else if (elem_bytes == 4)
+    hipLaunchKernelGGL(mirror_lower_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)V, n, ld);
+  else if (elem_bytes == 2)
+    hipLaunchKernelGGL(mirror_lower_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint16_t*)V, n, ld);
+  else
+    return fail(PPL_E_ARG, "mirror of %d-byte elements", elem_bytes);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
 // ------------------------------------------------------------------ generic (i,j,a,b) -> +/- packing
 // With t1 ([i][a], row length v1) the packed tensor is X_ij^ab + t1_i^a t1_j^b.
 __global__ void pack_plus_kernel(const double* __restrict__ X, int64_t si, int64_t sj, int64_t sa,

@@ -119,6 +119,8 @@ struct MapBuild {        // block-upper-triangle of the (a,c) x (b,d) grid: only
 // ------------------------------------------------------------------ epilogues
 template <class Tc>
 struct EpiStore {        // C[split][m][c_col0 + n] = alpha * acc + beta * C (beta == 0: no read)
+  __device__ int64_t arow(int64_t r) const { return r; }   // operand rows of C row / column r
+  __device__ int64_t brow(int64_t r) const { return r; }
   Tc* C;
   int64_t ldc, c_col0, M, N;
   double alpha, beta;
@@ -137,6 +139,8 @@ struct EpiStore {        // C[split][m][c_col0 + n] = alpha * acc + beta * C (be
 
 template <class Tc>
 struct EpiSK {           // stream-K: whole tiles go to C, shared tiles to a dense BM x BN partial slot
+  __device__ int64_t arow(int64_t r) const { return r; }   // operand rows of C row / column r
+  __device__ int64_t brow(int64_t r) const { return r; }
   Tc* C;
   int64_t ldc, c_col0, M, N;
   Tc* P;                 // partial slot of this tile (to_part) or unused
@@ -160,6 +164,8 @@ struct EpiSK {           // stream-K: whole tiles go to C, shared tiles to a den
 
 template <class Tg>
 struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
+  __device__ int64_t arow(int64_t r) const { return r; }   // operand rows of C row / column r
+  __device__ int64_t brow(int64_t r) const { return r; }
   Tg* G;
   int64_t M, N;
   int v, a0;
@@ -178,6 +184,39 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
     const int64_t a = a0 + arel, b = a0 + brel;
     const int64_t pr = pair_plus(a, b, v) - pair_plus(a0, a0, v);
     G[(pr * v + c) * v + d] = x;
+  }
+};
+
+// Upper-triangle build of a resident plan. Rows are the packed pairs (a, c), c >= a, of
+// the step's virtuals a in [a0, a1) (packed pairs pr0 + m); columns are the operand rows
+// b * v + d listed in `cols` (ordered by min(b, d), starting at min(b, d) = a0). Only
+// (ac|bd) with b >= a and d >= a is kept: G[pair(a,b) - pr0][c - a0][d - a0], W = v - a0.
+template <class Tg>
+struct EpiBuildSym {
+  Tg* G;
+  int64_t M, N;
+  int v, a0, W;
+  int64_t pr0;
+  const int* tab;        // packed pair -> (first << 16) | second
+  const int* cols;       // column n -> operand row b * v + d
+  __device__ int64_t arow(int64_t m) const {
+    const int ac = tab[pr0 + m];
+    return (int64_t)pair_first(ac) * v + pair_second(ac);
+  }
+  __device__ int64_t brow(int64_t n) const { return cols[n]; }
+  __device__ void row(int, int64_t m, int64_t& base, bool& ok) const {
+    ok = m < M;
+    const int ac = ok ? tab[pr0 + m] : 0;
+    base = ((int64_t)pair_first(ac) << 20) | pair_second(ac);
+  }
+  __device__ void put(int64_t base, bool ok, int64_t n, Tg x) const {
+    if (!ok || n >= N) return;
+    const int a = (int)(base >> 20), c = (int)(base & ((1 << 20) - 1));
+    const int bd = cols[n];
+    const int b = bd / v, d = bd - b * v;
+    if (b < a || d < a) return;
+    const int64_t pr = pair_plus(a, b, v) - pr0;
+    G[(pr * W + (c - a0)) * W + (d - a0)] = x;
   }
 };
 
@@ -323,14 +362,14 @@ __device__ __forceinline__ void tile_body_direct(const TileJob& job, int64_t M, 
     const int g = wave + i * NW, r = g * RPI + lr;
     int64_t gr = job.m0 + r;
     if (gr > M - 1) gr = M - 1;
-    pa[i] = A + gr * lda + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
+    pa[i] = A + epi.arow(gr) * lda + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
   }
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
     const int g = wave + i * NW, r = g * RPI + lr;
     int64_t gr = job.n0 + r;
     if (gr > N - 1) gr = N - 1;
-    pb[i] = B + gr * ldb + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
+    pb[i] = B + epi.brow(gr) * ldb + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
   }
   // chunk c (relative to job.kc0) into LDS buffer `buf`
   auto issue = [&](int64_t c, int buf) __attribute__((always_inline)) {
@@ -446,7 +485,7 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = m0 + r;
     if (gr > M - 1) gr = M - 1;
-    pa[i] = A + gr * lda + kv * VEC + job.kc0 * KC;
+    pa[i] = A + epi.arow(gr) * lda + kv * VEC + job.kc0 * KC;
     oa[i] = lds_vec_off<VEC, VPR, LDSR>(r, kv);
   }
 #pragma unroll
@@ -456,7 +495,7 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = n0 + r;
     if (gr > N - 1) gr = N - 1;
-    pb[i] = B + gr * ldb + kv * VEC + job.kc0 * KC;
+    pb[i] = B + epi.brow(gr) * ldb + kv * VEC + job.kc0 * KC;
     ob[i] = lds_vec_off<VEC, VPR, LDSR>(r, kv);
   }
 
@@ -630,7 +669,7 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = m0 + r;
     if (gr > M - 1) gr = M - 1;
-    ga[i] = gr * lda + kv * VEC + job.kc0 * KC;
+    ga[i] = epi.arow(gr) * lda + kv * VEC + job.kc0 * KC;
     oa[i] = r * LDSR + (kv ^ Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>::key(r)) * VEC;
   }
 #pragma unroll
@@ -640,7 +679,7 @@ __device__ __forceinline__ void bf3_tile_body(const TileJob& job, int64_t M, int
     const int r = idx / VPR, kv = idx % VPR;
     int64_t gr = n0 + r;
     if (gr > N - 1) gr = N - 1;
-    gb[i] = gr * ldb + kv * VEC + job.kc0 * KC;
+    gb[i] = epi.brow(gr) * ldb + kv * VEC + job.kc0 * KC;
     ob[i] = r * LDSR + (kv ^ Bf3Geom<WM, WN, WAVES_M, WAVES_N, KC>::key(r)) * VEC;
   }
   f4 acc[WM][WN], accx[WM][WN];
@@ -837,6 +876,52 @@ void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& tiles, 
         tiles.push_back(mt);
         tiles.push_back(nt);
       }
+  }
+}
+
+// The upper-triangle build of one step (see EpiBuildSym): row tiles over the packed pairs
+// (a, c >= a) of a in [a0, a1), column tiles over the (v - a0)^2 columns ordered by
+// min(b, d). Columns with min(b, d) >= a start at v^2 - (v - a)^2 of that order, so a row
+// tile whose first virtual is a needs only the column tiles from there on. Launch order
+// as in build_tile_table (groups of row tiles walked column tile by column tile).
+void build_tile_table_sym(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mt, int& n_nt) {
+  constexpr int kBuildGroup = 8;
+  int bm, bn;
+  build_tile_dims(tile, &bm, &bn);
+  const int64_t pr0 = pair_plus(a0, a0, v);
+  const int64_t pr1 = a1 >= v ? npairs_plus(v) : pair_plus(a1, a1, v);
+  const int64_t M = pr1 - pr0, W = v - a0, N = W * W;
+  n_mt = (int)((M + bm - 1) / bm);
+  n_nt = (int)((N + bn - 1) / bn);
+  auto sfx = [&](int64_t a) { return (int64_t)v * v - (int64_t)(v - a) * (v - a); };
+  std::vector<int> nt_first(n_mt);
+  int a = a0;
+  for (int mt = 0; mt < n_mt; ++mt) {
+    const int64_t m = (int64_t)mt * bm + pr0;                 // first packed pair of the tile
+    while (a + 1 < a1 && pair_plus(a + 1, a + 1, v) <= m) ++a;
+    nt_first[mt] = (int)((sfx(a) - sfx(a0)) / bn);
+  }
+  tiles.clear();
+  for (int g0 = 0; g0 < n_mt; g0 += kBuildGroup) {
+    const int g1 = g0 + kBuildGroup < n_mt ? g0 + kBuildGroup : n_mt;
+    for (int nt = nt_first[g0]; nt < n_nt; ++nt)
+      for (int mt = g0; mt < g1; ++mt) {
+        if (nt < nt_first[mt]) break;   // nt_first grows with mt
+        tiles.push_back(mt);
+        tiles.push_back(nt);
+      }
+  }
+}
+
+// Operand rows b * v + d of every (b, d) ordered by m = min(b, d): for each m the pair
+// (m, m), then (m, d) for d > m, then (b, m) for b > m.
+void build_column_order(int v, std::vector<int>& cols) {
+  cols.clear();
+  cols.reserve((size_t)v * v);
+  for (int m = 0; m < v; ++m) {
+    cols.push_back(m * v + m);
+    for (int d = m + 1; d < v; ++d) cols.push_back(m * v + d);
+    for (int b = m + 1; b < v; ++b) cols.push_back(b * v + m);
   }
 }
 
@@ -1242,6 +1327,49 @@ static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpa
                                                         Xl, ldx, epi, map);
   }
   return fail(PPL_E_ARG, "unknown precision %d", prec);
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                         const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles,
+                         const int* tab_vp, const int* cols) {
+  constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  const int64_t pr0 = pair_plus(a0, a0, v);
+  const int64_t pr1 = a1 >= v ? npairs_plus(v) : pair_plus(a1, a1, v);
+  const int W = v - a0;
+  const int64_t M = pr1 - pr0, N = (int64_t)W * W;
+  const int* cstep = cols + ((int64_t)v * v - N);       // first column with min(b, d) = a0
+  MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
+  map.nk = Kpad / (prec == PPL_BF16X3 ? bf3_kc(BM, BN) : kc_of_prec(prec));
+  if (prec == PPL_FP64) {
+    EpiBuildSym<double> epi{(double*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    return launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, n_valid_tiles, M, N, Kpad, (const double*)Xt, ldx,
+                                                            (const double*)Xt, ldx, epi, map);
+  }
+  if (prec == PPL_FP32) {
+    EpiBuildSym<float> epi{(float*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    return launch<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, (const float*)Xt, ldx,
+                                                           (const float*)Xt, ldx, epi, map);
+  }
+  if (prec == PPL_BF16X3) {
+    EpiBuildSym<float> epi{(float*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    return launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, n_valid_tiles, M, N, Kpad, (const __bf16*)Xt,
+                                                                (const __bf16*)Xt_lo, ldx, (const __bf16*)Xt,
+                                                                (const __bf16*)Xt_lo, ldx, epi, map);
+  }
+  return fail(PPL_E_ARG, "unknown precision %d", prec);
+}
+
+int gemm_build_sym(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                   const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles,
+                   const int* tab_vp, const int* cols) {
+  switch (tile) {
+    case 0: return build_sym_cfg<7, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
+    case 1: return build_sym_cfg<4, 4, 2, 2>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
+    case 5: return build_sym_cfg<6, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
+    case 8: return build_sym_cfg<4, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
+    default: return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
+  }
 }
 
 int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,

@@ -129,6 +129,9 @@ struct ppl_plan_s {
   ppl::Region diis_t, diis_e;          // diis_max slots of amplitudes t' and of errors t' - t (S'/A' scaling)
   ppl::Region diis_red;                // DIIS inner-product partials and results
   ppl::Region tiles;                   // per-batch (row tile, column tile) lists of the build GEMM (int32 pairs)
+  bool sym_build = false;              // resident: build the upper triangle of V+- and mirror it
+  ppl::Region cols;                    // operand rows of the upper-triangle build's columns (int32, v^2)
+  std::vector<int> cols_host;
   std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
   std::vector<int64_t> tiles_off;      // element offset of each batch's list in `tiles`
   std::vector<int64_t> tiles_n;        // tiles in each batch's list
@@ -208,6 +211,16 @@ int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t
 void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mtiles,
                       int& n_ntiles);
 int build_tile_dims(int tile, int* bm, int* bn);
+// Upper-triangle build of a resident plan: G[pair(a,b) - pair(a0,a0)][c - a0][d - a0] =
+// (ac|bd) for a in [a0, a1), b >= a, c >= a, d >= a (W = v - a0); rows are the packed
+// pairs (a, c >= a) decoded through tab_vp, columns the operand rows in `cols`
+// (build_column_order).
+int gemm_build_sym(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                   const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles,
+                   const int* tab_vp, const int* cols);
+void build_tile_table_sym(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mtiles,
+                          int& n_ntiles);
+void build_column_order(int v, std::vector<int>& cols);
 void contract_tile_dims(int tile, int* bm, int* bn, int* threads);
 int contract_tile_count();
 int contract_tile_default(int prec, int64_t Nrows);
@@ -221,6 +234,11 @@ int stage_ov(hipStream_t s, const double* L, int o, int v, int naux, int64_t ldx
 int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
              int64_t ldp, int64_t vp_row0, void* vm, void* vm_lo, int64_t ldm, int64_t vm_row0,
              const int* tab_vp, const int* tab_vm);
+// upper triangle of V+- rows from an upper-triangle build step (gemm_build_sym); resident rows
+int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
+                 int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp);
+// V[r][q] = V[q][r] for q < r (bit copy of elem_bytes-wide elements)
+int mirror_lower(hipStream_t s, int elem_bytes, void* V, int64_t n, int64_t ld);
 // pair tables
 int fill_tables(hipStream_t s, int o, int v, int* tab_vp, int* tab_vm, int* tab_op, int* tab_om);
 // generic pack of an (i,j,a,b)-indexed FP64 tensor into + / - packed rows:

@@ -219,3 +219,25 @@ def test_c2_sampled_entries(P):
     assert np.abs(got - ref).max() < 1e-12 * scale
     # properties that hold at any size: pair symmetry of the result
     assert rel(R, R.transpose(1, 0, 3, 2)) < 1e-14
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("o,v,naux,scratch", [(7, 37, 130, 0), (5, 70, 45, 1 << 20), (3, 130, 33, 3 << 20)])
+def test_upper_triangle_build_matches_full_rows(P, monkeypatch, prec, bound, o, v, naux, scratch):
+    """Resident plans build the upper triangle of V+- and mirror it (one or several build
+    steps); the result equals the full-row build and the oracle."""
+    say(f"upper-triangle vs full-row build {prec} ({o},{v},{naux}), build scratch {scratch}")
+    s = S.make_system(o, v, naux, 50)
+    t = S.make_amplitudes(o, v, 51)
+    out = {}
+    for sym in ("1", "0"):
+        monkeypatch.setenv("PPL_SYM_BUILD", sym)
+        eng = P.PPL(o, v, naux, prec=prec, build_scratch=scratch)
+        assert eng.info["resident"] == 1
+        if scratch:
+            assert eng.info["n_batches"] > 1
+        eng.build(dev(s["L"]))
+        out[sym] = eng.contract(dev(t)).cpu().numpy()
+        eng.close()
+    assert rel(out["1"], out["0"]) < (1e-14 if prec == "fp64" else bound / 10)
+    assert rel(out["1"], O.ppl(s["L"], o, t)) < bound

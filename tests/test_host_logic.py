@@ -53,7 +53,9 @@ def test_pair_counts_and_flops(P):
         i = plan_info(P, o, v, naux, hbm_budget=1 << 40)
         assert i["p_plus"] == v * (v + 1) // 2 and i["p_minus"] == v * (v - 1) // 2
         assert i["n_plus"] == o * (o + 1) // 2 and i["n_minus"] == o * (o - 1) // 2
-        assert i["flops_build"] == 2.0 * naux * v * v * i["p_plus"]
+        # resident plans build the upper triangle of V+-: rows (a, c >= a) times columns
+        # (b >= a, d >= a), sum_a (v - a)^3 = P+^2 entries of 2 naux flops each
+        assert i["resident"] == 1 and i["flops_build"] == 2.0 * naux * i["p_plus"] ** 2
         assert i["flops_contract"] == 2.0 * (i["p_plus"] ** 2 * i["n_plus"] + i["p_minus"] ** 2 * i["n_minus"])
 
 
@@ -72,6 +74,8 @@ def test_budget_forces_streaming_batches(P):
     i = plan_info(P, 20, 200, 600, hbm_budget=1 << 30)
     assert i["resident"] == 0 and i["n_batches"] > 1
     assert i["workspace_bytes"] <= 1 << 30
+    # streamed rows are built in full: 2 naux v^2 flops per pair (a <= b)
+    assert i["flops_build"] == 2.0 * 600 * 200 * 200 * i["p_plus"]
 
 
 def test_streaming_plan_of_the_largest_benchmark_shape(P):
