@@ -89,7 +89,8 @@ typedef struct {
   int32_t  splits_contract_minus; /* split-K slices of the R- contraction GEMM (0 = stream-K) */
   uint64_t build_scratch_bytes;   /* bytes of the integral-build scratch */
   int64_t  max_step_pairs;        /* largest number of (a<=b) pairs one build step holds */
-  double   flops_build;       /* useful flops of one integral build: 2 naux v^2 P+ */
+  double   flops_build;       /* useful flops of one integral build: 2 naux P+^2 (resident, upper triangle)
+                                 or 2 naux v^2 P+ (streaming, full rows) */
   double   flops_contract;    /* useful flops of one contraction: 2 (P+^2 N+ + P-^2 N-) */
 } ppl_plan_info_t;
 
@@ -118,8 +119,11 @@ int ppl_bind_workspace(ppl_plan_t plan, void* dptr, uint64_t bytes);
 
 /*
  * ppl_build_batch: form V+- rows from the Cholesky vectors (eq. (cholesky)).
- * batch in [0, n_batches) builds one row batch, -1 builds every batch of a
- * resident plan. The plan remembers L; a non-resident plan rebuilds its
+ * Every L^P must be symmetric (real orbitals, as the paper assumes), which makes
+ * V+ and V- symmetric matrices: a resident plan builds their upper triangle
+ * (rows (a, c >= a) of the integrals) and mirrors it once its last batch is built;
+ * a streaming plan builds full rows. batch in [0, n_batches) builds one row
+ * batch, -1 builds every batch of a resident plan. The plan remembers L; a non-resident plan rebuilds its
  * batches from it inside ppl_contract, so L must stay valid until the next
  * ppl_build_batch or ppl_destroy.
  */
