@@ -188,6 +188,17 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   }
   p->tiles = L.take((uint64_t)p->tiles_host.size() * 4);
   p->cols = p->sym_build ? L.take((uint64_t)v * v * 4) : Region{};
+  p->r2p = p->r2m = p->ut = Region{};
+  if (p->sym_build && !resident) {
+    // the K range of a step starts at its first pair rounded down to 64, so it spans at
+    // most the step's pairs plus 63
+    p->ldq = pad_ld(p->Np);
+    p->ldqm = pad_ld(std::max<int64_t>(p->Nm, 1));
+    p->ldk = pad_ld(max_batch_pairs + 63);
+    p->r2p = L.take((uint64_t)p->Pp * p->ldq * 8);
+    p->r2m = L.take((uint64_t)std::max<int64_t>(p->Pm, 1) * p->ldqm * 8);
+    p->ut = L.take((uint64_t)p->Pp * p->ldk * 8);
+  }
   return L.cur;
 }
 
@@ -300,9 +311,11 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
                              nvalid, at<int>(p, p->tab_vp), at<int>(p, p->cols)));
     }
     ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
+    const bool str = !p->resident;
     return pack_vpm_sym(st, s.prec, p->v, b.a0, b.a1, at<void>(p, p->g), at<void>(p, s.vp),
                         s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr, p->ldp, at<void>(p, s.vm),
-                        s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm, at<int>(p, p->tab_vp));
+                        s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm, at<int>(p, p->tab_vp),
+                        str ? b.p0 : 0, str ? b.q0 : 0, str ? 1 : 0, b.p0 / 64 * 64, b.q0 / 64 * 64);
   }
   {
     ProfScope ps(p, PPL_PROF_BUILD_GEMM, build_flops(p, b.a0, b.a1));
@@ -328,6 +341,65 @@ static int build_all(ppl_plan_t p, OperandSet& s, const double* L) {
 }
 
 // ------------------------------------------------------------------ contraction of packed operands
+// Streaming with upper-triangle steps (FP64): V = U + U^T, U the rows of a step from their
+// own pair on, diagonal halved. Per step, R[:, step] = S' U_step^T over K from the step's
+// first pair (rounded down to 64; U is zero before its own pair there), and
+// R^T[k0:, :] += U_step^T S'[:, step]^T with the step's pairs as K, through a transposed
+// copy of the step's rows. The transposed sums are added into R+- after the last step.
+static int contract_stream_sym(ppl_plan_t p, OperandSet& s, int tile, int tile_m, int split_p, int split_m,
+                               void* part) {
+  hipStream_t st = p->stream;
+  if (s.prec != PPL_FP64 || !p->r2p.bytes || !p->ut.bytes)
+    return fail(PPL_E_STATE, "streaming upper-triangle plan without its buffers");
+  double* sp = at<double>(p, s.sp);
+  double* am = at<double>(p, s.am);
+  double* vp = at<double>(p, s.vp);
+  double* vm = at<double>(p, s.vm);
+  double* rp = at<double>(p, p->rp);
+  double* rm = at<double>(p, p->rm);
+  double* r2p = at<double>(p, p->r2p);
+  double* r2m = at<double>(p, p->r2m);
+  double* ut = at<double>(p, p->ut);
+  PPL_TRY(zero_bytes(st, r2p, p->r2p.bytes));
+  if (p->Nm > 0) PPL_TRY(zero_bytes(st, r2m, p->r2m.bytes));
+  int t2p = -1, s2p = 1, t2m = -1, s2m = 1;
+  contract_choose(PPL_FP64, p->Pp, p->Np, p->ldk, 1, &t2p, &s2p);
+  if (p->Nm > 0) contract_choose(PPL_FP64, p->Pm, p->Nm, p->ldk, 1, &t2m, &s2m);
+  // one half (U or U^T) of a step's rows [r0, r1) of an n-row block: useful flops
+  auto half_flops = [](int64_t rows, int64_t n, int64_t r0, int64_t r1) {
+    const double w = (double)(r1 - r0);
+    return 2.0 * rows * (w * n - (double)(r0 + r1 - 1) * w / 2.0);
+  };
+  for (int bi = 0; bi < (int)p->batches.size(); ++bi) {
+    const Batch& b = p->batches[bi];
+    PPL_TRY(build_one(p, s, p->L_last, bi, bi > 0));
+    {
+      ProfScope ps(p, PPL_PROF_CONTRACT_PLUS, 2.0 * half_flops(p->Np, p->Pp, b.p0, b.p1));
+      const int64_t k0 = b.p0 / 64 * 64, w = b.p1 - b.p0, K2 = pad_ld(b.p1 - k0), nr = p->Pp - k0;
+      if (K2 > p->ldk) return fail(PPL_E_STATE, "step %d exceeds the transposed block", bi);
+      PPL_TRY(gemm_contract(st, PPL_FP64, tile, p->Np, w, p->ldp - k0, sp + k0, nullptr, p->ldp, vp + k0, nullptr,
+                            p->ldp, rp, p->ldp, b.p0, split_p, part, p->ld_part, p->part.bytes));
+      PPL_TRY(transpose_block(st, 8, vp, p->ldp, b.p0, b.p1, k0, k0, ut, p->ldk, nr, K2));
+      PPL_TRY(gemm_contract(st, PPL_FP64, t2p, nr, p->Np, K2, ut, nullptr, p->ldk, sp + k0, nullptr, p->ldp,
+                            r2p + k0 * p->ldq, p->ldq, 0, 1, nullptr, p->ldq, 0, true));
+    }
+    if (p->Nm > 0 && b.q1 > b.q0) {
+      ProfScope ps(p, PPL_PROF_CONTRACT_MINUS, 2.0 * half_flops(p->Nm, p->Pm, b.q0, b.q1));
+      const int64_t k0 = b.q0 / 64 * 64, w = b.q1 - b.q0, K2 = pad_ld(b.q1 - k0), nr = p->Pm - k0;
+      if (K2 > p->ldk) return fail(PPL_E_STATE, "step %d exceeds the transposed block", bi);
+      PPL_TRY(gemm_contract(st, PPL_FP64, tile_m, p->Nm, w, p->ldm - k0, am + k0, nullptr, p->ldm, vm + k0, nullptr,
+                            p->ldm, rm, p->ldm, b.q0, split_m, part, p->ld_part, p->part.bytes));
+      PPL_TRY(transpose_block(st, 8, vm, p->ldm, b.q0, b.q1, k0, k0, ut, p->ldk, nr, K2));
+      PPL_TRY(gemm_contract(st, PPL_FP64, t2m, nr, p->Nm, K2, ut, nullptr, p->ldk, am + k0, nullptr, p->ldm,
+                            r2m + k0 * p->ldqm, p->ldqm, 0, 1, nullptr, p->ldqm, 0, true));
+    }
+  }
+  ProfScope ps(p, PPL_PROF_OTHER, 0.0);
+  PPL_TRY(add_transposed(st, rp, p->ldp, r2p, p->ldq, p->Np, p->Pp));
+  if (p->Nm > 0) PPL_TRY(add_transposed(st, rm, p->ldm, r2m, p->ldqm, p->Nm, p->Pm));
+  return PPL_OK;
+}
+
 // R+ = S' V+^T, R- = A' V-^T with the operand set s (its S'/A' must be current).
 static int contract_packed(ppl_plan_t p, OperandSet& s) {
   hipStream_t st = p->stream;
@@ -360,6 +432,7 @@ static int contract_packed(ppl_plan_t p, OperandSet& s) {
     return PPL_OK;
   }
   if (!p->L_last) return fail(PPL_E_STATE, "streaming plan has no Cholesky vectors (call ppl_build_batch)");
+  if (p->sym_build) return contract_stream_sym(p, s, tile, tile_m, split_p, split_m, part);
   for (int bi = 0; bi < (int)p->batches.size(); ++bi) {
     const Batch& b = p->batches[bi];
     PPL_TRY(build_one(p, s, p->L_last, bi, bi > 0));
@@ -597,7 +670,8 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
     p->resident = true;
     if (p->sym_build) build_column_order(p->v, p->cols_host);
   } else {
-    p->sym_build = false;
+    // streaming: upper-triangle steps contracted as U and U^T (FP64 plans with one operand set)
+    p->sym_build = p->sym_build && p->prec == PPL_FP64 && !p->keep_fp64;
     // streaming: V+- rows of one build step at a time; the largest step that fits
     // (the need grows with the step's pair count, so a bisection over it suffices)
     p->resident = false;
@@ -627,6 +701,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
     }
     need = need_for(lo);
     gcap = lo;
+    if (p->sym_build) build_column_order(p->v, p->cols_host);
   }
   p->g_pairs_cap = gcap;
   p->a_per_batch = p->batches.empty() ? 0 : p->batches[0].a1 - p->batches[0].a0;

@@ -219,11 +219,14 @@ int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void
 // block of pair (a, b) writes V+[ab][cd] and V-[ab][cd] for the columns (cd) >= (ab) in
 // packed order (c > a, or c == a and d >= b), which need only c, d >= a. The columns
 // before (ab) are the mirror image of earlier rows (mirror_lower) and are left alone.
+// Streaming form (half_diag): rows are stored from vp_row0 / vm_row0 on, the diagonal
+// entry is halved (V = U + U^T) and the columns [zp, own) and [zm, own) before the row's
+// own pair are zeroed, so that a K range starting at zp (zm) sees U exactly.
 template <class Tg, int PREC>
 __global__ void __launch_bounds__(256)
 pack_vpm_sym_kernel(int v, int a0, int64_t pair0, const Tg* __restrict__ G, const int* __restrict__ tab_vp,
                     void* vp, void* vp_lo, int64_t ldp, void* vm, void* vm_lo, int64_t ldm, int64_t Pp,
-                    int64_t Pm) {
+                    int64_t Pm, int64_t vp_row0, int64_t vm_row0, int half_diag, int64_t zp, int64_t zm) {
   __shared__ double t1[32][33], t2[32][33];
   const int W = v - a0;
   const int64_t pr = pair0 + blockIdx.x;
@@ -231,7 +234,9 @@ pack_vpm_sym_kernel(int v, int a0, int64_t pair0, const Tg* __restrict__ G, cons
   const int a = pair_first(ab), b = pair_second(ab);
   const Tg* g = G + (int64_t)blockIdx.x * W * W;
   const bool has_minus = a < b;
-  const int64_t rowm = has_minus ? pair_minus(a, b, v) : 0;
+  const int64_t qr = has_minus ? pair_minus(a, b, v) : 0;
+  const int64_t rowp = pr - vp_row0, rowm = qr - vm_row0;
+  const double dscale = half_diag ? 0.25 : 0.5;
   const int tid = threadIdx.x;
   const int nt = (v - a + 31) / 32;            // 32-wide tiles of c and d, starting at a
   for (int ci = 0; ci < nt; ++ci) {
@@ -250,21 +255,28 @@ pack_vpm_sym_kernel(int v, int a0, int64_t pair0, const Tg* __restrict__ G, cons
         const int c = cB + r, d = dB + q;
         if (c < v && d < v && c <= d && (c > a || d >= b)) {
           const double gcd = t1[r][q], gdc = t2[r][q];
-          Store<PREC>::put(vp, vp_lo, pr * ldp + pair_plus(c, d, v), 0.5 * (gcd + gdc));
+          const bool diag = c == a && d == b;
+          Store<PREC>::put(vp, vp_lo, rowp * ldp + pair_plus(c, d, v), (diag ? dscale : 0.5) * (gcd + gdc));
           if (has_minus && c < d)
-            Store<PREC>::put(vm, vm_lo, rowm * ldm + pair_minus(c, d, v), 0.5 * (gcd - gdc));
+            Store<PREC>::put(vm, vm_lo, rowm * ldm + pair_minus(c, d, v), (diag ? dscale : 0.5) * (gcd - gdc));
         }
       }
       __syncthreads();
     }
   }
-  for (int64_t k = Pp + tid; k < ldp; k += 256) Store<PREC>::put(vp, vp_lo, pr * ldp + k, 0.0);
+  for (int64_t k = Pp + tid; k < ldp; k += 256) Store<PREC>::put(vp, vp_lo, rowp * ldp + k, 0.0);
   if (has_minus)
     for (int64_t k = Pm + tid; k < ldm; k += 256) Store<PREC>::put(vm, vm_lo, rowm * ldm + k, 0.0);
+  if (half_diag) {
+    for (int64_t k = zp + tid; k < pr; k += 256) Store<PREC>::put(vp, vp_lo, rowp * ldp + k, 0.0);
+    if (has_minus)
+      for (int64_t k = zm + tid; k < qr; k += 256) Store<PREC>::put(vm, vm_lo, rowm * ldm + k, 0.0);
+  }
 }
 
 int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
-                 int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp) {
+                 int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp, int64_t vp_row0,
+                 int64_t vm_row0, int half_diag, int64_t zp, int64_t zm) {
   const int64_t p0 = pair_plus(a0, a0, v);
   const int64_t p1 = (a1 >= v) ? npairs_plus(v) : pair_plus(a1, a1, v);
   const int64_t npairs = p1 - p0;
@@ -273,15 +285,94 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
   dim3 grid((unsigned)npairs);
   if (prec == PPL_FP64)
     hipLaunchKernelGGL((pack_vpm_sym_kernel<double, PPL_FP64>), grid, dim3(256), 0, s, v, a0, p0, (const double*)G,
-                       tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+                       tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm, vp_row0, vm_row0, half_diag, zp, zm);
   else if (prec == PPL_FP32)
     hipLaunchKernelGGL((pack_vpm_sym_kernel<float, PPL_FP32>), grid, dim3(256), 0, s, v, a0, p0, (const float*)G,
-                       tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+                       tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm, vp_row0, vm_row0, half_diag, zp, zm);
   else if (prec == PPL_BF16X3)
     hipLaunchKernelGGL((pack_vpm_sym_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, a0, p0,
-                       (const float*)G, tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+                       (const float*)G, tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm, vp_row0, vm_row0, half_diag,
+                       zp, zm);
   else
     return fail(PPL_E_ARG, "pack_vpm_sym: unknown precision %d", prec);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// Ut[r][k] = U[k0 + k - u0][c0 + r] for rows u0 <= k0 + k < u1 of the block U (row length
+// ldu, its first row is global row u0), zero for the other k; r < nr, k < nk (row length
+// ldt). A bit copy of elements of type E through 64 x 64 LDS tiles.
+template <class E>
+__global__ void __launch_bounds__(256)
+transpose_block_kernel(const E* __restrict__ U, int64_t ldu, int64_t u0, int64_t u1, int64_t c0, int64_t k0,
+                       E* __restrict__ Ut, int64_t ldt, int64_t nr, int64_t nk, int64_t tiles_k) {
+  __shared__ E sh[64][65];
+  const int64_t tr = blockIdx.x / tiles_k, tk = blockIdx.x % tiles_k;
+  const int64_t r0 = tr * 64, kb = tk * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int kl = e >> 6, rl = e & 63;                   // read U row k0 + kb + kl, column c0 + r0 + rl
+    const int64_t gk = k0 + kb + kl, r = r0 + rl;
+    E x = E(0);
+    if (gk >= u0 && gk < u1 && r < nr) x = U[(gk - u0) * ldu + c0 + r];
+    sh[kl][rl] = x;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int rl = e >> 6, kl = e & 63;                   // write Ut row r0 + rl, column kb + kl
+    const int64_t r = r0 + rl, k = kb + kl;
+    if (r < nr && k < nk) Ut[r * ldt + k] = sh[kl][rl];
+  }
+}
+
+int transpose_block(hipStream_t s, int elem_bytes, const void* U, int64_t ldu, int64_t u0, int64_t u1, int64_t c0,
+                    int64_t k0, void* Ut, int64_t ldt, int64_t nr, int64_t nk) {
+  if (nr <= 0 || nk <= 0) return PPL_OK;
+  const int64_t tr = (nr + 63) / 64, tk = (nk + 63) / 64;
+  if (tr * tk > 0x7fffffffLL) return fail(PPL_E_ARG, "transpose of %lld x %lld too large", (long long)nr, (long long)nk);
+  const dim3 grid((unsigned)(tr * tk));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(transpose_block_kernel<uint64_t>, grid, dim3(256), 0, s, (const uint64_t*)U, ldu, u0, u1, c0,
+                       k0, (uint64_t*)Ut, ldt, nr, nk, tk);
+  else if (elem_bytes == 4)
+    hipLaunchKernelGGL(transpose_block_kernel<uint32_t>, grid, dim3(256), 0, s, (const uint32_t*)U, ldu, u0, u1, c0,
+                       k0, (uint32_t*)Ut, ldt, nr, nk, tk);
+  else if (elem_bytes == 2)
+    hipLaunchKernelGGL(transpose_block_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)U, ldu, u0, u1, c0,
+                       k0, (uint16_t*)Ut, ldt, nr, nk, tk);
+  else
+    return fail(PPL_E_ARG, "transpose of %d-byte elements", elem_bytes);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// C[q][p] += T[p][q] for q < nq, p < np (C rows of ldc, T rows of ldt), 64 x 64 LDS tiles.
+__global__ void __launch_bounds__(256)
+add_transposed_kernel(double* __restrict__ C, int64_t ldc, const double* __restrict__ T, int64_t ldt, int64_t nq,
+                      int64_t np, int64_t tiles_p) {
+  __shared__ double sh[64][65];
+  const int64_t tq = blockIdx.x / tiles_p, tp = blockIdx.x % tiles_p;
+  const int64_t q0 = tq * 64, p0 = tp * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int pl = e >> 6, ql = e & 63;                   // read T row p0 + pl, column q0 + ql
+    const int64_t pp = p0 + pl, q = q0 + ql;
+    sh[pl][ql] = (pp < np && q < nq) ? T[pp * ldt + q] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int ql = e >> 6, pl = e & 63;                   // update C row q0 + ql, column p0 + pl
+    const int64_t q = q0 + ql, pp = p0 + pl;
+    if (q < nq && pp < np) C[q * ldc + pp] += sh[pl][ql];
+  }
+}
+
+int add_transposed(hipStream_t s, double* C, int64_t ldc, const double* T, int64_t ldt, int64_t nq, int64_t np) {
+  if (nq <= 0 || np <= 0) return PPL_OK;
+  const int64_t tq = (nq + 63) / 64, tp = (np + 63) / 64;
+  if (tq * tp > 0x7fffffffLL) return fail(PPL_E_ARG, "transposed add of %lld x %lld too large", (long long)nq,
+                                          (long long)np);
+  hipLaunchKernelGGL(add_transposed_kernel, dim3((unsigned)(tq * tp)), dim3(256), 0, s, C, ldc, T, ldt, nq, np, tp);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

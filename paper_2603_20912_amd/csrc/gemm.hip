@@ -1159,8 +1159,11 @@ template <int WM, int WN, int WAVES_M, int WAVES_N>
 static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad,
                         const void* S, const void* S_lo, int64_t lds_, const void* V,
                         const void* V_lo, int64_t ldv, void* C, int64_t ldc, int64_t c_col0,
-                        int splits, void* partial, int64_t partial_ld, uint64_t partial_bytes) {
+                        int splits, void* partial, int64_t partial_ld, uint64_t partial_bytes,
+                        bool accumulate) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  if (accumulate && splits != 1) return fail(PPL_E_ARG, "an accumulating contraction runs one K slice");
+  const double cbeta = accumulate ? 1.0 : 0.0;
   if (splits == 0) {   // stream-K
     if (prec == PPL_FP64)
       return launch_streamk<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(
@@ -1190,17 +1193,17 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
   const int64_t pstride = Nrows * partial_ld;
   int rc = PPL_OK;
   if (prec == PPL_FP64) {
-    EpiStore<double> epi = direct ? EpiStore<double>{(double*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
+    EpiStore<double> epi = direct ? EpiStore<double>{(double*)C, ldc, c_col0, Nrows, Prows, 1.0, cbeta, 0}
                                   : EpiStore<double>{(double*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
     rc = launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, grid, Nrows, Prows, Kpad, (const double*)S, lds_,
                                                       (const double*)V, ldv, epi, map);
   } else if (prec == PPL_FP32) {
-    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
+    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, cbeta, 0}
                                  : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
     rc = launch<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(s, grid, Nrows, Prows, Kpad, (const float*)S, lds_,
                                                      (const float*)V, ldv, epi, map);
   } else if (prec == PPL_BF16X3) {
-    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, 0.0, 0}
+    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, cbeta, 0}
                                  : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
     rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
                                                   (const __bf16*)S_lo, lds_, (const __bf16*)V,
@@ -1225,12 +1228,12 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
 int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
                   const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
                   int64_t ldv, void* C, int64_t ldc, int64_t c_col0, int splits, void* partial,
-                  int64_t partial_ld, uint64_t partial_bytes) {
+                  int64_t partial_ld, uint64_t partial_bytes, bool accumulate) {
   if (Nrows <= 0 || Prows <= 0) return PPL_OK;
 #define PPL_CFG(id, a, b, c, d)                                                                  \
   case id:                                                                                       \
     return contract_cfg<a, b, c, d>(s, prec, Nrows, Prows, Kpad, S, S_lo, lds_, V, V_lo, ldv, C,  \
-                                    ldc, c_col0, splits, partial, partial_ld, partial_bytes);
+                                    ldc, c_col0, splits, partial, partial_ld, partial_bytes, accumulate);
   switch (tile) {
     PPL_CFG(0, 7, 2, 1, 4)
     PPL_CFG(1, 4, 4, 2, 2)

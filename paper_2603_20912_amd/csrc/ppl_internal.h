@@ -129,7 +129,12 @@ struct ppl_plan_s {
   ppl::Region diis_t, diis_e;          // diis_max slots of amplitudes t' and of errors t' - t (S'/A' scaling)
   ppl::Region diis_red;                // DIIS inner-product partials and results
   ppl::Region tiles;                   // per-batch (row tile, column tile) lists of the build GEMM (int32 pairs)
-  bool sym_build = false;              // resident: build the upper triangle of V+- and mirror it
+  bool sym_build = false;              // build the upper triangle of V+- (resident: then mirror it;
+                                       // streaming: contract U and U^T of each step, V = U + U^T)
+  int64_t ldq = 0, ldqm = 0;           // row lengths of the transposed streaming results (pad N+, N-)
+  int64_t ldk = 0;                     // row length of a transposed row block (its K range)
+  ppl::Region r2p, r2m;                // streaming U^T term, transposed: [P+][ldq], [P-][ldqm] (FP64)
+  ppl::Region ut;                      // one transposed row block of U+ or U-: [P+][ldk] (FP64)
   ppl::Region cols;                    // operand rows of the upper-triangle build's columns (int32, v^2)
   std::vector<int> cols_host;
   std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
@@ -167,11 +172,12 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 // Contraction C[N][P] = sum_k S[n][k] V[p][k] for one operand set (R+ or R-).
 // Output in the accumulator precision (double for FP64, float otherwise).
 // splits > 1 splits K into that many slices written to `partial` ([splits][Nrows][partial_ld],
-// accumulator type) and summed in slice order into C.
+// accumulator type) and summed in slice order into C. accumulate: C += the product (one
+// K slice only; PPL_E_ARG with split-K or stream-K).
 int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prows, int64_t Kpad,
                   const void* S, const void* S_lo, int64_t lds_, const void* V, const void* V_lo,
                   int64_t ldv, void* C, int64_t ldc, int64_t c_col0, int splits, void* partial,
-                  int64_t partial_ld, uint64_t partial_bytes);
+                  int64_t partial_ld, uint64_t partial_bytes, bool accumulate = false);
 // bytes of partial slots a stream-K contraction (splits == 0) with this tile needs at most
 uint64_t streamk_part_bytes(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad);
 int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits);
@@ -235,8 +241,17 @@ int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void
              int64_t ldp, int64_t vp_row0, void* vm, void* vm_lo, int64_t ldm, int64_t vm_row0,
              const int* tab_vp, const int* tab_vm);
 // upper triangle of V+- rows from an upper-triangle build step (gemm_build_sym); resident rows
+// (resident: vp_row0 = vm_row0 = 0, half_diag = 0; streaming: rows relative to the
+// step's first pair, diagonal halved so that V = U + U^T, columns from zp / zm up to
+// the row's own pair zeroed)
 int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
-                 int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp);
+                 int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp, int64_t vp_row0 = 0,
+                 int64_t vm_row0 = 0, int half_diag = 0, int64_t zp = 0, int64_t zm = 0);
+// C[q][p] += T[p][q] for q < nq, p < np (FP64)
+int add_transposed(hipStream_t s, double* C, int64_t ldc, const double* T, int64_t ldt, int64_t nq, int64_t np);
+// Ut[r][k] = U[k0 + k - u0][c0 + r] for u0 <= k0 + k < u1, else 0 (r < nr, k < nk)
+int transpose_block(hipStream_t s, int elem_bytes, const void* U, int64_t ldu, int64_t u0, int64_t u1, int64_t c0,
+                    int64_t k0, void* Ut, int64_t ldt, int64_t nr, int64_t nk);
 // V[r][q] = V[q][r] for q < r (bit copy of elem_bytes-wide elements)
 int mirror_lower(hipStream_t s, int elem_bytes, void* V, int64_t n, int64_t ld);
 // pair tables

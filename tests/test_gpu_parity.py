@@ -122,16 +122,42 @@ def test_autotuned_contraction_matches(P):
     assert rel(R, O.ppl(s["L"], 12, t)) < 1e-12
 
 
-def test_streaming_batches_are_bitwise_equal_to_resident(P):
-    say("contract fp64 streaming vs resident (6,60,50), split-K")
+def test_streaming_batches_match_resident(P):
+    say("contract fp64 streaming (upper-triangle steps, U + U^T) vs resident (6,60,50), split-K")
     s = S.make_system(6, 60, 50, 40)
     t = S.make_amplitudes(6, 60, 41)
-    # split-K sums every column over the same K slices whatever the column batch
     R_res, i_res = gpu_contract(P, s, t, config=(5, 2, 0, 3))
     R_str, i_str = gpu_contract(P, s, t, budget=i_res["workspace_bytes"] // 3, config=(5, 2, 0, 3))
     assert i_res["resident"] == 1 and i_str["resident"] == 0 and i_str["n_batches"] > 1
-    assert np.array_equal(R_res, R_str)
+    # V = U + U^T splits every sum into two GEMMs: equal up to rounding
+    assert rel(R_str, R_res) < 1e-14
     assert rel(R_res, O.ppl(s["L"], 6, t)) < 1e-12
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("bf16x3", 4e-5)])
+def test_streaming_full_rows_low_precision(P, prec, bound):
+    say(f"contract {prec} streaming (full rows) vs resident (6,60,50)")
+    s = S.make_system(6, 60, 50, 42)
+    t = S.make_amplitudes(6, 60, 43)
+    R_res, i_res = gpu_contract(P, s, t, prec=prec)
+    R_str, i_str = gpu_contract(P, s, t, prec=prec, budget=i_res["workspace_bytes"] // 3)
+    assert i_res["resident"] == 1 and i_str["resident"] == 0 and i_str["n_batches"] > 1
+    ref = O.ppl(s["L"], 6, t)
+    assert rel(R_str, ref) < bound and rel(R_res, ref) < bound
+
+
+@pytest.mark.parametrize("o,v,naux", [(1, 70, 20), (5, 130, 40), (9, 97, 61)])
+def test_streaming_upper_triangle_steps(P, o, v, naux):
+    say(f"contract fp64 streaming upper-triangle steps ({o},{v},{naux}), many steps")
+    s = S.make_system(o, v, naux, 44)
+    t = S.make_amplitudes(o, v, 45)
+    eng = P.PPL(o, v, naux)
+    budget = eng.info["workspace_bytes"] // 4
+    eng.close()
+    R, info = gpu_contract(P, s, t, budget=budget)
+    assert info["resident"] == 0 and info["n_batches"] > 2
+    assert info["flops_build"] == 2.0 * naux * info["p_plus"] ** 2
+    assert rel(R, O.ppl(s["L"], o, t)) < 1e-12
 
 
 def test_streaming_batches_stream_k(P):
@@ -141,7 +167,8 @@ def test_streaming_batches_stream_k(P):
     R_res, i_res = gpu_contract(P, s, t, config=(0, 0, 5, 0))
     R_str, i_str = gpu_contract(P, s, t, budget=i_res["workspace_bytes"] // 3, config=(0, 0, 5, 0))
     assert i_res["resident"] == 1 and i_str["resident"] == 0 and i_str["n_batches"] > 1
-    # the K ranges of shared tiles follow each launch's partition: equal up to rounding
+    # the K ranges of shared tiles follow each launch's partition, and V = U + U^T splits
+    # the sums: equal up to rounding
     assert rel(R_str, R_res) < 1e-14
     assert rel(R_res, O.ppl(s["L"], 6, t)) < 1e-12
     # a repeated launch gives the same bits
