@@ -56,6 +56,12 @@ typedef enum {
 
 typedef struct ppl_plan_s* ppl_plan_t;
 
+/* ppl_desc_t.flags: the plan serves ppl_contract, ppl_contract_tau and ppl_hhl only. It
+ * keeps none of the iteration's buffers ((ia|jb), their scratch, the checked-start copy),
+ * which leaves more of the budget to V+- rows (larger streaming steps); ppl_iterate and
+ * ppl_mp2 return PPL_E_STATE on it. */
+#define PPL_PLAN_CONTRACT_ONLY 1
+
 /* Problem description (input of ppl_plan). */
 typedef struct {
   int32_t  o;           /* occupied orbitals, >= 1 */
@@ -69,6 +75,7 @@ typedef struct {
   uint64_t build_scratch; /* bytes of integral-build scratch (0 = up to 4 GiB); larger = fewer build steps */
   int32_t  diis_max;    /* DIIS subspace capacity kept in the workspace, 0 .. PPL_DIIS_MAX (0 = none);
                            costs 2 * diis_max packed FP64 amplitude vectors */
+  int32_t  flags;       /* PPL_PLAN_* bits */
 } ppl_desc_t;
 
 /* What the planner decided (output of ppl_plan_query). */

@@ -144,8 +144,9 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     }
   }
   // build scratch G (accumulator precision) doubles as the (ia|jb) scratch
+  // (the (ia|jb) scratch of the iteration only when the plan iterates)
   const uint64_t gbytes = std::max<uint64_t>(std::max<uint64_t>((uint64_t)gcap * v * v * g_acc_bytes(p),
-                                                               (uint64_t)(o * v) * (o * v) * 8),
+                                                               p->contract_only ? 0 : (uint64_t)(o * v) * (o * v) * 8),
                                              hhl_scratch(p).bytes);
   p->g = L.take(gbytes);
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
@@ -168,11 +169,15 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     p->s64 = p->ops[0].sp;
     p->a64 = p->ops[0].am;
   }
-  p->bs = L.take((uint64_t)p->Np * p->ldp * 8);     // backup of S'/A' for checked starts
-  p->ba = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
-  p->vs = L.take((uint64_t)p->Np * p->ldp * 8);
-  p->va = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
-  p->xov = L.take((uint64_t)o * v * p->ldx * 8);
+  if (p->contract_only) {
+    p->bs = p->ba = p->vs = p->va = p->xov = Region{};
+  } else {
+    p->bs = L.take((uint64_t)p->Np * p->ldp * 8);     // backup of S'/A' for checked starts
+    p->ba = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+    p->vs = L.take((uint64_t)p->Np * p->ldp * 8);
+    p->va = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
+    p->xov = L.take((uint64_t)o * v * p->ldx * 8);
+  }
   p->tab_vp = L.take((uint64_t)p->Pp * 4);
   p->tab_vm = L.take((uint64_t)std::max<int64_t>(p->Pm, 1) * 4);
   p->tab_op = L.take((uint64_t)p->Np * 4);
@@ -585,6 +590,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
     return fail(PPL_E_ARG, "tile_contract %d out of range", d->tile_contract);
   if (d->diis_max < 0 || d->diis_max > PPL_DIIS_MAX)
     return fail(PPL_E_ARG, "diis_max %d out of range [0, %d]", d->diis_max, PPL_DIIS_MAX);
+  if (d->flags & ~PPL_PLAN_CONTRACT_ONLY) return fail(PPL_E_ARG, "unknown plan flags 0x%x", d->flags);
   // 64-bit size sanity: the largest products used anywhere
   {
     uint64_t x;
@@ -601,7 +607,8 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   p->naux = d->naux;
   p->prec = d->prec;
   p->keep_fp64 = (d->prec != PPL_FP64) && d->keep_fp64;
-  p->diis_max = d->diis_max;
+  p->contract_only = (d->flags & PPL_PLAN_CONTRACT_ONLY) != 0;
+  p->diis_max = p->contract_only ? 0 : d->diis_max;
   p->stream = (hipStream_t)d->stream;
   p->Pp = npairs_plus(p->v);
   p->Pm = npairs_minus(p->v);
@@ -882,6 +889,7 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
                 const ppl_iter_opts_t* opts, ppl_iter_report_t* rep) {
   g_err[0] = 0;
   PPL_TRY(check_bound(p));
+  if (p->contract_only) return fail(PPL_E_STATE, "a PPL_PLAN_CONTRACT_ONLY plan cannot iterate");
   if (!L || !e_occ || !e_vir || !t2) return fail(PPL_E_ARG, "null device pointer");
   ppl_iter_opts_t o;
   if (opts) o = *opts; else ppl_iter_opts_default(&o);
@@ -1216,6 +1224,7 @@ int ppl_mp2(ppl_plan_t p, const double* L, const double* e_occ, const double* e_
             double* e_mp2) {
   g_err[0] = 0;
   PPL_TRY(check_bound(p));
+  if (p->contract_only) return fail(PPL_E_STATE, "a PPL_PLAN_CONTRACT_ONLY plan has no (ia|jb) buffers");
   if (!L || !e_occ || !e_vir || !t2_out) return fail(PPL_E_ARG, "null device pointer");
   hipStream_t st = p->stream;
   double* partials = at<double>(p, p->red);
@@ -1597,6 +1606,7 @@ int ppl_batch_plan(int32_t n, const ppl_desc_t* descs, ppl_batch_t* out) {
     }
     d.keep_fp64 = 0;
     d.diis_max = 0;                      // batched instances are contracted, not iterated
+    d.flags |= PPL_PLAN_CONTRACT_ONLY;
     if (d.hbm_budget == 0) d.hbm_budget = (uint64_t)1 << 62;
     if (d.build_scratch == 0) d.build_scratch = (uint64_t)256 << 20;   // builds run one instance at a time
     ppl_plan_t p = nullptr;

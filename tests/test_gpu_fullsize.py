@@ -109,7 +109,7 @@ def test_benchmark_shape_streaming_sampled(P):
     R = torch.empty_like(t)      # before the plan, which takes 90% of the free memory
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    eng = P.PPL(o, v, naux, build_scratch=64 << 30)
+    eng = P.PPL(o, v, naux, build_scratch=64 << 30, contract_only=True)
     assert eng.info["resident"] == 0 and eng.info["n_batches"] > 1
     say(f"  {eng.info['n_batches']} row batches of up to {eng.info['max_step_pairs']} pairs")
     eng.build(L)

@@ -268,3 +268,24 @@ def test_upper_triangle_build_matches_full_rows(P, monkeypatch, prec, bound, o, 
         eng.close()
     assert rel(out["1"], out["0"]) < (1e-14 if prec == "fp64" else bound / 10)
     assert rel(out["1"], O.ppl(s["L"], o, t)) < bound
+
+
+def test_contract_only_plan(P):
+    o, v, naux = 6, 40, 50
+    say(f"contract-only plan ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 60, "contractive")
+    t = S.make_amplitudes(o, v, 61)
+    eng = P.PPL(o, v, naux, contract_only=True)
+    L = dev(s["L"])
+    eng.build(L)
+    R = eng.contract(dev(t)).cpu().numpy()
+    assert rel(R, O.ppl(s["L"], o, t)) < 1e-12
+    H = eng.hhl(L, dev(t)).cpu().numpy()
+    assert rel(H, O.hhl(s["L"], o, t)) < 1e-12
+    t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PPLError) as e:
+        eng.iterate(L, dev(s["e_occ"]), dev(s["e_vir"]), t2, max_sweeps=2)
+    assert e.value.code == -7
+    with pytest.raises(P.PPLError):
+        eng.mp2(L, dev(s["e_occ"]), dev(s["e_vir"]))
+    eng.close()

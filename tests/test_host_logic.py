@@ -99,6 +99,19 @@ def test_streaming_plan_of_the_largest_benchmark_shape(P):
     assert j["max_step_pairs"] < i["max_step_pairs"] and j["n_batches"] > i["n_batches"]
 
 
+def test_contract_only_plans(P):
+    full = plan_info(P, 100, 700, 4000, hbm_budget=186 << 30, build_scratch=64 << 30)
+    lean = plan_info(P, 100, 700, 4000, hbm_budget=186 << 30, build_scratch=64 << 30, flags=1)
+    # the iteration's buffers go to V+- rows: larger streaming steps, fewer of them
+    assert lean["max_step_pairs"] > full["max_step_pairs"] and lean["n_batches"] < full["n_batches"]
+    assert lean["flops_build"] == full["flops_build"]
+    small = plan_info(P, 20, 200, 600, hbm_budget=1 << 40, flags=1)
+    assert small["workspace_bytes"] < plan_info(P, 20, 200, 600, hbm_budget=1 << 40)["workspace_bytes"]
+    with pytest.raises(P.PPLError) as e:
+        plan_info(P, 20, 200, 600, hbm_budget=1 << 40, flags=2)
+    assert e.value.code == -1
+
+
 def test_diis_slots_in_the_workspace(P):
     o, v, naux = 20, 200, 600
     base = plan_info(P, o, v, naux, hbm_budget=64 << 30)
