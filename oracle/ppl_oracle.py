@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
     "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
-    "jacobi", "jacobi_diis", "fixed_point", "spectral_radius", "nominal_flops",
+    "jacobi", "jacobi_diis", "fixed_point", "fixed_point_hhl", "spectral_radius", "nominal_flops",
 ]
 
 
@@ -203,14 +203,18 @@ def energy(V: np.ndarray, t: np.ndarray) -> float:
 # linearized doubles iteration (the PPL-only vector function with the Fock
 # denominators), its exact fixed point and its contraction rate
 # ---------------------------------------------------------------------------
-def jacobi_sweep(L, o, V, D, t):
-    """One simultaneous update t_new = (V + PPL(t)) / D; returns (t_new, ||t_new - t||_F)."""
-    t_new = (V + ppl(L, o, t)) / D
+def jacobi_sweep(L, o, V, D, t, with_hhl: bool = False):
+    """One simultaneous update t_new = (V + PPL(t) [+ HHL(t)]) / D; returns (t_new, ||t_new - t||_F)."""
+    g = V + ppl(L, o, t)
+    if with_hhl:
+        g = g + hhl(L, o, t)
+    t_new = g / D
     return t_new, float(np.linalg.norm(t_new - t))
 
 
-def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7):
-    """Iterate from t0 (MP2 when None) until r < tol or max_sweeps.
+def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7, with_hhl: bool = False):
+    """Iterate from t0 (MP2 when None) until r < tol or max_sweeps; with_hhl adds the
+    hole-hole ladder to every sweep.
 
     Returns (t, residual_history, E(t)).
     """
@@ -218,14 +222,15 @@ def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7
     t = V / D if t0 is None else np.array(t0, dtype=np.float64)
     hist = []
     for _ in range(max_sweeps):
-        t, r = jacobi_sweep(L, o, V, D, t)
+        t, r = jacobi_sweep(L, o, V, D, t, with_hhl)
         hist.append(r)
         if not np.isfinite(r) or r < tol:
             break
     return t, hist, energy(V, t)
 
 
-def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, tol: float = 1e-7):
+def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, tol: float = 1e-7,
+                with_hhl: bool = False):
     """Jacobi iteration accelerated by direct inversion in the iterative subspace
     (DIIS; P. Pulay, Chem. Phys. Lett. 73, 393 (1980)).
 
@@ -246,7 +251,7 @@ def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, 
     t = V / D if t0 is None else np.array(t0, dtype=np.float64)
     Ts, Es, hist = [], [], []
     for _ in range(max_sweeps):
-        t_new = (V + ppl(L, o, t)) / D
+        t_new, _ = jacobi_sweep(L, o, V, D, t, with_hhl)
         e = t_new - t
         r = float(np.linalg.norm(e))
         hist.append(r)
@@ -280,6 +285,23 @@ def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, 
             Es.pop(0)
         t = sum(ci * Ti for ci, Ti in zip(c, Ts))
     return t, hist, energy(V, t)
+
+
+def fixed_point_hhl(L, o, e_occ, e_vir) -> np.ndarray:
+    """Exact solution of t = (V + PPL(t) + HHL(t)) / D by one dense solve over all
+    (i, j, a, b): the operator is K[(ijab),(klcd)] = (ac|bd) d_ik d_jl + (ki|lj) d_ac d_bd.
+    Tiny sizes only ((o v)^2 x (o v)^2 system)."""
+    L = np.asarray(L, dtype=np.float64)
+    Lvv, Loo = vv_block(L, o), oo_block(L, o)
+    v = Lvv.shape[1]
+    Kv = np.einsum("Pac,Pbd->abcd", Lvv, Lvv)          # (ac|bd)
+    Ko = np.einsum("Pki,Plj->ijkl", Loo, Loo)          # (ki|lj)
+    Io, Iv = np.eye(o), np.eye(v)
+    K = (np.einsum("abcd,ik,jl->ijabklcd", Kv, Io, Io) + np.einsum("ijkl,ac,bd->ijabklcd", Ko, Iv, Iv))
+    n = o * o * v * v
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    A = np.diag(D.ravel()) - K.reshape(n, n)
+    return np.linalg.solve(A, V.ravel()).reshape(o, o, v, v)
 
 
 def fixed_point(L, o, e_occ, e_vir) -> np.ndarray:

@@ -396,3 +396,23 @@ def test_planted_hhl_mistakes_are_caught(mutant):
     s = S.make_system(o, v, naux, 5)
     t = general_t(o, v, 6)
     assert rel(mutant(s["L"], o, t), O.hhl(s["L"], o, t)) > 1e-3
+
+
+def test_iteration_with_hhl_reaches_the_dense_fixed_point():
+    o, v, naux = 4, 12, 36
+    s = S.make_system(o, v, naux, 5, "contractive")
+    args = (s["L"], o, s["e_occ"], s["e_vir"])
+    tstar = O.fixed_point_hhl(*args)
+    V, D = O.mp2_parts(*args)
+    # the dense operator (built from einsum definitions) and the two term functions agree
+    assert rel(D * tstar - O.ppl(s["L"], o, tstar) - O.hhl(s["L"], o, tstar), V) < 1e-13
+    t, hist, E = O.jacobi(*args, max_sweeps=200, tol=1e-11, with_hhl=True)
+    assert hist[-1] < 1e-11 and rel(t, tstar) < 1e-9
+    # the hole-hole ladder moves the fixed point by far more than the tolerance
+    assert rel(O.fixed_point(*args), tstar) > 1e-2
+    # DIIS reaches it too, where the plain sweeps crawl
+    s3 = S.make_system(3, 16, 48, 6, "contractive")
+    a3 = (s3["L"], 3, s3["e_occ"], s3["e_vir"])
+    _, hj, _ = O.jacobi(*a3, max_sweeps=40, tol=1e-11, with_hhl=True)
+    td, hd, _ = O.jacobi_diis(*a3, m=8, max_sweeps=60, tol=1e-11, with_hhl=True)
+    assert hj[-1] > 1e-6 and hd[-1] < 1e-11 and rel(td, O.fixed_point_hhl(*a3)) < 1e-9
