@@ -183,6 +183,8 @@ typedef struct {
   double  diverge_factor;   /* PPL_E_DIVERGED when r > diverge_factor * r_first (0 = off) */
   double* history;          /* optional host array of max_sweeps residuals (NULL = none) */
   int32_t diis;             /* DIIS subspace size (<= the plan's diis_max); 0 or 1 = plain Jacobi */
+  int32_t hhl;              /* 1: sweeps solve t = (V + PPL(t) + HHL(t)) / D (hole-hole ladder, ppl_hhl;
+                               resident plans only, PPL_E_UNSUPPORTED otherwise) */
 } ppl_iter_opts_t;
 
 typedef struct {

@@ -77,7 +77,7 @@ class PPL:
 
     def iterate(self, L, e_occ, e_vir, t2, max_sweeps=100, tol=1e-7, start="mp2", switch_tol=0.0,
                 stagnation=0.95, min_fp64_sweeps=2, diverge_factor=1e3, fail_on_noconv=True,
-                history=True, raise_on_status=True, diis=0):
+                history=True, raise_on_status=True, diis=0, hhl=False):
         opts = ppl_iter_opts_default()
         opts.max_sweeps = int(max_sweeps)
         opts.tol = float(tol)
@@ -89,6 +89,7 @@ class PPL:
         opts.diverge_factor = float(diverge_factor)
         opts.fail_on_noconv = int(bool(fail_on_noconv))
         opts.diis = int(diis)
+        opts.hhl = int(bool(hhl))
         hist = (ctypes.c_double * max_sweeps)() if history else None
         if hist is not None:
             opts.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))

@@ -57,7 +57,7 @@ class ppl_iter_opts_t(ctypes.Structure):
                 ("switch_tol", ctypes.c_double), ("stagnation", ctypes.c_double),
                 ("min_fp64_sweeps", ctypes.c_int32), ("fail_on_noconv", ctypes.c_int32),
                 ("diverge_factor", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
-                ("diis", ctypes.c_int32)]
+                ("diis", ctypes.c_int32), ("hhl", ctypes.c_int32)]
 
 
 class ppl_iter_report_t(ctypes.Structure):

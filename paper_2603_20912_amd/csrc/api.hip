@@ -400,8 +400,8 @@ static int contract_stream_sym(ppl_plan_t p, OperandSet& s, int tile, int tile_m
     }
   }
   ProfScope ps(p, PPL_PROF_OTHER, 0.0);
-  PPL_TRY(add_transposed(st, rp, p->ldp, r2p, p->ldq, p->Np, p->Pp));
-  if (p->Nm > 0) PPL_TRY(add_transposed(st, rm, p->ldm, r2m, p->ldqm, p->Nm, p->Pm));
+  PPL_TRY(add_transposed(st, PPL_FP64, rp, p->ldp, r2p, p->ldq, p->Np, p->Pp));
+  if (p->Nm > 0) PPL_TRY(add_transposed(st, PPL_FP64, rm, p->ldm, r2m, p->ldqm, p->Nm, p->Pm));
   return PPL_OK;
 }
 
@@ -574,6 +574,7 @@ void ppl_iter_opts_default(ppl_iter_opts_t* o) {
   o->diverge_factor = 1e3;
   o->history = nullptr;
   o->diis = 0;
+  o->hhl = 0;
 }
 
 int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
@@ -812,6 +813,58 @@ int ppl_build_batch(ppl_plan_t p, const double* L, int32_t batch) {
 }  // extern "C"
 
 namespace ppl {
+// (ki|lj) from the occupied block of L and W+-_{ij,kl} = ((ki|lj) +- (li|kj)) / 2 on the
+// i<=j (i<j) rows and k<=l (k<l) columns, in the hole-hole scratch
+static int hhl_integrals(ppl_plan_t p, const double* L) {
+  const HhlScratch h = hhl_scratch(p);
+  char* g = at<char>(p, p->g);
+  double *xoo = (double*)(g + h.xoo), *woo = (double*)(g + h.woo);
+  const int64_t o = p->o, oo = o * o;
+  const int *tab_op = at<int>(p, p->tab_op), *tab_om = at<int>(p, p->tab_om);
+  PPL_TRY(stage_oo(p->stream, L, p->o, p->v, p->naux, p->ldx, xoo));
+  PPL_TRY(gemm_store_f64(p->stream, oo, oo, p->ldx, xoo, p->ldx, xoo, p->ldx, woo, oo));
+  // X_ij^kl = Woo[(k,i)][(l,j)]
+  return pack_pm(p->stream, p->o, p->o, woo, oo, 1, o * oo, o, 0.5, 0.5, 0.5, (double*)(g + h.wp), h.ldq,
+                 (double*)(g + h.wm), h.ldqm, tab_op, tab_om, tab_op, tab_om);
+}
+
+// C+ = sT W+^T and C- = aT W-^T (K = occupied pairs) from the transposed amplitudes in the scratch
+static int hhl_contract(ppl_plan_t p) {
+  const HhlScratch h = hhl_scratch(p);
+  char* g = at<char>(p, p->g);
+  int tile = -1, sp = 1;
+  contract_choose(PPL_FP64, p->Pp, p->Np, h.ldq, 1, &tile, &sp);
+  PPL_TRY(gemm_contract(p->stream, PPL_FP64, tile, p->Pp, p->Np, h.ldq, g + h.st, nullptr, h.ldq, g + h.wp, nullptr,
+                        h.ldq, g + h.cp, h.ldq, 0, 1, nullptr, h.ldq, 0));
+  if (p->Nm > 0) {
+    tile = -1;
+    sp = 1;
+    contract_choose(PPL_FP64, p->Pm, p->Nm, h.ldqm, 1, &tile, &sp);
+    PPL_TRY(gemm_contract(p->stream, PPL_FP64, tile, p->Pm, p->Nm, h.ldqm, g + h.at, nullptr, h.ldqm, g + h.wm,
+                          nullptr, h.ldqm, g + h.cm, h.ldqm, 0, 1, nullptr, h.ldqm, 0));
+  }
+  return PPL_OK;
+}
+
+// R+- += the hole-hole ladder of the packed amplitudes S'/A' (FP64 masters), in the
+// accumulator type of the operand set's results
+static int hhl_add_packed(ppl_plan_t p, const OperandSet& s) {
+  const HhlScratch h = hhl_scratch(p);
+  char* g = at<char>(p, p->g);
+  hipStream_t st = p->stream;
+  PPL_TRY(transpose_pm(st, at<double>(p, p->s64), p->ldp, (double*)(g + h.st), h.ldq, p->Np, p->Pp,
+                       at<int>(p, p->tab_op), at<int>(p, p->tab_vp), 1));
+  if (p->Nm > 0)
+    PPL_TRY(transpose_pm(st, at<double>(p, p->a64), p->ldm, (double*)(g + h.at), h.ldqm, p->Nm, p->Pm, nullptr,
+                         nullptr, 0));
+  PPL_TRY(hhl_contract(p));
+  const int cprec = s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32;
+  PPL_TRY(add_transposed(st, cprec, at<void>(p, p->rp), p->ldp, (const double*)(g + h.cp), h.ldq, p->Np, p->Pp));
+  if (p->Nm > 0)
+    PPL_TRY(add_transposed(st, cprec, at<void>(p, p->rm), p->ldm, (const double*)(g + h.cm), h.ldqm, p->Nm, p->Pm));
+  return PPL_OK;
+}
+
 static int contract_impl(ppl_plan_t p, const double* t2, const double* t1, double* R, double alpha,
                          double beta) {
   g_err[0] = 0;
@@ -852,37 +905,16 @@ int ppl_hhl(ppl_plan_t p, const double* L, const double* t2, double* R, double a
   if (h.bytes > p->g.bytes)
     return fail(PPL_E_STATE, "hole-hole scratch needs %llu B, the plan has %llu B",
                 (unsigned long long)h.bytes, (unsigned long long)p->g.bytes);
-  hipStream_t st = p->stream;
   char* g = at<char>(p, p->g);
-  double *xoo = (double*)(g + h.xoo), *woo = (double*)(g + h.woo), *wp = (double*)(g + h.wp),
-         *wm = (double*)(g + h.wm), *sT = (double*)(g + h.st), *aT = (double*)(g + h.at),
-         *cp = (double*)(g + h.cp), *cm = (double*)(g + h.cm);
-  const int64_t o = p->o, v = p->v, oo = o * o;
-  const int *tab_op = at<int>(p, p->tab_op), *tab_om = at<int>(p, p->tab_om), *tab_vp = at<int>(p, p->tab_vp),
-            *tab_vm = at<int>(p, p->tab_vm);
+  const int64_t o = p->o, v = p->v;
   ProfScope ps(p, PPL_PROF_OTHER, 2.0 * (double)p->Pp * p->Np * p->Np + 2.0 * (double)p->Pm * p->Nm * p->Nm);
-  // (ki|lj) = sum_P L^P_ki L^P_lj as Woo[(k,i)][(l,j)]
-  PPL_TRY(stage_oo(st, L, p->o, p->v, p->naux, p->ldx, xoo));
-  PPL_TRY(gemm_store_f64(st, oo, oo, p->ldx, xoo, p->ldx, xoo, p->ldx, woo, oo));
-  // W+-_{ij,kl} = ((ki|lj) +- (li|kj)) / 2 on the i<=j (i<j) rows and k<=l (k<l) columns
-  PPL_TRY(pack_pm(st, p->o, p->o, woo, oo, 1, o * oo, o, 0.5, 0.5, 0.5, wp, h.ldq, wm, h.ldqm, tab_op, tab_om,
-                  tab_op, tab_om));
+  PPL_TRY(hhl_integrals(p, L));
   // transposed packed amplitudes: sT[(a<=b)][(k<=l)] = (2 - d_kl) s_kl^ab, aT[(a<b)][(k<l)] = 2 a_kl^ab
-  PPL_TRY(pack_pm(st, p->v, p->o, t2, v, 1, o * v * v, v * v, 1.0, 0.5, 1.0, sT, h.ldq, aT, h.ldqm, tab_vp, tab_vm,
-                  tab_op, tab_om));
-  // C+ = sT W+^T, C- = aT W-^T (K = occupied pairs)
-  int tile = -1, sp = 1;
-  contract_choose(PPL_FP64, p->Pp, p->Np, h.ldq, 1, &tile, &sp);
-  PPL_TRY(gemm_contract(st, PPL_FP64, tile, p->Pp, p->Np, h.ldq, sT, nullptr, h.ldq, wp, nullptr, h.ldq, cp, h.ldq,
-                        0, 1, nullptr, h.ldq, 0));
-  if (p->Nm > 0) {
-    tile = -1;
-    sp = 1;
-    contract_choose(PPL_FP64, p->Pm, p->Nm, h.ldqm, 1, &tile, &sp);
-    PPL_TRY(gemm_contract(st, PPL_FP64, tile, p->Pm, p->Nm, h.ldqm, aT, nullptr, h.ldqm, wm, nullptr, h.ldqm, cm,
-                          h.ldqm, 0, 1, nullptr, h.ldqm, 0));
-  }
-  return unpack_rt(st, p->o, p->v, cp, h.ldq, cm, h.ldqm, R, alpha, beta);
+  PPL_TRY(pack_pm(p->stream, p->v, p->o, t2, v, 1, o * v * v, v * v, 1.0, 0.5, 1.0, (double*)(g + h.st), h.ldq,
+                  (double*)(g + h.at), h.ldqm, at<int>(p, p->tab_vp), at<int>(p, p->tab_vm), at<int>(p, p->tab_op),
+                  at<int>(p, p->tab_om)));
+  PPL_TRY(hhl_contract(p));
+  return unpack_rt(p->stream, p->o, p->v, (double*)(g + h.cp), h.ldq, (double*)(g + h.cm), h.ldqm, R, alpha, beta);
 }
 
 int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,
@@ -895,6 +927,9 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   if (opts) o = *opts; else ppl_iter_opts_default(&o);
   if (o.max_sweeps < 1) return fail(PPL_E_ARG, "max_sweeps must be >= 1");
   if (o.start < PPL_START_MP2 || o.start > PPL_START_GIVEN_CHECKED) return fail(PPL_E_ARG, "bad start");
+  if (o.hhl && !p->resident)
+    return fail(PPL_E_UNSUPPORTED, "the hole-hole ladder in the iteration needs a resident plan");
+  if (o.hhl && hhl_scratch(p).bytes > p->g.bytes) return fail(PPL_E_STATE, "hole-hole scratch too small");
   if (o.diis < 0 || o.diis > p->diis_max)
     return fail(PPL_E_ARG, "diis %d exceeds the plan's subspace capacity %d (ppl_desc_t.diis_max)", o.diis,
                 p->diis_max);
@@ -905,9 +940,11 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   double* red_out = partials + kReduceBlocks * 4;
   double h[4];
 
-  // integrals: V = (ia|jb) packed into VS / VA, then V+- of every operand set
+  // integrals: V = (ia|jb) packed into VS / VA, then V+- of every operand set, then the
+  // hole-hole W+- (the build scratch holds them for the sweeps of a resident plan)
   PPL_TRY(setup_ov_integrals(p, L));
   PPL_TRY(ppl_build_batch(p, L, -1));
+  if (o.hhl) PPL_TRY(hhl_integrals(p, L));
 
   const int* tabs[4] = {at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp),
                         at<int>(p, p->tab_vm)};
@@ -958,6 +995,10 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   auto sweep_once = [&](OperandSet& s) -> int {
     PPL_TRY(refresh_operands(p, s));
     PPL_TRY(contract_packed(p, s));
+    if (o.hhl) {
+      ProfScope ph(p, PPL_PROF_OTHER, 2.0 * (double)p->Pp * p->Np * p->Np + 2.0 * (double)p->Pm * p->Nm * p->Nm);
+      PPL_TRY(hhl_add_packed(p, s));
+    }
     ProfScope ps(p, PPL_PROF_UPDATE, 0.0);
     double* ts = slot >= 0 ? dT + slot * p->diis_slot_n : nullptr;
     double* es = slot >= 0 ? dE + slot * p->diis_slot_n : nullptr;

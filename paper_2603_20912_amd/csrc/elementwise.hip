@@ -346,9 +346,57 @@ int transpose_block(hipStream_t s, int elem_bytes, const void* U, int64_t ldu, i
   return PPL_OK;
 }
 
-// C[q][p] += T[p][q] for q < nq, p < np (C rows of ldc, T rows of ldt), 64 x 64 LDS tiles.
+// Y[p][q] = w X[q][p] for q < nq, p < np, and Y[p][q] = 0 for nq <= q < ldy (rows of X
+// hold ldx, rows of Y ldy doubles). scaled: w = (2 - d_kl) / (2 - d_ab) with (k, l) =
+// tab_q[q] and (a, b) = tab_p[p] (S' rows to the transposed symmetric operand of the
+// hole-hole ladder); otherwise w = 1.
 __global__ void __launch_bounds__(256)
-add_transposed_kernel(double* __restrict__ C, int64_t ldc, const double* __restrict__ T, int64_t ldt, int64_t nq,
+transpose_pm_kernel(const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, int64_t ldy, int64_t nq,
+                    int64_t np, const int* __restrict__ tab_q, const int* __restrict__ tab_p, int scaled,
+                    int64_t tiles_q) {
+  __shared__ double sh[64][65];
+  const int64_t tp = blockIdx.x / tiles_q, tq = blockIdx.x % tiles_q;
+  const int64_t p0 = tp * 64, q0 = tq * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int ql = e >> 6, pl = e & 63;                   // read X row q0 + ql, column p0 + pl
+    const int64_t q = q0 + ql, p = p0 + pl;
+    double x = 0.0;
+    if (q < nq && p < np) {
+      x = X[q * ldx + p];
+      if (scaled) {
+        const int kl = tab_q[q], ab = tab_p[p];
+        const double wq = pair_first(kl) == pair_second(kl) ? 1.0 : 2.0;
+        const double wp = pair_first(ab) == pair_second(ab) ? 1.0 : 2.0;
+        x *= wq / wp;
+      }
+    }
+    sh[ql][pl] = x;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int pl = e >> 6, ql = e & 63;                   // write Y row p0 + pl, column q0 + ql
+    const int64_t p = p0 + pl, q = q0 + ql;
+    if (p < np && q < ldy) Y[p * ldy + q] = sh[ql][pl];
+  }
+}
+
+int transpose_pm(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nq, int64_t np,
+                 const int* tab_q, const int* tab_p, int scaled) {
+  if (np <= 0 || ldy <= 0) return PPL_OK;
+  const int64_t tq = (ldy + 63) / 64, tp = (np + 63) / 64;
+  if (tq * tp > 0x7fffffffLL) return fail(PPL_E_ARG, "transpose of %lld x %lld too large", (long long)np,
+                                          (long long)ldy);
+  hipLaunchKernelGGL(transpose_pm_kernel, dim3((unsigned)(tq * tp)), dim3(256), 0, s, X, ldx, Y, ldy, nq, np, tab_q,
+                     tab_p, scaled, tq);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// C[q][p] += T[p][q] for q < nq, p < np (C rows of ldc, T rows of ldt), 64 x 64 LDS tiles.
+template <class Tc>
+__global__ void __launch_bounds__(256)
+add_transposed_kernel(Tc* __restrict__ C, int64_t ldc, const double* __restrict__ T, int64_t ldt, int64_t nq,
                       int64_t np, int64_t tiles_p) {
   __shared__ double sh[64][65];
   const int64_t tq = blockIdx.x / tiles_p, tp = blockIdx.x % tiles_p;
@@ -363,16 +411,22 @@ add_transposed_kernel(double* __restrict__ C, int64_t ldc, const double* __restr
   for (int e = tid; e < 64 * 64; e += 256) {
     const int ql = e >> 6, pl = e & 63;                   // update C row q0 + ql, column p0 + pl
     const int64_t q = q0 + ql, pp = p0 + pl;
-    if (q < nq && pp < np) C[q * ldc + pp] += sh[pl][ql];
+    if (q < nq && pp < np) C[q * ldc + pp] = (Tc)((double)C[q * ldc + pp] + sh[pl][ql]);
   }
 }
 
-int add_transposed(hipStream_t s, double* C, int64_t ldc, const double* T, int64_t ldt, int64_t nq, int64_t np) {
+int add_transposed(hipStream_t s, int c_prec, void* C, int64_t ldc, const double* T, int64_t ldt, int64_t nq,
+                   int64_t np) {
   if (nq <= 0 || np <= 0) return PPL_OK;
   const int64_t tq = (nq + 63) / 64, tp = (np + 63) / 64;
   if (tq * tp > 0x7fffffffLL) return fail(PPL_E_ARG, "transposed add of %lld x %lld too large", (long long)nq,
                                           (long long)np);
-  hipLaunchKernelGGL(add_transposed_kernel, dim3((unsigned)(tq * tp)), dim3(256), 0, s, C, ldc, T, ldt, nq, np, tp);
+  if (c_prec == PPL_FP64)
+    hipLaunchKernelGGL(add_transposed_kernel<double>, dim3((unsigned)(tq * tp)), dim3(256), 0, s, (double*)C, ldc, T,
+                       ldt, nq, np, tp);
+  else
+    hipLaunchKernelGGL(add_transposed_kernel<float>, dim3((unsigned)(tq * tp)), dim3(256), 0, s, (float*)C, ldc, T,
+                       ldt, nq, np, tp);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

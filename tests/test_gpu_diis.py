@@ -113,3 +113,54 @@ def test_diis_beyond_the_plan_capacity_is_rejected(P):
     with pytest.raises(P.PPLError) as e:
         run(P, s, 5, diis_max=4, max_sweeps=5, tol=0.0)
     assert e.value.code == -1
+
+
+def test_iteration_with_hhl_matches_oracle(P):
+    o, v, naux = 4, 12, 36
+    say(f"iterate fp64 with the hole-hole ladder to 1e-11 ({o},{v},{naux}) contractive seed 5")
+    s = S.make_system(o, v, naux, 5, "contractive")
+    rep, t = run(P, s, 0, diis_max=0, max_sweeps=200, tol=1e-11, hhl=True)
+    tref, href, Eref = O.jacobi(s["L"], o, s["e_occ"], s["e_vir"], max_sweeps=200, tol=1e-11, with_hhl=True)
+    assert rep["status"] == 0 and len(rep["history"]) == len(href)
+    h, hr = np.array(rep["history"]), np.array(href)
+    # residuals agree to rounding (an absolute 1e-16 of amplitudes of order one) until they approach it
+    assert np.all(np.abs(h - hr) <= 1e-9 * hr + 1e-14)
+    assert rel(t, O.fixed_point_hhl(s["L"], o, s["e_occ"], s["e_vir"])) < 1e-9
+    assert abs(rep["energy"] - Eref) < 1e-10
+
+
+def test_diis_with_hhl_matches_oracle(P):
+    o, v, naux = 3, 16, 48
+    say(f"iterate fp64 diis 8 with the hole-hole ladder ({o},{v},{naux}) contractive seed 6")
+    s = S.make_system(o, v, naux, 6, "contractive")
+    rep, t = run(P, s, 8, max_sweeps=60, tol=1e-11, hhl=True)
+    tref, href, _ = O.jacobi_diis(s["L"], o, s["e_occ"], s["e_vir"], m=8, max_sweeps=60, tol=1e-11, with_hhl=True)
+    assert rep["status"] == 0 and len(rep["history"]) == len(href)
+    assert rel(t, O.fixed_point_hhl(s["L"], o, s["e_occ"], s["e_vir"])) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_mixed_iteration_with_hhl(P, prec):
+    o, v, naux = 10, 100, 300
+    say(f"mixed {prec} -> fp64 with the hole-hole ladder and diis 8 to 1e-7 ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 1, "contractive")
+    rep, t = run(P, s, 8, prec=prec, keep=True, max_sweeps=200, tol=1e-7, hhl=True)
+    assert rep["status"] == 0 and rep["residual"] < 1e-7 and rep["sweeps_fp64"] >= 2
+    tstar, _, Estar = O.jacobi(s["L"], o, s["e_occ"], s["e_vir"], max_sweeps=200, tol=1e-10, with_hhl=True)
+    assert rel(t, tstar) < 1e-6
+    assert abs(rep["energy"] - Estar) < 1e-6
+
+
+def test_hhl_iteration_needs_a_resident_plan(P):
+    o, v, naux = 4, 30, 20
+    s = S.make_system(o, v, naux, 7, "contractive")
+    eng = P.PPL(o, v, naux)
+    budget = eng.info["workspace_bytes"] // 3
+    eng.close()
+    eng = P.PPL(o, v, naux, hbm_budget=budget)
+    assert eng.info["resident"] == 0
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PPLError) as e:
+        eng.iterate(dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"]), t, max_sweeps=3, hhl=True)
+    assert e.value.code == -8
+    eng.close()

@@ -175,7 +175,7 @@ def test_calls_out_of_order_are_state_errors(P):
 
 def test_iteration_defaults(P):
     o = P.ppl_iter_opts_default()
-    assert o.max_sweeps == 100 and o.tol == 1e-7 and o.min_fp64_sweeps == 2 and o.diis == 0
+    assert o.max_sweeps == 100 and o.tol == 1e-7 and o.min_fp64_sweeps == 2 and o.diis == 0 and o.hhl == 0
     assert o.start == 0 and abs(o.stagnation - 0.95) < 1e-15 and o.switch_tol == 0.0
 
 
