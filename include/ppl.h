@@ -129,7 +129,10 @@ int ppl_bind_workspace(ppl_plan_t plan, void* dptr, uint64_t bytes);
  * Every L^P must be symmetric (real orbitals, as the paper assumes), which makes
  * V+ and V- symmetric matrices: a resident plan builds their upper triangle
  * (rows (a, c >= a) of the integrals) and mirrors it once its last batch is built;
- * a streaming plan builds full rows. batch in [0, n_batches) builds one row
+ * an FP64 streaming plan builds upper-triangle steps as well (contracted as U and
+ * U^T), other streaming plans build full rows. Plans that build upper triangles
+ * first check (batch 0 or -1) that the virtual block of L is symmetric to a relative
+ * Frobenius asymmetry of 1e-10 and return PPL_E_ARG otherwise. batch in [0, n_batches) builds one row
  * batch, -1 builds every batch of a resident plan. The plan remembers L; a non-resident plan rebuilds its
  * batches from it inside ppl_contract, so L must stay valid until the next
  * ppl_build_batch or ppl_destroy.

@@ -791,6 +791,16 @@ int ppl_build_batch(ppl_plan_t p, const double* L, int32_t batch) {
   if (!L) return fail(PPL_E_ARG, "null L");
   const int nb = (int)p->batches.size();
   if (batch < -1 || batch >= nb) return fail(PPL_E_ARG, "batch %d out of range [-1, %d)", batch, nb);
+  if (p->sym_build && batch <= 0) {
+    // the upper-triangle build relies on symmetric Cholesky vectors (V+- symmetric)
+    double* partials = at<double>(p, p->red);
+    double h[4];
+    PPL_TRY(asymmetry_vv(p->stream, L, p->o, p->v, p->naux, partials, partials + kReduceBlocks * 4));
+    PPL_TRY(read_red(p, h));
+    if (!(h[0] <= 1e-20 * h[1]))
+      return fail(PPL_E_ARG, "Cholesky vectors are not symmetric in their virtual block (relative asymmetry %.3g)",
+                  h[1] > 0.0 ? sqrt(h[0] / h[1]) : 0.0);
+  }
   p->L_last = L;
   if (!p->resident) return PPL_OK;       // streaming plans build inside ppl_contract
   for (int k = 0; k < 2; ++k) {

@@ -967,6 +967,35 @@ int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va,
                                  (double*)am, partials, red_out);
 }
 
+// Sums of (L^P_ac - L^P_ca)^2 and (L^P_ac)^2 + (L^P_ca)^2 over the virtual block, a < c
+// (red_out[0], red_out[1]): the relative asymmetry of the Cholesky vectors.
+__global__ void __launch_bounds__(kReduceThreads)
+asym_kernel(const double* __restrict__ L, int n, int o, int v, int naux, double* partials) {
+  double d2 = 0.0, l2 = 0.0;
+  const int64_t total = (int64_t)naux * v * v;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int c = (int)(x % v);
+    const int64_t y = x / v;
+    const int a = (int)(y % v);
+    const int64_t P = y / v;
+    if (a >= c) continue;
+    const double lac = L[(P * n + o + a) * n + o + c], lca = L[(P * n + o + c) * n + o + a];
+    d2 += (lac - lca) * (lac - lca);
+    l2 += lac * lac + lca * lca;
+  }
+  double vals[3] = {d2, l2, 0.0};
+  block_reduce_store<3>(vals, partials);
+}
+
+int asymmetry_vv(hipStream_t s, const double* L, int o, int v, int naux, double* partials, double* red_out) {
+  hipLaunchKernelGGL(asym_kernel, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, L, o + v, o, v, naux, partials);
+  PPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, kReduceBlocks, red_out);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 nonfinite_kernel(const double* __restrict__ x, int64_t n, double* partials) {
   double bad = 0.0;

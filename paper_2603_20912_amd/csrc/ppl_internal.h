@@ -318,6 +318,8 @@ int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va,
                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out);
 // zero a device range (a fill kernel, never hipMemsetAsync)
 int zero_bytes(hipStream_t s, void* p, uint64_t bytes);
+// red_out[0] = sum (L^P_ac - L^P_ca)^2, red_out[1] = sum (L^P_ac)^2 + (L^P_ca)^2 over a < c (virtual block)
+int asymmetry_vv(hipStream_t s, const double* L, int o, int v, int naux, double* partials, double* red_out);
 // count non-finite values of an FP64 array (red_out[2])
 int count_nonfinite(hipStream_t s, const double* x, int64_t n, double* partials, double* red_out);
 

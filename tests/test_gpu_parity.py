@@ -289,3 +289,19 @@ def test_contract_only_plan(P):
     with pytest.raises(P.PPLError):
         eng.mp2(L, dev(s["e_occ"]), dev(s["e_vir"]))
     eng.close()
+
+
+def test_asymmetric_cholesky_vectors_are_rejected(P):
+    o, v, naux = 3, 20, 10
+    say(f"build with asymmetric L ({o},{v},{naux}) is an argument error")
+    s = S.make_system(o, v, naux, 70)
+    L = s["L"].copy()
+    L[2, o + 1, o + 5] += 1e-6 * np.abs(L).max()
+    eng = P.PPL(o, v, naux)
+    with pytest.raises(P.PPLError) as e:
+        eng.build(dev(L))
+    assert e.value.code == -1 and "symmetric" in str(e.value)
+    eng.build(dev(s["L"]))                        # the symmetric vectors still build
+    R = eng.contract(dev(S.make_amplitudes(o, v, 71))).cpu().numpy()
+    assert rel(R, O.ppl(s["L"], o, S.make_amplitudes(o, v, 71))) < 1e-12
+    eng.close()
