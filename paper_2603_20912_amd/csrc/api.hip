@@ -918,13 +918,25 @@ int ppl_hhl(ppl_plan_t p, const double* L, const double* t2, double* R, double a
   char* g = at<char>(p, p->g);
   const int64_t o = p->o, v = p->v;
   ProfScope ps(p, PPL_PROF_OTHER, 2.0 * (double)p->Pp * p->Np * p->Np + 2.0 * (double)p->Pm * p->Nm * p->Nm);
+  hipStream_t st = p->stream;
+  double* s64 = at<double>(p, p->s64);
+  double* a64 = at<double>(p, p->a64);
+  const int *tab_op = at<int>(p, p->tab_op), *tab_om = at<int>(p, p->tab_om), *tab_vp = at<int>(p, p->tab_vp),
+            *tab_vm = at<int>(p, p->tab_vm);
   PPL_TRY(hhl_integrals(p, L));
-  // transposed packed amplitudes: sT[(a<=b)][(k<=l)] = (2 - d_kl) s_kl^ab, aT[(a<b)][(k<l)] = 2 a_kl^ab
-  PPL_TRY(pack_pm(p->stream, p->v, p->o, t2, v, 1, o * v * v, v * v, 1.0, 0.5, 1.0, (double*)(g + h.st), h.ldq,
-                  (double*)(g + h.at), h.ldqm, at<int>(p, p->tab_vp), at<int>(p, p->tab_vm), at<int>(p, p->tab_op),
-                  at<int>(p, p->tab_om)));
+  // S'/A' of t2 into the FP64 packed rows (coalesced), then the transposed operands
+  // sT[(a<=b)][(k<=l)] = (2 - d_kl) s_kl^ab and aT[(a<b)][(k<l)] = 2 a_kl^ab through LDS tiles
+  PPL_TRY(pack_pm(st, p->o, p->v, t2, o * v * v, v * v, v, 1, 1.0, 0.5, 1.0, s64, p->ldp, a64, p->ldm, tab_op, tab_om,
+                  tab_vp, tab_vm));
+  PPL_TRY(transpose_pm(st, s64, p->ldp, (double*)(g + h.st), h.ldq, p->Np, p->Pp, tab_op, tab_vp, 1));
+  if (p->Nm > 0)
+    PPL_TRY(transpose_pm(st, a64, p->ldm, (double*)(g + h.at), h.ldqm, p->Nm, p->Pm, nullptr, nullptr, 0));
   PPL_TRY(hhl_contract(p));
-  return unpack_rt(p->stream, p->o, p->v, (double*)(g + h.cp), h.ldq, (double*)(g + h.cm), h.ldqm, R, alpha, beta);
+  // results back to [pairs (i<=j)][pairs (a<=b)] (zero padding) and unpacked
+  PPL_TRY(transpose_pm(st, (const double*)(g + h.cp), h.ldq, s64, p->ldp, p->Pp, p->Np, nullptr, nullptr, 0));
+  if (p->Nm > 0)
+    PPL_TRY(transpose_pm(st, (const double*)(g + h.cm), h.ldqm, a64, p->ldm, p->Pm, p->Nm, nullptr, nullptr, 0));
+  return unpack_r(st, PPL_FP64, p->o, p->v, s64, p->ldp, a64, p->ldm, R, alpha, beta);
 }
 
 int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,

@@ -606,39 +606,6 @@ int unpack_r(hipStream_t s, int acc_prec, int o, int v, const void* rp, int64_t 
   return PPL_OK;
 }
 
-// R = beta R + alpha (C+ +- C-) from transposed packed results: C+[(a<=b)][(i<=j)] and
-// C-[(a<b)][(i<j)] (rows of ldcp / ldcm doubles).
-__global__ void unpack_rt_kernel(int o, int v, const double* __restrict__ cp, int64_t ldcp,
-                                 const double* __restrict__ cm, int64_t ldcm, double* R, double alpha,
-                                 double beta) {
-  const int64_t total = (int64_t)o * o * v * v;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
-    const int b = (int)(x % v);
-    const int64_t y = x / v;
-    const int a = (int)(y % v);
-    const int64_t z = y / v;
-    const int j = (int)(z % o), i = (int)(z / o);
-    const int i0 = i < j ? i : j, j0 = i < j ? j : i;
-    const int a0 = a < b ? a : b, b0 = a < b ? b : a;
-    double r = cp[pair_plus(a0, b0, v) * ldcp + pair_plus(i0, j0, o)];
-    if (i != j && a != b) {
-      const double m = cm[pair_minus(a0, b0, v) * ldcm + pair_minus(i0, j0, o)];
-      r += ((i < j) == (a < b)) ? m : -m;
-    }
-    R[x] = (beta == 0.0) ? alpha * r : alpha * r + beta * R[x];
-  }
-}
-
-int unpack_rt(hipStream_t s, int o, int v, const double* cp, int64_t ldcp, const double* cm, int64_t ldcm,
-              double* R, double alpha, double beta) {
-  const int64_t total = (int64_t)o * o * v * v;
-  hipLaunchKernelGGL(unpack_rt_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v, cp, ldcp, cm, ldcm, R,
-                     alpha, beta);
-  PPL_LAUNCH_CHECK();
-  return PPL_OK;
-}
-
 __global__ void unpack_t_kernel(int o, int v, const double* __restrict__ sp, int64_t ldp,
                                 const double* __restrict__ am, int64_t ldm, double* t2) {
   const int64_t total = (int64_t)o * o * v * v;

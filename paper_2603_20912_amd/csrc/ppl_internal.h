@@ -271,9 +271,7 @@ int pack_pm(hipStream_t s, int o, int v, const double* X, int64_t si, int64_t sj
             const int* tab_vm, const double* t1 = nullptr);
 // staging: Xoo[(k,i)][P] = L[P][k][i] (FP64)
 int stage_oo(hipStream_t s, const double* L, int o, int v, int naux, int64_t ldx, double* xoo);
-// R = beta R + alpha (C+ +- C-) from C+[(a<=b)][(i<=j)], C-[(a<b)][(i<j)]
-int unpack_rt(hipStream_t s, int o, int v, const double* cp, int64_t ldcp, const double* cm, int64_t ldcm,
-              double* R, double alpha, double beta);
+
 // convert FP64 packed rows to an operand precision (FP32 or BF16 hi/lo), zero padding kept
 int convert_rows(hipStream_t s, int prec, const double* src, int64_t rows, int64_t cols, int64_t ld,
                  void* dst, void* dst_lo);
