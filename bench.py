@@ -264,6 +264,8 @@ def study_paper(args):
     print(json.dumps({"inputs_s": round(time.perf_counter() - t0, 2),
                       "free_GB": torch.cuda.mem_get_info()[0] / 1e9}), file=sys.stderr, flush=True)
     eng = P.PPL(o, v, naux, prec="fp64", build_scratch=64 << 30, contract_only=True)
+    if args.contract_config:
+        eng.set_contract_config(*[int(x) for x in args.contract_config.split(",")])
     info = eng.info
     # useful flops as the plan executes them (upper-triangle build steps: 2 naux P+^2)
     out["useful_flops"] = info["flops_build"] + info["flops_contract"]
