@@ -88,15 +88,18 @@ static int g_acc_bytes(ppl_plan_t p) {
 }
 
 // Scratch of the hole-hole ladder, carved from the build scratch G: staged occupied
-// block, (ki|lj), W+- [N+][ldq] / [N-][ldqm], the transposed packed amplitudes
-// [P+][ldq] / [P-][ldqm] and the transposed results of the same shapes.
+// block, (ki|lj), W+- [N+][ldq] / [N-][ldqm], and one chunk of virtual-pair rows of the
+// transposed amplitudes and of the transposed results ([chunk][ldq] each; ldq >= ldqm).
+// The floor (avail == 0) takes chunks of at most kHhlChunk rows; given the scratch
+// actually available, chunks grow to use it.
+constexpr int64_t kHhlChunk = 8192;
 struct HhlScratch {
-  int64_t ldq, ldqm;
-  uint64_t xoo, woo, wp, wm, st, at, cp, cm, bytes;
+  int64_t ldq, ldqm, chunk;
+  uint64_t xoo, woo, wp, wm, st, cp, bytes;
 };
-static HhlScratch hhl_scratch(ppl_plan_t p) {
+static HhlScratch hhl_scratch(ppl_plan_t p, uint64_t avail = 0) {
   HhlScratch h{};
-  const int64_t o = p->o, Nmq = std::max<int64_t>(p->Nm, 1), Pmq = std::max<int64_t>(p->Pm, 1);
+  const int64_t o = p->o, Nmq = std::max<int64_t>(p->Nm, 1);
   h.ldq = pad_ld(p->Np);
   h.ldqm = pad_ld(Nmq);
   uint64_t cur = 0;
@@ -109,10 +112,12 @@ static HhlScratch hhl_scratch(ppl_plan_t p) {
   h.woo = take((uint64_t)o * o * o * o * 8);
   h.wp = take((uint64_t)p->Np * h.ldq * 8);
   h.wm = take((uint64_t)Nmq * h.ldqm * 8);
-  h.st = take((uint64_t)p->Pp * h.ldq * 8);
-  h.at = take((uint64_t)Pmq * h.ldqm * 8);
-  h.cp = take((uint64_t)p->Pp * h.ldq * 8);
-  h.cm = take((uint64_t)Pmq * h.ldqm * 8);
+  const uint64_t row = (uint64_t)h.ldq * 8;
+  h.chunk = std::min<int64_t>(p->Pp, kHhlChunk);
+  if (avail > cur + 2 * (uint64_t)h.chunk * row + 1024)
+    h.chunk = std::min<int64_t>(p->Pp, (int64_t)((avail - cur - 1024) / (2 * row)));
+  h.st = take((uint64_t)h.chunk * row);
+  h.cp = take((uint64_t)h.chunk * row);
   h.bytes = cur;
   return h;
 }
@@ -838,20 +843,34 @@ static int hhl_integrals(ppl_plan_t p, const double* L) {
                  (double*)(g + h.wm), h.ldqm, tab_op, tab_om, tab_op, tab_om);
 }
 
-// C+ = sT W+^T and C- = aT W-^T (K = occupied pairs) from the transposed amplitudes in the scratch
-static int hhl_contract(ppl_plan_t p) {
-  const HhlScratch h = hhl_scratch(p);
+// The hole-hole ladder of packed amplitudes X (S' rows [N+][ldp] or A' rows [N-][ldm],
+// FP64), one chunk of virtual pairs at a time: the chunk's columns of X transposed into
+// sT (S' scaled by (2 - d_kl)/(2 - d_ab)), C = sT W^T with K = the occupied pairs, then
+// C^T added into the same columns of the results (add: R rows of the operand set's
+// accumulator type) or written over the chunk's columns of X itself (!add).
+static int hhl_pass(ppl_plan_t p, const HhlScratch& h, bool plus, double* X, void* R, int rprec, bool add) {
   char* g = at<char>(p, p->g);
-  int tile = -1, sp = 1;
-  contract_choose(PPL_FP64, p->Pp, p->Np, h.ldq, 1, &tile, &sp);
-  PPL_TRY(gemm_contract(p->stream, PPL_FP64, tile, p->Pp, p->Np, h.ldq, g + h.st, nullptr, h.ldq, g + h.wp, nullptr,
-                        h.ldq, g + h.cp, h.ldq, 0, 1, nullptr, h.ldq, 0));
-  if (p->Nm > 0) {
-    tile = -1;
-    sp = 1;
-    contract_choose(PPL_FP64, p->Pm, p->Nm, h.ldqm, 1, &tile, &sp);
-    PPL_TRY(gemm_contract(p->stream, PPL_FP64, tile, p->Pm, p->Nm, h.ldqm, g + h.at, nullptr, h.ldqm, g + h.wm,
-                          nullptr, h.ldqm, g + h.cm, h.ldqm, 0, 1, nullptr, h.ldqm, 0));
+  hipStream_t st = p->stream;
+  const int64_t Nq = plus ? p->Np : p->Nm, Pq = plus ? p->Pp : p->Pm;
+  const int64_t ldx = plus ? p->ldp : p->ldm, ldk = plus ? h.ldq : h.ldqm;
+  if (Nq <= 0 || Pq <= 0) return PPL_OK;
+  const int* tab_q = at<int>(p, p->tab_op);
+  const int* tab_p = at<int>(p, p->tab_vp);
+  double* sT = (double*)(g + h.st);
+  double* C = (double*)(g + h.cp);
+  const double* W = (const double*)(g + (plus ? h.wp : h.wm));
+  for (int64_t p0 = 0; p0 < Pq; p0 += h.chunk) {
+    const int64_t np = std::min<int64_t>(h.chunk, Pq - p0);
+    PPL_TRY(transpose_pm(st, X + p0, ldx, sT, ldk, Nq, np, plus ? tab_q : nullptr, plus ? tab_p + p0 : nullptr,
+                         plus ? 1 : 0));
+    int tile = -1, sp = 1;
+    contract_choose(PPL_FP64, np, Nq, ldk, 1, &tile, &sp);
+    PPL_TRY(gemm_contract(st, PPL_FP64, tile, np, Nq, ldk, sT, nullptr, ldk, W, nullptr, ldk, C, ldk, 0, 1, nullptr,
+                          ldk, 0));
+    if (add)
+      PPL_TRY(add_transposed(st, rprec, (char*)R + p0 * (rprec == PPL_FP64 ? 8 : 4), ldx, C, ldk, Nq, np));
+    else
+      PPL_TRY(transpose_pm(st, C, ldk, X + p0, ldx, np, Nq, nullptr, nullptr, 0, 0));
   }
   return PPL_OK;
 }
@@ -859,20 +878,10 @@ static int hhl_contract(ppl_plan_t p) {
 // R+- += the hole-hole ladder of the packed amplitudes S'/A' (FP64 masters), in the
 // accumulator type of the operand set's results
 static int hhl_add_packed(ppl_plan_t p, const OperandSet& s) {
-  const HhlScratch h = hhl_scratch(p);
-  char* g = at<char>(p, p->g);
-  hipStream_t st = p->stream;
-  PPL_TRY(transpose_pm(st, at<double>(p, p->s64), p->ldp, (double*)(g + h.st), h.ldq, p->Np, p->Pp,
-                       at<int>(p, p->tab_op), at<int>(p, p->tab_vp), 1));
-  if (p->Nm > 0)
-    PPL_TRY(transpose_pm(st, at<double>(p, p->a64), p->ldm, (double*)(g + h.at), h.ldqm, p->Nm, p->Pm, nullptr,
-                         nullptr, 0));
-  PPL_TRY(hhl_contract(p));
+  const HhlScratch h = hhl_scratch(p, p->g.bytes);
   const int cprec = s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32;
-  PPL_TRY(add_transposed(st, cprec, at<void>(p, p->rp), p->ldp, (const double*)(g + h.cp), h.ldq, p->Np, p->Pp));
-  if (p->Nm > 0)
-    PPL_TRY(add_transposed(st, cprec, at<void>(p, p->rm), p->ldm, (const double*)(g + h.cm), h.ldqm, p->Nm, p->Pm));
-  return PPL_OK;
+  PPL_TRY(hhl_pass(p, h, true, at<double>(p, p->s64), at<void>(p, p->rp), cprec, true));
+  return hhl_pass(p, h, false, at<double>(p, p->a64), at<void>(p, p->rm), cprec, true);
 }
 
 static int contract_impl(ppl_plan_t p, const double* t2, const double* t1, double* R, double alpha,
@@ -915,27 +924,19 @@ int ppl_hhl(ppl_plan_t p, const double* L, const double* t2, double* R, double a
   if (h.bytes > p->g.bytes)
     return fail(PPL_E_STATE, "hole-hole scratch needs %llu B, the plan has %llu B",
                 (unsigned long long)h.bytes, (unsigned long long)p->g.bytes);
-  char* g = at<char>(p, p->g);
   const int64_t o = p->o, v = p->v;
   ProfScope ps(p, PPL_PROF_OTHER, 2.0 * (double)p->Pp * p->Np * p->Np + 2.0 * (double)p->Pm * p->Nm * p->Nm);
   hipStream_t st = p->stream;
   double* s64 = at<double>(p, p->s64);
   double* a64 = at<double>(p, p->a64);
-  const int *tab_op = at<int>(p, p->tab_op), *tab_om = at<int>(p, p->tab_om), *tab_vp = at<int>(p, p->tab_vp),
-            *tab_vm = at<int>(p, p->tab_vm);
   PPL_TRY(hhl_integrals(p, L));
-  // S'/A' of t2 into the FP64 packed rows (coalesced), then the transposed operands
-  // sT[(a<=b)][(k<=l)] = (2 - d_kl) s_kl^ab and aT[(a<b)][(k<l)] = 2 a_kl^ab through LDS tiles
-  PPL_TRY(pack_pm(st, p->o, p->v, t2, o * v * v, v * v, v, 1, 1.0, 0.5, 1.0, s64, p->ldp, a64, p->ldm, tab_op, tab_om,
-                  tab_vp, tab_vm));
-  PPL_TRY(transpose_pm(st, s64, p->ldp, (double*)(g + h.st), h.ldq, p->Np, p->Pp, tab_op, tab_vp, 1));
-  if (p->Nm > 0)
-    PPL_TRY(transpose_pm(st, a64, p->ldm, (double*)(g + h.at), h.ldqm, p->Nm, p->Pm, nullptr, nullptr, 0));
-  PPL_TRY(hhl_contract(p));
-  // results back to [pairs (i<=j)][pairs (a<=b)] (zero padding) and unpacked
-  PPL_TRY(transpose_pm(st, (const double*)(g + h.cp), h.ldq, s64, p->ldp, p->Pp, p->Np, nullptr, nullptr, 0));
-  if (p->Nm > 0)
-    PPL_TRY(transpose_pm(st, (const double*)(g + h.cm), h.ldqm, a64, p->ldm, p->Pm, p->Nm, nullptr, nullptr, 0));
+  // S'/A' of t2 into the FP64 packed rows, the ladder chunk by chunk over the virtual
+  // pairs written back over them, then unpacked
+  PPL_TRY(pack_pm(st, p->o, p->v, t2, o * v * v, v * v, v, 1, 1.0, 0.5, 1.0, s64, p->ldp, a64, p->ldm,
+                  at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp), at<int>(p, p->tab_vm)));
+  const HhlScratch hs = hhl_scratch(p, p->g.bytes);
+  PPL_TRY(hhl_pass(p, hs, true, s64, nullptr, PPL_FP64, false));
+  PPL_TRY(hhl_pass(p, hs, false, a64, nullptr, PPL_FP64, false));
   return unpack_r(st, PPL_FP64, p->o, p->v, s64, p->ldp, a64, p->ldm, R, alpha, beta);
 }
 

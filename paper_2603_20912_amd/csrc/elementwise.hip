@@ -353,7 +353,7 @@ int transpose_block(hipStream_t s, int elem_bytes, const void* U, int64_t ldu, i
 __global__ void __launch_bounds__(256)
 transpose_pm_kernel(const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, int64_t ldy, int64_t nq,
                     int64_t np, const int* __restrict__ tab_q, const int* __restrict__ tab_p, int scaled,
-                    int64_t tiles_q) {
+                    int64_t qwrite, int64_t tiles_q) {
   __shared__ double sh[64][65];
   const int64_t tp = blockIdx.x / tiles_q, tq = blockIdx.x % tiles_q;
   const int64_t p0 = tp * 64, q0 = tq * 64;
@@ -377,18 +377,19 @@ transpose_pm_kernel(const double* __restrict__ X, int64_t ldx, double* __restric
   for (int e = tid; e < 64 * 64; e += 256) {
     const int pl = e >> 6, ql = e & 63;                   // write Y row p0 + pl, column q0 + ql
     const int64_t p = p0 + pl, q = q0 + ql;
-    if (p < np && q < ldy) Y[p * ldy + q] = sh[ql][pl];
+    if (p < np && q < qwrite) Y[p * ldy + q] = sh[ql][pl];
   }
 }
 
 int transpose_pm(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nq, int64_t np,
-                 const int* tab_q, const int* tab_p, int scaled) {
+                 const int* tab_q, const int* tab_p, int scaled, int pad) {
   if (np <= 0 || ldy <= 0) return PPL_OK;
-  const int64_t tq = (ldy + 63) / 64, tp = (np + 63) / 64;
+  const int64_t qwrite = pad ? ldy : nq;          // columns written per row of Y
+  const int64_t tq = (qwrite + 63) / 64, tp = (np + 63) / 64;
   if (tq * tp > 0x7fffffffLL) return fail(PPL_E_ARG, "transpose of %lld x %lld too large", (long long)np,
                                           (long long)ldy);
   hipLaunchKernelGGL(transpose_pm_kernel, dim3((unsigned)(tq * tp)), dim3(256), 0, s, X, ldx, Y, ldy, nq, np, tab_q,
-                     tab_p, scaled, tq);
+                     tab_p, scaled, qwrite, tq);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

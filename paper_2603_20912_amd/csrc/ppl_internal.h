@@ -251,9 +251,10 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
 // C[q][p] += T[p][q] for q < nq, p < np (T FP64; C FP64 or FP32 by c_prec)
 int add_transposed(hipStream_t s, int c_prec, void* C, int64_t ldc, const double* T, int64_t ldt, int64_t nq,
                    int64_t np);
-// Y[p][q] = w X[q][p] (q < nq, p < np), zero for nq <= q < ldy; scaled: w = (2 - d_kl) / (2 - d_ab)
+// Y[p][q] = w X[q][p] (q < nq, p < np), and with pad zero for nq <= q < ldy; scaled:
+// w = (2 - d_kl) / (2 - d_ab) with (k, l) = tab_q[q], (a, b) = tab_p[p]
 int transpose_pm(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nq, int64_t np,
-                 const int* tab_q, const int* tab_p, int scaled);
+                 const int* tab_q, const int* tab_p, int scaled, int pad = 1);
 // Ut[r][k] = U[k0 + k - u0][c0 + r] for u0 <= k0 + k < u1, else 0 (r < nr, k < nk)
 int transpose_block(hipStream_t s, int elem_bytes, const void* U, int64_t ldu, int64_t u0, int64_t u1, int64_t c0,
                     int64_t k0, void* Ut, int64_t ldt, int64_t nr, int64_t nk);

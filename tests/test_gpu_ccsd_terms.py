@@ -84,3 +84,17 @@ def test_hhl_in_a_streaming_plan(P):
     str_.close()
     assert np.array_equal(R1, R2)
     assert rel(R1, O.hhl(s["L"], o, t2)) < 1e-12
+
+
+def test_hhl_in_chunks_of_virtual_pairs(P):
+    # a contract-only plan with a small build scratch: the transposed operands of the
+    # hole-hole ladder go through it in several chunks of virtual pairs
+    o, v, naux = 60, 140, 30
+    say(f"hhl fp64 ({o},{v},{naux}) in chunks of virtual pairs")
+    s = S.make_system(o, v, naux, 34)
+    t2 = S.make_amplitudes(o, v, 35)
+    eng = P.PPL(o, v, naux, contract_only=True, build_scratch=1 << 20)
+    L = dev(s["L"])
+    R = eng.hhl(L, dev(t2)).cpu().numpy()
+    eng.close()
+    assert rel(R, O.hhl(s["L"], o, t2)) < 1e-12
