@@ -109,7 +109,10 @@ typedef struct {
  * hbm_budget == 0 it queries the free device memory (PPL_E_HIP without a GPU).
  * Returns PPL_E_ARG for o<1, v<2, naux<1, an unknown precision or sizes whose
  * byte counts overflow 64 bits, and PPL_E_NOMEM when the budget cannot hold the
- * fixed buffers plus one batch of V+- rows.
+ * fixed buffers plus one batch of V+- rows. A resident plan, and an FP64 streaming
+ * plan, builds the upper triangle of V+- only (see ppl_build_batch); the environment
+ * variable PPL_SYM_BUILD=0, read here, makes the plan build full rows instead (for
+ * comparisons).
  */
 int ppl_plan(const ppl_desc_t* desc, ppl_plan_t* out);
 
