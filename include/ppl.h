@@ -76,6 +76,11 @@ typedef struct {
   int32_t  diis_max;    /* DIIS subspace capacity kept in the workspace, 0 .. PPL_DIIS_MAX (0 = none);
                            costs 2 * diis_max packed FP64 amplitude vectors */
   int32_t  flags;       /* PPL_PLAN_* bits */
+  const char* tune_cache; /* optional path of a text file of tuned contraction configurations (NULL =
+                             none): ppl_plan takes the last entry for (prec, o, v) if there is one
+                             (an explicit tile_contract wins); ppl_autotune appends its choice.
+                             One entry per line: "ppl-tune 1 <prec> <o> <v> <tile+> <splits+>
+                             <tile-> <splits->". A missing or unreadable file is no entry. */
 } ppl_desc_t;
 
 /* What the planner decided (output of ppl_plan_query). */
@@ -306,7 +311,8 @@ int ppl_set_contract_config(ppl_plan_t plan, int32_t tile_plus, int32_t splits_p
  * ones in the workspace (the last packed amplitudes): the matrix-core rate depends
  * on operand values through the power draw, so tune after a contraction of
  * representative amplitudes. Synchronous. best_ms (optional, 2 doubles)
- * receives the winning average times.
+ * receives the winning average times. With a tune cache (ppl_desc_t.tune_cache) the
+ * choice is appended to it; PPL_E_ARG if the file cannot be written.
  */
 int ppl_autotune(ppl_plan_t plan, int32_t reps, double* best_ms);
 

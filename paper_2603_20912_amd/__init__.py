@@ -39,7 +39,8 @@ class PPL:
     """One planned problem with its device workspace (allocated by torch, owned here)."""
 
     def __init__(self, o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None,
-                 tile_contract=-1, device="cuda", build_scratch=0, diis_max=0, contract_only=False):
+                 tile_contract=-1, device="cuda", build_scratch=0, diis_max=0, contract_only=False,
+                 tune_cache=None):
         if not torch.cuda.is_available():
             raise RuntimeError("PPL needs a HIP device (no CPU fallback)")
         self.o, self.v, self.naux = o, v, naux
@@ -49,7 +50,7 @@ class PPL:
             # blocks torch holds cached but unused back first, so that they count as free
             torch.cuda.empty_cache()
         self.plan = ppl_plan(o, v, naux, prec, keep_fp64, hbm_budget, self.stream, tile_contract, build_scratch,
-                             diis_max, _lib.PPL_PLAN_CONTRACT_ONLY if contract_only else 0)
+                             diis_max, _lib.PPL_PLAN_CONTRACT_ONLY if contract_only else 0, tune_cache)
         self.info = ppl_plan_query(self.plan)
         nbytes = int(self.info["workspace_bytes"])
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)

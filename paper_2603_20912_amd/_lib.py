@@ -37,7 +37,7 @@ class ppl_desc_t(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("keep_fp64", ctypes.c_int32),
                 ("tile_contract", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("build_scratch", ctypes.c_uint64), ("diis_max", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class ppl_plan_info_t(ctypes.Structure):
@@ -180,11 +180,11 @@ PPL_PLAN_CONTRACT_ONLY = 1
 
 
 def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None, tile_contract=-1,
-             build_scratch=0, diis_max=0, flags=0):
+             build_scratch=0, diis_max=0, flags=0, tune_cache=None):
     d = ppl_desc_t(o, v, naux, PREC[prec] if isinstance(prec, str) else int(prec), int(bool(keep_fp64)),
                    int(tile_contract), int(hbm_budget),
                    _stream_handle(stream) if stream is not False else None, int(build_scratch), int(diis_max),
-                   int(flags))
+                   int(flags), os.fsencode(tune_cache) if tune_cache else None)
     h = ctypes.c_void_p()
     _check(load().ppl_plan(ctypes.byref(d), ctypes.byref(h)), "ppl_plan")
     return h

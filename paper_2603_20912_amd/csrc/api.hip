@@ -87,6 +87,38 @@ static int g_acc_bytes(ppl_plan_t p) {
   return w;
 }
 
+// Tuned contraction configurations: "ppl-tune 1 prec o v tile+ splits+ tile- splits-" per
+// line; the last line matching (prec, o, v) wins. Unreadable files and foreign lines are
+// skipped.
+static bool tune_cache_lookup(const std::string& path, int prec, int o, int v, int cfg[4]) {
+  if (path.empty()) return false;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    int ver, pr, oo, vv, c[4];
+    if (sscanf(line, "ppl-tune %d %d %d %d %d %d %d %d", &ver, &pr, &oo, &vv, &c[0], &c[1], &c[2], &c[3]) != 8)
+      continue;
+    if (ver != 1 || pr != prec || oo != o || vv != v) continue;
+    if (c[0] < 0 || c[0] >= contract_tile_count() || c[2] < 0 || c[2] >= contract_tile_count()) continue;
+    if (c[1] < 0 || c[1] > kMaxSplits || c[3] < 0 || c[3] > kMaxSplits) continue;
+    for (int k = 0; k < 4; ++k) cfg[k] = c[k];
+    found = true;
+  }
+  fclose(f);
+  return found;
+}
+
+static int tune_cache_append(const std::string& path, int prec, int o, int v, const int cfg[4]) {
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return fail(PPL_E_ARG, "cannot write the tune cache %s", path.c_str());
+  const int n = fprintf(f, "ppl-tune 1 %d %d %d %d %d %d %d\n", prec, o, v, cfg[0], cfg[1], cfg[2], cfg[3]);
+  const int c = fclose(f);
+  if (n < 0 || c != 0) return fail(PPL_E_ARG, "cannot write the tune cache %s", path.c_str());
+  return PPL_OK;
+}
+
 // Scratch of the hole-hole ladder, carved from the build scratch G: staged occupied
 // block, (ki|lj), W+- [N+][ldq] / [N-][ldqm], and one chunk of virtual-pair rows of the
 // transposed amplitudes and of the transposed results ([chunk][ldq] each; ldq >= ldqm).
@@ -650,6 +682,17 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
       if (p->Nm > 0) contract_choose(PPL_FP64, p->Nm, p->Pm, p->ldm, kMaxSplits, &t, &sp);
       f.tile_m = t < 0 ? 0 : t;
       f.split_m = sp;
+    }
+  }
+
+  if (d->tune_cache) p->tune_cache = d->tune_cache;
+  if (d->tile_contract < 0) {
+    int cfg[4];
+    if (tune_cache_lookup(p->tune_cache, p->prec, p->o, p->v, cfg)) {
+      p->tile_contract = cfg[0];
+      p->split_p = cfg[1];
+      p->tile_m = cfg[2];
+      p->split_m = cfg[3];
     }
   }
 
@@ -1248,6 +1291,10 @@ int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms) {
   p->split_p = bs[0];
   p->tile_m = bt[1];
   p->split_m = bs[1];
+  if (!p->tune_cache.empty()) {
+    const int cfg[4] = {bt[0], bs[0], bt[1], bs[1]};
+    PPL_TRY(tune_cache_append(p->tune_cache, p->prec, p->o, p->v, cfg));
+  }
   if (best_ms) {
     best_ms[0] = best[0] < 1e300 ? best[0] : 0.0;
     best_ms[1] = best[1] < 1e300 ? best[1] : 0.0;

@@ -126,6 +126,7 @@ struct ppl_plan_s {
   ppl::Region red;                     // reduction partials
   int diis_max = 0;                    // DIIS subspace capacity
   bool contract_only = false;          // no iteration buffers (PPL_PLAN_CONTRACT_ONLY)
+  std::string tune_cache;              // path of the tuned-configuration file ("" = none)
   int64_t diis_slot_n = 0;             // doubles per DIIS slot: S' rows [N+][ldp], then A' rows [N-][ldm]
   ppl::Region diis_t, diis_e;          // diis_max slots of amplitudes t' and of errors t' - t (S'/A' scaling)
   ppl::Region diis_red;                // DIIS inner-product partials and results

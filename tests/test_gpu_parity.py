@@ -305,3 +305,22 @@ def test_asymmetric_cholesky_vectors_are_rejected(P):
     R = eng.contract(dev(S.make_amplitudes(o, v, 71))).cpu().numpy()
     assert rel(R, O.ppl(s["L"], o, S.make_amplitudes(o, v, 71))) < 1e-12
     eng.close()
+
+
+def test_autotune_writes_the_tune_cache(P, tmp_path):
+    o, v, naux = 5, 40, 30
+    say(f"autotune with a tune cache ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 80)
+    path = tmp_path / "tune.txt"
+    eng = P.PPL(o, v, naux, tune_cache=str(path))
+    eng.build(dev(s["L"]))
+    eng.contract(dev(S.make_amplitudes(o, v, 81)))
+    eng.autotune(reps=1)
+    cfg = eng.contract_config()
+    eng.close()
+    line = path.read_text().strip().splitlines()[-1].split()
+    assert line[:5] == ["ppl-tune", "1", "0", str(o), str(v)] and tuple(int(x) for x in line[5:]) == cfg
+    # a new plan of the shape starts from the tuned configuration
+    eng2 = P.PPL(o, v, naux, tune_cache=str(path))
+    assert eng2.contract_config() == cfg
+    eng2.close()

@@ -99,6 +99,31 @@ def test_streaming_plan_of_the_largest_benchmark_shape(P):
     assert j["max_step_pairs"] < i["max_step_pairs"] and j["n_batches"] > i["n_batches"]
 
 
+def test_tune_cache_entries(P, tmp_path):
+    path = tmp_path / "tune.txt"
+    path.write_text("# a comment\n"
+                    "ppl-tune 1 0 20 200 5 3 7 2\n"
+                    "garbage line\n"
+                    "ppl-tune 1 1 20 200 2 2 2 2\n"       # FP32: another key
+                    "ppl-tune 1 0 20 200 6 0 8 6\n"       # the last FP64 entry wins
+                    "ppl-tune 1 0 20 200 99 1 0 1\n")     # out of range: skipped
+    i = plan_info(P, 20, 200, 600, hbm_budget=1 << 40, tune_cache=str(path))
+    assert (i["tile_contract"], i["splits_contract"], i["tile_contract_minus"], i["splits_contract_minus"]) == \
+        (6, 0, 8, 6)
+    j = plan_info(P, 20, 200, 600, prec="fp32", hbm_budget=1 << 40, tune_cache=str(path))
+    assert (j["tile_contract"], j["splits_contract"]) == (2, 2)
+    # no entry for the shape, a missing file, or an explicit tile: the planner's own choice
+    base = plan_info(P, 20, 200, 600, hbm_budget=1 << 40)
+    for kw in (dict(tune_cache=str(tmp_path / "missing.txt")), dict(tune_cache=str(path), tile_contract=1)):
+        k = plan_info(P, 20, 200, 600, hbm_budget=1 << 40, **kw)
+        if "tile_contract" in kw:
+            assert k["tile_contract"] == 1
+        else:
+            assert k["tile_contract"] == base["tile_contract"] and k["splits_contract"] == base["splits_contract"]
+    other = plan_info(P, 21, 200, 600, hbm_budget=1 << 40, tune_cache=str(path))
+    assert other["tile_contract"] == plan_info(P, 21, 200, 600, hbm_budget=1 << 40)["tile_contract"]
+
+
 def test_contract_only_plans(P):
     full = plan_info(P, 100, 700, 4000, hbm_budget=186 << 30, build_scratch=64 << 30)
     lean = plan_info(P, 100, 700, 4000, hbm_budget=186 << 30, build_scratch=64 << 30, flags=1)
