@@ -9,7 +9,13 @@ operands where a low-precision GEMM pipeline has to:
   * "fp32":   operands rounded to FP32, products and sums exact (FP64 here);
   * "bf16x3": operands rounded to FP32, then x = hi + lo with hi = bf16(x),
               lo = bf16(x - hi) (round to nearest even), and x*y replaced by
-              hi*hi + hi*lo + lo*hi (the lo*lo term dropped).
+              hi*hi + hi*lo + lo*hi (the lo*lo term dropped);
+  * "bf16x6": operands rounded to FP32, then x = hi + mid + lo with hi = bf16(x),
+              mid = bf16(x - hi), lo = bf16(x - hi - mid), and x*y replaced by the
+              six products whose plane indices sum to at most two (hi*hi, hi*mid,
+              mid*hi, mid*mid, hi*lo, lo*hi; mid*lo, lo*mid and lo*lo dropped).
+These are the split-and-product schemes of Henry, Tang and Heinecke (ARITH 2019),
+the low-precision products the paper's introduction points to (Sec. 1).
 Rounding points: the virtual block of L (build operands), the integrals
 G_ab[c][d] (FP32 accumulator output), V+- (operand precision), the packed
 amplitudes S', A' (operand precision), and R (FP32 accumulator output).
@@ -20,7 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["round_fp32", "round_bf16", "split_bf16x3", "ppl_lowprec"]
+__all__ = ["round_fp32", "round_bf16", "split_bf16x3", "split_bf16x6", "ppl_lowprec"]
 
 
 def round_fp32(x):
@@ -44,6 +50,16 @@ def split_bf16x3(x):
     return hi, lo
 
 
+def split_bf16x6(x):
+    """x -> (hi, mid, lo): hi = bf16(fp32(x)), mid = bf16(fp32(x) - hi), lo = bf16(fp32(x) - hi - mid)."""
+    x32 = round_fp32(x)
+    hi = round_bf16(x32)
+    r1 = round_fp32(x32 - hi)
+    mid = round_bf16(r1)
+    lo = round_bf16(round_fp32(r1 - mid))
+    return hi, mid, lo
+
+
 def _mul_form(prec):
     if prec == "fp32":
         def prep(x):
@@ -57,13 +73,20 @@ def _mul_form(prec):
 
         def mm(a, b):
             return a[0] @ b[0].T + a[0] @ b[1].T + a[1] @ b[0].T
+    elif prec == "bf16x6":
+        def prep(x):
+            return split_bf16x6(x)
+
+        def mm(a, b):
+            return (a[0] @ b[0].T + a[0] @ b[1].T + a[1] @ b[0].T
+                    + a[1] @ b[1].T + a[0] @ b[2].T + a[2] @ b[0].T)
     else:
         raise ValueError(prec)
     return prep, mm
 
 
 def ppl_lowprec(L, o, t, prec):
-    """R_ij^ab of the pair method with the operand roundings of `prec` ("fp32" / "bf16x3")."""
+    """R_ij^ab of the pair method with the operand roundings of `prec` ("fp32" / "bf16x3" / "bf16x6")."""
     prep, mm = _mul_form(prec)
     L = np.asarray(L, dtype=np.float64)
     v = L.shape[1] - o
