@@ -85,8 +85,8 @@ def measured_traffic(config):
 
 def study_c3(args):
     """Time to an amplitude residual of 1e-7 at (40, 400, 1200), contractive generator
-    seed 2: FP64, BF16x3 / FP32 sweeps refined in FP64, and the same from the learned
-    start, each also with DIIS (subspace 8); plus single-evaluation errors of the
+    seed 2: FP64, BF16x3 / BF16x6 / FP32 sweeps refined in FP64, and the same from the
+    learned start, each also with DIIS (subspace 8); plus single-evaluation errors of the
     low-precision GEMMs."""
     import numpy as np
     import torch
@@ -103,18 +103,19 @@ def study_c3(args):
         mlp.set_params(np.fromfile(args.weights, dtype="<f4"))
     # warm-up of every code path on a small instance
     small = ppl_synth.make_system(4, 24, 72, 99, "contractive")
-    for start, prec, keep in (("mp2", "fp64", False), ("mp2", "bf16x3", True), ("mp2", "fp32", True)):
+    for start, prec, keep in (("mp2", "fp64", False), ("mp2", "bf16x3", True), ("mp2", "fp32", True),
+                              ("mp2", "bf16x6", True)):
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep)
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=8)
     if mlp is not None:
         Lr.time_to_tol(small, "learned", mlp=mlp, prec="bf16x3", keep_fp64=True)
     runs = [("fp64", "mp2", "fp64", False, 0), ("bf16x3+fp64", "mp2", "bf16x3", True, 0),
-            ("fp32+fp64", "mp2", "fp32", True, 0)]
+            ("fp32+fp64", "mp2", "fp32", True, 0), ("bf16x6+fp64", "mp2", "bf16x6", True, 0)]
     if mlp is not None:
         runs += [("bf16x3+fp64 learned", "learned", "bf16x3", True, 0), ("fp64 learned", "learned", "fp64", False, 0)]
     # the same with DIIS (subspace of 8)
     runs += [("fp64 diis", "mp2", "fp64", False, 8), ("bf16x3+fp64 diis", "mp2", "bf16x3", True, 8),
-             ("fp32+fp64 diis", "mp2", "fp32", True, 8)]
+             ("fp32+fp64 diis", "mp2", "fp32", True, 8), ("bf16x6+fp64 diis", "mp2", "bf16x6", True, 8)]
     if mlp is not None:
         runs += [("bf16x3+fp64 learned diis", "learned", "bf16x3", True, 8),
                  ("fp64 learned diis", "learned", "fp64", False, 8)]
@@ -139,7 +140,7 @@ def study_c3(args):
     # single-evaluation errors of R (MP2 amplitudes) against the FP64 path
     d = Lr.upload_system(sysd)
     Rs = {}
-    for prec in ("fp64", "fp32", "bf16x3"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
         eng = P.PPL(o, v, naux, prec=prec)
         tm, _ = eng.mp2(d["L"], d["e_occ"], d["e_vir"])
         eng.build(d["L"])
@@ -147,7 +148,7 @@ def study_c3(args):
         eng.close()
         del eng
         torch.cuda.empty_cache()
-    for prec in ("fp32", "bf16x3"):
+    for prec in ("fp32", "bf16x3", "bf16x6"):
         out[f"single_R_rel_err_{prec}"] = (torch.linalg.norm(Rs[prec] - Rs["fp64"]) /
                                            torch.linalg.norm(Rs["fp64"])).item()
     print(json.dumps({"study": out}), flush=True)

@@ -51,7 +51,10 @@ extern "C" {
 typedef enum {
   PPL_FP64   = 0,  /* FP64 operands, FP64 MFMA, FP64 accumulation */
   PPL_FP32   = 1,  /* FP32 operands, FP32 MFMA, FP32 accumulation */
-  PPL_BF16X3 = 2   /* x = hi + lo (two bf16 terms), hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+  PPL_BF16X3 = 2,  /* x = hi + lo (two bf16 terms), hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+  PPL_BF16X6 = 3   /* x = hi + mid + lo (three bf16 terms, the 24 bits of FP32), the six products
+                      whose plane indices sum to at most two on BF16 MFMA, FP32 accumulation:
+                      about FP32 accuracy (Henry, Tang and Heinecke, ARITH 2019) */
 } ppl_prec_t;
 
 typedef struct ppl_plan_s* ppl_plan_t;
@@ -187,7 +190,7 @@ typedef struct {
   int32_t max_sweeps;       /* hard cap on sweeps (all precisions), >= 1 */
   int32_t start;            /* PPL_START_* */
   double  tol;              /* stop when the FP64 residual ||t_new - t||_F < tol (0 = never) */
-  double  switch_tol;       /* mixed: go to FP64 sweeps when the residual < switch_tol (0 = 1e-6 for BF16X3, 1e-7 for FP32) */
+  double  switch_tol;       /* mixed: go to FP64 sweeps when the residual < switch_tol (0 = 1e-6 for BF16X3, 1e-7 for FP32 and BF16X6) */
   double  stagnation;       /* mixed: go to FP64 sweeps when r_n / r_{n-1} > stagnation */
   int32_t min_fp64_sweeps;  /* mixed: at least this many FP64 sweeps after the switch */
   int32_t fail_on_noconv;   /* 1: return PPL_E_NOCONV when max_sweeps is reached (else OK) */

@@ -27,8 +27,8 @@ PPL_E_UNSUPPORTED = -8
 ERROR_NAMES = {0: "PPL_OK", -1: "PPL_E_ARG", -2: "PPL_E_NOMEM", -3: "PPL_E_HIP", -4: "PPL_E_NONFINITE",
                -5: "PPL_E_NOCONV", -6: "PPL_E_DIVERGED", -7: "PPL_E_STATE", -8: "PPL_E_UNSUPPORTED"}
 
-PPL_FP64, PPL_FP32, PPL_BF16X3 = 0, 1, 2
-PREC = {"fp64": PPL_FP64, "fp32": PPL_FP32, "bf16x3": PPL_BF16X3}
+PPL_FP64, PPL_FP32, PPL_BF16X3, PPL_BF16X6 = 0, 1, 2, 3
+PREC = {"fp64": PPL_FP64, "fp32": PPL_FP32, "bf16x3": PPL_BF16X3, "bf16x6": PPL_BF16X6}
 PPL_START_MP2, PPL_START_GIVEN, PPL_START_GIVEN_CHECKED = 0, 1, 2
 
 

@@ -32,7 +32,7 @@ static uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
 
 // bytes per element of an operand plane and number of planes
 static int elem_bytes(int prec) { return prec == PPL_FP64 ? 8 : (prec == PPL_FP32 ? 4 : 2); }
-static int planes(int prec) { return prec == PPL_BF16X3 ? 2 : 1; }
+static int planes(int prec) { return prec == PPL_BF16X3 ? 2 : (prec == PPL_BF16X6 ? 3 : 1); }
 static int acc_bytes(int prec) { return prec == PPL_FP64 ? 8 : 4; }
 
 // overflow-checked multiply of non-negative sizes
@@ -165,6 +165,20 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     const int np = planes(s.prec);
     const int64_t vrows_p = resident ? p->Pp : max_batch_pairs;
     const int64_t vrows_m = resident ? p->Pm : max_batch_pairs;
+    if (np == 3) {
+      // BF16x6: the mid and lo planes follow their hi plane directly (three planes spaced
+      // one plane apart; the kernels find lo at mid + (mid - hi))
+      auto three = [&](Region& hi, Region& rest, uint64_t bytes) {
+        hi = L.take(bytes);
+        rest = L.take(2 * hi.bytes);
+      };
+      three(s.xt, s.xt_lo, (uint64_t)v * v * p->ldx * w);
+      three(s.vp, s.vp_lo, (uint64_t)vrows_p * p->ldp * w);
+      three(s.vm, s.vm_lo, (uint64_t)std::max<int64_t>(vrows_m, 1) * p->ldm * w);
+      three(s.sp, s.sp_lo, (uint64_t)p->Np * p->ldp * w);
+      three(s.am, s.am_lo, (uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * w);
+      continue;
+    }
     s.xt = L.take((uint64_t)v * v * p->ldx * w);
     s.vp = L.take((uint64_t)vrows_p * p->ldp * w);
     s.vm = L.take((uint64_t)std::max<int64_t>(vrows_m, 1) * p->ldm * w);
@@ -314,11 +328,16 @@ static int mirror_vpm(ppl_plan_t p, OperandSet& s) {
   if (!p->sym_build) return PPL_OK;
   ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
   const int w = elem_bytes(s.prec);
-  PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vp), p->Pp, p->ldp));
-  if (s.vp_lo.bytes) PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vp_lo), p->Pp, p->ldp));
-  if (p->Pm > 0) {
-    PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vm), p->Pm, p->ldm));
-    if (s.vm_lo.bytes) PPL_TRY(mirror_lower(p->stream, w, at<void>(p, s.vm_lo), p->Pm, p->ldm));
+  const int np = planes(s.prec);
+  // plane k of a region starts k plane sizes after its hi plane (the lo planes of BF16x6
+  // follow the hi plane directly; the lo plane of BF16x3 lies elsewhere)
+  for (int k = 0; k < np; ++k) {
+    char* vp = k == 0 ? at<char>(p, s.vp) : at<char>(p, s.vp_lo) + (uint64_t)(k - 1) * s.vp.bytes;
+    PPL_TRY(mirror_lower(p->stream, w, vp, p->Pp, p->ldp));
+    if (p->Pm > 0) {
+      char* vm = k == 0 ? at<char>(p, s.vm) : at<char>(p, s.vm_lo) + (uint64_t)(k - 1) * s.vm.bytes;
+      PPL_TRY(mirror_lower(p->stream, w, vm, p->Pm, p->ldm));
+    }
   }
   return PPL_OK;
 }
@@ -622,7 +641,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   if (d->v < 2) return fail(PPL_E_ARG, "v must be >= 2 (got %d)", d->v);
   if (d->naux < 1) return fail(PPL_E_ARG, "naux must be >= 1 (got %d)", d->naux);
   if (d->v > 32767 || d->o > 32767) return fail(PPL_E_ARG, "o and v must be < 32768");
-  if (d->prec != PPL_FP64 && d->prec != PPL_FP32 && d->prec != PPL_BF16X3)
+  if (d->prec != PPL_FP64 && d->prec != PPL_FP32 && d->prec != PPL_BF16X3 && d->prec != PPL_BF16X6)
     return fail(PPL_E_ARG, "unknown precision %d", d->prec);
   if (d->tile_contract < -1 || d->tile_contract >= contract_tile_count())
     return fail(PPL_E_ARG, "tile_contract %d out of range", d->tile_contract);
@@ -1040,7 +1059,7 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   const bool mixed = p->ops[0].prec != PPL_FP64;
   // automatic switch point: a few times above the rounding floor of the low-precision GEMMs
   // (relative single-evaluation errors ~3e-6 for BF16x3 and ~2e-7 for FP32)
-  if (o.switch_tol <= 0.0) o.switch_tol = p->ops[0].prec == PPL_FP32 ? 1e-7 : 1e-6;
+  if (o.switch_tol <= 0.0) o.switch_tol = p->ops[0].prec == PPL_BF16X3 ? 1e-6 : 1e-7;
   const int fp64_set = mixed ? (p->ops[1].present ? 1 : -1) : 0;
   bool lp_phase = mixed;
   int fp64_sweeps = 0;

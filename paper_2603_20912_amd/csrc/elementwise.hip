@@ -79,6 +79,23 @@ template <> struct Store<PPL_BF16X3> {
     ((__bf16*)lo)[i] = l;
   }
 };
+template <> struct Store<PPL_BF16X6> {
+  // x -> FP32 (round to nearest), hi = bf16(x32), mid = bf16(x32 - hi), lo = bf16(x32 - hi - mid),
+  // each rounded to nearest even (both differences are exact in FP32). The three planes lie
+  // equally far apart: hi at h, mid at m, lo at m + (m - h).
+  __device__ static void put(void* hi, void* mid, int64_t i, double x) {
+    const float xf = (float)x;
+    const __bf16 h = (__bf16)xf;
+    const float r1 = xf - (float)h;
+    const __bf16 m = (__bf16)r1;
+    const __bf16 l = (__bf16)(r1 - (float)m);
+    __bf16* ph = (__bf16*)hi;
+    __bf16* pm = (__bf16*)mid;
+    ph[i] = h;
+    pm[i] = m;
+    (pm + (pm - ph))[i] = l;
+  }
+};
 
 // ------------------------------------------------------------------ staging (transposing copy)
 // X[r1*R2 + r2][P] = L[P][r1_off + r1][r2_off + r2] for P < naux, 0 for naux <= P < ldx.
@@ -133,6 +150,7 @@ int stage_vv(hipStream_t s, int prec, const double* L, int o, int v, int naux, i
   if (prec == PPL_FP64) return stage_launch<PPL_FP64>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
   if (prec == PPL_FP32) return stage_launch<PPL_FP32>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
   if (prec == PPL_BF16X3) return stage_launch<PPL_BF16X3>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
+  if (prec == PPL_BF16X6) return stage_launch<PPL_BF16X6>(s, L, n, naux, o, o, v, v, ldx, xt, xt_lo);
   return fail(PPL_E_ARG, "stage_vv: unknown precision %d", prec);
 }
 
@@ -207,6 +225,9 @@ int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void
                        (const float*)G, tab_vp, vp, vp_lo, ldp, vp_row0, vm, vm_lo, ldm, vm_row0, Pp, Pm);
   else if (prec == PPL_BF16X3)
     hipLaunchKernelGGL((pack_vpm_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, p0,
+                       (const float*)G, tab_vp, vp, vp_lo, ldp, vp_row0, vm, vm_lo, ldm, vm_row0, Pp, Pm);
+  else if (prec == PPL_BF16X6)
+    hipLaunchKernelGGL((pack_vpm_kernel<float, PPL_BF16X6>), grid, dim3(256), 0, s, v, p0,
                        (const float*)G, tab_vp, vp, vp_lo, ldp, vp_row0, vm, vm_lo, ldm, vm_row0, Pp, Pm);
   else
     return fail(PPL_E_ARG, "pack_vpm: unknown precision %d", prec);
@@ -291,6 +312,10 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
                        tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm, vp_row0, vm_row0, half_diag, zp, zm);
   else if (prec == PPL_BF16X3)
     hipLaunchKernelGGL((pack_vpm_sym_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, a0, p0,
+                       (const float*)G, tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm, vp_row0, vm_row0, half_diag,
+                       zp, zm);
+  else if (prec == PPL_BF16X6)
+    hipLaunchKernelGGL((pack_vpm_sym_kernel<float, PPL_BF16X6>), grid, dim3(256), 0, s, v, a0, p0,
                        (const float*)G, tab_vp, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm, vp_row0, vm_row0, half_diag,
                        zp, zm);
   else
@@ -562,6 +587,8 @@ int convert_rows(hipStream_t s, int prec, const double* src, int64_t rows, int64
     hipLaunchKernelGGL(convert_kernel<PPL_FP32>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
   else if (prec == PPL_BF16X3)
     hipLaunchKernelGGL(convert_kernel<PPL_BF16X3>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
+  else if (prec == PPL_BF16X6)
+    hipLaunchKernelGGL(convert_kernel<PPL_BF16X6>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
   else if (prec == PPL_FP64)
     hipLaunchKernelGGL(convert_kernel<PPL_FP64>, dim3(grid_for(n, 256)), dim3(256), 0, s, src, n, dst, dst_lo);
   else

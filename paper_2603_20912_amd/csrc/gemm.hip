@@ -793,6 +793,166 @@ gemm_nt_bf16x3_kernel(int64_t M, int64_t N, int64_t Kpad, const __bf16* __restri
   bf3_tile_body<WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, Ah, Al, lda, Bh, Bl, ldb, epi, sAh, sAl, sBh, sBl);
 }
 
+// ------------------------------------------------------------------ the kernel (BF16 x 6)
+// x (in FP32) = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid):
+// 24 significant bits, those of FP32. x*y ~ the six products whose plane indices sum to at
+// most two (hi*hi; hi*mid, mid*hi; mid*mid, hi*lo, lo*hi), the five small ones in a second
+// FP32 register set added to the hi*hi set at the end (the bf16x6 scheme of Henry, Tang and
+// Heinecke, ARITH 2019). The planes of an operand lie equally far apart in memory: hi at h,
+// mid at m, lo at m + (m - h). K chunks of 32: two buffers of three planes of BM + BN rows
+// take 384 (BM + BN) bytes of LDS, 132 KB for the largest tile (224 + 128 rows).
+constexpr int kKcBf6 = 32;
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+struct Bf6Geom {
+  static constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  static constexpr int LDSR = kKcBf6;
+  static constexpr int BUF_A = BM * LDSR, BUF_B = BN * LDSR;     // one buffer of one plane
+  static constexpr int LDS_A = 6 * BUF_A, LDS_B = 6 * BUF_B;     // [plane][buffer]
+  static_assert((LDS_A + LDS_B) * 2 <= 160 * 1024, "BF16x6 tile exceeds the LDS");
+};
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, class Epi>
+__device__ __forceinline__ void bf6_tile_body(const TileJob& job, int64_t M, int64_t N, const __bf16* Ah,
+                                              const __bf16* Am, int64_t lda, const __bf16* Bh,
+                                              const __bf16* Bm, int64_t ldb, const Epi& epi,
+                                              __bf16* __restrict__ sA, __bf16* __restrict__ sB) {
+  constexpr int KC = kKcBf6;
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
+  using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
+  constexpr int BM = G::BM, BN = G::BN, LDSR = G::LDSR;
+  constexpr int VEC = 8;                           // bf16 per 16-byte load
+  constexpr int VPR = KC / VEC;                    // 4 vectors per staged row
+  constexpr int NLA = (BM * VPR + NT - 1) / NT;
+  constexpr int NLB = (BN * VPR + NT - 1) / NT;
+  const int64_t m0 = job.m0, n0 = job.n0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const __bf16* Ap[3] = {Ah, Am, Am + (Am - Ah)};
+  const __bf16* Bp[3] = {Bh, Bm, Bm + (Bm - Bh)};
+
+  // swizzled slot of vector kv of staged row r (64-byte rows: key (r / 2) mod 4)
+  auto key = [](int r) { return (r >> 1) & 3; };
+  int64_t ga[NLA], gb[NLB];
+  int oa[NLA], ob[NLB];
+#pragma unroll
+  for (int i = 0; i < NLA; ++i) {
+    int idx = tid + i * NT;
+    if (idx >= BM * VPR) idx = BM * VPR - 1;
+    const int r = idx / VPR, kv = idx % VPR;
+    int64_t gr = m0 + r;
+    if (gr > M - 1) gr = M - 1;
+    ga[i] = epi.arow(gr) * lda + kv * VEC + job.kc0 * KC;
+    oa[i] = r * LDSR + (kv ^ key(r)) * VEC;
+  }
+#pragma unroll
+  for (int i = 0; i < NLB; ++i) {
+    int idx = tid + i * NT;
+    if (idx >= BN * VPR) idx = BN * VPR - 1;
+    const int r = idx / VPR, kv = idx % VPR;
+    int64_t gr = n0 + r;
+    if (gr > N - 1) gr = N - 1;
+    gb[i] = epi.brow(gr) * ldb + kv * VEC + job.kc0 * KC;
+    ob[i] = r * LDSR + (kv ^ key(r)) * VEC;
+  }
+  f4 acc[WM][WN], accx[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      acc[i][j] = f4{0, 0, 0, 0};
+      accx[i][j] = f4{0, 0, 0, 0};
+    }
+  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR;
+  const int brow = (wn * WN * 16 + (lane & 15)) * LDSR;
+  const int col = (((lane >> 4)) ^ key(lane & 15)) * 8;   // this lane's 8-element fragment vector
+  const int64_t nk = job.kc1 - job.kc0;
+
+#define PPL_BF6_LOAD(k0)                                                                  \
+  _Pragma("unroll") for (int q = 0; q < 3; ++q) {                                         \
+    _Pragma("unroll") for (int i = 0; i < NLA; ++i)                                       \
+      ra[q][i] = *reinterpret_cast<const uint4*>(Ap[q] + ga[i] + (k0));                   \
+    _Pragma("unroll") for (int i = 0; i < NLB; ++i)                                       \
+      rb[q][i] = *reinterpret_cast<const uint4*>(Bp[q] + gb[i] + (k0));                   \
+  }
+#define PPL_BF6_STORE(buf)                                                                \
+  _Pragma("unroll") for (int q = 0; q < 3; ++q) {                                         \
+    _Pragma("unroll") for (int i = 0; i < NLA; ++i)                                       \
+      *reinterpret_cast<uint4*>(&sA[(2 * q + (buf)) * G::BUF_A + oa[i]]) = ra[q][i];      \
+    _Pragma("unroll") for (int i = 0; i < NLB; ++i)                                       \
+      *reinterpret_cast<uint4*>(&sB[(2 * q + (buf)) * G::BUF_B + ob[i]]) = rb[q][i];      \
+  }
+#define PPL_BF6_COMPUTE(buf)                                                                               \
+  {                                                                                                        \
+    bf8 a[3][WM], b[3][WN];                                                                                \
+    _Pragma("unroll") for (int q = 0; q < 3; ++q) {                                                        \
+      _Pragma("unroll") for (int i = 0; i < WM; ++i)                                                       \
+        a[q][i] = *reinterpret_cast<const bf8*>(&sA[(2 * q + (buf)) * G::BUF_A + arow + i * 16 * LDSR + col]); \
+      _Pragma("unroll") for (int j = 0; j < WN; ++j)                                                       \
+        b[q][j] = *reinterpret_cast<const bf8*>(&sB[(2 * q + (buf)) * G::BUF_B + brow + j * 16 * LDSR + col]); \
+    }                                                                                                      \
+    _Pragma("unroll") for (int i = 0; i < WM; ++i)                                                         \
+    _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                                       \
+      accx[i][j] = mfma16(a[2][i], b[0][j], accx[i][j]);                                                   \
+      accx[i][j] = mfma16(a[0][i], b[2][j], accx[i][j]);                                                   \
+      accx[i][j] = mfma16(a[1][i], b[1][j], accx[i][j]);                                                   \
+      accx[i][j] = mfma16(a[1][i], b[0][j], accx[i][j]);                                                   \
+      accx[i][j] = mfma16(a[0][i], b[1][j], accx[i][j]);                                                   \
+      acc[i][j] = mfma16(a[0][i], b[0][j], acc[i][j]);                                                     \
+    }                                                                                                      \
+  }
+
+  {
+    uint4 ra[3][NLA], rb[3][NLB];
+    PPL_BF6_LOAD(0)
+    PPL_BF6_STORE(0)
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    uint4 ra[3][NLA], rb[3][NLB];
+    PPL_BF6_LOAD((kt + 1) * KC)
+    PPL_BF6_COMPUTE(buf)
+    PPL_BF6_STORE(buf ^ 1)
+    __syncthreads();
+  }
+  {
+    const int buf = (int)((nk - 1) & 1);
+    PPL_BF6_COMPUTE(buf)
+  }
+#undef PPL_BF6_LOAD
+#undef PPL_BF6_STORE
+#undef PPL_BF6_COMPUTE
+
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm * WM * 16 + i * 16 + AccOf<__bf16>::row(lane, r);
+      int64_t base;
+      bool ok;
+      epi.row(job.split, m, base, ok);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int64_t n = n0 + wn * WN * 16 + j * 16 + (lane & 15);
+        epi.put(base, ok, n, acc[i][j][r] + accx[i][j][r]);
+      }
+    }
+  }
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, class Epi, class Map>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
+gemm_nt_bf16x6_kernel(int64_t M, int64_t N, const __bf16* Ah, const __bf16* Am, int64_t lda, const __bf16* Bh,
+                      const __bf16* Bm, int64_t ldb, Epi epi, Map map) {
+  using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[G::LDS_B];
+  TileJob job;
+  if (!map(blockIdx.x, job)) return;
+  bf6_tile_body<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
+}
+
 // ------------------------------------------------------------------ tile configurations
 struct TileCfg {
   int wm, wn, waves_m, waves_n;
@@ -952,6 +1112,20 @@ static int launch_bf3(hipStream_t s, int64_t grid, int64_t M, int64_t N, int64_t
   return PPL_OK;
 }
 
+template <int WM, int WN, int WAVES_M, int WAVES_N, class Epi, class Map>
+static int launch_bf6(hipStream_t s, int64_t grid, int64_t M, int64_t N, int64_t Kpad, const __bf16* Ah,
+                      const __bf16* Am, int64_t lda, const __bf16* Bh, const __bf16* Bm, int64_t ldb, Epi epi,
+                      Map map) {
+  if (grid <= 0) return PPL_OK;
+  if (grid > 0x7fffffffLL) return fail(PPL_E_ARG, "GEMM grid too large (%lld tiles)", (long long)grid);
+  if (Kpad % kKcBf6 != 0) return fail(PPL_E_ARG, "K padding %lld not a multiple of %d", (long long)Kpad, kKcBf6);
+  if (!Am || !Bm) return fail(PPL_E_ARG, "BF16x6 operands need their mid planes");
+  hipLaunchKernelGGL((gemm_nt_bf16x6_kernel<WM, WN, WAVES_M, WAVES_N, Epi, Map>), dim3((unsigned)grid),
+                     dim3(64 * WAVES_M * WAVES_N), 0, s, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, map);
+  PPL_HIP_TRY(hipGetLastError());
+  return PPL_OK;
+}
+
 // sum of the split-K slices in slice order: C[m][c_col0 + n] = sum_s P[s][m][n]
 template <class Tc>
 __global__ void splitk_reduce_kernel(const Tc* __restrict__ P, int splits, int64_t split_stride,
@@ -1033,6 +1207,31 @@ gemm_streamk_bf16x3_kernel(int64_t M, int64_t N, const __bf16* __restrict__ Ah, 
   }
 }
 
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
+gemm_streamk_bf16x6_kernel(int64_t M, int64_t N, const __bf16* Ah, const __bf16* Am, int64_t lda, const __bf16* Bh,
+                           const __bf16* Bm, int64_t ldb, float* C, int64_t ldc, int64_t c_col0, float* part,
+                           StreamK sk) {
+  using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[G::LDS_B];
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t begin = sk.start(w), end = sk.start(w + 1);
+  const int64_t first_tile = begin / sk.nk;
+  for (int64_t it = begin; it < end;) {
+    const int64_t tile = it / sk.nk, t0 = tile * sk.nk;
+    const int64_t k0 = it - t0, k1 = end - t0 < sk.nk ? end - t0 : sk.nk;
+    TileJob job{(tile % sk.n_mt) * G::BM, (tile / sk.n_mt) * G::BN, k0, k1, 0};
+    const bool whole = k0 == 0 && k1 == sk.nk;
+    EpiSK<float> epi{C, ldc, c_col0, M, N,
+                     part + (w * 2 + (tile == first_tile ? 0 : 1)) * (int64_t)(G::BM * G::BN),
+                     job.m0, job.n0, G::BN, !whole};
+    bf6_tile_body<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
+    it = t0 + k1;
+    __syncthreads();   // the next tile refills the LDS buffers
+  }
+}
+
 // C tile `blockIdx.x` = sum of the partial slots of the workgroups that shared it
 template <class T>
 __global__ void __launch_bounds__(256)
@@ -1087,9 +1286,14 @@ static int64_t streamk_grid(int64_t resident, int64_t iters) {
   return g > 1 ? g : 1;
 }
 
+// K elements per staged chunk of a precision on a tile of bm x bn
+static int kc_of(int prec, int bm, int bn) {
+  return prec == PPL_BF16X3 ? bf3_kc(bm, bn) : (prec == PPL_BF16X6 ? kKcBf6 : kc_of_prec(prec));
+}
+
 uint64_t streamk_part_bytes(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad) {
   const TileCfg& c = kContract[tile];
-  const int KC = prec == PPL_BF16X3 ? bf3_kc(c.bm(), c.bn()) : kc_of_prec(prec);
+  const int KC = kc_of(prec, c.bm(), c.bn());
   const int64_t iters = ((Nrows + c.bm() - 1) / c.bm()) * ((Prows + c.bn() - 1) / c.bn()) * (Kpad / KC);
   return (uint64_t)streamk_grid(kStreamKMaxGrid, iters) * 2 * c.bm() * c.bn() * (prec == PPL_FP64 ? 8 : 4);
 }
@@ -1126,6 +1330,29 @@ static int launch_streamk_bf3(hipStream_t s, int64_t M, int64_t N, int64_t Kpad,
   if (sk.iters <= 0) return PPL_OK;
   hipLaunchKernelGGL(kern, dim3((unsigned)sk.G), dim3(G::NT), 0, s, M, N, Ah, Al, lda, Bh, Bl, ldb, C, ldc,
                      c_col0, (float*)part, sk);
+  PPL_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(streamk_fixup_kernel<float>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const float*)part,
+                     C, ldc, c_col0, M, N, G::BM, G::BN, sk);
+  PPL_HIP_TRY(hipGetLastError());
+  return PPL_OK;
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+static int launch_streamk_bf6(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const __bf16* Ah,
+                              const __bf16* Am, int64_t lda, const __bf16* Bh, const __bf16* Bm, int64_t ldb,
+                              float* C, int64_t ldc, int64_t c_col0, void* part, uint64_t part_bytes) {
+  using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
+  if (Kpad % kKcBf6 != 0) return fail(PPL_E_ARG, "K padding %lld not a multiple of %d", (long long)Kpad, kKcBf6);
+  if (!Am || !Bm) return fail(PPL_E_ARG, "BF16x6 operands need their mid planes");
+  auto kern = gemm_streamk_bf16x6_kernel<WM, WN, WAVES_M, WAVES_N>;
+  StreamK sk;
+  int64_t n_tiles = 0;
+  PPL_TRY(streamk_setup(resident_workgroups(kern, NT), M, N, Kpad / kKcBf6, G::BM, G::BN, sizeof(float), part,
+                        part_bytes, sk, n_tiles));
+  if (sk.iters <= 0) return PPL_OK;
+  hipLaunchKernelGGL(kern, dim3((unsigned)sk.G), dim3(NT), 0, s, M, N, Ah, Am, lda, Bh, Bm, ldb, C, ldc, c_col0,
+                     (float*)part, sk);
   PPL_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(streamk_fixup_kernel<float>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const float*)part,
                      C, ldc, c_col0, M, N, G::BM, G::BN, sk);
@@ -1177,9 +1404,14 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
       return launch_streamk_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(
           s, Nrows, Prows, Kpad, (const __bf16*)S, (const __bf16*)S_lo, lds_, (const __bf16*)V,
           (const __bf16*)V_lo, ldv, (float*)C, ldc, c_col0, partial, partial_bytes);
+    if (prec == PPL_BF16X6)
+      return launch_streamk_bf6<WM, WN, WAVES_M, WAVES_N>(s, Nrows, Prows, Kpad, (const __bf16*)S,
+                                                          (const __bf16*)S_lo, lds_, (const __bf16*)V,
+                                                          (const __bf16*)V_lo, ldv, (float*)C, ldc, c_col0, partial,
+                                                          partial_bytes);
     return fail(PPL_E_ARG, "unknown precision %d", prec);
   }
-  const int KC = prec == PPL_BF16X3 ? bf3_kc(BM, BN) : kc_of_prec(prec);
+  const int KC = kc_of(prec, BM, BN);
   const int64_t nk = Kpad / KC;
   if (splits < 1) splits = 1;
   if (splits > nk) splits = (int)nk;
@@ -1208,6 +1440,11 @@ static int contract_cfg(hipStream_t s, int prec, int64_t Nrows, int64_t Prows, i
     rc = launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S,
                                                   (const __bf16*)S_lo, lds_, (const __bf16*)V,
                                                   (const __bf16*)V_lo, ldv, epi, map);
+  } else if (prec == PPL_BF16X6) {
+    EpiStore<float> epi = direct ? EpiStore<float>{(float*)C, ldc, c_col0, Nrows, Prows, 1.0, cbeta, 0}
+                                 : EpiStore<float>{(float*)partial, partial_ld, 0, Nrows, Prows, 1.0, 0.0, pstride};
+    rc = launch_bf6<WM, WN, WAVES_M, WAVES_N>(s, grid, Nrows, Prows, Kpad, (const __bf16*)S, (const __bf16*)S_lo,
+                                              lds_, (const __bf16*)V, (const __bf16*)V_lo, ldv, epi, map);
   } else {
     return fail(PPL_E_ARG, "unknown precision %d", prec);
   }
@@ -1255,7 +1492,7 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
 // Workgroups of one contraction launch for a (tile, splits) choice.
 int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits) {
   const TileCfg& c = kContract[tile];
-  const int KC = prec == PPL_BF16X3 ? bf3_kc(c.bm(), c.bn()) : kc_of_prec(prec);
+  const int KC = kc_of(prec, c.bm(), c.bn());
   const int64_t nk = Kpad / KC;
   if (splits > nk) splits = (int)nk;
   const int64_t kps = (nk + splits - 1) / splits;
@@ -1266,10 +1503,12 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 // Relative per-tile throughput on large problems, measured with HIP events on
 // gfx950: best over 1, 2 and 4 K slices, averaged over R+ and R- at (30, 300, 900)
 // and (40, 400, 1200) (FP32 at the first only); 1.0 = best tile of the precision.
-static const double kTileEff[3][11] = {
+// BF16x6 starts from the BF16x3 row (same staging, twice the matrix-core work per chunk).
+static const double kTileEff[4][11] = {
     /* FP64   */ {1.00, 0.97, 0.87, 0.91, 0.99, 0.99, 0.95, 0.97, 1.00, 0.87, 0.83},
     /* FP32   */ {0.93, 0.92, 0.74, 0.90, 0.93, 0.96, 0.96, 0.97, 1.00, 0.81, 0.87},
-    /* BF16x3 */ {0.93, 0.73, 0.53, 0.51, 0.56, 0.92, 0.59, 0.76, 0.82, 1.00, 0.66}};
+    /* BF16x3 */ {0.93, 0.73, 0.53, 0.51, 0.56, 0.92, 0.59, 0.76, 0.82, 1.00, 0.66},
+    /* BF16x6 */ {0.93, 0.73, 0.53, 0.51, 0.56, 0.92, 0.59, 0.76, 0.82, 1.00, 0.66}};
 static_assert(sizeof(kTileEff[0]) / sizeof(double) == kNumContract, "one efficiency per tile");
 
 // Model choice of (tile, splits): useful work over the work of the padded tiles,
@@ -1290,7 +1529,7 @@ void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int m
       const double rounds = (double)jobs / 256.0;
       const double fill = rounds / std::ceil(rounds);
       // small penalty per extra slice (partial traffic, reduction launch)
-      const int pi = prec == PPL_FP64 ? 0 : (prec == PPL_FP32 ? 1 : 2);
+      const int pi = prec == PPL_FP64 ? 0 : (prec == PPL_FP32 ? 1 : (prec == PPL_BF16X3 ? 2 : 3));
       const double score = pad * fill * (1.0 - 0.01 * (sp - 1)) * kTileEff[pi][t];
       if (score > best + 1e-9) {
         best = score;
@@ -1309,7 +1548,7 @@ static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpa
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
   MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
-  map.nk = Kpad / (prec == PPL_BF16X3 ? bf3_kc(BM, BN) : kc_of_prec(prec));
+  map.nk = Kpad / kc_of(prec, BM, BN);
   if (prec == PPL_FP64) {
     const double* X = (const double*)Xt + (int64_t)a0 * v * ldx;
     EpiBuild<double> epi{(double*)G, M, N, v, a0};
@@ -1329,6 +1568,12 @@ static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpa
     return launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, n_valid_tiles, M, N, Kpad, Xh, Xl, ldx, Xh,
                                                         Xl, ldx, epi, map);
   }
+  if (prec == PPL_BF16X6) {
+    const __bf16* Xh = (const __bf16*)Xt + (int64_t)a0 * v * ldx;
+    const __bf16* Xm = (const __bf16*)Xt_lo + (int64_t)a0 * v * ldx;
+    EpiBuild<float> epi{(float*)G, M, N, v, a0};
+    return launch_bf6<WM, WN, WAVES_M, WAVES_N>(s, n_valid_tiles, M, N, Kpad, Xh, Xm, ldx, Xh, Xm, ldx, epi, map);
+  }
   return fail(PPL_E_ARG, "unknown precision %d", prec);
 }
 
@@ -1343,7 +1588,7 @@ static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t
   const int64_t M = pr1 - pr0, N = (int64_t)W * W;
   const int* cstep = cols + ((int64_t)v * v - N);       // first column with min(b, d) = a0
   MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
-  map.nk = Kpad / (prec == PPL_BF16X3 ? bf3_kc(BM, BN) : kc_of_prec(prec));
+  map.nk = Kpad / kc_of(prec, BM, BN);
   if (prec == PPL_FP64) {
     EpiBuildSym<double> epi{(double*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
     return launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, n_valid_tiles, M, N, Kpad, (const double*)Xt, ldx,
@@ -1359,6 +1604,12 @@ static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t
     return launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, n_valid_tiles, M, N, Kpad, (const __bf16*)Xt,
                                                                 (const __bf16*)Xt_lo, ldx, (const __bf16*)Xt,
                                                                 (const __bf16*)Xt_lo, ldx, epi, map);
+  }
+  if (prec == PPL_BF16X6) {
+    EpiBuildSym<float> epi{(float*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    return launch_bf6<WM, WN, WAVES_M, WAVES_N>(s, n_valid_tiles, M, N, Kpad, (const __bf16*)Xt,
+                                                (const __bf16*)Xt_lo, ldx, (const __bf16*)Xt, (const __bf16*)Xt_lo,
+                                                ldx, epi, map);
   }
   return fail(PPL_E_ARG, "unknown precision %d", prec);
 }

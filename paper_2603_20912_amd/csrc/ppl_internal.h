@@ -191,7 +191,7 @@ void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int m
 #ifndef PPL_BUILD_TILE
 #define PPL_BUILD_TILE 1     // FP64 / FP32 integral-build tile (contraction tile id)
 #endif
-inline int build_tile_for_prec(int prec) { return prec == PPL_BF16X3 ? 5 : PPL_BUILD_TILE; }
+inline int build_tile_for_prec(int prec) { return prec == PPL_BF16X3 || prec == PPL_BF16X6 ? 5 : PPL_BUILD_TILE; }
 constexpr int kMaxSplits = 8;          // split-K slices 1 .. kMaxSplits; 0 selects stream-K
 constexpr int64_t kStreamKMaxGrid = 1024;   // stream-K workgroups at most (partial slots: 2 each)
 constexpr int64_t kStreamKMinChunks = 8;    // and at least this many K chunks per workgroup

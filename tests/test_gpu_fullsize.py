@@ -2,7 +2,7 @@
 (40, 400, 1200) and (30, 300, 900), on entries the oracle computes one by one
 (each from its own (ac|bd) slab), plus properties that hold at any size.
 
-Bounds: FP64 1e-12 of the largest sampled |R|. FP32 and BF16x3 accumulate over
+Bounds: FP64 1e-12 of the largest sampled |R|. FP32, BF16x3 and BF16x6 accumulate over
 K = v(v+1)/2 = 80200 terms in FP32 (unit roundoff 6e-8; a random-walk growth of
 sqrt(K) ~ 283 gives ~2e-5), so they are held to 1e-4 of the largest |R|, which
 still fails any wrong index or dropped term by orders of magnitude.
@@ -49,7 +49,7 @@ def c3():
     return s, t, idx, ref
 
 
-@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 1e-4), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 1e-4), ("bf16x3", 1e-4), ("bf16x6", 1e-4)])
 def test_c3_sampled_entries(P, c3, prec, bound):
     s, t, idx, ref = c3
     o, v, naux = s["o"], s["v"], s["naux"]

@@ -37,7 +37,7 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 def test_single_evaluation_error_matches_emulation(P, prec):
     o, v, naux = 6, 36, 108
     say(f"{prec} single R vs emulation ({o},{v},{naux})")
@@ -56,7 +56,7 @@ def test_single_evaluation_error_matches_emulation(P, prec):
     assert e_gpu > 0.2 * e_emu
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "bf16x6"])
 def test_mixed_iteration_reaches_fp64_fixed_point(P, prec):
     o, v, naux = 10, 100, 300
     say(f"mixed {prec} -> fp64 iteration to 1e-7 ({o},{v},{naux}) contractive")

@@ -93,7 +93,7 @@ def test_alpha_beta_accumulate(P):
     assert rel(R, ref) < 1e-12
 
 
-@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
 @pytest.mark.parametrize("tile", range(11))
 def test_every_contraction_tile_and_split(P, tile, prec, bound):
     say(f"contract {prec} tile {tile} splits 1..8 and stream-K (7,37,130)")
@@ -134,7 +134,7 @@ def test_streaming_batches_match_resident(P):
     assert rel(R_res, O.ppl(s["L"], 6, t)) < 1e-12
 
 
-@pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
 def test_streaming_full_rows_low_precision(P, prec, bound):
     say(f"contract {prec} streaming (full rows) vs resident (6,60,50)")
     s = S.make_system(6, 60, 50, 42)
@@ -176,7 +176,7 @@ def test_streaming_batches_stream_k(P):
     assert np.array_equal(R_res, R_again)
 
 
-@pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
 def test_contract_low_precision(P, prec, bound):
     say(f"contract {prec} (8,60,180)")
     s = S.make_system(8, 60, 180, 50)
@@ -248,7 +248,7 @@ def test_c2_sampled_entries(P):
     assert rel(R, R.transpose(1, 0, 3, 2)) < 1e-14
 
 
-@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)])
 @pytest.mark.parametrize("o,v,naux,scratch", [(7, 37, 130, 0), (5, 70, 45, 1 << 20), (3, 130, 33, 3 << 20)])
 def test_upper_triangle_build_matches_full_rows(P, monkeypatch, prec, bound, o, v, naux, scratch):
     """Resident plans build the upper triangle of V+- and mirror it (one or several build

@@ -164,6 +164,11 @@ def test_mixed_precision_keeps_both_copies(P):
     assert mix["vpm_bytes"] == f64["vpm_bytes"] + lp["vpm_bytes"]
     assert lp["vpm_bytes"] * 2 == f64["vpm_bytes"]      # hi + lo bf16 planes = 4 bytes per element
     assert mix["workspace_bytes"] < 280 << 30 and mix["resident"] == 1
+    x6 = plan_info(P, 40, 400, 1200, prec="bf16x6", keep_fp64=False, hbm_budget=280 << 30)
+    x6mix = plan_info(P, 40, 400, 1200, prec="bf16x6", keep_fp64=True, hbm_budget=280 << 30)
+    assert x6["vpm_bytes"] * 4 == f64["vpm_bytes"] * 3     # hi, mid and lo bf16 planes: 6 bytes
+    assert x6mix["vpm_bytes"] == f64["vpm_bytes"] + x6["vpm_bytes"]
+    assert x6mix["resident"] == 1 and x6mix["workspace_bytes"] < 280 << 30
 
 
 @pytest.mark.parametrize("args,code", [
