@@ -91,7 +91,7 @@ def test_diis_converges_where_jacobi_diverges(P):
     assert rel(t, O.fixed_point(s["L"], o, s["e_occ"], s["e_vir"])) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "bf16x6"])
 def test_mixed_diis_reaches_fp64_fixed_point_in_fewer_sweeps(P, prec):
     o, v, naux = 10, 100, 300
     say(f"mixed {prec} -> fp64 with diis 8 to 1e-7 ({o},{v},{naux}) contractive")
