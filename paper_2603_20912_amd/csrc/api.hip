@@ -1277,6 +1277,8 @@ int autotune_impl(ppl_plan_t p, int32_t reps, double* best_ms) {
     for (int t = 0; t < nt && rc == PPL_OK; ++t)
       for (int k = 1; k <= kMaxSplits + 1 && rc == PPL_OK; ++k) {
         const int sp = k <= kMaxSplits ? k : 0;
+        // BF16x6 keeps its K slices short (accuracy); stream-K ranges are not bounded
+        if (s.prec == PPL_BF16X6 && (sp == 0 || sp < contract_min_splits(s.prec, ld))) continue;
         if (sp > 1 && contract_jobs(t, s.prec, Nr, Pr, ld, sp) == contract_jobs(t, s.prec, Nr, Pr, ld, sp - 1))
           continue;   // same effective split count as a smaller request
         double ms = 0.0;

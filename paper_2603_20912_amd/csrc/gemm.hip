@@ -1512,6 +1512,18 @@ static const double kTileEff[4][11] = {
     /* BF16x6 */ {0.73, 0.76, 0.59, 0.48, 0.65, 0.71, 0.59, 0.68, 0.75, 1.00, 0.71}};
 static_assert(sizeof(kTileEff[0]) / sizeof(double) == kNumContract, "one efficiency per tile");
 
+// BF16x6 products carry FP32's 24 bits, so its error is set by the length of each FP32
+// accumulation: a K slice spans at most kBf6SliceK elements. Measured at (40,400,1200)
+// (K = 80256, HIP path against FP64): one R lies 1.8e-6 from FP64 with one slice, then
+// 1.3e-6, 9.5e-7 and 7.0e-7 with 2, 4 and 8 (the error goes as the square root of the
+// slice length); 12288 gives 7 slices there, below 1e-6.
+constexpr int64_t kBf6SliceK = 12288;
+int contract_min_splits(int prec, int64_t Kpad) {
+  if (prec != PPL_BF16X6) return 1;
+  const int64_t sp = (Kpad + kBf6SliceK - 1) / kBf6SliceK;
+  return (int)(sp < 1 ? 1 : (sp > kMaxSplits ? kMaxSplits : sp));
+}
+
 // Model choice of (tile, splits): useful work over the work of the padded tiles,
 // times the fill of the last round of workgroups over 256 CUs, times the
 // measured relative throughput of the tile.
@@ -1525,7 +1537,8 @@ void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int m
     const TileCfg& c = kContract[t];
     const int64_t mp = (Nrows + c.bm() - 1) / c.bm() * c.bm(), np = (Prows + c.bn() - 1) / c.bn() * c.bn();
     const double pad = (double)Nrows * Prows / ((double)mp * np);
-    for (int sp = 1; sp <= max_splits; ++sp) {
+    const int sp_min = std::min(contract_min_splits(prec, Kpad), std::max(max_splits, 1));
+    for (int sp = sp_min; sp <= max_splits; ++sp) {
       const int64_t jobs = contract_jobs(t, prec, Nrows, Prows, Kpad, sp);
       const double rounds = (double)jobs / 256.0;
       const double fill = rounds / std::ceil(rounds);

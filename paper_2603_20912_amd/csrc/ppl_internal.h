@@ -183,6 +183,9 @@ int gemm_contract(hipStream_t s, int prec, int tile, int64_t Nrows, int64_t Prow
 // bytes of partial slots a stream-K contraction (splits == 0) with this tile needs at most
 uint64_t streamk_part_bytes(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad);
 int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int splits);
+// fewest K slices the planner and the autotuner use for a precision (more than one only
+// for BF16x6, whose accuracy is limited by the length of its FP32 accumulations)
+int contract_min_splits(int prec, int64_t Kpad);
 // *tile_out >= 0 on entry fixes the tile and only chooses the split count
 void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
                      int* splits_out);

@@ -157,3 +157,33 @@ def test_c3_hhl_and_tau_sampled(P, c3):
     eng.close()
     del L, td, H, Rt
     torch.cuda.empty_cache()
+
+
+def test_c3_bf16x6_single_evaluation_within_1e6(P, c3):
+    """BF16x6 in the planner's configuration (K slices of at most 12288 elements) gives
+    one R within 1e-6 of FP64 (relative Frobenius) at (40,400,1200); the FP64 result is
+    held to the oracle at the sampled entries."""
+    s, t, idx, ref = c3
+    o, v, naux = s["o"], s["v"], s["naux"]
+    say("contract bf16x6 vs fp64 (40,400,1200), whole tensor")
+    L = torch.from_numpy(s["L"]).cuda()
+    td = torch.from_numpy(t).cuda()
+    e64 = P.PPL(o, v, naux, contract_only=True)
+    e64.build(L)
+    R64 = e64.contract(td)
+    e64.close()
+    del e64
+    torch.cuda.empty_cache()
+    got = np.array([R64[k].item() for k in idx])
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    e6 = P.PPL(o, v, naux, prec="bf16x6", contract_only=True)
+    assert e6.info["splits_contract"] >= 7 and e6.info["splits_contract_minus"] >= 7
+    e6.build(L)
+    R6 = e6.contract(td)
+    torch.cuda.synchronize()
+    err = (torch.linalg.norm(R6 - R64) / torch.linalg.norm(R64)).item()
+    say(f"  |R_bf16x6 - R_fp64| / |R_fp64| = {err:.2e}")
+    assert err < 1e-6
+    e6.close()
+    del L, td, R64, R6
+    torch.cuda.empty_cache()

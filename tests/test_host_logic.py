@@ -157,6 +157,16 @@ def test_budget_too_small_is_nomem(P):
     assert e.value.code == -2
 
 
+def test_bf16x6_keeps_its_k_slices_short(P):
+    # BF16x6 accuracy is set by the length of its FP32 accumulations: the planner splits K
+    # into slices of at most 12288 elements (P+ = 80200 at v = 400: 7 slices; P- = 79800: 7)
+    for (o, v, naux), want in (((40, 400, 1200), 7), ((30, 300, 900), 4), ((10, 100, 300), 1)):
+        i = plan_info(P, o, v, naux, prec="bf16x6", hbm_budget=280 << 30)
+        assert i["splits_contract"] >= want and i["splits_contract_minus"] >= want
+        f = plan_info(P, o, v, naux, prec="fp32", hbm_budget=280 << 30)
+        assert f["splits_contract"] >= 1
+
+
 def test_mixed_precision_keeps_both_copies(P):
     f64 = plan_info(P, 40, 400, 1200, prec="fp64", hbm_budget=280 << 30)
     mix = plan_info(P, 40, 400, 1200, prec="bf16x3", keep_fp64=True, hbm_budget=280 << 30)
