@@ -86,8 +86,9 @@ def measured_traffic(config):
 def study_c3(args):
     """Time to an amplitude residual of 1e-7 at (40, 400, 1200), contractive generator
     seed 2: FP64, BF16x3 / BF16x6 / FP32 sweeps refined in FP64, and the same from the
-    learned start, each also with DIIS (subspace 8); plus single-evaluation errors of the
-    low-precision GEMMs."""
+    learned start, each also with DIIS (subspace 8); FP64 and BF16x3 + FP64 with DIIS for
+    the iteration that also carries the hole-hole ladder; plus single-evaluation errors of
+    the low-precision GEMMs."""
     import numpy as np
     import torch
 
@@ -107,6 +108,7 @@ def study_c3(args):
                               ("mp2", "bf16x6", True)):
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep)
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=8)
+    Lr.time_to_tol(small, "mp2", prec="bf16x3", keep_fp64=True, diis=8, hhl=True)
     if mlp is not None:
         Lr.time_to_tol(small, "learned", mlp=mlp, prec="bf16x3", keep_fp64=True)
     runs = [("fp64", "mp2", "fp64", False, 0), ("bf16x3+fp64", "mp2", "bf16x3", True, 0),
@@ -119,18 +121,23 @@ def study_c3(args):
     if mlp is not None:
         runs += [("bf16x3+fp64 learned diis", "learned", "bf16x3", True, 8),
                  ("fp64 learned diis", "learned", "fp64", False, 8)]
+    runs = [r + (False,) for r in runs]
+    # the linearized doubles iteration with the hole-hole ladder too (its own fixed point,
+    # compared with its own FP64 run)
+    runs += [("fp64 diis hhl", "mp2", "fp64", False, 8, True), ("bf16x3+fp64 diis hhl", "mp2", "bf16x3", True, 8, True)]
     out = {"config": {"o": o, "v": v, "naux": naux, "generator": "contractive", "seed": 2, "tol": 1e-7}}
-    ref_t, ref_E = None, None
-    for label, start, prec, keep, diis in runs:
+    refs = {}
+    for label, start, prec, keep, diis, hhl in runs:
         torch.cuda.empty_cache()
         free_gib = torch.cuda.mem_get_info()[0] / 2 ** 30
-        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep, diis=diis)
+        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep, diis=diis, hhl=hhl)
         row = {"seconds": round(rep["seconds"], 3), "sweeps_lp": rep["sweeps_lp"], "sweeps_fp64": rep["sweeps_fp64"],
                "residual": rep["residual"], "energy": rep["energy"], "status": rep["status"],
                "resident": rep["resident"], "free_GiB_before": round(free_gib, 1), "kernel_ms": rep["kernel_ms"]}
-        if ref_t is None:
-            ref_t, ref_E = t.clone(), rep["energy"]
+        if hhl not in refs:
+            refs[hhl] = (t.clone(), rep["energy"])
         else:
+            ref_t, ref_E = refs[hhl]
             row["rel_err_t_vs_fp64"] = (torch.linalg.norm(t - ref_t) / torch.linalg.norm(ref_t)).item()
             row["abs_err_E_vs_fp64"] = abs(rep["energy"] - ref_E)
         out[label] = row

@@ -64,12 +64,13 @@ def train(mlp: MLP, X, Y, steps=2000, batch=4096, lr=1e-3, seed=0, log_every=0):
 
 
 def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, max_sweeps=300,
-                device="cuda", switch_tol=0.0, diis=0):
+                device="cuda", switch_tol=0.0, diis=0, hhl=False):
     """Wall time and sweeps from inputs in HBM to a converged residual below tol.
 
     start: 'mp2' (plain), 'learned' (network guess, unchecked) or 'checked'
     (network guess, restarted from MP2 when its first residual is larger).
-    diis >= 2 accelerates the sweeps with a DIIS subspace of that size.
+    diis >= 2 accelerates the sweeps with a DIIS subspace of that size; hhl adds the
+    hole-hole ladder to every sweep (t = (V + PPL(t) + HHL(t)) / D).
     The timed region covers the first-order amplitudes, the network guess, the
     integral builds and every sweep.
     """
@@ -83,13 +84,13 @@ def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, m
     t0 = time.perf_counter()
     if start == "mp2":
         rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t, max_sweeps=max_sweeps, tol=tol, start="mp2",
-                          switch_tol=switch_tol, raise_on_status=False, diis=diis)
+                          switch_tol=switch_tol, raise_on_status=False, diis=diis, hhl=hhl)
     else:
         eng.mp2(d["L"], d["e_occ"], d["e_vir"], tm)
         mlp.guess(eng, tm, d["e_occ"], d["e_vir"], t2_out=t)
         rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t, max_sweeps=max_sweeps, tol=tol,
                           start="checked" if start == "checked" else "given", switch_tol=switch_tol,
-                          raise_on_status=False, diis=diis)
+                          raise_on_status=False, diis=diis, hhl=hhl)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rep = dict(rep)

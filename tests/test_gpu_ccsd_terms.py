@@ -35,7 +35,8 @@ def dev(x):
 
 
 @pytest.mark.parametrize("o,v,naux,prec,bound", [(7, 37, 130, "fp64", 1e-12), (3, 20, 17, "fp64", 1e-12),
-                                                 (7, 37, 130, "fp32", 2e-6), (7, 37, 130, "bf16x3", 4e-5)])
+                                                 (7, 37, 130, "fp32", 2e-6), (7, 37, 130, "bf16x3", 4e-5),
+                                                 (7, 37, 130, "bf16x6", 2e-6)])
 def test_contract_tau_matches_oracle(P, o, v, naux, prec, bound):
     say(f"contract_tau {prec} ({o},{v},{naux})")
     s = S.make_system(o, v, naux, 21)

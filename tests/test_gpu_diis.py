@@ -139,7 +139,7 @@ def test_diis_with_hhl_matches_oracle(P):
     assert rel(t, O.fixed_point_hhl(s["L"], o, s["e_occ"], s["e_vir"])) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "bf16x6"])
 def test_mixed_iteration_with_hhl(P, prec):
     o, v, naux = 10, 100, 300
     say(f"mixed {prec} -> fp64 with the hole-hole ladder and diis 8 to 1e-7 ({o},{v},{naux})")
