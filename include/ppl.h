@@ -300,6 +300,9 @@ int ppl_mlp_destroy(ppl_mlp_t mlp);
  * per workgroup the device holds at once; tiles shared by several workgroups are
  * summed afterwards in workgroup order). Split-K slices are summed in slice order,
  * so a fixed configuration on a given device gives bitwise reproducible results.
+ * The planner (and ppl_autotune) give PPL_BF16X6 plans K slices of at most 12288
+ * elements, because its error grows with the length of each FP32 accumulation; a
+ * configuration set here with fewer slices, or stream-K, runs but is less accurate.
  * PPL_E_ARG for out-of-range values.
  */
 int ppl_set_contract_config(ppl_plan_t plan, int32_t tile_plus, int32_t splits_plus,

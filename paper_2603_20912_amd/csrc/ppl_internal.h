@@ -173,6 +173,8 @@ int gemm_store_f64(hipStream_t s, int64_t M, int64_t N, int64_t Kpad, const doub
 
 // Contraction C[N][P] = sum_k S[n][k] V[p][k] for one operand set (R+ or R-).
 // Output in the accumulator precision (double for FP64, float otherwise).
+// S_lo / V_lo (and Xt_lo of the builds) point at the second bf16 plane: lo for BF16x3,
+// mid for BF16x6, whose lo plane lies one plane further on (mid + (mid - hi)).
 // splits > 1 splits K into that many slices written to `partial` ([splits][Nrows][partial_ld],
 // accumulator type) and summed in slice order into C. accumulate: C += the product (one
 // K slice only; PPL_E_ARG with split-K or stream-K).
