@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
-    "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
+    "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "ring", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
     "jacobi", "jacobi_diis", "fixed_point", "fixed_point_hhl", "spectral_radius", "nominal_flops",
 ]
 
@@ -170,6 +170,25 @@ def hhl(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
     v = t.shape[2]
     M = W.transpose(1, 3, 0, 2).reshape(o * o, o * o)  # [(i,j)][(k,l)]
     return (M @ t.reshape(o * o, v * v)).reshape(o, o, v, v)
+
+
+def ring(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
+    """Ring (particle-hole) terms of the closed-shell linearized doubles residual,
+    R_ij^ab = Y_ij^ab + Y_ji^ba with
+        Y_ij^ab = sum_kc [ (2 t_ik^ac - t_ik^ca) (kc|jb) - t_ik^ac (kj|bc) - t_ik^cb (kj|ac) ],
+    the closed-shell (alpha-beta) block of the spin-orbital term
+    P(ij) P(ab) sum_kc <kb||cj> t_ik^ac (checked against that definition in the pins)."""
+    L = np.asarray(L, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    Lov = L[:, :o, o:]
+    Loo = L[:, :o, :o]
+    Lvv = L[:, o:, o:]
+    J = np.einsum("Pkc,Pjb->kcjb", Lov, Lov)          # (kc|jb)
+    K = np.einsum("Pkj,Pbc->kjbc", Loo, Lvv)          # (kj|bc)
+    Y = (np.einsum("ikac,kcjb->ijab", 2.0 * t - t.transpose(0, 1, 3, 2), J)
+         - np.einsum("ikac,kjbc->ijab", t, K)
+         - np.einsum("ikcb,kjac->ijab", t, K))
+    return Y + Y.transpose(1, 0, 3, 2)
 
 
 # ---------------------------------------------------------------------------

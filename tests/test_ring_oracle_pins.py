@@ -1,0 +1,105 @@
+"""Pins of the closed-shell terms next to the ladder against the spin-orbital
+linearized doubles equations. From closed-shell amplitudes t_ij^ab the spin-orbital
+amplitudes are
+    t_{I J}^{A B} = d(sI,sA) d(sJ,sB) t_ij^ab - d(sI,sB) d(sJ,sA) t_ij^ba
+(s = spin, lower case = spatial index), and the antisymmetrized integrals are
+<pq||rs> = (pr|qs) d(sp,sr) d(sq,ss) - (ps|qr) d(sp,ss) d(sq,sr). The textbook
+spin-orbital terms
+    ladder  1/2 sum_cd <ab||cd> t_ij^cd
+    hole    1/2 sum_kl <kl||ij> t_kl^ab
+    ring    P(ij) P(ab) sum_kc <kb||cj> t_ik^ac
+must then have alpha-beta blocks equal to the closed-shell oracle functions ppl, hhl
+and ring, and alpha-alpha blocks equal to R_ij^ab - R_ij^ba of the same functions.
+This checks the spin adaptation of all three terms with no formula in common."""
+import numpy as np
+import pytest
+
+import oracle as O
+import ppl_synth as S
+
+
+def spin_orbital_terms(L, o, t):
+    n = L.shape[1]
+    v = n - o
+    eri = np.einsum("Ppq,Prs->pqrs", L, L)                       # (pq|rs)
+    sp = np.repeat(np.arange(n), 2)                               # spatial index of spin orbital
+    sg = np.tile([0, 1], n)                                       # spin of spin orbital
+    same = (sg[:, None] == sg[None, :]).astype(float)
+    # <pq|rs> = (pr|qs) d(sp,sr) d(sq,ss)
+    g = eri[np.ix_(sp, sp, sp, sp)].transpose(0, 2, 1, 3) * same[:, None, :, None] * same[None, :, None, :]
+    gA = g - g.transpose(0, 1, 3, 2)
+    O2, V2 = slice(0, 2 * o), slice(2 * o, 2 * n)
+    so, sv = sg[:2 * o], sg[2 * o:]
+    io, iv = sp[:2 * o], sp[2 * o:] - o
+    dIA = (so[:, None] == sv[None, :]).astype(float)              # d(sI, sA)
+    tt = t[np.ix_(io, io, iv, iv)]                                # t_ij^ab over spin orbitals
+    ts = t.transpose(0, 1, 3, 2)[np.ix_(io, io, iv, iv)]          # t_ij^ba
+    t_so = dIA[:, None, :, None] * dIA[None, :, None, :] * tt - dIA[:, None, None, :] * dIA[None, :, :, None] * ts
+    ladder = 0.5 * np.einsum("abcd,ijcd->ijab", gA[V2, V2, V2, V2], t_so)
+    hole = 0.5 * np.einsum("klij,klab->ijab", gA[O2, O2, O2, O2], t_so)
+    X = np.einsum("kbcj,ikac->ijab", gA[O2, V2, V2, O2], t_so)
+    ring = X - X.transpose(1, 0, 2, 3) - X.transpose(0, 1, 3, 2) + X.transpose(1, 0, 3, 2)
+    return t_so, {"ppl": ladder, "hhl": hole, "ring": ring}
+
+
+def blocks(R_so):
+    ab = R_so[0::2, 1::2, 0::2, 1::2]        # i alpha, j beta, a alpha, b beta
+    aa = R_so[0::2, 0::2, 0::2, 0::2]        # all alpha
+    return ab, aa
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(2, 3, 2, 0), (3, 4, 5, 1), (2, 5, 3, 2)])
+def test_closed_shell_terms_are_the_spin_orbital_ones(o, v, naux, seed):
+    s = S.make_system(o, v, naux, seed)
+    t = S.make_amplitudes(o, v, seed + 10)
+    t_so, terms = spin_orbital_terms(s["L"], o, t)
+    # the spin-orbital amplitudes are antisymmetric (t is pair symmetric)
+    assert np.allclose(t_so, -t_so.transpose(1, 0, 2, 3), atol=1e-14)
+    assert np.allclose(t_so, -t_so.transpose(0, 1, 3, 2), atol=1e-14)
+    for name, fn in (("ppl", O.ppl), ("hhl", O.hhl), ("ring", O.ring)):
+        R = fn(s["L"], o, t)
+        ab, aa = blocks(terms[name])
+        scale = np.abs(R).max()
+        assert np.abs(ab - R).max() < 1e-12 * scale, name
+        assert np.abs(aa - (R - R.transpose(0, 1, 3, 2))).max() < 1e-12 * scale, name
+
+
+def test_ring_is_pair_symmetric_and_linear():
+    s = S.make_system(3, 6, 7, 3)
+    t1 = S.make_amplitudes(3, 6, 4)
+    t2 = S.make_amplitudes(3, 6, 5)
+    R1, R2 = O.ring(s["L"], 3, t1), O.ring(s["L"], 3, t2)
+    assert np.abs(R1 - R1.transpose(1, 0, 3, 2)).max() < 1e-14 * np.abs(R1).max()
+    R12 = O.ring(s["L"], 3, 0.7 * t1 - 1.3 * t2)
+    assert np.abs(R12 - (0.7 * R1 - 1.3 * R2)).max() < 1e-13 * np.abs(R12).max()
+    # R(gamma L) = gamma^2 R(L): every integral is quadratic in L
+    assert np.abs(O.ring(2.0 * s["L"], 3, t1) - 4.0 * R1).max() < 1e-13 * np.abs(R1).max()
+
+
+def _ring_mutant(kind):
+    def f(L, o, t):
+        Lov, Loo, Lvv = L[:, :o, o:], L[:, :o, :o], L[:, o:, o:]
+        J = np.einsum("Pkc,Pjb->kcjb", Lov, Lov)
+        K = np.einsum("Pkj,Pbc->kjbc", Loo, Lvv)
+        two = 1.0 if kind == "factor" else 2.0
+        Y = np.einsum("ikac,kcjb->ijab", two * t - t.transpose(0, 1, 3, 2), J)
+        Y -= np.einsum("ikac,kjbc->ijab", t, K)
+        if kind != "dropped":
+            Y -= np.einsum("ikcb,kjac->ijab", t, K) * (-1.0 if kind == "sign" else 1.0)
+        if kind == "index":
+            Y = (np.einsum("ikac,kcjb->ijab", 2.0 * t - t.transpose(0, 1, 3, 2), J.transpose(0, 3, 2, 1))
+                 - np.einsum("ikac,kjbc->ijab", t, K) - np.einsum("ikcb,kjac->ijab", t, K))
+        return Y + Y.transpose(1, 0, 3, 2)
+    return f
+
+
+@pytest.mark.parametrize("kind", ["factor", "dropped", "sign", "index"])
+def test_planted_ring_mistakes_are_caught(kind):
+    o, v = 2, 4
+    s = S.make_system(o, v, 3, 6)
+    t = S.make_amplitudes(o, v, 7)
+    _, terms = spin_orbital_terms(s["L"], o, t)
+    ab, _ = blocks(terms["ring"])
+    assert np.abs(O.ring(s["L"], o, t) - ab).max() < 1e-12 * np.abs(ab).max()
+    R = _ring_mutant(kind)(s["L"], o, t)
+    assert np.abs(R - ab).max() > 1e-6 * np.abs(ab).max()
