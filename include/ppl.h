@@ -180,6 +180,25 @@ int ppl_contract_tau(ppl_plan_t plan, const double* t2, const double* t1, double
  */
 int ppl_hhl(ppl_plan_t plan, const double* L, const double* t2, double* R, double alpha, double beta);
 
+/*
+ * ppl_ring: the ring (particle-hole) terms of the closed-shell linearized doubles
+ * residual, R = beta * R + alpha * RING(t2) with RING_ij^ab = Y_ij^ab + Y_ji^ba and
+ *   Y_ij^ab = sum_kc [ (2 t_ik^ac - t_ik^ca) (kc|jb) - t_ik^ac (kj|bc) - t_ik^cb (kj|ac) ],
+ * the standard closed-shell CCD terms next to the ladder (the paper batches them with
+ * its generic engine; integrals from the same Cholesky vectors, eq. (cholesky)). Three
+ * FP64 MFMA GEMMs of (o v) x (o v) x (o v) over pair matrices: (2A - B) J + (-A) K and
+ * B K with A[(i,a)][(k,c)] = t_ik^ac, B[(i,a)][(k,c)] = t_ik^ca, J[(k,c)][(j,b)] = (kc|jb),
+ * K[(k,c)][(j,b)] = (kj|bc) (both symmetric), 2 (o v)^3 flops each. Needs no plan: L
+ * device FP64 [naux][o+v][o+v], t2 and R device FP64 [o][o][v][v] (t2 pair-symmetric, R
+ * not aliasing t2), `scratch` device memory of at least ppl_ring_scratch_bytes(o, v,
+ * naux) bytes (256-byte aligned, caller-owned, its contents overwritten), `stream` a
+ * hipStream_t (NULL = default). Asynchronous. PPL_E_ARG for bad sizes, null or aliased
+ * pointers, misalignment or too small a scratch.
+ */
+uint64_t ppl_ring_scratch_bytes(int32_t o, int32_t v, int32_t naux);
+int ppl_ring(int32_t o, int32_t v, int32_t naux, const double* L, const double* t2, double* R, double alpha,
+             double beta, void* scratch, uint64_t scratch_bytes, void* stream);
+
 /* ------------------------------------------------ linearized doubles iteration */
 #define PPL_START_MP2   0  /* start from t = V / D */
 #define PPL_START_GIVEN 1  /* start from the t2 passed in */

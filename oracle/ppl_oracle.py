@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
-    "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "ring", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
+    "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "ring", "ring_entry", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
     "jacobi", "jacobi_diis", "fixed_point", "fixed_point_hhl", "spectral_radius", "nominal_flops",
 ]
 
@@ -189,6 +189,23 @@ def ring(L: np.ndarray, o: int, t: np.ndarray) -> np.ndarray:
          - np.einsum("ikac,kjbc->ijab", t, K)
          - np.einsum("ikcb,kjac->ijab", t, K))
     return Y + Y.transpose(1, 0, 3, 2)
+
+
+def ring_entry(L: np.ndarray, o: int, t: np.ndarray, i: int, j: int, a: int, b: int) -> float:
+    """One element R_ij^ab of ring(), from the slices of L it needs (for large sizes)."""
+    L = np.asarray(L, dtype=np.float64)
+    Lov, Loo, Lvv = L[:, :o, o:], L[:, :o, :o], L[:, o:, o:]
+
+    def Y(i, j, a, b):
+        Jb = np.einsum("Pkc,P->kc", Lov, Lov[:, j, b])          # (kc|jb) over k, c
+        Kb = np.einsum("Pk,Pc->kc", Loo[:, :, j], Lvv[:, b, :])  # (kj|bc)
+        Ka = np.einsum("Pk,Pc->kc", Loo[:, :, j], Lvv[:, a, :])  # (kj|ac)
+        tia = t[i, :, a, :]                                      # t_ik^ac over k, c
+        tic = t[i, :, :, a]                                      # t_ik^ca
+        tib = t[i, :, :, b]                                      # t_ik^cb
+        return float(np.sum((2.0 * tia - tic) * Jb) - np.sum(tia * Kb) - np.sum(tib * Ka))
+
+    return Y(i, j, a, b) + Y(j, i, b, a)
 
 
 # ---------------------------------------------------------------------------

@@ -18,13 +18,15 @@ from ._lib import (ppl_mp2, ppl_mlp_create, ppl_mlp_workspace_bytes, ppl_mlp_bin
                    ppl_mlp_param_count, ppl_mlp_init, ppl_mlp_set_params, ppl_mlp_get_params, ppl_mlp_grad,
                    ppl_mlp_train_step, ppl_mlp_sigma, ppl_mlp_samples, ppl_mlp_guess, ppl_mlp_destroy,
                    PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_contract_tau, ppl_hhl,
+                   ppl_ring, ppl_ring_scratch_bytes,
                    ppl_destroy,
                    ppl_iter_opts_default, ppl_iterate, ppl_last_error, ppl_plan, ppl_plan_query,
                    ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_tile_dims, ppl_version,
                    ppl_set_contract_config, ppl_autotune)
 
 __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace", "ppl_build_batch",
-           "ppl_contract", "ppl_contract_tau", "ppl_hhl", "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count", "ppl_tile_dims",
+           "ppl_contract", "ppl_contract_tau", "ppl_hhl", "ppl_ring", "ppl_ring_scratch_bytes", "ring",
+           "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count", "ppl_tile_dims",
            "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read",
            "ppl_set_contract_config", "ppl_autotune", "ppl_mp2", "MLP", "ppl_mlp_create",
            "ppl_mlp_workspace_bytes", "ppl_mlp_bind_workspace", "ppl_mlp_param_count", "ppl_mlp_init",
@@ -141,6 +143,21 @@ class PPL:
             self.close()
         except Exception:
             pass
+
+
+def ring(L, t2, R=None, alpha=1.0, beta=0.0, stream=None, scratch=None):
+    """R = beta R + alpha * (ring terms of the closed-shell doubles residual) on the GPU:
+    Y_ij^ab + Y_ji^ba with Y_ij^ab = sum_kc [(2 t_ik^ac - t_ik^ca)(kc|jb) - t_ik^ac (kj|bc)
+    - t_ik^cb (kj|ac)]. L is [naux][o+v][o+v], t2 and R [o][o][v][v], all FP64 on the
+    device; the scratch (ppl_ring_scratch_bytes) is allocated here unless given."""
+    o, v = t2.shape[0], t2.shape[2]
+    naux = L.shape[0]
+    if R is None:
+        R = torch.empty_like(t2)
+    if scratch is None:
+        scratch = torch.empty(ppl_ring_scratch_bytes(o, v, naux), dtype=torch.uint8, device=t2.device)
+    ppl_ring(o, v, naux, L, t2, R, scratch, alpha, beta, stream)
+    return R
 
 
 class MLP:

@@ -87,6 +87,9 @@ SIGNATURES = {
     "ppl_contract": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "ppl_contract_tau": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "ppl_hhl": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
+    "ppl_ring_scratch_bytes": (ctypes.c_uint64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ppl_ring": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_double,
+                                ctypes.c_double, _P, ctypes.c_uint64, _P]),
     "ppl_iter_opts_default": (None, [ctypes.POINTER(ppl_iter_opts_t)]),
     "ppl_iterate": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ppl_iter_opts_t),
                                    ctypes.POINTER(ppl_iter_report_t)]),
@@ -212,6 +215,16 @@ def ppl_contract(plan, t2, R, alpha=1.0, beta=0.0):
 def ppl_contract_tau(plan, t2, t1, R, alpha=1.0, beta=0.0):
     _check(load().ppl_contract_tau(plan, _ptr(t2), _ptr(t1), _ptr(R), float(alpha), float(beta)),
            "ppl_contract_tau")
+
+
+def ppl_ring_scratch_bytes(o, v, naux):
+    return int(load().ppl_ring_scratch_bytes(int(o), int(v), int(naux)))
+
+
+def ppl_ring(o, v, naux, L, t2, R, scratch, alpha=1.0, beta=0.0, stream=None):
+    _check(load().ppl_ring(int(o), int(v), int(naux), _ptr(L), _ptr(t2), _ptr(R), float(alpha), float(beta),
+                           _ptr(scratch), int(scratch.numel() * scratch.element_size()), _stream_handle(stream)),
+           "ppl_ring")
 
 
 def ppl_hhl(plan, L, t2, R, alpha=1.0, beta=0.0):

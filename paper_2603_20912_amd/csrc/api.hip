@@ -1002,6 +1002,81 @@ int ppl_hhl(ppl_plan_t p, const double* L, const double* t2, double* R, double a
   return unpack_r(st, PPL_FP64, p->o, p->v, s64, p->ldp, a64, p->ldm, R, alpha, beta);
 }
 
+// Scratch of the ring terms: staged Cholesky blocks (ov, oo, vv rows of P), the (kj|bc)
+// product, and seven (o v) x (o v) pair matrices.
+struct RingLayout {
+  int64_t ldx = 0, ldk = 0, ldg = 0;
+  uint64_t xov = 0, xoo = 0, xvv = 0, g = 0, j = 0, k = 0, xa = 0, an = 0, b = 0, c1 = 0, c2 = 0, bytes = 0;
+};
+
+static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r) {
+  if (o < 1 || v < 1 || naux < 1 || o > 32767 || v > 32767) return false;
+  r.ldx = pad_ld(naux);
+  r.ldk = pad_ld(o * v);
+  r.ldg = pad_ld(v * v);
+  uint64_t x;
+  if (!mul_ok((uint64_t)(o * v), (uint64_t)r.ldk, &x) || !mul_ok(x, 16, &x)) return false;
+  if (!mul_ok((uint64_t)(v * v), (uint64_t)r.ldx, &x) || !mul_ok(x, 16, &x)) return false;
+  Layout L;
+  r.xov = L.take((uint64_t)o * v * r.ldx * 8).off;
+  r.xoo = L.take((uint64_t)o * o * r.ldx * 8).off;
+  r.xvv = L.take((uint64_t)v * v * r.ldx * 8).off;
+  r.g = L.take((uint64_t)o * o * r.ldg * 8).off;
+  const uint64_t m = (uint64_t)o * v * r.ldk * 8;
+  r.j = L.take(m).off;
+  r.k = L.take(m).off;
+  r.xa = L.take(m).off;
+  r.an = L.take(m).off;
+  r.b = L.take(m).off;
+  r.c1 = L.take(m).off;
+  r.c2 = L.take(m).off;
+  r.bytes = L.cur;
+  return true;
+}
+
+uint64_t ppl_ring_scratch_bytes(int32_t o, int32_t v, int32_t naux) {
+  RingLayout r;
+  return ring_layout(o, v, naux, r) ? r.bytes : 0;
+}
+
+int ppl_ring(int32_t o, int32_t v, int32_t naux, const double* L, const double* t2, double* R, double alpha,
+             double beta, void* scratch, uint64_t scratch_bytes, void* stream) {
+  g_err[0] = 0;
+  RingLayout r;
+  if (!ring_layout(o, v, naux, r)) return fail(PPL_E_ARG, "bad sizes o=%d v=%d naux=%d", o, v, naux);
+  if (!L || !t2 || !R || !scratch) return fail(PPL_E_ARG, "null device pointer");
+  if ((const void*)t2 == (const void*)R) return fail(PPL_E_ARG, "R may not alias t2");
+  if ((uintptr_t)scratch % 256 != 0) return fail(PPL_E_ARG, "scratch must be 256-byte aligned");
+  if (scratch_bytes < r.bytes)
+    return fail(PPL_E_ARG, "ring scratch holds %llu B, needs %llu B", (unsigned long long)scratch_bytes,
+                (unsigned long long)r.bytes);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)scratch;
+  auto d = [&](uint64_t off) { return (double*)(w + off); };
+  const int64_t ov = (int64_t)o * v;
+  // the K-dimension padding of J and K must read as zero (their GEMMs write n < o v only)
+  PPL_TRY(zero_bytes(st, w + r.j, 2 * (uint64_t)ov * r.ldk * 8));
+  PPL_TRY(stage_ov(st, L, o, v, naux, r.ldx, d(r.xov)));
+  PPL_TRY(stage_oo(st, L, o, v, naux, r.ldx, d(r.xoo)));
+  PPL_TRY(stage_vv(st, PPL_FP64, L, o, v, naux, r.ldx, d(r.xvv), nullptr));
+  // J[(k,c)][(j,b)] = sum_P L^P_kc L^P_jb;  G[(k,j)][(b,c)] = sum_P L^P_kj L^P_bc -> K
+  PPL_TRY(gemm_store_f64(st, ov, ov, r.ldx, d(r.xov), r.ldx, d(r.xov), r.ldx, d(r.j), r.ldk));
+  PPL_TRY(gemm_store_f64(st, (int64_t)o * o, (int64_t)v * v, r.ldx, d(r.xoo), r.ldx, d(r.xvv), r.ldx, d(r.g),
+                         r.ldg));
+  PPL_TRY(ring_exchange(st, o, v, d(r.g), r.ldg, d(r.k), r.ldk));
+  PPL_TRY(ring_pack(st, o, v, t2, r.ldk, d(r.xa), d(r.an), d(r.b)));
+  // C1 = Xa J^T + An K^T, C2 = B K^T (J and K are symmetric: their rows are their columns)
+  int tile = -1, sp = 1;
+  contract_choose(PPL_FP64, ov, ov, r.ldk, 1, &tile, &sp);
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.xa), nullptr, r.ldk, d(r.j), nullptr, r.ldk,
+                        d(r.c1), r.ldk, 0, 1, nullptr, 0, 0, false));
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.an), nullptr, r.ldk, d(r.k), nullptr, r.ldk,
+                        d(r.c1), r.ldk, 0, 1, nullptr, 0, 0, true));
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.b), nullptr, r.ldk, d(r.k), nullptr, r.ldk,
+                        d(r.c2), r.ldk, 0, 1, nullptr, 0, 0, false));
+  return ring_unpack(st, o, v, d(r.c1), d(r.c2), r.ldk, R, alpha, beta);
+}
+
 int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,
                 const ppl_iter_opts_t* opts, ppl_iter_report_t* rep) {
   g_err[0] = 0;

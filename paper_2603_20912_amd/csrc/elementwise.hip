@@ -1010,4 +1010,89 @@ int count_nonfinite(hipStream_t s, const double* x, int64_t n, double* partials,
   return PPL_OK;
 }
 
+
+// ------------------------------------------------------------------ ring terms
+// Operands of the ring terms as (o v) x (o v) matrices over the pairs (i,a) and (k,c),
+// rows of ld elements (columns from o v on zero):
+//   Xa[(i,a)][(k,c)] = 2 t_ik^ac - t_ik^ca,  An[(i,a)][(k,c)] = -t_ik^ac,  B[(i,a)][(k,c)] = t_ik^ca.
+__global__ void __launch_bounds__(256)
+ring_pack_kernel(int o, int v, const double* __restrict__ t, int64_t ld, double* Xa, double* An, double* B) {
+  const int64_t ov = (int64_t)o * v, total = ov * ld;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int64_t row = x / ld, col = x - row * ld;
+    double xa = 0.0, an = 0.0, b = 0.0;
+    if (col < ov) {
+      const int64_t i = row / v, a = row - i * v, k = col / v, c = col - k * v;
+      const int64_t base = (i * o + k) * v * v;
+      const double tac = t[base + a * v + c], tca = t[base + c * v + a];
+      xa = 2.0 * tac - tca;
+      an = -tac;
+      b = tca;
+    }
+    Xa[x] = xa;
+    An[x] = an;
+    B[x] = b;
+  }
+}
+
+int ring_pack(hipStream_t s, int o, int v, const double* t, int64_t ld, double* Xa, double* An, double* B) {
+  const int64_t n = (int64_t)o * v * ld;
+  if (n <= 0) return PPL_OK;
+  hipLaunchKernelGGL(ring_pack_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, t, ld, Xa, An, B);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// K[(k,c)][(j,b)] = (kj|bc) = G[(k,j)][(b,c)] (G rows of ldg elements); columns from o v on zero
+__global__ void __launch_bounds__(256)
+ring_exchange_kernel(int o, int v, const double* __restrict__ G, int64_t ldg, double* K, int64_t ld) {
+  const int64_t ov = (int64_t)o * v, total = ov * ld;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const int64_t row = x / ld, col = x - row * ld;
+    double y = 0.0;
+    if (col < ov) {
+      const int64_t k = row / v, c = row - k * v, j = col / v, b = col - j * v;
+      y = G[(k * o + j) * ldg + b * v + c];
+    }
+    K[x] = y;
+  }
+}
+
+int ring_exchange(hipStream_t s, int o, int v, const double* G, int64_t ldg, double* K, int64_t ld) {
+  const int64_t n = (int64_t)o * v * ld;
+  if (n <= 0) return PPL_OK;
+  hipLaunchKernelGGL(ring_exchange_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, G, ldg, K, ld);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// R_ij^ab = beta R_ij^ab + alpha (Y_ij^ab + Y_ji^ba) with Y_ij^ab = C1[(i,a)][(j,b)] - C2[(i,b)][(j,a)]
+__global__ void __launch_bounds__(256)
+ring_unpack_kernel(int o, int v, const double* __restrict__ C1, const double* __restrict__ C2, int64_t ld, double* R,
+                   double alpha, double beta) {
+  const int64_t total = (int64_t)o * o * v * v;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    int64_t r = x;
+    const int64_t b = r % v; r /= v;
+    const int64_t a = r % v; r /= v;
+    const int64_t j = r % o, i = r / o;
+    const double y1 = C1[(i * v + a) * ld + j * v + b] - C2[(i * v + b) * ld + j * v + a];
+    const double y2 = C1[(j * v + b) * ld + i * v + a] - C2[(j * v + a) * ld + i * v + b];
+    const double y = alpha * (y1 + y2);
+    R[x] = beta == 0.0 ? y : beta * R[x] + y;
+  }
+}
+
+int ring_unpack(hipStream_t s, int o, int v, const double* C1, const double* C2, int64_t ld, double* R, double alpha,
+                double beta) {
+  const int64_t n = (int64_t)o * o * v * v;
+  if (n <= 0) return PPL_OK;
+  hipLaunchKernelGGL(ring_unpack_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, C1, C2, ld, R, alpha, beta);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
 }  // namespace ppl

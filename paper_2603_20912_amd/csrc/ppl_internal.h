@@ -326,6 +326,11 @@ int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va,
                 const int* tab_vp, const int* tab_vm, double* partials, double* red_out);
 // zero a device range (a fill kernel, never hipMemsetAsync)
 int zero_bytes(hipStream_t s, void* p, uint64_t bytes);
+// ring terms: (o v) x (o v) operands over the pairs (i,a), (k,c) (rows of ld elements)
+int ring_pack(hipStream_t s, int o, int v, const double* t, int64_t ld, double* Xa, double* An, double* B);
+int ring_exchange(hipStream_t s, int o, int v, const double* G, int64_t ldg, double* K, int64_t ld);
+int ring_unpack(hipStream_t s, int o, int v, const double* C1, const double* C2, int64_t ld, double* R, double alpha,
+                double beta);
 // red_out[0] = sum (L^P_ac - L^P_ca)^2, red_out[1] = sum (L^P_ac)^2 + (L^P_ca)^2 over a < c (virtual block)
 int asymmetry_vv(hipStream_t s, const double* L, int o, int v, int naux, double* partials, double* red_out);
 // count non-finite values of an FP64 array (red_out[2])

@@ -99,3 +99,54 @@ def test_hhl_in_chunks_of_virtual_pairs(P):
     R = eng.hhl(L, dev(t2)).cpu().numpy()
     eng.close()
     assert rel(R, O.hhl(s["L"], o, t2)) < 1e-12
+
+
+@pytest.mark.parametrize("o,v,naux", [(7, 37, 130), (3, 20, 17), (1, 5, 3), (9, 70, 61)])
+def test_ring_matches_oracle(P, o, v, naux):
+    say(f"ring fp64 ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 71)
+    t = S.make_amplitudes(o, v, 72)
+    R0 = np.random.default_rng(73).standard_normal((o, o, v, v))
+    R = dev(R0.copy())
+    P.ring(dev(s["L"]), dev(t), R, alpha=-0.5, beta=2.0)
+    ref = 2.0 * R0 - 0.5 * O.ring(s["L"], o, t)
+    got = R.cpu().numpy()
+    assert rel(got, ref) < 1e-12
+    # beta = 0 overwrites (R may hold anything, NaN included)
+    Rn = torch.full((o, o, v, v), float("nan"), dtype=torch.float64, device="cuda")
+    P.ring(dev(s["L"]), dev(t), Rn)
+    assert rel(Rn.cpu().numpy(), O.ring(s["L"], o, t)) < 1e-12
+
+
+def test_ring_rejects_small_scratch_and_aliasing(P):
+    o, v, naux = 3, 20, 17
+    say(f"ring argument checks ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 74)
+    L, t = dev(s["L"]), dev(S.make_amplitudes(o, v, 75))
+    need = P.ppl_ring_scratch_bytes(o, v, naux)
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.PPLError) as e:
+        P.ring(L, t, torch.empty_like(t), scratch=small)
+    assert e.value.code == -1
+    with pytest.raises(P.PPLError):
+        P.ring(L, t, t)
+
+
+def test_ring_c3_sampled(P):
+    o, v, naux = 40, 400, 1200
+    say(f"ring fp64 ({o},{v},{naux}) sampled")
+    s = S.make_system(o, v, naux, 2, "contractive")
+    t = S.make_amplitudes(o, v, 3)
+    R = P.ring(dev(s["L"]), dev(t))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(76)
+    idx = [tuple(int(x) for x in (rng.integers(o), rng.integers(o), rng.integers(v), rng.integers(v)))
+           for _ in range(12)] + [(0, 0, 0, 0), (o - 1, o - 1, v - 1, v - 1), (0, o - 1, v - 1, 0)]
+    ref = np.array([O.ring_entry(s["L"], o, t, *k) for k in idx])
+    got = np.array([R[k].item() for k in idx])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"  max |R_gpu - R_oracle| / max |R| = {err:.2e}")
+    assert err < 1e-12
+    assert (torch.linalg.norm(R - R.permute(1, 0, 3, 2)) / torch.linalg.norm(R)).item() < 1e-14
+    del R
+    torch.cuda.empty_cache()

@@ -167,6 +167,20 @@ def test_bf16x6_keeps_its_k_slices_short(P):
         assert f["splits_contract"] >= 1
 
 
+def test_ring_scratch_and_argument_checks(P):
+    # staged ov, oo, vv blocks, the (kj|bc) product and seven (o v) x pad(o v) FP64 matrices
+    o, v, naux = 40, 400, 1200
+    ov, ldk, ldx = o * v, (o * v + 63) // 64 * 64, (naux + 63) // 64 * 64
+    need = P.ppl_ring_scratch_bytes(o, v, naux)
+    assert need >= 7 * ov * ldk * 8 + (ov + o * o + v * v) * ldx * 8
+    assert need < 18 << 30
+    assert P.ppl_ring_scratch_bytes(0, 4, 5) == 0 and P.ppl_ring_scratch_bytes(2, 4, 0) == 0
+    from paper_2603_20912_amd import _lib
+    # argument errors are caught on the host, before any device work
+    rc = _lib.load().ppl_ring(2, 4, 5, None, None, None, 1.0, 0.0, None, 0, None)
+    assert rc == _lib.PPL_E_ARG
+
+
 def test_mixed_precision_keeps_both_copies(P):
     f64 = plan_info(P, 40, 400, 1200, prec="fp64", hbm_budget=280 << 30)
     mix = plan_info(P, 40, 400, 1200, prec="bf16x3", keep_fp64=True, hbm_budget=280 << 30)

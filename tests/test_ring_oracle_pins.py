@@ -103,3 +103,15 @@ def test_planted_ring_mistakes_are_caught(kind):
     assert np.abs(O.ring(s["L"], o, t) - ab).max() < 1e-12 * np.abs(ab).max()
     R = _ring_mutant(kind)(s["L"], o, t)
     assert np.abs(R - ab).max() > 1e-6 * np.abs(ab).max()
+
+
+def test_ring_entry_matches_the_full_term():
+    o, v = 3, 7
+    s = S.make_system(o, v, 5, 8)
+    t = S.make_amplitudes(o, v, 9)
+    R = O.ring(s["L"], o, t)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        i, j = rng.integers(o, size=2)
+        a, b = rng.integers(v, size=2)
+        assert abs(O.ring_entry(s["L"], o, t, i, j, a, b) - R[i, j, a, b]) < 1e-13 * np.abs(R).max()
