@@ -331,8 +331,9 @@ def study_paper(args):
 
 def study_terms(args):
     """Times of the CCSD terms next to the ladder at (40, 400, 1200), FP64, inputs in HBM:
-    the ladder PPL(t2), the ladder with singles PPL(t2 + t1 t1) and the hole-hole ladder
-    sum_kl (ki|lj) t_kl^ab (integrals from L included), each averaged over 5 calls."""
+    the ladder PPL(t2), the ladder with singles PPL(t2 + t1 t1), the hole-hole ladder
+    sum_kl (ki|lj) t_kl^ab and the ring terms (integrals from L included in both), each
+    averaged over 5 calls."""
     import numpy as np
     import torch
 
@@ -348,10 +349,14 @@ def study_terms(args):
     eng = P.PPL(o, v, naux)
     eng.build(L)
     Pp, Pm, Np, Nm = v * (v + 1) // 2, v * (v - 1) // 2, o * (o + 1) // 2, o * (o - 1) // 2
+    ring_scratch = torch.empty(P.ppl_ring_scratch_bytes(o, v, naux), dtype=torch.uint8, device="cuda")
     calls = {"ppl": lambda: eng.contract(t2, R), "ppl_tau": lambda: eng.contract(t2, R, t1=t1),
-             "hhl": lambda: eng.hhl(L, t2, R)}
+             "hhl": lambda: eng.hhl(L, t2, R), "ring": lambda: P.ring(L, t2, R, scratch=ring_scratch)}
+    ov = o * v
     flops = {"ppl": nominal(o, v, naux)["contract"], "ppl_tau": nominal(o, v, naux)["contract"],
-             "hhl": 2.0 * (Pp * Np * Np + Pm * Nm * Nm)}
+             "hhl": 2.0 * (Pp * Np * Np + Pm * Nm * Nm),
+             # three (ov)^3 GEMMs and the (kc|jb), (kj|bc) integrals
+             "ring": 6.0 * ov ** 3 + 4.0 * ov * ov * naux}
     out = {"config": {"o": o, "v": v, "naux": naux, "precision": "fp64"}}
     for name, fn in calls.items():
         fn()
