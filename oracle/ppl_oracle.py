@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "vv_block", "ov_block", "eri_vvvv_for_a", "ppl", "ppl_loops", "ppl_factored",
     "ppl_sampled", "ppl_entry", "oo_block", "tau", "ppl_tau", "hhl", "ring", "ring_entry", "mp2_parts", "mp2_amplitudes", "energy", "jacobi_sweep",
-    "jacobi", "jacobi_diis", "fixed_point", "fixed_point_hhl", "spectral_radius", "nominal_flops",
+    "jacobi", "jacobi_diis", "fixed_point", "fixed_point_hhl", "fixed_point_terms", "spectral_radius", "nominal_flops",
 ]
 
 
@@ -239,18 +239,22 @@ def energy(V: np.ndarray, t: np.ndarray) -> float:
 # linearized doubles iteration (the PPL-only vector function with the Fock
 # denominators), its exact fixed point and its contraction rate
 # ---------------------------------------------------------------------------
-def jacobi_sweep(L, o, V, D, t, with_hhl: bool = False):
-    """One simultaneous update t_new = (V + PPL(t) [+ HHL(t)]) / D; returns (t_new, ||t_new - t||_F)."""
+def jacobi_sweep(L, o, V, D, t, with_hhl: bool = False, with_ring: bool = False):
+    """One simultaneous update t_new = (V + PPL(t) [+ HHL(t)] [+ RING(t)]) / D; returns
+    (t_new, ||t_new - t||_F)."""
     g = V + ppl(L, o, t)
     if with_hhl:
         g = g + hhl(L, o, t)
+    if with_ring:
+        g = g + ring(L, o, t)
     t_new = g / D
     return t_new, float(np.linalg.norm(t_new - t))
 
 
-def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7, with_hhl: bool = False):
+def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7, with_hhl: bool = False,
+           with_ring: bool = False):
     """Iterate from t0 (MP2 when None) until r < tol or max_sweeps; with_hhl adds the
-    hole-hole ladder to every sweep.
+    hole-hole ladder and with_ring the ring terms to every sweep.
 
     Returns (t, residual_history, E(t)).
     """
@@ -258,7 +262,7 @@ def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7
     t = V / D if t0 is None else np.array(t0, dtype=np.float64)
     hist = []
     for _ in range(max_sweeps):
-        t, r = jacobi_sweep(L, o, V, D, t, with_hhl)
+        t, r = jacobi_sweep(L, o, V, D, t, with_hhl, with_ring)
         hist.append(r)
         if not np.isfinite(r) or r < tol:
             break
@@ -266,7 +270,7 @@ def jacobi(L, o, e_occ, e_vir, t0=None, max_sweeps: int = 100, tol: float = 1e-7
 
 
 def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, tol: float = 1e-7,
-                with_hhl: bool = False):
+                with_hhl: bool = False, with_ring: bool = False):
     """Jacobi iteration accelerated by direct inversion in the iterative subspace
     (DIIS; P. Pulay, Chem. Phys. Lett. 73, 393 (1980)).
 
@@ -287,7 +291,7 @@ def jacobi_diis(L, o, e_occ, e_vir, t0=None, m: int = 6, max_sweeps: int = 100, 
     t = V / D if t0 is None else np.array(t0, dtype=np.float64)
     Ts, Es, hist = [], [], []
     for _ in range(max_sweeps):
-        t_new, _ = jacobi_sweep(L, o, V, D, t, with_hhl)
+        t_new, _ = jacobi_sweep(L, o, V, D, t, with_hhl, with_ring)
         e = t_new - t
         r = float(np.linalg.norm(e))
         hist.append(r)
@@ -338,6 +342,29 @@ def fixed_point_hhl(L, o, e_occ, e_vir) -> np.ndarray:
     V, D = mp2_parts(L, o, e_occ, e_vir)
     A = np.diag(D.ravel()) - K.reshape(n, n)
     return np.linalg.solve(A, V.ravel()).reshape(o, o, v, v)
+
+
+def fixed_point_terms(L, o, e_occ, e_vir, with_hhl: bool = True, with_ring: bool = True) -> np.ndarray:
+    """Exact solution of t = (V + PPL(t) [+ HHL(t)] [+ RING(t)]) / D by one dense solve:
+    the linear operator is tabulated column by column, applying the term functions to
+    every unit tensor. Tiny sizes only ((o v)^2 x (o v)^2 system)."""
+    L = np.asarray(L, dtype=np.float64)
+    V, D = mp2_parts(L, o, e_occ, e_vir)
+    shape = V.shape
+    n = V.size
+    M = np.empty((n, n))
+    for q in range(n):
+        e = np.zeros(n)
+        e[q] = 1.0
+        e = e.reshape(shape)
+        g = ppl(L, o, e)
+        if with_hhl:
+            g = g + hhl(L, o, e)
+        if with_ring:
+            g = g + ring(L, o, e)
+        M[:, q] = g.ravel()
+    A = np.diag(D.ravel()) - M
+    return np.linalg.solve(A, V.ravel()).reshape(shape)
 
 
 def fixed_point(L, o, e_occ, e_vir) -> np.ndarray:

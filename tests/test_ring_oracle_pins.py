@@ -115,3 +115,39 @@ def test_ring_entry_matches_the_full_term():
         i, j = rng.integers(o, size=2)
         a, b = rng.integers(v, size=2)
         assert abs(O.ring_entry(s["L"], o, t, i, j, a, b) - R[i, j, a, b]) < 1e-13 * np.abs(R).max()
+
+
+def test_terms_fixed_point_reduces_to_the_known_ones():
+    # the tabulated operator reproduces the two dense solves that are written out directly
+    s = S.make_system(2, 4, 6, 11, "contractive")
+    a = O.fixed_point_terms(s["L"], 2, s["e_occ"], s["e_vir"], with_hhl=False, with_ring=False)
+    assert np.abs(a - O.fixed_point(s["L"], 2, s["e_occ"], s["e_vir"])).max() < 1e-12 * np.abs(a).max()
+    b = O.fixed_point_terms(s["L"], 2, s["e_occ"], s["e_vir"], with_hhl=True, with_ring=False)
+    assert np.abs(b - O.fixed_point_hhl(s["L"], 2, s["e_occ"], s["e_vir"])).max() < 1e-12 * np.abs(b).max()
+
+
+def test_iteration_with_ring_reaches_the_dense_fixed_point():
+    # at this tiny size the plain iteration diverges with the ring terms (the contractive
+    # generator keeps only the ladder's spectral radius below one); DIIS converges
+    o, v, naux = 2, 5, 8
+    s = S.make_system(o, v, naux, 12, "contractive")
+    tstar = O.fixed_point_terms(s["L"], o, s["e_occ"], s["e_vir"])
+    t, hist, _ = O.jacobi_diis(s["L"], o, s["e_occ"], s["e_vir"], m=6, max_sweeps=200, tol=1e-12,
+                               with_hhl=True, with_ring=True)
+    assert hist[-1] < 1e-12
+    assert np.abs(t - tstar).max() < 1e-10 * np.abs(tstar).max()
+    # the ring terms change the fixed point
+    t0 = O.fixed_point_terms(s["L"], o, s["e_occ"], s["e_vir"], with_ring=False)
+    assert np.abs(t0 - tstar).max() > 1e-4 * np.abs(tstar).max()
+
+
+def test_plain_and_diis_iterations_with_ring_agree():
+    o, v, naux = 6, 40, 120
+    s = S.make_system(o, v, naux, 1, "contractive")
+    tp, hp, Ep = O.jacobi(s["L"], o, s["e_occ"], s["e_vir"], max_sweeps=100, tol=1e-10, with_hhl=True,
+                          with_ring=True)
+    td, hd, Ed = O.jacobi_diis(s["L"], o, s["e_occ"], s["e_vir"], m=8, max_sweeps=100, tol=1e-10,
+                               with_hhl=True, with_ring=True)
+    assert hp[-1] < 1e-10 and hd[-1] < 1e-10 and len(hd) < len(hp)
+    assert np.abs(tp - td).max() < 1e-8 * np.abs(tp).max()
+    assert abs(Ep - Ed) < 1e-8
