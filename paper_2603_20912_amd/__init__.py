@@ -42,7 +42,7 @@ class PPL:
 
     def __init__(self, o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None,
                  tile_contract=-1, device="cuda", build_scratch=0, diis_max=0, contract_only=False,
-                 tune_cache=None):
+                 tune_cache=None, ring=False):
         if not torch.cuda.is_available():
             raise RuntimeError("PPL needs a HIP device (no CPU fallback)")
         self.o, self.v, self.naux = o, v, naux
@@ -52,7 +52,8 @@ class PPL:
             # blocks torch holds cached but unused back first, so that they count as free
             torch.cuda.empty_cache()
         self.plan = ppl_plan(o, v, naux, prec, keep_fp64, hbm_budget, self.stream, tile_contract, build_scratch,
-                             diis_max, _lib.PPL_PLAN_CONTRACT_ONLY if contract_only else 0, tune_cache)
+                             diis_max, (_lib.PPL_PLAN_CONTRACT_ONLY if contract_only else 0)
+                             | (_lib.PPL_PLAN_RING if ring else 0), tune_cache)
         self.info = ppl_plan_query(self.plan)
         nbytes = int(self.info["workspace_bytes"])
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
@@ -80,7 +81,7 @@ class PPL:
 
     def iterate(self, L, e_occ, e_vir, t2, max_sweeps=100, tol=1e-7, start="mp2", switch_tol=0.0,
                 stagnation=0.95, min_fp64_sweeps=2, diverge_factor=1e3, fail_on_noconv=True,
-                history=True, raise_on_status=True, diis=0, hhl=False):
+                history=True, raise_on_status=True, diis=0, hhl=False, ring=False):
         opts = ppl_iter_opts_default()
         opts.max_sweeps = int(max_sweeps)
         opts.tol = float(tol)
@@ -93,6 +94,7 @@ class PPL:
         opts.fail_on_noconv = int(bool(fail_on_noconv))
         opts.diis = int(diis)
         opts.hhl = int(bool(hhl))
+        opts.ring = int(bool(ring))
         hist = (ctypes.c_double * max_sweeps)() if history else None
         if hist is not None:
             opts.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))

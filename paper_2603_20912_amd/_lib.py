@@ -57,7 +57,7 @@ class ppl_iter_opts_t(ctypes.Structure):
                 ("switch_tol", ctypes.c_double), ("stagnation", ctypes.c_double),
                 ("min_fp64_sweeps", ctypes.c_int32), ("fail_on_noconv", ctypes.c_int32),
                 ("diverge_factor", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
-                ("diis", ctypes.c_int32), ("hhl", ctypes.c_int32)]
+                ("diis", ctypes.c_int32), ("hhl", ctypes.c_int32), ("ring", ctypes.c_int32)]
 
 
 class ppl_iter_report_t(ctypes.Structure):
@@ -180,6 +180,7 @@ def _stream_handle(stream):
 
 # ---------------------------------------------------------------- same names as the C ABI
 PPL_PLAN_CONTRACT_ONLY = 1
+PPL_PLAN_RING = 2
 
 
 def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None, tile_contract=-1,

@@ -53,6 +53,38 @@ struct Layout {
   }
 };
 
+// Scratch of the ring terms: staged Cholesky blocks (ov, oo, vv rows of P), the (kj|bc)
+// product, and seven (o v) x (o v) pair matrices.
+struct RingLayout {
+  int64_t ldx = 0, ldk = 0, ldg = 0;
+  uint64_t xov = 0, xoo = 0, xvv = 0, g = 0, j = 0, k = 0, xa = 0, an = 0, b = 0, c1 = 0, c2 = 0, bytes = 0;
+};
+
+static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r) {
+  if (o < 1 || v < 1 || naux < 1 || o > 32767 || v > 32767) return false;
+  r.ldx = pad_ld(naux);
+  r.ldk = pad_ld(o * v);
+  r.ldg = pad_ld(v * v);
+  uint64_t x;
+  if (!mul_ok((uint64_t)(o * v), (uint64_t)r.ldk, &x) || !mul_ok(x, 16, &x)) return false;
+  if (!mul_ok((uint64_t)(v * v), (uint64_t)r.ldx, &x) || !mul_ok(x, 16, &x)) return false;
+  Layout L;
+  r.xov = L.take((uint64_t)o * v * r.ldx * 8).off;
+  r.xoo = L.take((uint64_t)o * o * r.ldx * 8).off;
+  r.xvv = L.take((uint64_t)v * v * r.ldx * 8).off;
+  r.g = L.take((uint64_t)o * o * r.ldg * 8).off;
+  const uint64_t m = (uint64_t)o * v * r.ldk * 8;
+  r.j = L.take(m).off;
+  r.k = L.take(m).off;
+  r.xa = L.take(m).off;
+  r.an = L.take(m).off;
+  r.b = L.take(m).off;
+  r.c1 = L.take(m).off;
+  r.c2 = L.take(m).off;
+  r.bytes = L.cur;
+  return true;
+}
+
 // Split virtual rows a into build steps whose pair count (sum of v - a) stays
 // within cap (at least one row per step).
 static void make_batches(int v, int64_t cap, std::vector<Batch>& out) {
@@ -200,6 +232,15 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
                                                                p->contract_only ? 0 : (uint64_t)(o * v) * (o * v) * 8),
                                              hhl_scratch(p).bytes);
   p->g = L.take(gbytes);
+  if (p->ring) {
+    RingLayout rl;
+    ring_layout(p->o, p->v, p->naux, rl);
+    p->ring_ws = L.take(rl.bytes);
+    p->tfull = L.take((uint64_t)o * o * v * v * 8);
+    p->rfull = L.take((uint64_t)o * o * v * v * 8);
+  } else {
+    p->ring_ws = p->tfull = p->rfull = Region{};
+  }
   p->rp = L.take((uint64_t)p->Np * p->ldp * 8);
   p->rm = L.take((uint64_t)std::max<int64_t>(p->Nm, 1) * p->ldm * 8);
   // split-K slices for up to kMaxSplits (autotuning may pick any count), sized for FP64,
@@ -631,6 +672,7 @@ void ppl_iter_opts_default(ppl_iter_opts_t* o) {
   o->history = nullptr;
   o->diis = 0;
   o->hhl = 0;
+  o->ring = 0;
 }
 
 int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
@@ -647,7 +689,9 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
     return fail(PPL_E_ARG, "tile_contract %d out of range", d->tile_contract);
   if (d->diis_max < 0 || d->diis_max > PPL_DIIS_MAX)
     return fail(PPL_E_ARG, "diis_max %d out of range [0, %d]", d->diis_max, PPL_DIIS_MAX);
-  if (d->flags & ~PPL_PLAN_CONTRACT_ONLY) return fail(PPL_E_ARG, "unknown plan flags 0x%x", d->flags);
+  if (d->flags & ~(PPL_PLAN_CONTRACT_ONLY | PPL_PLAN_RING)) return fail(PPL_E_ARG, "unknown plan flags 0x%x", d->flags);
+  if ((d->flags & PPL_PLAN_CONTRACT_ONLY) && (d->flags & PPL_PLAN_RING))
+    return fail(PPL_E_ARG, "PPL_PLAN_RING serves the iteration, which a PPL_PLAN_CONTRACT_ONLY plan cannot run");
   // 64-bit size sanity: the largest products used anywhere
   {
     uint64_t x;
@@ -665,6 +709,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   p->prec = d->prec;
   p->keep_fp64 = (d->prec != PPL_FP64) && d->keep_fp64;
   p->contract_only = (d->flags & PPL_PLAN_CONTRACT_ONLY) != 0;
+  p->ring = (d->flags & PPL_PLAN_RING) != 0;
   p->diis_max = p->contract_only ? 0 : d->diis_max;
   p->stream = (hipStream_t)d->stream;
   p->Pp = npairs_plus(p->v);
@@ -1002,36 +1047,38 @@ int ppl_hhl(ppl_plan_t p, const double* L, const double* t2, double* R, double a
   return unpack_r(st, PPL_FP64, p->o, p->v, s64, p->ldp, a64, p->ldm, R, alpha, beta);
 }
 
-// Scratch of the ring terms: staged Cholesky blocks (ov, oo, vv rows of P), the (kj|bc)
-// product, and seven (o v) x (o v) pair matrices.
-struct RingLayout {
-  int64_t ldx = 0, ldk = 0, ldg = 0;
-  uint64_t xov = 0, xoo = 0, xvv = 0, g = 0, j = 0, k = 0, xa = 0, an = 0, b = 0, c1 = 0, c2 = 0, bytes = 0;
-};
+// J[(k,c)][(j,b)] = (kc|jb) and K[(k,c)][(j,b)] = (kj|bc) from L (scratch w laid out by r)
+static int ring_integrals(hipStream_t st, int o, int v, int naux, const double* L, char* w, const RingLayout& r) {
+  auto d = [&](uint64_t off) { return (double*)(w + off); };
+  const int64_t ov = (int64_t)o * v;
+  // the K-dimension padding of J and K must read as zero (their GEMMs write n < o v only)
+  PPL_TRY(zero_bytes(st, w + r.j, 2 * (uint64_t)ov * r.ldk * 8));
+  PPL_TRY(stage_ov(st, L, o, v, naux, r.ldx, d(r.xov)));
+  PPL_TRY(stage_oo(st, L, o, v, naux, r.ldx, d(r.xoo)));
+  PPL_TRY(stage_vv(st, PPL_FP64, L, o, v, naux, r.ldx, d(r.xvv), nullptr));
+  // J[(k,c)][(j,b)] = sum_P L^P_kc L^P_jb;  G[(k,j)][(b,c)] = sum_P L^P_kj L^P_bc -> K
+  PPL_TRY(gemm_store_f64(st, ov, ov, r.ldx, d(r.xov), r.ldx, d(r.xov), r.ldx, d(r.j), r.ldk));
+  PPL_TRY(gemm_store_f64(st, (int64_t)o * o, (int64_t)v * v, r.ldx, d(r.xoo), r.ldx, d(r.xvv), r.ldx, d(r.g),
+                         r.ldg));
+  return ring_exchange(st, o, v, d(r.g), r.ldg, d(r.k), r.ldk);
+}
 
-static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r) {
-  if (o < 1 || v < 1 || naux < 1 || o > 32767 || v > 32767) return false;
-  r.ldx = pad_ld(naux);
-  r.ldk = pad_ld(o * v);
-  r.ldg = pad_ld(v * v);
-  uint64_t x;
-  if (!mul_ok((uint64_t)(o * v), (uint64_t)r.ldk, &x) || !mul_ok(x, 16, &x)) return false;
-  if (!mul_ok((uint64_t)(v * v), (uint64_t)r.ldx, &x) || !mul_ok(x, 16, &x)) return false;
-  Layout L;
-  r.xov = L.take((uint64_t)o * v * r.ldx * 8).off;
-  r.xoo = L.take((uint64_t)o * o * r.ldx * 8).off;
-  r.xvv = L.take((uint64_t)v * v * r.ldx * 8).off;
-  r.g = L.take((uint64_t)o * o * r.ldg * 8).off;
-  const uint64_t m = (uint64_t)o * v * r.ldk * 8;
-  r.j = L.take(m).off;
-  r.k = L.take(m).off;
-  r.xa = L.take(m).off;
-  r.an = L.take(m).off;
-  r.b = L.take(m).off;
-  r.c1 = L.take(m).off;
-  r.c2 = L.take(m).off;
-  r.bytes = L.cur;
-  return true;
+// R = beta R + alpha RING(t2) with J and K already in the scratch
+static int ring_apply(hipStream_t st, int o, int v, const double* t2, double* R, double alpha, double beta, char* w,
+                      const RingLayout& r) {
+  auto d = [&](uint64_t off) { return (double*)(w + off); };
+  const int64_t ov = (int64_t)o * v;
+  PPL_TRY(ring_pack(st, o, v, t2, r.ldk, d(r.xa), d(r.an), d(r.b)));
+  // C1 = Xa J^T + An K^T, C2 = B K^T (J and K are symmetric: their rows are their columns)
+  int tile = -1, sp = 1;
+  contract_choose(PPL_FP64, ov, ov, r.ldk, 1, &tile, &sp);
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.xa), nullptr, r.ldk, d(r.j), nullptr, r.ldk,
+                        d(r.c1), r.ldk, 0, 1, nullptr, 0, 0, false));
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.an), nullptr, r.ldk, d(r.k), nullptr, r.ldk,
+                        d(r.c1), r.ldk, 0, 1, nullptr, 0, 0, true));
+  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.b), nullptr, r.ldk, d(r.k), nullptr, r.ldk,
+                        d(r.c2), r.ldk, 0, 1, nullptr, 0, 0, false));
+  return ring_unpack(st, o, v, d(r.c1), d(r.c2), r.ldk, R, alpha, beta);
 }
 
 uint64_t ppl_ring_scratch_bytes(int32_t o, int32_t v, int32_t naux) {
@@ -1051,30 +1098,8 @@ int ppl_ring(int32_t o, int32_t v, int32_t naux, const double* L, const double* 
     return fail(PPL_E_ARG, "ring scratch holds %llu B, needs %llu B", (unsigned long long)scratch_bytes,
                 (unsigned long long)r.bytes);
   hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)scratch;
-  auto d = [&](uint64_t off) { return (double*)(w + off); };
-  const int64_t ov = (int64_t)o * v;
-  // the K-dimension padding of J and K must read as zero (their GEMMs write n < o v only)
-  PPL_TRY(zero_bytes(st, w + r.j, 2 * (uint64_t)ov * r.ldk * 8));
-  PPL_TRY(stage_ov(st, L, o, v, naux, r.ldx, d(r.xov)));
-  PPL_TRY(stage_oo(st, L, o, v, naux, r.ldx, d(r.xoo)));
-  PPL_TRY(stage_vv(st, PPL_FP64, L, o, v, naux, r.ldx, d(r.xvv), nullptr));
-  // J[(k,c)][(j,b)] = sum_P L^P_kc L^P_jb;  G[(k,j)][(b,c)] = sum_P L^P_kj L^P_bc -> K
-  PPL_TRY(gemm_store_f64(st, ov, ov, r.ldx, d(r.xov), r.ldx, d(r.xov), r.ldx, d(r.j), r.ldk));
-  PPL_TRY(gemm_store_f64(st, (int64_t)o * o, (int64_t)v * v, r.ldx, d(r.xoo), r.ldx, d(r.xvv), r.ldx, d(r.g),
-                         r.ldg));
-  PPL_TRY(ring_exchange(st, o, v, d(r.g), r.ldg, d(r.k), r.ldk));
-  PPL_TRY(ring_pack(st, o, v, t2, r.ldk, d(r.xa), d(r.an), d(r.b)));
-  // C1 = Xa J^T + An K^T, C2 = B K^T (J and K are symmetric: their rows are their columns)
-  int tile = -1, sp = 1;
-  contract_choose(PPL_FP64, ov, ov, r.ldk, 1, &tile, &sp);
-  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.xa), nullptr, r.ldk, d(r.j), nullptr, r.ldk,
-                        d(r.c1), r.ldk, 0, 1, nullptr, 0, 0, false));
-  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.an), nullptr, r.ldk, d(r.k), nullptr, r.ldk,
-                        d(r.c1), r.ldk, 0, 1, nullptr, 0, 0, true));
-  PPL_TRY(gemm_contract(st, PPL_FP64, tile, ov, ov, r.ldk, d(r.b), nullptr, r.ldk, d(r.k), nullptr, r.ldk,
-                        d(r.c2), r.ldk, 0, 1, nullptr, 0, 0, false));
-  return ring_unpack(st, o, v, d(r.c1), d(r.c2), r.ldk, R, alpha, beta);
+  PPL_TRY(ring_integrals(st, o, v, naux, L, (char*)scratch, r));
+  return ring_apply(st, o, v, t2, R, alpha, beta, (char*)scratch, r);
 }
 
 int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,
@@ -1090,6 +1115,8 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   if (o.hhl && !p->resident)
     return fail(PPL_E_UNSUPPORTED, "the hole-hole ladder in the iteration needs a resident plan");
   if (o.hhl && hhl_scratch(p).bytes > p->g.bytes) return fail(PPL_E_STATE, "hole-hole scratch too small");
+  if (o.ring && (!p->ring || !p->resident))
+    return fail(PPL_E_STATE, "the ring terms in the iteration need a resident plan made with PPL_PLAN_RING");
   if (o.diis < 0 || o.diis > p->diis_max)
     return fail(PPL_E_ARG, "diis %d exceeds the plan's subspace capacity %d (ppl_desc_t.diis_max)", o.diis,
                 p->diis_max);
@@ -1105,6 +1132,11 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   PPL_TRY(setup_ov_integrals(p, L));
   PPL_TRY(ppl_build_batch(p, L, -1));
   if (o.hhl) PPL_TRY(hhl_integrals(p, L));
+  RingLayout rl;
+  if (o.ring) {
+    ring_layout(p->o, p->v, p->naux, rl);
+    PPL_TRY(ring_integrals(st, p->o, p->v, p->naux, L, at<char>(p, p->ring_ws), rl));
+  }
 
   const int* tabs[4] = {at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp),
                         at<int>(p, p->tab_vm)};
@@ -1158,6 +1190,16 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
     if (o.hhl) {
       ProfScope ph(p, PPL_PROF_OTHER, 2.0 * (double)p->Pp * p->Np * p->Np + 2.0 * (double)p->Pm * p->Nm * p->Nm);
       PPL_TRY(hhl_add_packed(p, s));
+    }
+    if (o.ring) {
+      // the ring terms of the current FP64 amplitudes, added to R+- in their precision
+      const double ov = (double)p->o * p->v;
+      ProfScope pr(p, PPL_PROF_OTHER, 6.0 * ov * ov * ov);
+      PPL_TRY(unpack_t(st, p->o, p->v, s64, p->ldp, a64, p->ldm, at<double>(p, p->tfull)));
+      PPL_TRY(ring_apply(st, p->o, p->v, at<double>(p, p->tfull), at<double>(p, p->rfull), 1.0, 0.0,
+                         at<char>(p, p->ring_ws), rl));
+      PPL_TRY(add_pm(st, s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, at<double>(p, p->rfull),
+                     at<void>(p, p->rp), p->ldp, at<void>(p, p->rm), p->ldm, tabs[0], tabs[1], tabs[2], tabs[3]));
     }
     ProfScope ps(p, PPL_PROF_UPDATE, 0.0);
     double* ts = slot >= 0 ? dT + slot * p->diis_slot_n : nullptr;

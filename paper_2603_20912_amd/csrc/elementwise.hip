@@ -1095,4 +1095,46 @@ int ring_unpack(hipStream_t s, int o, int v, const double* C1, const double* C2,
   return PPL_OK;
 }
 
+// R+- += the pair parts of a pair-symmetric full tensor (the inverse of unpack_r)
+template <class Tc>
+__global__ void __launch_bounds__(256)
+add_pm_kernel(int o, int v, const double* __restrict__ R, Tc* rp, int64_t ldp, Tc* rm, int64_t ldm, int64_t Np,
+              int64_t Pp, int64_t Nm, int64_t Pm, const int* __restrict__ tab_op, const int* __restrict__ tab_om,
+              const int* __restrict__ tab_vp, const int* __restrict__ tab_vm) {
+  const int64_t np = Np * Pp, total = np + Nm * Pm;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
+    const bool plus = x < np;
+    const int64_t y = plus ? x : x - np;
+    const int64_t P = plus ? Pp : Pm;
+    const int64_t q = y / P, c = y - q * P;
+    const int ij = plus ? tab_op[q] : tab_om[q];
+    const int ab = plus ? tab_vp[c] : tab_vm[c];
+    const int64_t i = pair_first(ij), j = pair_second(ij), a = pair_first(ab), b = pair_second(ab);
+    const double r1 = R[((i * o + j) * v + a) * v + b], r2 = R[((i * o + j) * v + b) * v + a];
+    if (plus) {
+      Tc* d = rp + q * ldp + c;
+      *d = (Tc)((double)*d + 0.5 * (r1 + r2));
+    } else {
+      Tc* d = rm + q * ldm + c;
+      *d = (Tc)((double)*d + 0.5 * (r1 - r2));
+    }
+  }
+}
+
+int add_pm(hipStream_t s, int c_prec, int o, int v, const double* R, void* rp, int64_t ldp, void* rm, int64_t ldm,
+           const int* tab_op, const int* tab_om, const int* tab_vp, const int* tab_vm) {
+  const int64_t Np = npairs_plus(o), Nm = npairs_minus(o), Pp = npairs_plus(v), Pm = npairs_minus(v);
+  const int64_t n = Np * Pp + Nm * Pm;
+  if (n <= 0) return PPL_OK;
+  if (c_prec == PPL_FP64)
+    hipLaunchKernelGGL(add_pm_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, R, (double*)rp, ldp,
+                       (double*)rm, ldm, Np, Pp, Nm, Pm, tab_op, tab_om, tab_vp, tab_vm);
+  else
+    hipLaunchKernelGGL(add_pm_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, R, (float*)rp, ldp,
+                       (float*)rm, ldm, Np, Pp, Nm, Pm, tab_op, tab_om, tab_vp, tab_vm);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
 }  // namespace ppl

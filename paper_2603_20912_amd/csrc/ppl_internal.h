@@ -126,6 +126,8 @@ struct ppl_plan_s {
   ppl::Region red;                     // reduction partials
   int diis_max = 0;                    // DIIS subspace capacity
   bool contract_only = false;          // no iteration buffers (PPL_PLAN_CONTRACT_ONLY)
+  bool ring = false;                   // ring-term buffers reserved (PPL_PLAN_RING)
+  ppl::Region ring_ws, tfull, rfull;   // ring scratch, full amplitudes and ring result
   std::string tune_cache;              // path of the tuned-configuration file ("" = none)
   int64_t diis_slot_n = 0;             // doubles per DIIS slot: S' rows [N+][ldp], then A' rows [N-][ldm]
   ppl::Region diis_t, diis_e;          // diis_max slots of amplitudes t' and of errors t' - t (S'/A' scaling)
@@ -331,6 +333,10 @@ int ring_pack(hipStream_t s, int o, int v, const double* t, int64_t ld, double* 
 int ring_exchange(hipStream_t s, int o, int v, const double* G, int64_t ldg, double* K, int64_t ld);
 int ring_unpack(hipStream_t s, int o, int v, const double* C1, const double* C2, int64_t ld, double* R, double alpha,
                 double beta);
+// rp[(ij)][(ab)] += (R_ij^ab + R_ij^ba) / 2 (i <= j, a <= b), rm[(ij)][(ab)] += (R_ij^ab - R_ij^ba) / 2
+// (i < j, a < b): a pair-symmetric [o][o][v][v] tensor added to R+- (accumulator precision c_prec)
+int add_pm(hipStream_t s, int c_prec, int o, int v, const double* R, void* rp, int64_t ldp, void* rm, int64_t ldm,
+           const int* tab_op, const int* tab_om, const int* tab_vp, const int* tab_vm);
 // red_out[0] = sum (L^P_ac - L^P_ca)^2, red_out[1] = sum (L^P_ac)^2 + (L^P_ca)^2 over a < c (virtual block)
 int asymmetry_vv(hipStream_t s, const double* L, int o, int v, int naux, double* partials, double* red_out);
 // count non-finite values of an FP64 array (red_out[2])

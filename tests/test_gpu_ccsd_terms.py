@@ -150,3 +150,68 @@ def test_ring_c3_sampled(P):
     assert (torch.linalg.norm(R - R.permute(1, 0, 3, 2)) / torch.linalg.norm(R)).item() < 1e-14
     del R
     torch.cuda.empty_cache()
+
+
+def test_iteration_with_ring_matches_oracle_sweep_by_sweep(P):
+    """Plain FP64 sweeps of t = (V + PPL(t) + HHL(t) + RING(t)) / D against the oracle's,
+    residual by residual, to r < 1e-7 (the contractive generator converges at this size)."""
+    o, v, naux = 6, 40, 120
+    say(f"iterate fp64 with hhl + ring ({o},{v},{naux}) contractive")
+    s = S.make_system(o, v, naux, 1, "contractive")
+    eng = P.PPL(o, v, naux, ring=True)
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    rep = eng.iterate(dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"]), t, max_sweeps=100, tol=1e-7, hhl=True,
+                      ring=True)
+    eng.close()
+    tref, hist, E = O.jacobi(s["L"], o, s["e_occ"], s["e_vir"], max_sweeps=100, tol=1e-7, with_hhl=True,
+                             with_ring=True)
+    say(f"  sweeps {rep['sweeps_fp64']} (oracle {len(hist)}), residual {rep['residual']:.2e}")
+    assert rep["status"] == 0 and rep["sweeps_fp64"] == len(hist)
+    np.testing.assert_allclose(rep["history"], hist, rtol=1e-8)
+    assert rel(t.cpu().numpy(), tref) < 1e-10
+    assert abs(rep["energy"] - E) < 1e-10 * abs(E)
+
+
+def test_diis_with_ring_reaches_the_dense_fixed_point(P):
+    """At this tiny size the plain sweeps diverge with the ring terms; DIIS reaches the
+    fixed point of the full operator, solved densely by the oracle."""
+    o, v, naux = 2, 5, 8
+    say(f"iterate fp64 diis 6 with hhl + ring ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 12, "contractive")
+    eng = P.PPL(o, v, naux, ring=True, diis_max=6)
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    rep = eng.iterate(dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"]), t, max_sweeps=200, tol=1e-11, hhl=True,
+                      ring=True, diis=6)
+    eng.close()
+    tstar = O.fixed_point_terms(s["L"], o, s["e_occ"], s["e_vir"])
+    assert rep["status"] == 0
+    assert np.abs(t.cpu().numpy() - tstar).max() < 1e-9 * np.abs(tstar).max()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_mixed_iteration_with_ring(P, prec):
+    o, v, naux = 10, 100, 300
+    say(f"mixed {prec} -> fp64 with hhl + ring and diis 8 to 1e-7 ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 1, "contractive")
+    eng = P.PPL(o, v, naux, prec=prec, keep_fp64=True, ring=True, diis_max=8)
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    rep = eng.iterate(dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"]), t, max_sweeps=200, tol=1e-7, hhl=True,
+                      ring=True, diis=8)
+    eng.close()
+    assert rep["status"] == 0 and rep["residual"] < 1e-7 and rep["sweeps_lp"] > 0 and rep["sweeps_fp64"] >= 2
+    tstar, _, Estar = O.jacobi_diis(s["L"], o, s["e_occ"], s["e_vir"], m=8, max_sweeps=200, tol=1e-10,
+                                    with_hhl=True, with_ring=True)
+    assert rel(t.cpu().numpy(), tstar) < 1e-6
+    assert abs(rep["energy"] - Estar) < 1e-6
+
+
+def test_ring_iteration_needs_a_ring_plan(P):
+    o, v, naux = 3, 12, 20
+    say(f"iterate with ring on a plan without PPL_PLAN_RING ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 5, "contractive")
+    eng = P.PPL(o, v, naux)
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PPLError) as e:
+        eng.iterate(dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"]), t, max_sweeps=3, ring=True)
+    assert e.value.code == -7
+    eng.close()

@@ -133,7 +133,7 @@ def test_contract_only_plans(P):
     small = plan_info(P, 20, 200, 600, hbm_budget=1 << 40, flags=1)
     assert small["workspace_bytes"] < plan_info(P, 20, 200, 600, hbm_budget=1 << 40)["workspace_bytes"]
     with pytest.raises(P.PPLError) as e:
-        plan_info(P, 20, 200, 600, hbm_budget=1 << 40, flags=2)
+        plan_info(P, 20, 200, 600, hbm_budget=1 << 40, flags=4)
     assert e.value.code == -1
 
 
@@ -179,6 +179,19 @@ def test_ring_scratch_and_argument_checks(P):
     # argument errors are caught on the host, before any device work
     rc = _lib.load().ppl_ring(2, 4, 5, None, None, None, 1.0, 0.0, None, 0, None)
     assert rc == _lib.PPL_E_ARG
+
+
+def test_ring_plan_reserves_its_buffers(P):
+    from paper_2603_20912_amd import _lib
+    o, v, naux = 10, 100, 300
+    base = plan_info(P, o, v, naux, hbm_budget=64 << 30)
+    ring = plan_info(P, o, v, naux, hbm_budget=64 << 30, flags=_lib.PPL_PLAN_RING)
+    extra = ring["workspace_bytes"] - base["workspace_bytes"]
+    assert extra >= P.ppl_ring_scratch_bytes(o, v, naux) + 2 * o * o * v * v * 8
+    assert extra < P.ppl_ring_scratch_bytes(o, v, naux) + 2 * o * o * v * v * 8 + (1 << 20)
+    with pytest.raises(_lib.PPLError) as e:
+        plan_info(P, o, v, naux, hbm_budget=64 << 30, flags=_lib.PPL_PLAN_RING | _lib.PPL_PLAN_CONTRACT_ONLY)
+    assert e.value.code == _lib.PPL_E_ARG
 
 
 def test_mixed_precision_keeps_both_copies(P):
