@@ -87,7 +87,8 @@ def study_c3(args):
     """Time to an amplitude residual of 1e-7 at (40, 400, 1200), contractive generator
     seed 2: FP64, BF16x3 / BF16x6 / FP32 sweeps refined in FP64, and the same from the
     learned start, each also with DIIS (subspace 8); FP64 and BF16x3 + FP64 with DIIS for
-    the iteration that also carries the hole-hole ladder; plus single-evaluation errors of
+    the iteration that also carries the hole-hole ladder, and that with the ring terms too;
+    plus single-evaluation errors of
     the low-precision GEMMs."""
     import numpy as np
     import torch
@@ -109,6 +110,7 @@ def study_c3(args):
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep)
         Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=8)
     Lr.time_to_tol(small, "mp2", prec="bf16x3", keep_fp64=True, diis=8, hhl=True)
+    Lr.time_to_tol(small, "mp2", prec="bf16x3", keep_fp64=True, diis=8, hhl=True, ring=True)
     if mlp is not None:
         Lr.time_to_tol(small, "learned", mlp=mlp, prec="bf16x3", keep_fp64=True)
     runs = [("fp64", "mp2", "fp64", False, 0), ("bf16x3+fp64", "mp2", "bf16x3", True, 0),
@@ -121,23 +123,27 @@ def study_c3(args):
     if mlp is not None:
         runs += [("bf16x3+fp64 learned diis", "learned", "bf16x3", True, 8),
                  ("fp64 learned diis", "learned", "fp64", False, 8)]
-    runs = [r + (False,) for r in runs]
-    # the linearized doubles iteration with the hole-hole ladder too (its own fixed point,
-    # compared with its own FP64 run)
-    runs += [("fp64 diis hhl", "mp2", "fp64", False, 8, True), ("bf16x3+fp64 diis hhl", "mp2", "bf16x3", True, 8, True)]
+    runs = [r + (False, False) for r in runs]
+    # the linearized doubles iteration with the hole-hole ladder too, then also with the
+    # ring terms (each its own fixed point, compared with its own FP64 run)
+    runs += [("fp64 diis hhl", "mp2", "fp64", False, 8, True, False),
+             ("bf16x3+fp64 diis hhl", "mp2", "bf16x3", True, 8, True, False),
+             ("fp64 diis hhl ring", "mp2", "fp64", False, 8, True, True),
+             ("bf16x3+fp64 diis hhl ring", "mp2", "bf16x3", True, 8, True, True)]
     out = {"config": {"o": o, "v": v, "naux": naux, "generator": "contractive", "seed": 2, "tol": 1e-7}}
     refs = {}
-    for label, start, prec, keep, diis, hhl in runs:
+    for label, start, prec, keep, diis, hhl, ring in runs:
         torch.cuda.empty_cache()
         free_gib = torch.cuda.mem_get_info()[0] / 2 ** 30
-        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep, diis=diis, hhl=hhl)
+        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=1e-7, prec=prec, keep_fp64=keep, diis=diis, hhl=hhl,
+                                ring=ring)
         row = {"seconds": round(rep["seconds"], 3), "sweeps_lp": rep["sweeps_lp"], "sweeps_fp64": rep["sweeps_fp64"],
                "residual": rep["residual"], "energy": rep["energy"], "status": rep["status"],
                "resident": rep["resident"], "free_GiB_before": round(free_gib, 1), "kernel_ms": rep["kernel_ms"]}
-        if hhl not in refs:
-            refs[hhl] = (t.clone(), rep["energy"])
+        if (hhl, ring) not in refs:
+            refs[(hhl, ring)] = (t.clone(), rep["energy"])
         else:
-            ref_t, ref_E = refs[hhl]
+            ref_t, ref_E = refs[(hhl, ring)]
             row["rel_err_t_vs_fp64"] = (torch.linalg.norm(t - ref_t) / torch.linalg.norm(ref_t)).item()
             row["abs_err_E_vs_fp64"] = abs(rep["energy"] - ref_E)
         out[label] = row

@@ -64,19 +64,19 @@ def train(mlp: MLP, X, Y, steps=2000, batch=4096, lr=1e-3, seed=0, log_every=0):
 
 
 def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, max_sweeps=300,
-                device="cuda", switch_tol=0.0, diis=0, hhl=False):
+                device="cuda", switch_tol=0.0, diis=0, hhl=False, ring=False):
     """Wall time and sweeps from inputs in HBM to a converged residual below tol.
 
     start: 'mp2' (plain), 'learned' (network guess, unchecked) or 'checked'
     (network guess, restarted from MP2 when its first residual is larger).
     diis >= 2 accelerates the sweeps with a DIIS subspace of that size; hhl adds the
-    hole-hole ladder to every sweep (t = (V + PPL(t) + HHL(t)) / D).
+    hole-hole ladder to every sweep (t = (V + PPL(t) + HHL(t)) / D), ring the ring terms.
     The timed region covers the first-order amplitudes, the network guess, the
     integral builds and every sweep.
     """
     o, v, naux = sysd["o"], sysd["v"], sysd["naux"]
     d = upload_system(sysd, device)
-    eng = PPL(o, v, naux, prec=prec, keep_fp64=keep_fp64, diis_max=diis)
+    eng = PPL(o, v, naux, prec=prec, keep_fp64=keep_fp64, diis_max=diis, ring=ring)
     t = torch.empty((o, o, v, v), dtype=torch.float64, device=device)
     tm = torch.empty_like(t) if start != "mp2" else None
     torch.cuda.synchronize()
@@ -84,13 +84,13 @@ def time_to_tol(sysd, start, mlp=None, tol=1e-7, prec="fp64", keep_fp64=False, m
     t0 = time.perf_counter()
     if start == "mp2":
         rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t, max_sweeps=max_sweeps, tol=tol, start="mp2",
-                          switch_tol=switch_tol, raise_on_status=False, diis=diis, hhl=hhl)
+                          switch_tol=switch_tol, raise_on_status=False, diis=diis, hhl=hhl, ring=ring)
     else:
         eng.mp2(d["L"], d["e_occ"], d["e_vir"], tm)
         mlp.guess(eng, tm, d["e_occ"], d["e_vir"], t2_out=t)
         rep = eng.iterate(d["L"], d["e_occ"], d["e_vir"], t, max_sweeps=max_sweeps, tol=tol,
                           start="checked" if start == "checked" else "given", switch_tol=switch_tol,
-                          raise_on_status=False, diis=diis, hhl=hhl)
+                          raise_on_status=False, diis=diis, hhl=hhl, ring=ring)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rep = dict(rep)
