@@ -19,6 +19,15 @@ library's clamping); each is counted together with the split-K reduction that
 follows it, which is what the bench times as one R+ launch. The JSON gives the
 bytes per R+ launch keyed by "tile,splits", with the sha256 of the GEMM source,
 so that the bench reports traffic only for the kernel code that was measured.
+
+    python -m paper_2603_20912_amd.profsum mfma --counters MFMA_counter_collection.csv \
+        --command "rocprofv3 ..." --md OUT.md
+
+summarises one `--pmc SQ_INSTS_VALU_MFMA_MOPS_F64 GRBM_GUI_ACTIVE` run: per
+kernel, the FP64 matrix-core work it executed (the counter counts units of 512
+flops, padded tile rows included) over its profiled dispatch time, as TF/s and
+as a fraction of the FP64 MFMA peak, and the shader clock (GRBM_GUI_ACTIVE is
+summed over the 8 XCDs).
 """
 from __future__ import annotations
 
@@ -165,5 +174,55 @@ def main(argv=None):
     print(f"wrote {a.md} and {a.json}")
 
 
+FP64_MFMA_PEAK_TFS = 78.6
+
+
+def mfma_main(argv):
+    ap = argparse.ArgumentParser(description="per-kernel FP64 MFMA work from one rocprofv3 --pmc run")
+    ap.add_argument("--counters", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--md", required=True)
+    a = ap.parse_args(argv)
+    mops, gui, span, name = defaultdict(float), defaultdict(float), {}, {}
+    for r in csv.DictReader(open(a.counters)):
+        d = int(r["Dispatch_Id"])
+        name[d] = short_name(r["Kernel_Name"])
+        span[d] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        if r["Counter_Name"] == "SQ_INSTS_VALU_MFMA_MOPS_F64":
+            mops[d] += float(r["Counter_Value"])
+        elif r["Counter_Name"] == "GRBM_GUI_ACTIVE":
+            gui[d] += float(r["Counter_Value"])
+    per = defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    for d, k in name.items():
+        p = per[k]
+        p[0] += 1
+        p[1] += span[d]
+        p[2] += mops[d] * 512.0
+        p[3] += gui[d] / 8.0
+    sha = hashlib.sha256(open(os.path.join(ROOT, GEMM_SRC), "rb").read()).hexdigest()[:16]
+    lines = ["# FP64 MFMA work per kernel, PPL step at (o, v, naux) = (20, 200, 600)", "",
+             "Commands (run from the repository root on one MI355X, ROCm 7.2, `export TMPDIR=/tmp`):", "", "```"]
+    lines += a.command + ["```", "", f"Kernel source: `{GEMM_SRC}` sha256[:16] = `{sha}`.", "",
+                          "TF/s = SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 flops over the profiled dispatch time "
+                          f"(padded tile rows included); peak {FP64_MFMA_PEAK_TFS} TF/s. Clock from "
+                          "GRBM_GUI_ACTIVE / 8 XCDs, shown for dispatches of 0.5 ms or more (launch overhead "
+                          "inflates it on short ones).", "",
+                          "| kernel | dispatches | avg ms | MFMA F64 TF/s | % of peak | clock GHz |",
+                          "|---|---:|---:|---:|---:|---:|"]
+    for k, (n, t, fl, cyc) in sorted(per.items(), key=lambda kv: -kv[1][1])[:14]:
+        if t <= 0:
+            continue
+        tf = fl / t / 1e12
+        clk = f"{cyc / t / 1e9:.2f}" if t / n >= 5e-4 else "-"
+        lines.append(f"| `{k}` | {n} | {t / n * 1e3:.4f} | {tf:.2f} | {100 * tf / FP64_MFMA_PEAK_TFS:.1f} | {clk} |")
+    os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
+    open(a.md, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {a.md}")
+
+
 if __name__ == "__main__":
-    main()
+    import sys
+    if sys.argv[1:2] == ["mfma"]:
+        mfma_main(sys.argv[2:])
+    else:
+        main()
