@@ -13,7 +13,13 @@ value = useful flops of the pair method (one build of the upper triangle of V+-,
 2 naux P+^2, + 11 contractions) / step time. The dominant kernel is the R+ contraction GEMM; its roofline entry uses
 HIP-event timings of its launches inside the timed region.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+The same JSON line carries the metric's second half under "time_to_residual": wall time
+to an amplitude residual of 1e-7 at (40, 400, 1200) for plain FP64 and for BF16x3 sweeps
+refined in FP64 (MP2 and learned starts), without and with DIIS, with like-for-like
+speed-ups; and under "cpu_baseline" the oracle's timing on the host cores (median of 5
+after one untimed run) and its sampled residual of the mixed + learned + DIIS result.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-c3]
 """
 from __future__ import annotations
 
@@ -43,28 +49,89 @@ def nominal(o, v, naux, upper=True):
             "contract_plus": 2.0 * Pp * Pp * Np, "contract_minus": 2.0 * Pm * Pm * Nm}
 
 
-def cpu_baseline(s, o):
-    """Time one oracle PPL evaluation of the same inputs on the host cores."""
+def host_description():
+    """nproc, CPU model and the BLAS numpy calls, recorded with every oracle timing."""
     import numpy as np
-    import oracle as O
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = ""
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{b.get('name', '')} {b.get('version', '')}".strip()
+    except Exception:
+        pass
+    threads = os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
-                      or [os.cpu_count() or 1])
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            threads = max(i.get("num_threads", 1) for i in info)
+            blas = blas or f"{info[0].get('internal_api', '')} {info[0].get('version', '')}".strip()
     except Exception:
-        threads = os.cpu_count() or 1
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "blas": blas, "blas_threads": int(threads)}
+
+
+def cpu_baseline(s, o, reps=5, certify=None):
+    """The cpu_baseline leg: the oracle (NumPy FP64, all host cores) times one PPL evaluation
+    of the same (20,200,600) inputs with MP2 amplitudes, once untimed and then `reps` times
+    (median reported). With `certify` = (system, amplitudes on the device) of the converged
+    mixed run at (40,400,1200), the same leg also evaluates the oracle's residual
+    (V + PPL(t)) / D - t of those amplitudes at sampled entries."""
+    import numpy as np
+    import oracle as O
     V, D = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
     t = V / D
-    t0 = time.perf_counter()
-    R = O.ppl(s["L"], o, t)
-    dt = time.perf_counter() - t0
+    R = O.ppl(s["L"], o, t)                  # warm-up
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        R = O.ppl(s["L"], o, t)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     f = nominal(o, s["v"], s["naux"])
     assert np.isfinite(R).all()
-    return {"value": (f["build"] + f["contract"]) / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
-            "kind": "oracle", "seconds": dt,
-            "sample": f"one full oracle PPL evaluation (integrals + contraction) of the same "
-                      f"({o},{s['v']},{s['naux']}) inputs with MP2 amplitudes, scaled by the pair "
-                      f"method's useful flops of one evaluation"}
+    host = host_description()
+    out = {"value": (f["build"] + f["contract"]) / dt / 1e12, "unit": "TFLOP/s", "cores": host["blas_threads"],
+           "kind": "oracle", "seconds": dt, "seconds_each": [round(x, 3) for x in times], "host": host,
+           "sample": f"one full oracle PPL evaluation (integrals + contraction) of the same "
+                     f"({o},{s['v']},{s['naux']}) inputs with MP2 amplitudes, median of {reps} after one "
+                     f"untimed run, scaled by the pair method's useful flops of one evaluation"}
+    if certify is not None:
+        out["c3_certification"] = oracle_residual_sampled(O, *certify)
+    return out
+
+
+def oracle_residual_sampled(O, s, t, reported, n_pairs=24, n_ab=40, seed=23):
+    """Oracle residual of device amplitudes t at n_pairs occupied pairs x n_ab virtual pairs:
+    V_ij^ab, PPL(t)_ij^ab (ppl_entry) and D from the host inputs, t[i, j] one block each.
+    The full-tensor estimate sqrt(mean(d^2) o^2 v^2) is compared with the reported residual."""
+    import numpy as np
+    o, v, L = s["o"], s["v"], s["L"]
+    Lov, Lvv = L[:, :o, o:], L[:, o:, o:]
+    rng = np.random.default_rng(seed)
+    d = []
+    t0 = time.perf_counter()
+    for _ in range(n_pairs):
+        i, j = (int(x) for x in rng.integers(o, size=2))
+        tij = t[i, j].cpu().numpy()
+        for _ in range(n_ab):
+            a, b = (int(x) for x in rng.integers(v, size=2))
+            Pij = O.ppl_entry(Lvv[:, a, :], Lvv[:, b, :], tij)
+            Dij = s["e_occ"][i] + s["e_occ"][j] - s["e_vir"][a] - s["e_vir"][b]
+            d.append((float(Lov[:, i, a] @ Lov[:, j, b]) + Pij) / Dij - tij[a, b])
+    d = np.array(d)
+    est = float(np.sqrt(np.mean(d * d) * o * o * v * v))
+    return {"entries": int(d.size), "max_abs": float(np.abs(d).max()), "full_tensor_estimate": est,
+            "reported_residual": reported, "ratio": est / reported if reported > 0 else None,
+            "seconds": round(time.perf_counter() - t0, 2)}
 
 
 def measured_traffic(config):
@@ -81,6 +148,64 @@ def measured_traffic(config):
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("sha256_16"):
         return None
     return rec.get("bytes_per_launch", {}).get(f"{config[0]},{config[1]}")
+
+
+def c3_leg(args):
+    """Second half of the metric: wall time from inputs in HBM to an amplitude residual below
+    1e-7 at (40, 400, 1200), contractive generator seed 2 (every plan resident). Plain FP64
+    against BF16x3 sweeps refined in FP64, from the MP2 and from the learned start, each
+    without and with DIIS (subspace 8); speed-ups like for like (both sides without, or
+    both with DIIS). Returns the summary and the (system, amplitudes) of the mixed + learned
+    + DIIS run for the oracle's certification."""
+    import numpy as np
+    import torch
+
+    import paper_2603_20912_amd as P
+    from paper_2603_20912_amd import learned as Lr
+    import ppl_synth
+
+    o, v, naux, tol = 40, 400, 1200, 1e-7
+    t0 = time.perf_counter()
+    sysd = ppl_synth.make_system(o, v, naux, 2, "contractive")
+    gen_s = time.perf_counter() - t0
+    mlp = P.MLP(max_batch=1024)
+    mlp.set_params(np.fromfile(args.weights, dtype="<f4"))
+    runs = {"fp64": ("mp2", "fp64", False, 0), "bf16x3_fp64": ("mp2", "bf16x3", True, 0),
+            "bf16x3_fp64_learned": ("learned", "bf16x3", True, 0),
+            "fp64_diis": ("mp2", "fp64", False, 8), "bf16x3_fp64_diis": ("mp2", "bf16x3", True, 8),
+            "bf16x3_fp64_learned_diis": ("learned", "bf16x3", True, 8)}
+    small = ppl_synth.make_system(4, 24, 72, 99, "contractive")
+    for start, prec, keep, diis in runs.values():         # every code path once, untimed
+        Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=diis)
+    out = {"workload": f"({o},{v},{naux}) contractive generator seed 2, amplitude residual < {tol}",
+           "input_generation_s": round(gen_s, 2), "runs": {}}
+    kept = None
+    for label, (start, prec, keep, diis) in runs.items():
+        torch.cuda.empty_cache()
+        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=tol, prec=prec, keep_fp64=keep, diis=diis)
+        out["runs"][label] = {"seconds": round(rep["seconds"], 3), "sweeps_lp": rep["sweeps_lp"],
+                              "sweeps_fp64": rep["sweeps_fp64"], "residual": rep["residual"],
+                              "energy": rep["energy"], "status": rep["status"]}
+        print(json.dumps({"c3": {label: out["runs"][label]}}), file=sys.stderr, flush=True)
+        if label == "bf16x3_fp64_learned_diis":
+            kept = (sysd, t, rep["residual"])
+        else:
+            del t
+    mlp.close()
+    r = out["runs"]
+    for label in r:
+        r[label]["abs_err_E_vs_fp64"] = abs(r[label]["energy"] - r["fp64"]["energy"])
+
+    def ratio(a, b):
+        return round(r[a]["seconds"] / r[b]["seconds"], 3)
+    out["speedup"] = {"mixed_learned_vs_fp64_no_diis": ratio("fp64", "bf16x3_fp64_learned"),
+                      "mixed_learned_vs_fp64_both_diis": ratio("fp64_diis", "bf16x3_fp64_learned_diis"),
+                      "mixed_vs_fp64_no_diis": ratio("fp64", "bf16x3_fp64"),
+                      "mixed_vs_fp64_both_diis": ratio("fp64_diis", "bf16x3_fp64_diis"),
+                      "learned_vs_mp2_start_mixed_no_diis": ratio("bf16x3_fp64", "bf16x3_fp64_learned"),
+                      "learned_vs_mp2_start_mixed_diis": ratio("bf16x3_fp64_diis", "bf16x3_fp64_learned_diis"),
+                      "diis_vs_plain_fp64": ratio("fp64", "fp64_diis")}
+    return out, kept
 
 
 def study_c3(args):
@@ -383,6 +508,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the time-to-residual leg at (40, 400, 1200) (the metric's second half)")
     ap.add_argument("--contract-config", default="",
                     help="tile_plus,splits_plus,tile_minus,splits_minus instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -491,9 +618,14 @@ def main():
                      "flops_per_launch": fl_launch, "avg_launch_ms": round(avg_ms, 4)},
         "kernels": kernels,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(s, O_)
     eng.close()
+    del eng, L, eo, ev, t, R
+    torch.cuda.empty_cache()
+    kept = None
+    if not args.no_c3:
+        out["time_to_residual"], kept = c3_leg(args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, O_, certify=kept)
     print(json.dumps(out), flush=True)
 
 

@@ -207,7 +207,8 @@ int ppl_ring(int32_t o, int32_t v, int32_t naux, const double* L, const double* 
 /* ------------------------------------------------ linearized doubles iteration */
 #define PPL_START_MP2   0  /* start from t = V / D */
 #define PPL_START_GIVEN 1  /* start from the t2 passed in */
-#define PPL_START_GIVEN_CHECKED 2  /* start from t2, but restart from MP2 if its first residual is larger */
+#define PPL_START_GIVEN_CHECKED 2  /* start from t2, but restart from MP2 if its first residual is larger,
+                                      or at once if t2 holds a NaN or Inf (no sweep from it then) */
 #define PPL_DIIS_MAX 16            /* largest DIIS subspace */
 
 typedef struct {

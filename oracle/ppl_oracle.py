@@ -21,7 +21,8 @@ Conventions (readings of the paper, all stated in the design doc as well):
     r = ||t_new - t||_F over the full o*o*v*v tensor (absolute, FP64).
   * Correlation energy E = sum_{ijab} V_ij^ab (2 t_ij^ab - t_ij^ba).
 
-Parity pins of every function live in tests/test_oracle_pins.py.
+Parity pins of every function live in tests/test_oracle_pins.py and, for the terms and
+the energy checked against the spin-orbital equations, tests/test_ring_oracle_pins.py.
 """
 from __future__ import annotations
 
@@ -231,7 +232,8 @@ def mp2_amplitudes(L, o, e_occ, e_vir) -> np.ndarray:
 
 
 def energy(V: np.ndarray, t: np.ndarray) -> float:
-    """E = sum_{ijab} V_ij^ab (2 t_ij^ab - t_ij^ba)."""
+    """E = sum_{ijab} V_ij^ab (2 t_ij^ab - t_ij^ba), the closed-shell form of the spin-orbital
+    doubles energy 1/4 sum <IJ||AB> t_IJ^AB (pinned to it in tests/test_ring_oracle_pins.py)."""
     return float(np.sum(V * (2.0 * t - t.transpose(0, 1, 3, 2))))
 
 

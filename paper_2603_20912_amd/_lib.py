@@ -170,6 +170,83 @@ def _ptr(x):
     return x.data_ptr()
 
 
+# ---------------------------------------------------------------- argument validation
+# The C ABI receives bare device addresses and cannot see dtypes, shapes or devices: a
+# wrong tensor would be read or written out of bounds on the GPU. Every wrapper below
+# therefore checks each tensor against the layout include/ppl.h documents and raises
+# ValueError before anything reaches libppl.
+_DIMS = {}      # handle value -> {"o", "v", "naux"} (plans), list of shapes (batches), max_batch (MLPs)
+
+
+def _layout(x, name, dtype, shape=None, optional=False):
+    """Check dtype, shape and contiguity of tensor x (None only when optional)."""
+    if x is None:
+        if optional:
+            return
+        raise ValueError(f"{name}: a device tensor is required")
+    if not isinstance(x, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(x).__name__}")
+    if x.dtype != dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {x.dtype}")
+    if shape is not None and tuple(x.shape) != tuple(int(d) for d in shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: must be C-contiguous")
+
+
+def _ptrs(*specs):
+    """Device addresses of the tensors of specs (x, name, dtype, shape, optional): the
+    layouts of all of them are checked first, then that each lives on the GPU."""
+    for sp in specs:
+        _layout(*sp)
+    out = []
+    for x, name, *_ in specs:
+        if x is None:
+            out.append(None)
+            continue
+        if x.device.type != "cuda":
+            raise ValueError(f"{name}: must live on the GPU (got device {x.device})")
+        out.append(x.data_ptr())
+    return out
+
+
+def _dims(handle, what="plan"):
+    key = getattr(handle, "value", handle)
+    d = _DIMS.get(key)
+    if d is None:
+        raise ValueError(f"unknown or destroyed {what} handle")
+    return d
+
+
+def _L(x, d, name="L"):
+    n = d["o"] + d["v"]
+    return (x, name, torch.float64, (d["naux"], n, n), False)
+
+
+def _amp(x, d, name, optional=False):
+    return (x, name, torch.float64, (d["o"], d["o"], d["v"], d["v"]), optional)
+
+
+def _eo(x, d):
+    return (x, "e_occ", torch.float64, (d["o"],), False)
+
+
+def _ev(x, d):
+    return (x, "e_vir", torch.float64, (d["v"],), False)
+
+
+def _workspace(ws, nbytes):
+    if not isinstance(ws, torch.Tensor):
+        raise ValueError("workspace: expected a torch.Tensor")
+    if not ws.is_contiguous() or ws.device.type != "cuda":
+        raise ValueError("workspace: must be a contiguous GPU tensor")
+    have = ws.numel() * ws.element_size()
+    n = have if nbytes is None else int(nbytes)
+    if n > have:
+        raise ValueError(f"workspace: {n} bytes requested from a {have}-byte tensor")
+    return ws.data_ptr(), n
+
+
 def _stream_handle(stream):
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
@@ -191,6 +268,7 @@ def ppl_plan(o, v, naux, prec="fp64", keep_fp64=False, hbm_budget=0, stream=None
                    int(flags), os.fsencode(tune_cache) if tune_cache else None)
     h = ctypes.c_void_p()
     _check(load().ppl_plan(ctypes.byref(d), ctypes.byref(h)), "ppl_plan")
+    _DIMS[h.value] = {"o": int(o), "v": int(v), "naux": int(naux)}
     return h
 
 
@@ -201,21 +279,25 @@ def ppl_plan_query(plan) -> dict:
 
 
 def ppl_bind_workspace(plan, ws, nbytes=None):
-    n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
-    _check(load().ppl_bind_workspace(plan, _ptr(ws), n), "ppl_bind_workspace")
+    ptr, n = _workspace(ws, nbytes)
+    _check(load().ppl_bind_workspace(plan, ptr, n), "ppl_bind_workspace")
 
 
 def ppl_build_batch(plan, L, batch=-1):
-    _check(load().ppl_build_batch(plan, _ptr(L), int(batch)), "ppl_build_batch")
+    (pL,) = _ptrs(_L(L, _dims(plan)))
+    _check(load().ppl_build_batch(plan, pL, int(batch)), "ppl_build_batch")
 
 
 def ppl_contract(plan, t2, R, alpha=1.0, beta=0.0):
-    _check(load().ppl_contract(plan, _ptr(t2), _ptr(R), float(alpha), float(beta)), "ppl_contract")
+    d = _dims(plan)
+    pt, pr = _ptrs(_amp(t2, d, "t2"), _amp(R, d, "R"))
+    _check(load().ppl_contract(plan, pt, pr, float(alpha), float(beta)), "ppl_contract")
 
 
 def ppl_contract_tau(plan, t2, t1, R, alpha=1.0, beta=0.0):
-    _check(load().ppl_contract_tau(plan, _ptr(t2), _ptr(t1), _ptr(R), float(alpha), float(beta)),
-           "ppl_contract_tau")
+    d = _dims(plan)
+    pt, p1, pr = _ptrs(_amp(t2, d, "t2"), (t1, "t1", torch.float64, (d["o"], d["v"]), False), _amp(R, d, "R"))
+    _check(load().ppl_contract_tau(plan, pt, p1, pr, float(alpha), float(beta)), "ppl_contract_tau")
 
 
 def ppl_ring_scratch_bytes(o, v, naux):
@@ -223,13 +305,17 @@ def ppl_ring_scratch_bytes(o, v, naux):
 
 
 def ppl_ring(o, v, naux, L, t2, R, scratch, alpha=1.0, beta=0.0, stream=None):
-    _check(load().ppl_ring(int(o), int(v), int(naux), _ptr(L), _ptr(t2), _ptr(R), float(alpha), float(beta),
-                           _ptr(scratch), int(scratch.numel() * scratch.element_size()), _stream_handle(stream)),
-           "ppl_ring")
+    d = {"o": int(o), "v": int(v), "naux": int(naux)}
+    pL, pt, pr = _ptrs(_L(L, d), _amp(t2, d, "t2"), _amp(R, d, "R"))
+    sp, sn = _workspace(scratch, None)
+    _check(load().ppl_ring(d["o"], d["v"], d["naux"], pL, pt, pr, float(alpha), float(beta), sp, sn,
+                           _stream_handle(stream)), "ppl_ring")
 
 
 def ppl_hhl(plan, L, t2, R, alpha=1.0, beta=0.0):
-    _check(load().ppl_hhl(plan, _ptr(L), _ptr(t2), _ptr(R), float(alpha), float(beta)), "ppl_hhl")
+    d = _dims(plan)
+    pL, pt, pr = _ptrs(_L(L, d), _amp(t2, d, "t2"), _amp(R, d, "R"))
+    _check(load().ppl_hhl(plan, pL, pt, pr, float(alpha), float(beta)), "ppl_hhl")
 
 
 def ppl_iter_opts_default() -> ppl_iter_opts_t:
@@ -240,7 +326,9 @@ def ppl_iter_opts_default() -> ppl_iter_opts_t:
 
 def ppl_iterate(plan, L, e_occ, e_vir, t2, opts: ppl_iter_opts_t | None = None, raise_on_status=True):
     rep = ppl_iter_report_t()
-    rc = load().ppl_iterate(plan, _ptr(L), _ptr(e_occ), _ptr(e_vir), _ptr(t2),
+    d = _dims(plan)
+    pL, po, pv, pt = _ptrs(_L(L, d), _eo(e_occ, d), _ev(e_vir, d), _amp(t2, d, "t2"))
+    rc = load().ppl_iterate(plan, pL, po, pv, pt,
                             ctypes.byref(opts) if opts is not None else None, ctypes.byref(rep))
     if raise_on_status:
         _check(rc, "ppl_iterate")
@@ -273,7 +361,9 @@ def ppl_profile_read(plan) -> dict:
 
 def ppl_mp2(plan, L, e_occ, e_vir, t2_out, want_energy=True):
     e = ctypes.c_double(0.0)
-    _check(load().ppl_mp2(plan, _ptr(L), _ptr(e_occ), _ptr(e_vir), _ptr(t2_out),
+    d = _dims(plan)
+    pL, po, pv, pt = _ptrs(_L(L, d), _eo(e_occ, d), _ev(e_vir, d), _amp(t2_out, d, "t2_out"))
+    _check(load().ppl_mp2(plan, pL, po, pv, pt,
                           ctypes.byref(e) if want_energy else None), "ppl_mp2")
     return e.value if want_energy else None
 
@@ -282,6 +372,7 @@ def ppl_mlp_create(width=128, max_batch=65536, stream=None):
     h = ctypes.c_void_p()
     _check(load().ppl_mlp_create(int(width), int(max_batch), _stream_handle(stream), ctypes.byref(h)),
            "ppl_mlp_create")
+    _DIMS[h.value] = {"max_batch": int(max_batch)}
     return h
 
 
@@ -292,8 +383,8 @@ def ppl_mlp_workspace_bytes(mlp) -> int:
 
 
 def ppl_mlp_bind_workspace(mlp, ws, nbytes=None):
-    n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
-    _check(load().ppl_mlp_bind_workspace(mlp, _ptr(ws), n), "ppl_mlp_bind_workspace")
+    ptr, n = _workspace(ws, nbytes)
+    _check(load().ppl_mlp_bind_workspace(mlp, ptr, n), "ppl_mlp_bind_workspace")
 
 
 def ppl_mlp_param_count(mlp) -> int:
@@ -317,48 +408,77 @@ def ppl_mlp_get_params(mlp):
     return a
 
 
+def _xy(X, Y, n):
+    n = Y.numel() if (n is None and isinstance(Y, torch.Tensor)) else int(n if n is not None else -1)
+    if n < 0:
+        raise ValueError("Y: a device tensor is required")
+    px, py = _ptrs((X, "X", torch.float32, (n, 4), False), (Y, "Y", torch.float32, (n,), False))
+    return px, py, n
+
+
 def ppl_mlp_grad(mlp, X, Y, n=None):
     import numpy as np
-    n = Y.numel() if n is None else int(n)
+    px, py, n = _xy(X, Y, n)
     g = np.empty(ppl_mlp_param_count(mlp), dtype=np.float32)
     loss = ctypes.c_float(0.0)
-    _check(load().ppl_mlp_grad(mlp, _ptr(X), _ptr(Y), n, g.ctypes.data, ctypes.byref(loss)), "ppl_mlp_grad")
+    _check(load().ppl_mlp_grad(mlp, px, py, n, g.ctypes.data, ctypes.byref(loss)), "ppl_mlp_grad")
     return g, float(loss.value)
 
 
 def ppl_mlp_train_step(mlp, X, Y, lr, n=None, want_loss=False):
-    n = Y.numel() if n is None else int(n)
+    px, py, n = _xy(X, Y, n)
     loss = ctypes.c_float(0.0)
-    _check(load().ppl_mlp_train_step(mlp, _ptr(X), _ptr(Y), n, float(lr),
+    _check(load().ppl_mlp_train_step(mlp, px, py, n, float(lr),
                                      ctypes.byref(loss) if want_loss else None), "ppl_mlp_train_step")
     return float(loss.value) if want_loss else None
 
 
 def ppl_mlp_sigma(plan, t_mp2) -> float:
     s = ctypes.c_double(0.0)
-    _check(load().ppl_mlp_sigma(plan, _ptr(t_mp2), ctypes.byref(s)), "ppl_mlp_sigma")
+    (pt,) = _ptrs(_amp(t_mp2, _dims(plan), "t_mp2"))
+    _check(load().ppl_mlp_sigma(plan, pt, ctypes.byref(s)), "ppl_mlp_sigma")
     return float(s.value)
 
 
 def ppl_mlp_samples(plan, t_mp2, t_star, e_occ, e_vir, sigma, idx, X, Y=None):
-    _check(load().ppl_mlp_samples(plan, _ptr(t_mp2), _ptr(t_star), _ptr(e_occ), _ptr(e_vir), float(sigma),
-                                  _ptr(idx), idx.numel(), _ptr(X), _ptr(Y)), "ppl_mlp_samples")
+    d = _dims(plan)
+    if not isinstance(idx, torch.Tensor):
+        raise ValueError("idx: expected a torch.Tensor")
+    n = idx.numel()
+    if (t_star is None) != (Y is None):
+        raise ValueError("t_star and Y are given together or not at all")
+    p = _ptrs(_amp(t_mp2, d, "t_mp2"), _amp(t_star, d, "t_star", optional=True), _eo(e_occ, d), _ev(e_vir, d),
+              (idx, "idx", torch.int64, (n,), False), (X, "X", torch.float32, (n, 4), False),
+              (Y, "Y", torch.float32, (n,), True))
+    _check(load().ppl_mlp_samples(plan, p[0], p[1], p[2], p[3], float(sigma), p[4], n, p[5], p[6]),
+           "ppl_mlp_samples")
 
 
 def ppl_mlp_guess(mlp, plan, t_mp2, e_occ, e_vir, sigma, t2_out):
-    _check(load().ppl_mlp_guess(mlp, plan, _ptr(t_mp2), _ptr(e_occ), _ptr(e_vir), float(sigma),
-                                _ptr(t2_out)), "ppl_mlp_guess")
+    d = _dims(plan)
+    pt, po, pv, pg = _ptrs(_amp(t_mp2, d, "t_mp2"), _eo(e_occ, d), _ev(e_vir, d), _amp(t2_out, d, "t2_out"))
+    _check(load().ppl_mlp_guess(mlp, plan, pt, po, pv, float(sigma), pg), "ppl_mlp_guess")
 
 
 def ppl_mlp_destroy(mlp):
     if mlp is not None:
+        _DIMS.pop(getattr(mlp, "value", mlp), None)
         load().ppl_mlp_destroy(mlp)
 
 
-def _ptr_array(ts):
+def _ptr_array(ts, shapes, kind):
+    """Host array of the device addresses of one tensor per instance, each checked against
+    its instance's layout (kind "L": [naux][n][n]; "amp": [o][o][v][v])."""
+    ts = list(ts)
+    if len(ts) != len(shapes):
+        raise ValueError(f"expected {len(shapes)} tensors (one per instance), got {len(ts)}")
+    specs = []
+    for i, (t, (o, v, naux)) in enumerate(zip(ts, shapes)):
+        d = {"o": o, "v": v, "naux": naux}
+        specs.append(_L(t, d, f"L[{i}]") if kind == "L" else _amp(t, d, f"{kind}[{i}]"))
     arr = (ctypes.c_void_p * len(ts))()
-    for i, t in enumerate(ts):
-        arr[i] = _ptr(t)
+    for i, p in enumerate(_ptrs(*specs)):
+        arr[i] = p
     return arr
 
 
@@ -370,6 +490,7 @@ def ppl_batch_plan(shapes, prec="fp64", stream=None):
         descs[k] = ppl_desc_t(o, v, naux, PREC[prec], 0, -1, 0, sh, 0)
     h = ctypes.c_void_p()
     _check(load().ppl_batch_plan(n, descs, ctypes.byref(h)), "ppl_batch_plan")
+    _DIMS[h.value] = [(int(o), int(v), int(naux)) for (o, v, naux) in shapes]
     return h
 
 
@@ -381,12 +502,12 @@ def ppl_batch_query(batch):
 
 
 def ppl_batch_bind_workspace(batch, ws, nbytes=None):
-    n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
-    _check(load().ppl_batch_bind_workspace(batch, _ptr(ws), n), "ppl_batch_bind_workspace")
+    ptr, n = _workspace(ws, nbytes)
+    _check(load().ppl_batch_bind_workspace(batch, ptr, n), "ppl_batch_bind_workspace")
 
 
 def ppl_batch_build(batch, Ls):
-    _check(load().ppl_batch_build(batch, _ptr_array(Ls)), "ppl_batch_build")
+    _check(load().ppl_batch_build(batch, _ptr_array(Ls, _dims(batch, "batch"), "L")), "ppl_batch_build")
 
 
 def ppl_batch_autotune(batch, reps=2):
@@ -394,11 +515,15 @@ def ppl_batch_autotune(batch, reps=2):
 
 
 def ppl_batch_contract(batch, t2s, Rs):
-    _check(load().ppl_batch_contract(batch, _ptr_array(t2s), _ptr_array(Rs)), "ppl_batch_contract")
+    sh = _dims(batch, "batch")
+    _check(load().ppl_batch_contract(batch, _ptr_array(t2s, sh, "t2"), _ptr_array(Rs, sh, "R")),
+           "ppl_batch_contract")
 
 
 def ppl_batch_graph_capture(batch, t2s, Rs):
-    _check(load().ppl_batch_graph_capture(batch, _ptr_array(t2s), _ptr_array(Rs)), "ppl_batch_graph_capture")
+    sh = _dims(batch, "batch")
+    _check(load().ppl_batch_graph_capture(batch, _ptr_array(t2s, sh, "t2"), _ptr_array(Rs, sh, "R")),
+           "ppl_batch_graph_capture")
 
 
 def ppl_batch_graph_launch(batch):
@@ -407,11 +532,13 @@ def ppl_batch_graph_launch(batch):
 
 def ppl_batch_destroy(batch):
     if batch is not None:
+        _DIMS.pop(getattr(batch, "value", batch), None)
         load().ppl_batch_destroy(batch)
 
 
 def ppl_destroy(plan):
     if plan is not None:
+        _DIMS.pop(getattr(plan, "value", plan), None)
         load().ppl_destroy(plan)
 
 

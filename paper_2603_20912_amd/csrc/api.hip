@@ -121,8 +121,11 @@ static int g_acc_bytes(ppl_plan_t p) {
 
 // Tuned contraction configurations: "ppl-tune 1 prec o v tile+ splits+ tile- splits-" per
 // line; the last line matching (prec, o, v) wins. Unreadable files and foreign lines are
-// skipped.
-static bool tune_cache_lookup(const std::string& path, int prec, int o, int v, int cfg[4]) {
+// skipped, and so are BF16x6 lines whose K decomposition breaks the slice-length rule of
+// that precision (stream-K, or fewer slices than contract_min_splits for the padded K of
+// R+ (ldp) or R- (ldm)): the file is user-editable text and must not loosen accuracy.
+static bool tune_cache_lookup(const std::string& path, int prec, int o, int v, int64_t ldp, int64_t ldm,
+                              int cfg[4]) {
   if (path.empty()) return false;
   FILE* f = fopen(path.c_str(), "r");
   if (!f) return false;
@@ -135,6 +138,9 @@ static bool tune_cache_lookup(const std::string& path, int prec, int o, int v, i
     if (ver != 1 || pr != prec || oo != o || vv != v) continue;
     if (c[0] < 0 || c[0] >= contract_tile_count() || c[2] < 0 || c[2] >= contract_tile_count()) continue;
     if (c[1] < 0 || c[1] > kMaxSplits || c[3] < 0 || c[3] > kMaxSplits) continue;
+    if (prec == PPL_BF16X6 && (c[1] == 0 || c[1] < contract_min_splits(prec, ldp) || c[3] == 0 ||
+                               c[3] < contract_min_splits(prec, ldm)))
+      continue;
     for (int k = 0; k < 4; ++k) cfg[k] = c[k];
     found = true;
   }
@@ -752,7 +758,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   if (d->tune_cache) p->tune_cache = d->tune_cache;
   if (d->tile_contract < 0) {
     int cfg[4];
-    if (tune_cache_lookup(p->tune_cache, p->prec, p->o, p->v, cfg)) {
+    if (tune_cache_lookup(p->tune_cache, p->prec, p->o, p->v, p->ldp, p->ldm, cfg)) {
       p->tile_contract = cfg[0];
       p->split_p = cfg[1];
       p->tile_m = cfg[2];
@@ -1156,6 +1162,17 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
                       tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out));
   PPL_TRY(read_red(p, h));
   r.energy_start = h[1];
+  if ((h[2] != 0.0 || !isfinite(h[1])) && o.start == PPL_START_GIVEN_CHECKED) {
+    // a checked guess with NaN or Inf entries is rejected before any sweep: the
+    // iteration falls back to the MP2 start, which the checked start promises
+    PPL_TRY(load_mp2());
+    PPL_TRY(energy_only(st, p->o, p->v, at<double>(p, p->vs), at<double>(p, p->va), s64, a64, p->ldp, p->ldm,
+                        tabs[0], tabs[1], tabs[2], tabs[3], partials, red_out));
+    PPL_TRY(read_red(p, h));
+    r.energy_start = h[1];
+    r.restarted_mp2 = 1;
+    o.start = PPL_START_MP2;
+  }
   if (h[2] != 0.0 || !isfinite(h[1])) {
     r.status = PPL_E_NONFINITE;
     if (rep) *rep = r;

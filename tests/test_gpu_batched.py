@@ -91,11 +91,15 @@ def test_graph_replay_is_bitwise_equal_to_eager(P):
         b.close()
 
 
-def test_full_uneven_list_sampled(P):
+# FP32 accumulates K = v(v+1)/2 <= 28920 products per entry in FP32: a random-walk growth of
+# the unit roundoff 6e-8 over sqrt(K) ~ 170 terms gives ~1e-5 of the largest |R| at most
+# (measured single-evaluation errors of the FP32 GEMM are 2-5e-6 relative at K = 80256)
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_uneven_list_sampled(P, prec, bound):
     shapes = S.batched_shapes(32, seed=4)
-    say(f"batched fp64, 32 uneven instances: {[(d['o'], d['v']) for d in shapes]}")
+    say(f"batched {prec}, 32 uneven instances: {[(d['o'], d['v']) for d in shapes]}")
     sh = [(d["o"], d["v"], d["naux"]) for d in shapes]
-    b = P.Batch(sh, prec="fp64")
+    b = P.Batch(sh, prec=prec)
     Ls, ts, Rs, systems, amps = [], [], [], [], []
     for d in shapes:
         s = S.make_system(d["o"], d["v"], d["naux"], d["seed"])
@@ -118,5 +122,6 @@ def test_full_uneven_list_sampled(P):
         ref = O.ppl_sampled(s["L_host"], o, t, idx)
         R = Rs[k].cpu().numpy()
         got = np.array([R[i] for i in idx])
-        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max(), k
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err < bound, (k, err)
     b.close()

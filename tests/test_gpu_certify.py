@@ -1,0 +1,157 @@
+"""GPU results of the measured workloads certified by the CPU oracle at their own sizes.
+
+* The benchmark step at (20, 200, 600), literal generator seed 1, in the contraction
+  configuration the benchmark times (autotuned after one step): MP2 start, 10 Jacobi
+  sweeps t <- (V + PPL(t)) / D, one more evaluation R = PPL(t). The residual history is
+  held to the oracle's sweep by sweep (rtol 1e-11), the amplitudes, R and the energy to
+  1e-12 relative (Sec. 2, eq. (vfunction-chol); the linearized doubles iteration).
+* The converged result of the mixed path with the learned start and DIIS at
+  (40, 400, 1200), contractive generator seed 2: BF16x3 sweeps, then FP64 sweeps down to
+  an amplitude residual of 1e-7. The oracle evaluates the residual (V + PPL(t)) / D - t of
+  the returned amplitudes at sampled entries, each from the O(naux v^2) slices it needs,
+  and the energy sum V (2 t_ij^ab - t_ij^ba) of the returned amplitudes over the whole
+  tensor; the energy must also lie within 1e-6 Eh of the plain FP64 run's.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import ppl_synth as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2603_20912_amd", "weights", "mlp_start.f32")
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2603_20912_amd as P
+    return P
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.timeout(900)
+def test_bench_step_c2_matches_oracle(P):
+    o, v, naux, sweeps = 20, 200, 600, 10
+    say(f"bench step ({o},{v},{naux}) literal seed 1: MP2 start, {sweeps} sweeps, one evaluation")
+    s = S.make_system(o, v, naux, 1, "literal")
+    L = torch.from_numpy(s["L"]).cuda()
+    eo, ev = torch.from_numpy(s["e_occ"]).cuda(), torch.from_numpy(s["e_vir"]).cuda()
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    R = torch.empty_like(t)
+    eng = P.PPL(o, v, naux, prec="fp64")
+
+    def step():
+        rep = eng.iterate(L, eo, ev, t, max_sweeps=sweeps, tol=0.0, diverge_factor=0.0)
+        eng.contract(t, R)
+        return rep
+
+    # the benchmark's setup: build, one step, autotune on the workload's amplitudes
+    eng.build(L)
+    step()
+    eng.autotune(reps=3)
+    say(f"  tuned contraction config {eng.contract_config()}")
+    rep = step()
+    torch.cuda.synchronize()
+    t_gpu, R_gpu = t.cpu().numpy(), R.cpu().numpy()
+    eng.close()
+    del L, t, R
+    torch.cuda.empty_cache()
+    assert rep["sweeps_fp64"] == sweeps and rep["sweeps_lp"] == 0
+    # the oracle, sweep by sweep (about 5 s of host BLAS each)
+    V, D = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
+    tr = V / D
+    hist = []
+    for k in range(sweeps):
+        tr, r = O.jacobi_sweep(s["L"], o, V, D, tr)
+        hist.append(r)
+        say(f"  oracle sweep {k + 1}: r = {r:.6e}, gpu {rep['history'][k]:.6e}")
+    Rr = O.ppl(s["L"], o, tr)
+    E = O.energy(V, tr)
+    np.testing.assert_allclose(rep["history"], hist, rtol=1e-11)
+    e_t, e_R = rel(t_gpu, tr), rel(R_gpu, Rr)
+    say(f"  rel. error t {e_t:.2e}, R {e_R:.2e}, E {abs(rep['energy'] - E) / abs(E):.2e}")
+    assert e_t < 1e-12 and e_R < 1e-12
+    assert abs(rep["energy"] - E) < 1e-12 * abs(E)
+    assert abs(rep["energy_start"] - O.energy(V, V / D)) < 1e-12 * abs(rep["energy_start"])
+
+
+def sampled_residual(s, t, pairs_idx):
+    """Oracle residual (V + PPL(t)) / D - t at the sampled (i, j, a, b): V_ij^ab and
+    PPL(t)_ij^ab from the slices of L they need, t[i, j] one (v x v) block per (i, j)."""
+    o, L = s["o"], s["L"]
+    Lov, Lvv = L[:, :o, o:], L[:, o:, o:]
+    out = []
+    for (i, j), ab in pairs_idx:
+        tij = t[i, j].cpu().numpy()
+        for a, b in ab:
+            Vij = float(Lov[:, i, a] @ Lov[:, j, b])
+            Pij = O.ppl_entry(Lvv[:, a, :], Lvv[:, b, :], tij)
+            Dij = s["e_occ"][i] + s["e_occ"][j] - s["e_vir"][a] - s["e_vir"][b]
+            out.append((Vij + Pij) / Dij - tij[a, b])
+    return np.array(out)
+
+
+@pytest.mark.timeout(900)
+def test_c3_mixed_learned_diis_certified_by_oracle(P):
+    from paper_2603_20912_amd import learned as Lr
+    o, v, naux, tol = 40, 400, 1200, 1e-7
+    say(f"c3 ({o},{v},{naux}) contractive seed 2: BF16x3 + FP64, learned start, DIIS 8, to {tol}")
+    s = S.make_system(o, v, naux, 2, "contractive")
+    mlp = P.MLP(max_batch=1024)
+    mlp.set_params(np.fromfile(WEIGHTS, dtype="<f4"))
+    rep_m, t_m = Lr.time_to_tol(s, "learned", mlp=mlp, tol=tol, prec="bf16x3", keep_fp64=True, diis=8)
+    mlp.close()
+    say(f"  mixed + learned: {rep_m['sweeps_lp']} + {rep_m['sweeps_fp64']} sweeps, r {rep_m['residual']:.3e}, "
+        f"E {rep_m['energy']:.12f}, {rep_m['seconds']:.2f} s")
+    assert rep_m["status"] == 0 and rep_m["residual"] < tol and rep_m["sweeps_fp64"] >= 2
+    torch.cuda.empty_cache()
+    rep_f, t_f = Lr.time_to_tol(s, "mp2", tol=tol, prec="fp64", diis=8)
+    say(f"  fp64: {rep_f['sweeps_fp64']} sweeps, r {rep_f['residual']:.3e}, E {rep_f['energy']:.12f}")
+    assert rep_f["status"] == 0 and rep_f["residual"] < tol
+    del t_f
+    torch.cuda.empty_cache()
+    # the energy stated per result: within 1e-6 Eh of the plain FP64 run
+    assert abs(rep_m["energy"] - rep_f["energy"]) < 1e-6
+    # oracle residual of the returned amplitudes at 40 occupied pairs x 50 virtual pairs
+    rng = np.random.default_rng(23)
+    pairs = [(0, 0), (o - 1, o - 1), (0, o - 1), (o - 1, 0)] + [tuple(int(x) for x in rng.integers(o, size=2))
+                                                               for _ in range(36)]
+    pairs_idx = [(ij, [(0, 0), (v - 1, v - 1), (0, v - 1)] + [tuple(int(x) for x in rng.integers(v, size=2))
+                                                             for _ in range(47)]) for ij in pairs]
+    d = sampled_residual(s, t_m, pairs_idx)
+    n_all = o * o * v * v
+    r_est = float(np.sqrt(np.mean(d * d) * n_all))
+    # the returned t is the last sweep's output t' = (V + PPL(t_k)) / D, so its own residual is
+    # D^-1 K (t' - t_k): at most sqrt(max|D| / min|D|) rho times the reported one (rho < 1 for
+    # this generator); the sampled estimate carries sampling noise, hence the factor 1.5
+    Dmax = 2 * abs(s["e_occ"][0]) + 2 * s["e_vir"][-1]
+    Dmin = -2 * s["e_occ"][-1] + 2 * s["e_vir"][0]
+    bound = 1.5 * np.sqrt(Dmax / Dmin) * rep_m["residual"]
+    say(f"  oracle residual at {d.size} entries: max {np.abs(d).max():.2e}, full-tensor estimate {r_est:.2e} "
+        f"(reported {rep_m['residual']:.2e}, bound {bound:.2e})")
+    assert np.isfinite(d).all() and r_est < bound
+    # the oracle's energy of the returned amplitudes, over the whole tensor
+    V, _ = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
+    E = O.energy(V, t_m.cpu().numpy())
+    del V
+    say(f"  oracle energy of the mixed result {E:.12f} (GPU {rep_m['energy']:.12f})")
+    assert abs(E - rep_m["energy"]) < 1e-10 * abs(E)
+    assert abs(E - rep_f["energy"]) < 1e-6
+    del t_m
+    torch.cuda.empty_cache()

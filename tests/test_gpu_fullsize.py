@@ -3,9 +3,12 @@
 (each from its own (ac|bd) slab), plus properties that hold at any size.
 
 Bounds: FP64 1e-12 of the largest sampled |R|. FP32, BF16x3 and BF16x6 accumulate over
-K = v(v+1)/2 = 80200 terms in FP32 (unit roundoff 6e-8; a random-walk growth of
-sqrt(K) ~ 283 gives ~2e-5), so they are held to 1e-4 of the largest |R|, which
-still fails any wrong index or dropped term by orders of magnitude.
+K = v(v+1)/2 = 80200 terms in FP32 (unit roundoff 6e-8, growing like the square root of
+the slice length). Their measured whole-tensor errors against the FP64 path at this size
+are 5.1e-6 (FP32, one K slice, N(0,1) amplitudes), 3.0e-6 (BF16x3) and 7-9.6e-7 (BF16x6 in
+its 7 slices); they are held to about three times those levels, 1.5e-5, 1.5e-5 and 2e-6,
+both over the whole tensor (relative Frobenius, against the FP64 result that is itself
+checked against the oracle) and at the sampled entries (relative to the largest |R|).
 """
 import sys
 
@@ -49,8 +52,26 @@ def c3():
     return s, t, idx, ref
 
 
-@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 1e-4), ("bf16x3", 1e-4), ("bf16x6", 1e-4)])
-def test_c3_sampled_entries(P, c3, prec, bound):
+@pytest.fixture(scope="module")
+def c3_fp64(P, c3):
+    """The FP64 R of the c3 amplitudes (device), for whole-tensor comparisons."""
+    s, t, idx, ref = c3
+    o, v, naux = s["o"], s["v"], s["naux"]
+    eng = P.PPL(o, v, naux, contract_only=True)
+    L = torch.from_numpy(s["L"]).cuda()
+    eng.build(L)
+    R = eng.contract(torch.from_numpy(t).cuda())
+    torch.cuda.synchronize()
+    eng.close()
+    del eng, L
+    torch.cuda.empty_cache()
+    got = np.array([R[k].item() for k in idx])
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    return R
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("fp32", 1.5e-5), ("bf16x3", 1.5e-5), ("bf16x6", 2e-6)])
+def test_c3_sampled_entries(P, c3, c3_fp64, prec, bound):
     s, t, idx, ref = c3
     o, v, naux = s["o"], s["v"], s["naux"]
     say(f"contract {prec} (40,400,1200) sampled, planner's configuration")
@@ -64,8 +85,10 @@ def test_c3_sampled_entries(P, c3, prec, bound):
     got = np.array([R[k].item() for k in idx])
     scale = np.abs(ref).max()
     err = np.abs(got - ref).max() / scale
-    say(f"  max |R_gpu - R_oracle| / max |R| = {err:.2e}")
+    frob = (torch.linalg.norm(R - c3_fp64) / torch.linalg.norm(c3_fp64)).item()
+    say(f"  max |R_gpu - R_oracle| / max |R| = {err:.2e}; whole tensor vs FP64 {frob:.2e}")
     assert err < bound
+    assert frob < max(bound, 1e-13)
     # pair symmetry R_ij^ab = R_ji^ba (both come from one packed entry)
     Rt = R.permute(1, 0, 3, 2)
     assert (torch.linalg.norm(R - Rt) / torch.linalg.norm(R)).item() < 1e-14

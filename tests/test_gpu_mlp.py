@@ -28,6 +28,10 @@ def P():
     return P
 
 
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
 def dev(x, dtype=None):
     t = torch.from_numpy(np.ascontiguousarray(x))
     if dtype is not None:
@@ -198,3 +202,38 @@ def test_learned_start_gain_small(P):
     # the learned start never needs more sweeps than the plain start
     assert all(l <= m for m, l, _, _ in sw)
     mlp.close()
+
+
+@pytest.mark.parametrize("kind", ["nan", "inf", "worse"])
+def test_checked_start_falls_back_to_mp2(P, kind):
+    """A checked start whose guess holds a NaN or Inf is rejected before any sweep, and a
+    finite guess with a larger first residual is rejected after its first sweep; either
+    way the iteration continues from the MP2 amplitudes and ends where the MP2 start ends."""
+    o, v, naux = 6, 30, 90
+    say(f"checked start with a {kind} guess ({o},{v},{naux})")
+    s = S.make_system(o, v, naux, 41, "contractive")
+    L, eo, ev = dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"])
+    eng = P.PPL(o, v, naux)
+    t_ref = torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
+    rep_ref = eng.iterate(L, eo, ev, t_ref, max_sweeps=200, tol=1e-10)
+    tm, _ = eng.mp2(L, eo, ev)
+    g = tm.clone()
+    if kind == "nan":
+        g[1, 2, 3, 4] = float("nan")
+        g[2, 1, 4, 3] = float("nan")
+    elif kind == "inf":
+        g[0, 0, 5, 5] = float("inf")
+    else:
+        g.mul_(10.0)
+    rep = eng.iterate(L, eo, ev, g, max_sweeps=200, tol=1e-10, start="checked")
+    eng.close()
+    assert rep["restarted_mp2"] == 1 and rep["status"] == 0
+    assert rep["residual"] < 1e-10
+    assert torch.isfinite(g).all().item()
+    # the same MP2 sweeps as the plain start (the rejected guess adds its one sweep)
+    extra = 0 if kind in ("nan", "inf") else 1
+    assert rep["sweeps_fp64"] == rep_ref["sweeps_fp64"] + extra
+    assert rel(g.cpu().numpy(), t_ref.cpu().numpy()) < 1e-14
+    assert abs(rep["energy"] - rep_ref["energy"]) < 1e-13 * abs(rep_ref["energy"])
+    if kind in ("nan", "inf"):
+        assert abs(rep["energy_start"] - rep_ref["energy_start"]) < 1e-14 * abs(rep_ref["energy_start"])

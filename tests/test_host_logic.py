@@ -124,6 +124,24 @@ def test_tune_cache_entries(P, tmp_path):
     assert other["tile_contract"] == plan_info(P, 21, 200, 600, hbm_budget=1 << 40)["tile_contract"]
 
 
+def test_tune_cache_keeps_bf16x6_slices(P, tmp_path):
+    # at (40,400,1200) the padded K of both contractions needs at least 7 BF16x6 slices of
+    # at most 12288 elements: lines with stream-K or fewer slices are skipped, the last
+    # valid line wins
+    path = tmp_path / "tune.txt"
+    path.write_text("ppl-tune 1 3 40 400 9 7 9 8\n"
+                    "ppl-tune 1 3 40 400 9 0 9 8\n"        # stream-K on R+: skipped
+                    "ppl-tune 1 3 40 400 9 8 9 3\n")       # 3 slices on R-: skipped
+    i = plan_info(P, 40, 400, 1200, prec="bf16x6", hbm_budget=1 << 40, tune_cache=str(path))
+    assert (i["tile_contract"], i["splits_contract"], i["tile_contract_minus"], i["splits_contract_minus"]) == \
+        (9, 7, 9, 8)
+    path.write_text("ppl-tune 1 3 40 400 9 2 9 2\n")
+    base = plan_info(P, 40, 400, 1200, prec="bf16x6", hbm_budget=1 << 40)
+    j = plan_info(P, 40, 400, 1200, prec="bf16x6", hbm_budget=1 << 40, tune_cache=str(path))
+    assert j["splits_contract"] == base["splits_contract"] >= 7
+    assert j["splits_contract_minus"] == base["splits_contract_minus"] >= 7
+
+
 def test_contract_only_plans(P):
     full = plan_info(P, 100, 700, 4000, hbm_budget=186 << 30, build_scratch=64 << 30)
     lean = plan_info(P, 100, 700, 4000, hbm_budget=186 << 30, build_scratch=64 << 30, flags=1)
@@ -337,3 +355,78 @@ def test_tile_dims_and_contract_config_range(P):
             assert e.value.code == _lib.PPL_E_ARG
     finally:
         _lib.ppl_destroy(plan)
+
+
+def test_binding_rejects_bad_tensors_before_the_library(P):
+    """The C ABI sees bare addresses: the binding checks dtype, shape, contiguity and device
+    of every tensor against the documented layouts and raises ValueError first (CPU tensors
+    of the right layout fail on the device check only)."""
+    import numpy as np
+    import torch
+    o, v, naux = 3, 8, 6
+    h = P.ppl_plan(o, v, naux, hbm_budget=1 << 30, stream=0)
+    f64 = dict(dtype=torch.float64)
+    good = torch.zeros((o, o, v, v), **f64)
+    try:
+        bad_amps = [(torch.zeros((o, o, v, v), dtype=torch.float32), "dtype"),
+                    (torch.zeros((o, o, v, v + 1), **f64), "shape"),
+                    (torch.zeros((o, o, v, v), **f64).transpose(2, 3), "contiguous"),
+                    (good, "GPU"),
+                    (np.zeros((o, o, v, v)), "torch.Tensor"),
+                    (None, "required")]
+        for bad, msg in bad_amps:
+            with pytest.raises(ValueError, match=msg):
+                P.ppl_contract(h, bad, good)
+            with pytest.raises(ValueError, match=msg):
+                P.ppl_contract(h, good, bad)
+        n = o + v
+        for L, msg in [(torch.zeros((naux, n, n + 1), **f64), "shape"), (torch.zeros((naux, n, n)), "dtype"),
+                       (torch.zeros((naux, n, n), **f64), "GPU")]:
+            with pytest.raises(ValueError, match=msg):
+                P.ppl_build_batch(h, L)
+            with pytest.raises(ValueError, match=msg):
+                P.ppl_hhl(h, L, good, good)
+        eo, ev = torch.zeros(o, **f64), torch.zeros(v, **f64)
+        with pytest.raises(ValueError, match="e_occ.*shape"):
+            P.ppl_mp2(h, torch.zeros((naux, n, n), **f64), torch.zeros(o + 1, **f64), ev, good)
+        with pytest.raises(ValueError, match="e_vir.*dtype"):
+            P.ppl_iterate(h, torch.zeros((naux, n, n), **f64), eo, torch.zeros(v), good)
+        with pytest.raises(ValueError, match="t1.*shape"):
+            P.ppl_contract_tau(h, good, torch.zeros((v, o), **f64), good)
+    finally:
+        P.ppl_destroy(h)
+    # a destroyed plan is no longer known to the binding
+    with pytest.raises(ValueError, match="unknown"):
+        P.ppl_contract(h, good, good)
+    # the ring terms take their sizes as arguments
+    with pytest.raises(ValueError, match="R.*shape"):
+        P.ppl_ring(o, v, naux, torch.zeros((naux, o + v, o + v), **f64), good, torch.zeros((o, o, v, 1), **f64),
+                   torch.zeros(16, dtype=torch.uint8))
+    # the learned start: X [n][4] and Y [n] in FP32, index vectors in int64
+    m = P.ppl_mlp_create(128, 4096, stream=0)
+    try:
+        with pytest.raises(ValueError, match="X.*shape"):
+            P.ppl_mlp_train_step(m, torch.zeros((10, 3)), torch.zeros(10), 1e-3)
+        with pytest.raises(ValueError, match="Y.*dtype"):
+            P.ppl_mlp_grad(m, torch.zeros((10, 4)), torch.zeros(10, dtype=torch.float64))
+    finally:
+        P.ppl_mlp_destroy(m)
+    h = P.ppl_plan(o, v, naux, hbm_budget=1 << 30, stream=0)
+    try:
+        with pytest.raises(ValueError, match="idx.*dtype"):
+            P.ppl_mlp_samples(h, good, None, eo, ev, 1.0, torch.zeros(5, dtype=torch.int32), torch.zeros((5, 4)))
+    finally:
+        P.ppl_destroy(h)
+    # batched instances: one tensor per instance, each of its own instance's layout
+    shapes = [(2, 6, 5), (3, 8, 6)]
+    b = P.ppl_batch_plan(shapes, "fp64", stream=0)
+    try:
+        ts = [torch.zeros((2, 2, 6, 6), **f64), torch.zeros((3, 3, 8, 8), **f64)]
+        with pytest.raises(ValueError, match="one per instance"):
+            P.ppl_batch_contract(b, ts[:1], ts[:1])
+        with pytest.raises(ValueError, match=r"t2\[1\].*shape"):
+            P.ppl_batch_contract(b, [ts[0], ts[0]], ts)
+        with pytest.raises(ValueError, match=r"L\[0\].*GPU"):
+            P.ppl_batch_build(b, [torch.zeros((5, 8, 8), **f64), torch.zeros((6, 11, 11), **f64)])
+    finally:
+        P.ppl_batch_destroy(b)

@@ -10,7 +10,9 @@ spin-orbital terms
     ring    P(ij) P(ab) sum_kc <kb||cj> t_ik^ac
 must then have alpha-beta blocks equal to the closed-shell oracle functions ppl, hhl
 and ring, and alpha-alpha blocks equal to R_ij^ab - R_ij^ba of the same functions.
-This checks the spin adaptation of all three terms with no formula in common."""
+This checks the spin adaptation of all three terms with no formula in common. The
+closed-shell correlation energy sum V_ij^ab (2 t_ij^ab - t_ij^ba) is held the same way to
+the spin-orbital energy 1/4 sum_IJAB <IJ||AB> t_IJ^AB."""
 import numpy as np
 import pytest
 
@@ -19,6 +21,11 @@ import ppl_synth as S
 
 
 def spin_orbital_terms(L, o, t):
+    t_so, terms, _ = spin_orbital_parts(L, o, t)
+    return t_so, terms
+
+
+def spin_orbital_parts(L, o, t):
     n = L.shape[1]
     v = n - o
     eri = np.einsum("Ppq,Prs->pqrs", L, L)                       # (pq|rs)
@@ -39,7 +46,13 @@ def spin_orbital_terms(L, o, t):
     hole = 0.5 * np.einsum("klij,klab->ijab", gA[O2, O2, O2, O2], t_so)
     X = np.einsum("kbcj,ikac->ijab", gA[O2, V2, V2, O2], t_so)
     ring = X - X.transpose(1, 0, 2, 3) - X.transpose(0, 1, 3, 2) + X.transpose(1, 0, 3, 2)
-    return t_so, {"ppl": ladder, "hhl": hole, "ring": ring}
+    return t_so, {"ppl": ladder, "hhl": hole, "ring": ring}, gA[O2, O2, V2, V2]
+
+
+def spin_orbital_energy(L, o, t):
+    """1/4 sum_IJAB <IJ||AB> t_IJ^AB over the spin-orbital amplitudes of t."""
+    t_so, _, g_oovv = spin_orbital_parts(L, o, t)
+    return 0.25 * float(np.sum(g_oovv * t_so))
 
 
 def blocks(R_so):
@@ -151,3 +164,42 @@ def test_plain_and_diis_iterations_with_ring_agree():
     assert hp[-1] < 1e-10 and hd[-1] < 1e-10 and len(hd) < len(hp)
     assert np.abs(tp - td).max() < 1e-8 * np.abs(tp).max()
     assert abs(Ep - Ed) < 1e-8
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(2, 3, 2, 0), (3, 4, 5, 1), (2, 5, 3, 2), (3, 3, 4, 3)])
+def test_energy_is_the_spin_orbital_one(o, v, naux, seed):
+    # the closed-shell energy of random pair-symmetric amplitudes and of the MP2 ones
+    s = S.make_system(o, v, naux, seed)
+    V, D = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
+    for t in (S.make_amplitudes(o, v, seed + 20), V / D):
+        e_so = spin_orbital_energy(s["L"], o, t)
+        e = O.energy(V, t)
+        assert abs(e - e_so) < 1e-12 * max(abs(e_so), np.abs(V).sum() * np.abs(t).max())
+    # the MP2 energy of a closed shell is negative (every denominator is)
+    assert O.energy(V, V / D) < 0.0
+
+
+def _energy_mutant(kind):
+    def f(V, t):
+        tb = t.transpose(0, 1, 3, 2)
+        if kind == "factor":                 # dropped factor 2 on the direct term
+            return float(np.sum(V * (t - tb)))
+        if kind == "swap":                   # t^ab written for t^ba in the exchange term
+            return float(np.sum(V * (2.0 * t - t)))
+        if kind == "sign":                   # exchange term added
+            return float(np.sum(V * (2.0 * t + tb)))
+        if kind == "half":                   # a spin-orbital prefactor carried over
+            return 0.5 * float(np.sum(V * (2.0 * t - tb)))
+        raise ValueError(kind)
+    return f
+
+
+@pytest.mark.parametrize("kind", ["factor", "swap", "sign", "half"])
+def test_planted_energy_mistakes_are_caught(kind):
+    o, v, naux = 3, 4, 5
+    s = S.make_system(o, v, naux, 4)
+    V, _ = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
+    t = S.make_amplitudes(o, v, 24)
+    e_so = spin_orbital_energy(s["L"], o, t)
+    assert abs(O.energy(V, t) - e_so) < 1e-12 * abs(e_so)
+    assert abs(_energy_mutant(kind)(V, t) - e_so) > 1e-3 * abs(e_so)
