@@ -204,6 +204,23 @@ uint64_t ppl_ring_scratch_bytes(int32_t o, int32_t v, int32_t naux);
 int ppl_ring(int32_t o, int32_t v, int32_t naux, const double* L, const double* t2, double* R, double alpha,
              double beta, void* scratch, uint64_t scratch_bytes, void* stream);
 
+/*
+ * ppl_ring_static: ppl_ring for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc). It takes no
+ * scratch argument: its scratch is a static device array of PPL_RING_STATIC_BYTES that
+ * every GPU the library runs on holds until the process ends, so sizes whose
+ * ppl_ring_scratch_bytes(o, v, naux) exceeds that (about (o, v, naux) = (10, 100, 300)
+ * and beyond) return PPL_E_ARG. It allocates nothing and runs the same kernels as
+ * ppl_ring, with the same arguments, layouts and results; `stream` (NULL = default)
+ * must belong to the current device (PPL_E_ARG otherwise). Every call on one GPU shares
+ * that GPU's array, which keeps the last call's contents (each call rewrites what it
+ * reads first): calls that overlap on one GPU, on different streams or host threads,
+ * race and must not be issued.
+ */
+#define PPL_RING_STATIC_BYTES (128ull << 20)
+int ppl_ring_static(int32_t o, int32_t v, int32_t naux, const double* L, const double* t2, double* R,
+                    double alpha, double beta, void* stream);
+
 /* ------------------------------------------------ linearized doubles iteration */
 #define PPL_START_MP2   0  /* start from t = V / D */
 #define PPL_START_GIVEN 1  /* start from the t2 passed in */

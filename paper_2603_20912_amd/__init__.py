@@ -18,14 +18,14 @@ from ._lib import (ppl_mp2, ppl_mlp_create, ppl_mlp_workspace_bytes, ppl_mlp_bin
                    ppl_mlp_param_count, ppl_mlp_init, ppl_mlp_set_params, ppl_mlp_get_params, ppl_mlp_grad,
                    ppl_mlp_train_step, ppl_mlp_sigma, ppl_mlp_samples, ppl_mlp_guess, ppl_mlp_destroy,
                    PPLError, ppl_bind_workspace, ppl_build_batch, ppl_contract, ppl_contract_tau, ppl_hhl,
-                   ppl_ring, ppl_ring_scratch_bytes,
+                   ppl_ring, ppl_ring_scratch_bytes, ppl_ring_static,
                    ppl_destroy,
                    ppl_iter_opts_default, ppl_iterate, ppl_last_error, ppl_plan, ppl_plan_query,
                    ppl_profile_enable, ppl_profile_read, ppl_tile_count, ppl_tile_dims, ppl_version,
                    ppl_set_contract_config, ppl_autotune)
 
 __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace", "ppl_build_batch",
-           "ppl_contract", "ppl_contract_tau", "ppl_hhl", "ppl_ring", "ppl_ring_scratch_bytes", "ring",
+           "ppl_contract", "ppl_contract_tau", "ppl_hhl", "ppl_ring", "ppl_ring_scratch_bytes", "ppl_ring_static", "ring",
            "ppl_iterate", "ppl_destroy", "ppl_last_error", "ppl_tile_count", "ppl_tile_dims",
            "ppl_version", "ppl_iter_opts_default", "ppl_profile_enable", "ppl_profile_read",
            "ppl_set_contract_config", "ppl_autotune", "ppl_mp2", "MLP", "ppl_mlp_create",

@@ -90,6 +90,8 @@ SIGNATURES = {
     "ppl_ring_scratch_bytes": (ctypes.c_uint64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "ppl_ring": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_double,
                                 ctypes.c_double, _P, ctypes.c_uint64, _P]),
+    "ppl_ring_static": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_double,
+                                       ctypes.c_double, _P]),
     "ppl_iter_opts_default": (None, [ctypes.POINTER(ppl_iter_opts_t)]),
     "ppl_iterate": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ppl_iter_opts_t),
                                    ctypes.POINTER(ppl_iter_report_t)]),
@@ -310,6 +312,16 @@ def ppl_ring(o, v, naux, L, t2, R, scratch, alpha=1.0, beta=0.0, stream=None):
     sp, sn = _workspace(scratch, None)
     _check(load().ppl_ring(d["o"], d["v"], d["naux"], pL, pt, pr, float(alpha), float(beta), sp, sn,
                            _stream_handle(stream)), "ppl_ring")
+
+
+PPL_RING_STATIC_BYTES = 128 << 20
+
+
+def ppl_ring_static(o, v, naux, L, t2, R, alpha=1.0, beta=0.0, stream=None):
+    d = {"o": int(o), "v": int(v), "naux": int(naux)}
+    pL, pt, pr = _ptrs(_L(L, d), _amp(t2, d, "t2"), _amp(R, d, "R"))
+    _check(load().ppl_ring_static(d["o"], d["v"], d["naux"], pL, pt, pr, float(alpha), float(beta),
+                                  _stream_handle(stream)), "ppl_ring_static")
 
 
 def ppl_hhl(plan, L, t2, R, alpha=1.0, beta=0.0):

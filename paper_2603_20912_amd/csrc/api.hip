@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "ppl_internal.h"
@@ -1106,6 +1107,66 @@ int ppl_ring(int32_t o, int32_t v, int32_t naux, const double* L, const double* 
   hipStream_t st = (hipStream_t)stream;
   PPL_TRY(ring_integrals(st, o, v, naux, L, (char*)scratch, r));
   return ring_apply(st, o, v, t2, R, alpha, beta, (char*)scratch, r);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- ring terms without allocation
+// Scratch of ppl_ring_static: one file-scope device array, a copy of which every GPU the
+// library runs on holds until the process ends. Host code never uses its name as an
+// address: the device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device (with that device current) on the first call there and kept below.
+static __device__ __align__(256) char g_static_scratch[PPL_RING_STATIC_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxDevices] = {};
+
+// device address of the current device's copy of g_static_scratch; the stream (if any)
+// must belong to the current device
+static int static_scratch(hipStream_t st, void** out) {
+  int dev = 0;
+  PPL_HIP_TRY(hipGetDevice(&dev));
+  if (st) {
+    int sdev = -1;
+    PPL_HIP_TRY(hipStreamGetDevice(st, &sdev));
+    if (sdev != dev)
+      return fail(PPL_E_ARG, "the stream belongs to device %d, the current device is %d", sdev, dev);
+  }
+  if (dev < 0 || dev >= kMaxDevices) return fail(PPL_E_UNSUPPORTED, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_static_scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PPL_E_HIP, "hipGetSymbolAddress of the static scratch failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  return PPL_OK;
+}
+
+extern "C" {
+
+int ppl_ring_static(int32_t o, int32_t v, int32_t naux, const double* L, const double* t2, double* R,
+                    double alpha, double beta, void* stream) {
+  g_err[0] = 0;
+  RingLayout r;
+  if (!ring_layout(o, v, naux, r)) return fail(PPL_E_ARG, "bad sizes o=%d v=%d naux=%d", o, v, naux);
+  if (!L || !t2 || !R) return fail(PPL_E_ARG, "null device pointer");
+  if ((const void*)t2 == (const void*)R) return fail(PPL_E_ARG, "R may not alias t2");
+  if (r.bytes > (uint64_t)PPL_RING_STATIC_BYTES)
+    return fail(PPL_E_ARG,
+                "the ring terms at o=%d v=%d naux=%d need %llu B of scratch, more than the %llu B static "
+                "scratch (use ppl_ring with a caller scratch)",
+                o, v, naux, (unsigned long long)r.bytes, (unsigned long long)PPL_RING_STATIC_BYTES);
+  hipStream_t st = (hipStream_t)stream;
+  void* ws = nullptr;
+  PPL_TRY(static_scratch(st, &ws));
+  // the same kernels as ppl_ring, on this device's copy of the static scratch
+  PPL_TRY(ring_integrals(st, o, v, naux, L, (char*)ws, r));
+  return ring_apply(st, o, v, t2, R, alpha, beta, (char*)ws, r);
 }
 
 int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double* e_vir, double* t2,
