@@ -502,6 +502,91 @@ def study_terms(args):
     print(json.dumps({"study": out}), flush=True)
 
 
+def study_kernels(args):
+    """Every MFMA kernel family once more after an untimed first call, for per-kernel profiles
+    (rocprofv3 kernel traces and counters): at (40, 400, 1200), contractive generator seed 2
+    with N(0,1) pair-symmetric amplitudes, the integral build and one contraction in FP32,
+    BF16x3 and BF16x6 (contract-only plans, the planner's tiles), the hole-hole ladder and
+    the ring terms in FP64; the learned-start inference (BF16 MFMA) at (30, 300, 900); the
+    32 uneven batched instances (the grouped persistent contraction) in FP64 and FP32."""
+    import numpy as np
+    import torch
+
+    import paper_2603_20912_amd as P
+    import ppl_synth
+
+    # one plain 1 GiB device copy first: the reference that calibrates byte counters
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    o, v, naux = 40, 400, 1200
+    sysd = ppl_synth.make_system(o, v, naux, 2, "contractive")
+    L = torch.from_numpy(sysd["L"]).cuda()
+    t = torch.from_numpy(ppl_synth.make_amplitudes(o, v, 3)).cuda()
+    R = torch.empty_like(t)
+    out = {}
+    for prec in ("fp32", "bf16x3", "bf16x6"):
+        eng = P.PPL(o, v, naux, prec=prec, contract_only=True)
+        for _ in range(2):
+            eng.build(L)
+            eng.contract(t, R)
+        torch.cuda.synchronize()
+        out[prec] = {"contract_config": list(eng.contract_config())}
+        eng.close()
+        del eng
+        torch.cuda.empty_cache()
+        print(json.dumps({"done": prec}), file=sys.stderr, flush=True)
+    eng = P.PPL(o, v, naux, prec="fp64", contract_only=True)
+    for _ in range(2):
+        eng.hhl(L, t, R)
+    eng.close()
+    del eng
+    torch.cuda.empty_cache()
+    scratch = torch.empty(P.ppl_ring_scratch_bytes(o, v, naux), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        P.ring(L, t, R, scratch=scratch)
+    torch.cuda.synchronize()
+    del scratch, L, t, R
+    torch.cuda.empty_cache()
+    print(json.dumps({"done": "hhl, ring"}), file=sys.stderr, flush=True)
+    # learned-start inference on a held-out instance
+    o5, v5, n5 = 30, 300, 900
+    s5 = ppl_synth.make_system(o5, v5, n5, 3000, "contractive")
+    d = {k: torch.from_numpy(np.ascontiguousarray(s5[k])).cuda() for k in ("L", "e_occ", "e_vir")}
+    eng = P.PPL(o5, v5, n5, contract_only=False)
+    tm, _ = eng.mp2(d["L"], d["e_occ"], d["e_vir"])
+    mlp = P.MLP(max_batch=1024)
+    mlp.set_params(np.fromfile(args.weights, dtype="<f4"))
+    for _ in range(2):
+        g = mlp.guess(eng, tm, d["e_occ"], d["e_vir"])
+    torch.cuda.synchronize()
+    mlp.close()
+    eng.close()
+    del eng, tm, g, d
+    torch.cuda.empty_cache()
+    print(json.dumps({"done": "mlp"}), file=sys.stderr, flush=True)
+    # the batched instances
+    shapes = ppl_synth.batched_shapes(32, seed=4)
+    tup = [(x["o"], x["v"], x["naux"]) for x in shapes]
+    Ls = [torch.from_numpy(ppl_synth.make_system(*sh, x["seed"])["L"]).cuda() for sh, x in zip(tup, shapes)]
+    ts = [torch.from_numpy(ppl_synth.make_amplitudes(sh[0], sh[1], x["seed"] + 5000)).cuda()
+          for sh, x in zip(tup, shapes)]
+    Rs = [torch.empty_like(x) for x in ts]
+    for prec in ("fp64", "fp32"):
+        b = P.Batch(tup, prec=prec)
+        b.build(Ls)
+        for _ in range(2):
+            b.contract(ts, Rs)
+        torch.cuda.synchronize()
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+        print(json.dumps({"done": f"batched {prec}"}), file=sys.stderr, flush=True)
+    print(json.dumps({"study": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,7 +602,8 @@ def main():
     ap.add_argument("--study", default="", help="c3: time-to-1e-7 study at (40, 400, 1200); "
                     "batched: the 32 uneven instances, grouped graph launch vs one plan each; "
                     "paper: one streamed FP64 evaluation at (nocc, nvir, nvec) = (100, 700, 4000); "
-                    "terms: ladder, ladder with singles and hole-hole ladder at (40, 400, 1200)")
+                    "terms: ladder, ladder with singles and hole-hole ladder at (40, 400, 1200); "
+                    "kernels: every MFMA kernel family once, for rocprofv3 profiles")
     ap.add_argument("--paper-shape", default="100,700,4000", help="nocc,nvir,nvec of --study paper")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2603_20912_amd", "weights", "mlp_start.f32"))
     args = ap.parse_args()
@@ -529,6 +615,8 @@ def main():
         return study_paper(args)
     if args.study == "terms":
         return study_terms(args)
+    if args.study == "kernels":
+        return study_kernels(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(every box has a single MI355X); run with --gpus 1", file=sys.stderr)

@@ -220,9 +220,114 @@ def mfma_main(argv):
     print(f"wrote {a.md}")
 
 
+PEAK_TFS = {"F64": 78.6, "F32": 157.3, "BF16": 2500.0}   # MI355X dense matrix peaks
+# flops per unit of SQ_INSTS_VALU_MFMA_MOPS_<type> (checked against the known work of the
+# FP64 ring GEMM, the FP32 contraction and the BF16x3 contraction, padded rows included)
+MOPS_FLOPS = {"F64": 512.0, "F32": 512.0, "BF16": 512.0}
+N_SIMD = 1024                                               # 256 CUs x 4 SIMDs
+
+
+def _per_dispatch(path):
+    """{dispatch id: {"name", "grid", "t" (s), counter: value}} of one counter CSV."""
+    out = {}
+    for r in csv.DictReader(open(path)):
+        d = int(r["Dispatch_Id"])
+        e = out.setdefault(d, {"name": short_name(r["Kernel_Name"]), "grid": int(r["Grid_Size"]),
+                               "t": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def kernels_main(argv):
+    """Per-kernel summary of one --kernel-trace run and --pmc runs of the same command:
+    time, executed matrix-core work by type against its peak, matrix-core busy fraction,
+    clock, LDS bank conflicts and LDS-issue waits, and calibrated HBM bytes."""
+    ap = argparse.ArgumentParser(description=kernels_main.__doc__)
+    ap.add_argument("--trace", required=True, help="kernel_trace.csv of the --kernel-trace run")
+    ap.add_argument("--mfma", required=True, help="counter CSV with SQ_INSTS_VALU_MFMA_MOPS_*, "
+                    "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
+    ap.add_argument("--lds", required=True, help="counter CSV with SQ_LDS_BANK_CONFLICT, SQ_INSTS_LDS, "
+                    "SQ_WAIT_INST_LDS and SQ_WAVE_CYCLES")
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--top", type=int, default=30)
+    a = ap.parse_args(argv)
+    tr = defaultdict(lambda: [0, 0.0])       # (kernel, grid) -> dispatches, seconds
+    for r in csv.DictReader(open(a.trace)):
+        grid = int(r["Grid_Size"]) if "Grid_Size" in r else \
+            int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        k = (short_name(r["Kernel_Name"]), grid)
+        tr[k][0] += 1
+        tr[k][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+
+    def group(path):
+        g = defaultdict(lambda: defaultdict(float))
+        for e in _per_dispatch(path).values():
+            c = g[(e["name"], e["grid"])]
+            for name, x in e.items():
+                if name not in ("name", "grid"):
+                    c[name] += x
+        return g
+    mf, ld = group(a.mfma), group(a.lds)
+    fr, wr = read_counters(a.fetch), read_counters(a.write)
+    cal = calibration_dispatch(wr)
+    fscale = GIB_KIB / float(next(r for r in fr if int(r["Dispatch_Id"]) == cal)["Counter_Value"])
+    wscale = GIB_KIB / float(next(r for r in wr if int(r["Dispatch_Id"]) == cal)["Counter_Value"])
+    wmap = {int(r["Dispatch_Id"]): float(r["Counter_Value"]) for r in wr}
+    hbm = defaultdict(lambda: [0, 0.0])
+    for r in fr:
+        d = int(r["Dispatch_Id"])
+        if d == cal or d not in wmap:
+            continue
+        k = (short_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+        hbm[k][0] += 1
+        hbm[k][1] += (float(r["Counter_Value"]) * fscale + wmap[d] * wscale) * 1024.0
+    sha = hashlib.sha256(open(os.path.join(ROOT, GEMM_SRC), "rb").read()).hexdigest()[:16]
+    lines = [f"# {a.title}", "", "Commands (run from the repository root on one MI355X, ROCm 7.2, "
+             "`export TMPDIR=/tmp`):", "", "```"] + a.command + ["```", "",
+             f"Kernel source: `{GEMM_SRC}` sha256[:16] = `{sha}`.", "",
+             "Columns: kernel and grid (threads); dispatches and average time from the kernel trace; "
+             "executed matrix-core work per type (SQ_INSTS_VALU_MFMA_MOPS_<type> x 512 flops, padded tile "
+             "rows included) over the dispatch time of the counter run, as "
+             "TF/s and as a fraction of that type's dense peak (F64 78.6, F32 157.3, BF16 2500 TF/s); MFMA busy "
+             "= SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 1024 SIMDs); clock = GRBM_GUI_ACTIVE / 8 over "
+             "the dispatch time (dispatches of 0.4 ms or more); LDS conflict = SQ_LDS_BANK_CONFLICT cycles per "
+             "SQ_INSTS_LDS instruction; LDS wait = SQ_WAIT_INST_LDS over SQ_WAVE_CYCLES (share of wave time "
+             "spent waiting to issue an LDS instruction); HBM = FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB "
+             f"device copy (x {fscale:.4f} and x {wscale:.4f}), per dispatch.", "",
+             "| kernel | grid | n | avg ms | MFMA type | TF/s | % peak | MFMA busy % | GHz | LDS conflict | "
+             "LDS wait % | HBM GB |", "|---|---:|---:|---:|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(tr, key=lambda k: -tr[k][1])[:a.top]:
+        n, t = tr[k]
+        c, l = mf.get(k, {}), ld.get(k, {})
+        tf, typ, frac = "", "-", ""
+        tm = c.get("t", 0.0)
+        for ty in ("F64", "F32", "BF16"):
+            m = c.get(f"SQ_INSTS_VALU_MFMA_MOPS_{ty}", 0.0)
+            if m > 0 and tm > 0:
+                x = m * MOPS_FLOPS[ty] / tm / 1e12
+                typ, tf, frac = ty, f"{x:.1f}", f"{100 * x / PEAK_TFS[ty]:.1f}"
+        gui = c.get("GRBM_GUI_ACTIVE", 0.0)
+        busy = f"{100 * c['SQ_VALU_MFMA_BUSY_CYCLES'] / (gui / 8 * N_SIMD):.1f}" if gui else ""
+        clk = f"{gui / 8 / tm / 1e9:.2f}" if gui and tm and tm / max(1, n) > 4e-4 else "-"
+        conf = f"{l['SQ_LDS_BANK_CONFLICT'] / l['SQ_INSTS_LDS']:.2f}" if l.get("SQ_INSTS_LDS") else ""
+        wait = f"{100 * l['SQ_WAIT_INST_LDS'] / l['SQ_WAVE_CYCLES']:.1f}" if l.get("SQ_WAVE_CYCLES") else ""
+        hb = f"{hbm[k][1] / hbm[k][0] / 1e9:.3f}" if hbm.get(k) and hbm[k][0] else ""
+        lines.append(f"| `{k[0]}` | {k[1]} | {n} | {t / n * 1e3:.3f} | {typ} | {tf} | {frac} | {busy} | {clk} | "
+                     f"{conf} | {wait} | {hb} |")
+    os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
+    open(a.md, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {a.md}")
+
+
 if __name__ == "__main__":
     import sys
     if sys.argv[1:2] == ["mfma"]:
         mfma_main(sys.argv[2:])
+    elif sys.argv[1:2] == ["kernels"]:
+        kernels_main(sys.argv[2:])
     else:
         main()
