@@ -155,7 +155,8 @@ def c3_leg(args):
     1e-7 at (40, 400, 1200), contractive generator seed 2 (every plan resident). Plain FP64
     against BF16x3 sweeps refined in FP64, from the MP2 and from the learned start, each
     without and with DIIS (subspace 8); speed-ups like for like (both sides without, or
-    both with DIIS). Returns the summary and the (system, amplitudes) of the mixed + learned
+    both with DIIS). The same pair with DIIS also for the full linearized doubles operator
+    (ladder, hole-hole ladder and ring terms), whose fixed point differs. Returns the summary and the (system, amplitudes) of the mixed + learned
     + DIIS run for the oracle's certification."""
     import numpy as np
     import torch
@@ -170,19 +171,24 @@ def c3_leg(args):
     gen_s = time.perf_counter() - t0
     mlp = P.MLP(max_batch=1024)
     mlp.set_params(np.fromfile(args.weights, dtype="<f4"))
-    runs = {"fp64": ("mp2", "fp64", False, 0), "bf16x3_fp64": ("mp2", "bf16x3", True, 0),
-            "bf16x3_fp64_learned": ("learned", "bf16x3", True, 0),
-            "fp64_diis": ("mp2", "fp64", False, 8), "bf16x3_fp64_diis": ("mp2", "bf16x3", True, 8),
-            "bf16x3_fp64_learned_diis": ("learned", "bf16x3", True, 8)}
+    # (start, precision, FP64 copy, DIIS subspace, the full linearized doubles operator: ladder,
+    # hole-hole ladder and ring terms)
+    runs = {"fp64": ("mp2", "fp64", False, 0, False), "bf16x3_fp64": ("mp2", "bf16x3", True, 0, False),
+            "bf16x3_fp64_learned": ("learned", "bf16x3", True, 0, False),
+            "fp64_diis": ("mp2", "fp64", False, 8, False), "bf16x3_fp64_diis": ("mp2", "bf16x3", True, 8, False),
+            "bf16x3_fp64_learned_diis": ("learned", "bf16x3", True, 8, False),
+            "fp64_diis_full_operator": ("mp2", "fp64", False, 8, True),
+            "bf16x3_fp64_diis_full_operator": ("mp2", "bf16x3", True, 8, True)}
     small = ppl_synth.make_system(4, 24, 72, 99, "contractive")
-    for start, prec, keep, diis in runs.values():         # every code path once, untimed
-        Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=diis)
+    for start, prec, keep, diis, full in runs.values():   # every code path once, untimed
+        Lr.time_to_tol(small, start, mlp=mlp, prec=prec, keep_fp64=keep, diis=diis, hhl=full, ring=full)
     out = {"workload": f"({o},{v},{naux}) contractive generator seed 2, amplitude residual < {tol}",
            "input_generation_s": round(gen_s, 2), "runs": {}}
     kept = None
-    for label, (start, prec, keep, diis) in runs.items():
+    for label, (start, prec, keep, diis, full) in runs.items():
         torch.cuda.empty_cache()
-        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=tol, prec=prec, keep_fp64=keep, diis=diis)
+        rep, t = Lr.time_to_tol(sysd, start, mlp=mlp, tol=tol, prec=prec, keep_fp64=keep, diis=diis, hhl=full,
+                                ring=full)
         out["runs"][label] = {"seconds": round(rep["seconds"], 3), "sweeps_lp": rep["sweeps_lp"],
                               "sweeps_fp64": rep["sweeps_fp64"], "residual": rep["residual"],
                               "energy": rep["energy"], "status": rep["status"]}
@@ -194,7 +200,8 @@ def c3_leg(args):
     mlp.close()
     r = out["runs"]
     for label in r:
-        r[label]["abs_err_E_vs_fp64"] = abs(r[label]["energy"] - r["fp64"]["energy"])
+        ref = "fp64_diis_full_operator" if label.endswith("full_operator") else "fp64"
+        r[label]["abs_err_E_vs_fp64"] = abs(r[label]["energy"] - r[ref]["energy"])
 
     def ratio(a, b):
         return round(r[a]["seconds"] / r[b]["seconds"], 3)
@@ -204,7 +211,9 @@ def c3_leg(args):
                       "mixed_vs_fp64_both_diis": ratio("fp64_diis", "bf16x3_fp64_diis"),
                       "learned_vs_mp2_start_mixed_no_diis": ratio("bf16x3_fp64", "bf16x3_fp64_learned"),
                       "learned_vs_mp2_start_mixed_diis": ratio("bf16x3_fp64_diis", "bf16x3_fp64_learned_diis"),
-                      "diis_vs_plain_fp64": ratio("fp64", "fp64_diis")}
+                      "diis_vs_plain_fp64": ratio("fp64", "fp64_diis"),
+                      "mixed_vs_fp64_full_operator_both_diis": ratio("fp64_diis_full_operator",
+                                                                     "bf16x3_fp64_diis_full_operator")}
     return out, kept
 
 

@@ -65,9 +65,9 @@ typedef struct ppl_plan_s* ppl_plan_t;
  * ppl_mp2 return PPL_E_STATE on it. */
 #define PPL_PLAN_CONTRACT_ONLY 1
 /* ppl_desc_t.flags: the plan also reserves the buffers of the ring terms
- * (ppl_ring_scratch_bytes plus two [o][o][v][v] FP64 tensors), so that ppl_iterate can add
- * them to every sweep (ppl_iter_opts_t.ring). PPL_E_ARG together with
- * PPL_PLAN_CONTRACT_ONLY. */
+ * (ppl_ring_scratch_bytes plus two [o][o][v][v] FP64 tensors, and for a low-precision plan
+ * the ring integrals J and K in that precision), so that ppl_iterate can add them to every
+ * sweep (ppl_iter_opts_t.ring). PPL_E_ARG together with PPL_PLAN_CONTRACT_ONLY. */
 #define PPL_PLAN_RING 2
 
 /* Problem description (input of ppl_plan). */
@@ -241,9 +241,10 @@ typedef struct {
   int32_t diis;             /* DIIS subspace size (<= the plan's diis_max); 0 or 1 = plain Jacobi */
   int32_t hhl;              /* 1: sweeps solve t = (V + PPL(t) + HHL(t)) / D (hole-hole ladder, ppl_hhl;
                                resident plans only, PPL_E_UNSUPPORTED otherwise) */
-  int32_t ring;             /* 1: sweeps also add the ring terms RING(t) (ppl_ring), computed in FP64
-                               from the FP64 amplitudes; needs a resident PPL_PLAN_RING plan
-                               (PPL_E_STATE otherwise) */
+  int32_t ring;             /* 1: sweeps also add the ring terms RING(t) (ppl_ring) of the FP64
+                               amplitudes, their three GEMMs in the sweep's precision (low-precision
+                               sweeps: the plan's precision with FP32 accumulation; FP64 sweeps:
+                               FP64); needs a resident PPL_PLAN_RING plan (PPL_E_STATE otherwise) */
 } ppl_iter_opts_t;
 
 typedef struct {

@@ -55,13 +55,17 @@ struct Layout {
 };
 
 // Scratch of the ring terms: staged Cholesky blocks (ov, oo, vv rows of P), the (kj|bc)
-// product, and seven (o v) x (o v) pair matrices.
+// product, and seven (o v) x (o v) pair matrices. With lp_prec (a plan whose low-precision
+// sweeps run the ring GEMMs in that precision) also J and K in it, jl and kl: one region
+// each of its planes back to back (FP32: one; BF16x3: hi, lo; BF16x6: hi, mid, lo).
 struct RingLayout {
   int64_t ldx = 0, ldk = 0, ldg = 0;
   uint64_t xov = 0, xoo = 0, xvv = 0, g = 0, j = 0, k = 0, xa = 0, an = 0, b = 0, c1 = 0, c2 = 0, bytes = 0;
+  int lp_prec = PPL_FP64;
+  uint64_t jl = 0, kl = 0, lp_plane = 0;   // low-precision J, K and the bytes of one of their planes
 };
 
-static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r) {
+static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r, int lp_prec = PPL_FP64) {
   if (o < 1 || v < 1 || naux < 1 || o > 32767 || v > 32767) return false;
   r.ldx = pad_ld(naux);
   r.ldk = pad_ld(o * v);
@@ -82,6 +86,12 @@ static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r) {
   r.b = L.take(m).off;
   r.c1 = L.take(m).off;
   r.c2 = L.take(m).off;
+  r.lp_prec = lp_prec;
+  if (lp_prec != PPL_FP64) {
+    r.lp_plane = (uint64_t)o * v * r.ldk * elem_bytes(lp_prec);
+    r.jl = L.take(r.lp_plane * planes(lp_prec)).off;
+    r.kl = L.take(r.lp_plane * planes(lp_prec)).off;
+  }
   r.bytes = L.cur;
   return true;
 }
@@ -241,7 +251,7 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   p->g = L.take(gbytes);
   if (p->ring) {
     RingLayout rl;
-    ring_layout(p->o, p->v, p->naux, rl);
+    ring_layout(p->o, p->v, p->naux, rl, p->ops[0].prec);
     p->ring_ws = L.take(rl.bytes);
     p->tfull = L.take((uint64_t)o * o * v * v * 8);
     p->rfull = L.take((uint64_t)o * o * v * v * 8);
@@ -1088,6 +1098,38 @@ static int ring_apply(hipStream_t st, int o, int v, const double* t2, double* R,
   return ring_unpack(st, o, v, d(r.c1), d(r.c2), r.ldk, R, alpha, beta);
 }
 
+// J and K of the scratch (FP64, from ring_integrals) in the low precision of the layout
+static int ring_integrals_lp(hipStream_t st, int o, int v, char* w, const RingLayout& r) {
+  const int64_t ov = (int64_t)o * v;
+  const int prec = r.lp_prec;
+  PPL_TRY(convert_rows(st, prec, (const double*)(w + r.j), ov, ov, r.ldk, w + r.jl,
+                       prec == PPL_FP32 ? nullptr : w + r.jl + r.lp_plane));
+  return convert_rows(st, prec, (const double*)(w + r.k), ov, ov, r.ldk, w + r.kl,
+                      prec == PPL_FP32 ? nullptr : w + r.kl + r.lp_plane);
+}
+
+// R = RING(t2) with the three GEMMs in the layout's low precision (FP32 accumulation): the
+// operands are packed in that precision into the Xa, An and B regions (FP64-sized, so they
+// hold every plane), the FP32 results C1, C2 go to their FP64-sized regions.
+static int ring_apply_lp(hipStream_t st, int o, int v, const double* t2, double* R, char* w, const RingLayout& r) {
+  const int64_t ov = (int64_t)o * v;
+  const int prec = r.lp_prec;
+  const uint64_t pl = r.lp_plane;
+  auto lo = [&](uint64_t off) -> void* { return prec == PPL_FP32 ? nullptr : (void*)(w + off + pl); };
+  PPL_TRY(ring_pack_lp(st, prec, o, v, t2, r.ldk, w + r.xa, lo(r.xa), w + r.an, lo(r.an), w + r.b, lo(r.b)));
+  int tile = -1, sp = 1;
+  contract_choose(prec, ov, ov, r.ldk, 1, &tile, &sp);
+  float* c1 = (float*)(w + r.c1);
+  float* c2 = (float*)(w + r.c2);
+  PPL_TRY(gemm_contract(st, prec, tile, ov, ov, r.ldk, w + r.xa, lo(r.xa), r.ldk, w + r.jl, lo(r.jl), r.ldk, c1,
+                        r.ldk, 0, 1, nullptr, 0, 0, false));
+  PPL_TRY(gemm_contract(st, prec, tile, ov, ov, r.ldk, w + r.an, lo(r.an), r.ldk, w + r.kl, lo(r.kl), r.ldk, c1,
+                        r.ldk, 0, 1, nullptr, 0, 0, true));
+  PPL_TRY(gemm_contract(st, prec, tile, ov, ov, r.ldk, w + r.b, lo(r.b), r.ldk, w + r.kl, lo(r.kl), r.ldk, c2,
+                        r.ldk, 0, 1, nullptr, 0, 0, false));
+  return ring_unpack_f32(st, o, v, c1, c2, r.ldk, R, 1.0, 0.0);
+}
+
 uint64_t ppl_ring_scratch_bytes(int32_t o, int32_t v, int32_t naux) {
   RingLayout r;
   return ring_layout(o, v, naux, r) ? r.bytes : 0;
@@ -1201,8 +1243,9 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
   if (o.hhl) PPL_TRY(hhl_integrals(p, L));
   RingLayout rl;
   if (o.ring) {
-    ring_layout(p->o, p->v, p->naux, rl);
+    ring_layout(p->o, p->v, p->naux, rl, p->ops[0].prec);
     PPL_TRY(ring_integrals(st, p->o, p->v, p->naux, L, at<char>(p, p->ring_ws), rl));
+    if (rl.lp_prec != PPL_FP64) PPL_TRY(ring_integrals_lp(st, p->o, p->v, at<char>(p, p->ring_ws), rl));
   }
 
   const int* tabs[4] = {at<int>(p, p->tab_op), at<int>(p, p->tab_om), at<int>(p, p->tab_vp),
@@ -1274,8 +1317,12 @@ int ppl_iterate(ppl_plan_t p, const double* L, const double* e_occ, const double
       const double ov = (double)p->o * p->v;
       ProfScope pr(p, PPL_PROF_OTHER, 6.0 * ov * ov * ov);
       PPL_TRY(unpack_t(st, p->o, p->v, s64, p->ldp, a64, p->ldm, at<double>(p, p->tfull)));
-      PPL_TRY(ring_apply(st, p->o, p->v, at<double>(p, p->tfull), at<double>(p, p->rfull), 1.0, 0.0,
-                         at<char>(p, p->ring_ws), rl));
+      if (s.prec == PPL_FP64)
+        PPL_TRY(ring_apply(st, p->o, p->v, at<double>(p, p->tfull), at<double>(p, p->rfull), 1.0, 0.0,
+                           at<char>(p, p->ring_ws), rl));
+      else   // low-precision sweeps: the ring GEMMs in the sweep's precision as well
+        PPL_TRY(ring_apply_lp(st, p->o, p->v, at<double>(p, p->tfull), at<double>(p, p->rfull),
+                              at<char>(p, p->ring_ws), rl));
       PPL_TRY(add_pm(st, s.prec == PPL_FP64 ? PPL_FP64 : PPL_FP32, p->o, p->v, at<double>(p, p->rfull),
                      at<void>(p, p->rp), p->ldp, at<void>(p, p->rm), p->ldm, tabs[0], tabs[1], tabs[2], tabs[3]));
     }

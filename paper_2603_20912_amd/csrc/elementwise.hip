@@ -1013,10 +1013,13 @@ int count_nonfinite(hipStream_t s, const double* x, int64_t n, double* partials,
 
 // ------------------------------------------------------------------ ring terms
 // Operands of the ring terms as (o v) x (o v) matrices over the pairs (i,a) and (k,c),
-// rows of ld elements (columns from o v on zero):
+// rows of ld elements (columns from o v on zero), stored in the operand precision PREC
+// (FP64, FP32, or bf16 planes: the second pointer of each is its lo / mid plane):
 //   Xa[(i,a)][(k,c)] = 2 t_ik^ac - t_ik^ca,  An[(i,a)][(k,c)] = -t_ik^ac,  B[(i,a)][(k,c)] = t_ik^ca.
+template <int PREC>
 __global__ void __launch_bounds__(256)
-ring_pack_kernel(int o, int v, const double* __restrict__ t, int64_t ld, double* Xa, double* An, double* B) {
+ring_pack_kernel(int o, int v, const double* __restrict__ t, int64_t ld, void* Xa, void* Xa_lo, void* An,
+                 void* An_lo, void* B, void* B_lo) {
   const int64_t ov = (int64_t)o * v, total = ov * ld;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
@@ -1030,16 +1033,33 @@ ring_pack_kernel(int o, int v, const double* __restrict__ t, int64_t ld, double*
       an = -tac;
       b = tca;
     }
-    Xa[x] = xa;
-    An[x] = an;
-    B[x] = b;
+    Store<PREC>::put(Xa, Xa_lo, x, xa);
+    Store<PREC>::put(An, An_lo, x, an);
+    Store<PREC>::put(B, B_lo, x, b);
   }
 }
 
 int ring_pack(hipStream_t s, int o, int v, const double* t, int64_t ld, double* Xa, double* An, double* B) {
+  return ring_pack_lp(s, PPL_FP64, o, v, t, ld, Xa, nullptr, An, nullptr, B, nullptr);
+}
+
+int ring_pack_lp(hipStream_t s, int prec, int o, int v, const double* t, int64_t ld, void* Xa, void* Xa_lo,
+                 void* An, void* An_lo, void* B, void* B_lo) {
   const int64_t n = (int64_t)o * v * ld;
   if (n <= 0) return PPL_OK;
-  hipLaunchKernelGGL(ring_pack_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, t, ld, Xa, An, B);
+  const dim3 grid(grid_for(n, 256));
+  if (prec == PPL_FP64)
+    hipLaunchKernelGGL(ring_pack_kernel<PPL_FP64>, grid, dim3(256), 0, s, o, v, t, ld, Xa, Xa_lo, An, An_lo, B, B_lo);
+  else if (prec == PPL_FP32)
+    hipLaunchKernelGGL(ring_pack_kernel<PPL_FP32>, grid, dim3(256), 0, s, o, v, t, ld, Xa, Xa_lo, An, An_lo, B, B_lo);
+  else if (prec == PPL_BF16X3)
+    hipLaunchKernelGGL(ring_pack_kernel<PPL_BF16X3>, grid, dim3(256), 0, s, o, v, t, ld, Xa, Xa_lo, An, An_lo, B,
+                       B_lo);
+  else if (prec == PPL_BF16X6)
+    hipLaunchKernelGGL(ring_pack_kernel<PPL_BF16X6>, grid, dim3(256), 0, s, o, v, t, ld, Xa, Xa_lo, An, An_lo, B,
+                       B_lo);
+  else
+    return fail(PPL_E_ARG, "ring_pack: unknown precision %d", prec);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }
@@ -1069,8 +1089,10 @@ int ring_exchange(hipStream_t s, int o, int v, const double* G, int64_t ldg, dou
 }
 
 // R_ij^ab = beta R_ij^ab + alpha (Y_ij^ab + Y_ji^ba) with Y_ij^ab = C1[(i,a)][(j,b)] - C2[(i,b)][(j,a)]
+// (C1, C2 in the accumulator type Tc of the ring GEMMs)
+template <class Tc>
 __global__ void __launch_bounds__(256)
-ring_unpack_kernel(int o, int v, const double* __restrict__ C1, const double* __restrict__ C2, int64_t ld, double* R,
+ring_unpack_kernel(int o, int v, const Tc* __restrict__ C1, const Tc* __restrict__ C2, int64_t ld, double* R,
                    double alpha, double beta) {
   const int64_t total = (int64_t)o * o * v * v;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
@@ -1079,8 +1101,8 @@ ring_unpack_kernel(int o, int v, const double* __restrict__ C1, const double* __
     const int64_t b = r % v; r /= v;
     const int64_t a = r % v; r /= v;
     const int64_t j = r % o, i = r / o;
-    const double y1 = C1[(i * v + a) * ld + j * v + b] - C2[(i * v + b) * ld + j * v + a];
-    const double y2 = C1[(j * v + b) * ld + i * v + a] - C2[(j * v + a) * ld + i * v + b];
+    const double y1 = (double)C1[(i * v + a) * ld + j * v + b] - (double)C2[(i * v + b) * ld + j * v + a];
+    const double y2 = (double)C1[(j * v + b) * ld + i * v + a] - (double)C2[(j * v + a) * ld + i * v + b];
     const double y = alpha * (y1 + y2);
     R[x] = beta == 0.0 ? y : beta * R[x] + y;
   }
@@ -1090,7 +1112,18 @@ int ring_unpack(hipStream_t s, int o, int v, const double* C1, const double* C2,
                 double beta) {
   const int64_t n = (int64_t)o * o * v * v;
   if (n <= 0) return PPL_OK;
-  hipLaunchKernelGGL(ring_unpack_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, C1, C2, ld, R, alpha, beta);
+  hipLaunchKernelGGL(ring_unpack_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, C1, C2, ld, R, alpha,
+                     beta);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+int ring_unpack_f32(hipStream_t s, int o, int v, const float* C1, const float* C2, int64_t ld, double* R, double alpha,
+                    double beta) {
+  const int64_t n = (int64_t)o * o * v * v;
+  if (n <= 0) return PPL_OK;
+  hipLaunchKernelGGL(ring_unpack_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, o, v, C1, C2, ld, R, alpha,
+                     beta);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

@@ -330,9 +330,14 @@ int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va,
 int zero_bytes(hipStream_t s, void* p, uint64_t bytes);
 // ring terms: (o v) x (o v) operands over the pairs (i,a), (k,c) (rows of ld elements)
 int ring_pack(hipStream_t s, int o, int v, const double* t, int64_t ld, double* Xa, double* An, double* B);
+// the same operands in precision prec (FP32, or bf16 planes: each *_lo is the lo / mid plane)
+int ring_pack_lp(hipStream_t s, int prec, int o, int v, const double* t, int64_t ld, void* Xa, void* Xa_lo,
+                 void* An, void* An_lo, void* B, void* B_lo);
 int ring_exchange(hipStream_t s, int o, int v, const double* G, int64_t ldg, double* K, int64_t ld);
 int ring_unpack(hipStream_t s, int o, int v, const double* C1, const double* C2, int64_t ld, double* R, double alpha,
                 double beta);
+int ring_unpack_f32(hipStream_t s, int o, int v, const float* C1, const float* C2, int64_t ld, double* R, double alpha,
+                    double beta);
 // rp[(ij)][(ab)] += (R_ij^ab + R_ij^ba) / 2 (i <= j, a <= b), rm[(ij)][(ab)] += (R_ij^ab - R_ij^ba) / 2
 // (i < j, a < b): a pair-symmetric [o][o][v][v] tensor added to R+- (accumulator precision c_prec)
 int add_pm(hipStream_t s, int c_prec, int o, int v, const double* R, void* rp, int64_t ldp, void* rm, int64_t ldm,

@@ -188,7 +188,29 @@ def test_diis_with_ring_reaches_the_dense_fixed_point(P):
     assert np.abs(t.cpu().numpy() - tstar).max() < 1e-9 * np.abs(tstar).max()
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec,bound", [("bf16x3", 2e-5), ("fp32", 2e-6), ("bf16x6", 2e-6)])
+def test_low_precision_ring_sweep_matches_oracle(P, prec, bound):
+    """The first sweep of a mixed plan runs the ladder and the ring GEMMs in the low
+    precision: its residual must equal the oracle's FP64 first-sweep residual to the
+    level of the low-precision products (a wrong ring term would be off by O(1))."""
+    o, v, naux = 6, 40, 120
+    say(f"one {prec} sweep with hhl + ring ({o},{v},{naux}) against the oracle")
+    s = S.make_system(o, v, naux, 1, "contractive")
+    eng = P.PPL(o, v, naux, prec=prec, keep_fp64=True, ring=True)
+    t = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    rep = eng.iterate(dev(s["L"]), dev(s["e_occ"]), dev(s["e_vir"]), t, max_sweeps=1, tol=0.0, hhl=True,
+                      ring=True, switch_tol=1e-30, stagnation=10.0)
+    eng.close()
+    assert rep["sweeps_lp"] == 1 and rep["sweeps_fp64"] == 0
+    tref, hist, _ = O.jacobi(s["L"], o, s["e_occ"], s["e_vir"], max_sweeps=1, tol=0.0, with_hhl=True,
+                             with_ring=True)
+    err_r = abs(rep["history"][0] - hist[0]) / hist[0]
+    err_t = rel(t.cpu().numpy(), tref)
+    say(f"  residual {rep['history'][0]:.6e} vs {hist[0]:.6e} (rel {err_r:.1e}); amplitudes rel {err_t:.1e}")
+    assert err_r < bound and err_t < bound
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "bf16x6"])
 def test_mixed_iteration_with_ring(P, prec):
     o, v, naux = 10, 100, 300
     say(f"mixed {prec} -> fp64 with hhl + ring and diis 8 to 1e-7 ({o},{v},{naux})")
