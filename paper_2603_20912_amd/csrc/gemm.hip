@@ -1504,11 +1504,14 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 // gfx950: best over 1, 2 and 4 K slices, averaged over R+ and R- at (30, 300, 900)
 // and (40, 400, 1200) (FP32 at the first only); 1.0 = best tile of the precision.
 // BF16x6: best of 1, 2 and 4 slices, averaged over R+ and R- at (40, 400, 1200) and
-// (30, 300, 900).
+// (30, 300, 900). FP32 tiles 0 and 6 and BF16x3 tiles 0 and 5 re-measured on both
+// contractions at (40, 400, 1200), per padded flop: the FP32 tiles 0, 5, 8 and 9 run
+// alike there (tile 6 at 0.91 of them), and the BF16x3 tiles 0 and 5 reach 0.80-0.83 of
+// tile 9 (they re-read both operands from HBM for each of their row tiles).
 static const double kTileEff[4][11] = {
     /* FP64   */ {1.00, 0.97, 0.87, 0.91, 0.99, 0.99, 0.95, 0.97, 1.00, 0.87, 0.83},
-    /* FP32   */ {0.93, 0.92, 0.74, 0.90, 0.93, 0.96, 0.96, 0.97, 1.00, 0.81, 0.87},
-    /* BF16x3 */ {0.93, 0.73, 0.53, 0.51, 0.56, 0.92, 0.59, 0.76, 0.82, 1.00, 0.66},
+    /* FP32   */ {0.98, 0.92, 0.74, 0.90, 0.93, 0.96, 0.92, 0.97, 1.00, 0.81, 0.87},
+    /* BF16x3 */ {0.84, 0.73, 0.53, 0.51, 0.56, 0.83, 0.59, 0.76, 0.82, 1.00, 0.66},
     /* BF16x6 */ {0.73, 0.76, 0.59, 0.48, 0.65, 0.71, 0.59, 0.68, 0.75, 1.00, 0.71}};
 static_assert(sizeof(kTileEff[0]) / sizeof(double) == kNumContract, "one efficiency per tile");
 
