@@ -304,7 +304,10 @@ def study_c3(args):
 def study_batched(args):
     """The 32 uneven instances of the batched configuration (o in [8, 24], v in [80, 240],
     naux = 3v): contraction of all instances by one grouped persistent launch replayed
-    from a hipGraph, against one autotuned plan per instance launched one after another."""
+    from a hipGraph, against one autotuned plan per instance launched one after another;
+    and the whole evaluation from L (integral builds as concurrent branches, then the
+    grouped contraction) in one graph, against the plans' builds and contractions in turn
+    (the sequential builds include their symmetry check of L, a host round trip each)."""
     import torch
 
     import paper_2603_20912_amd as P
@@ -318,8 +321,10 @@ def study_batched(args):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 10
     with torch.cuda.stream(stream):
+        bflops = sum(nominal(*t)["build"] for t in tup)
+        out["useful_build_flops"] = bflops
         for prec in ("fp64", "fp32"):
-            seq_ms = 0.0
+            seq_ms = seq_full_ms = 0.0
             for d, (o, v, naux) in zip(shapes, tup):
                 sysd = ppl_synth.make_system(o, v, naux, d["seed"])
                 L = torch.from_numpy(sysd["L"]).cuda()
@@ -334,6 +339,14 @@ def study_batched(args):
                 e1.record(stream)
                 e1.synchronize()
                 seq_ms += e0.elapsed_time(e1) / reps
+                # the same plan's whole evaluation from L (build, then contraction)
+                e0.record(stream)
+                for _ in range(3):
+                    eng.build(L)
+                    eng.contract(t, R)
+                e1.record(stream)
+                e1.synchronize()
+                seq_full_ms += e0.elapsed_time(e1) / 3
                 eng.close()
                 del L, t, R, eng
             torch.cuda.empty_cache()
@@ -371,11 +384,24 @@ def study_batched(args):
             e1.record(stream)
             e1.synchronize()
             graph_ms = e0.elapsed_time(e1) / reps
+            # the whole evaluation from L and t2 (builds + contraction) in one graph
+            b.capture(ts, Rs, Ls=Ls)
+            b.replay()
+            e0.record(stream)
+            for _ in range(3):
+                b.replay()
+            e1.record(stream)
+            e1.synchronize()
+            graph_full_ms = e0.elapsed_time(e1) / 3
             out[prec] = {"graph_ms": round(graph_ms, 3), "eager_grouped_ms": round(eager_ms, 3),
                          "eager_grouped_model_tiles_ms": round(model_ms, 3),
                          "sequential_ms": round(seq_ms, 3), "graph_tflops": round(flops / graph_ms / 1e9, 2),
                          "sequential_tflops": round(flops / seq_ms / 1e9, 2),
-                         "speedup_vs_sequential": round(seq_ms / graph_ms, 3), "build_s": round(build_s, 3)}
+                         "speedup_vs_sequential": round(seq_ms / graph_ms, 3), "build_s": round(build_s, 3),
+                         "graph_build_and_contract_ms": round(graph_full_ms, 3),
+                         "sequential_build_and_contract_ms": round(seq_full_ms, 3),
+                         "speedup_build_and_contract_vs_sequential": round(seq_full_ms / graph_full_ms, 3),
+                         "build_and_contract_tflops": round((flops + bflops) / graph_full_ms / 1e9, 2)}
             print(json.dumps({prec: out[prec]}), file=sys.stderr, flush=True)
             b.close()
             del b, Ls, ts, Rs

@@ -373,9 +373,11 @@ int ppl_autotune(ppl_plan_t plan, int32_t reps, double* best_ms);
  * Many independent, uneven (o, v, naux) instances of the ladder term share one
  * workspace; their contractions run as one persistent grouped launch whose
  * workgroups pull (instance, R+/R-, tile) items from a queue sorted
- * longest-first, each instance with its own tile shape. The contraction
- * sequence (packing, grouped launch, unpacking) can be captured once in a
- * hipGraph and replayed. All instances use one precision (FP64 or FP32) and
+ * longest-first, each instance with its own tile shape. ppl_batch_build runs the
+ * integral builds of the instances as concurrent branches on side streams of the
+ * batch (joined back into its stream). The contraction sequence (packing, grouped
+ * launch, unpacking), or the builds and the contraction together, can be captured
+ * once in a hipGraph and replayed. All instances use one precision (FP64 or FP32) and
  * the stream of descs[0]; graph capture needs a non-default stream.
  */
 typedef struct ppl_batch_s* ppl_batch_t;
@@ -398,6 +400,18 @@ int ppl_batch_autotune(ppl_batch_t batch, int32_t reps);
 int ppl_batch_contract(ppl_batch_t batch, const double* const* t2, double* const* R);
 /* record ppl_batch_contract on these pointers into a graph (replaces a previous one) */
 int ppl_batch_graph_capture(ppl_batch_t batch, const double* const* t2, double* const* R);
+/*
+ * ppl_batch_graph_capture_build: record the whole evaluation of every instance into one graph
+ * (replaces a previous one): the integral builds from L[k] (staging, build steps, mirror, one
+ * instance after another on the batch stream) followed by the packing, the grouped
+ * contraction and the unpacking of ppl_batch_contract. One replay
+ * (ppl_batch_graph_launch) computes R_k = PPL_k(t2_k) from L and t2. L, t2, R: host arrays of
+ * n device pointers, kept by the graph. ppl_batch_build must have run once (it checks that
+ * every L is symmetric, which a replay does not re-check). PPL_E_STATE before that,
+ * PPL_E_ARG for null pointers or the default stream.
+ */
+int ppl_batch_graph_capture_build(ppl_batch_t batch, const double* const* L, const double* const* t2,
+                                  double* const* R);
 int ppl_batch_graph_launch(ppl_batch_t batch);
 int ppl_batch_destroy(ppl_batch_t batch);
 

@@ -12,8 +12,8 @@ import torch
 
 from . import _lib
 from ._lib import (ppl_batch_plan, ppl_batch_query, ppl_batch_bind_workspace, ppl_batch_build,
-                   ppl_batch_autotune, ppl_batch_contract, ppl_batch_graph_capture, ppl_batch_graph_launch,
-                   ppl_batch_destroy)
+                   ppl_batch_autotune, ppl_batch_contract, ppl_batch_graph_capture, ppl_batch_graph_capture_build,
+                   ppl_batch_graph_launch, ppl_batch_destroy)
 from ._lib import (ppl_mp2, ppl_mlp_create, ppl_mlp_workspace_bytes, ppl_mlp_bind_workspace,
                    ppl_mlp_param_count, ppl_mlp_init, ppl_mlp_set_params, ppl_mlp_get_params, ppl_mlp_grad,
                    ppl_mlp_train_step, ppl_mlp_sigma, ppl_mlp_samples, ppl_mlp_guess, ppl_mlp_destroy,
@@ -33,8 +33,8 @@ __all__ = ["PPL", "PPLError", "ppl_plan", "ppl_plan_query", "ppl_bind_workspace"
            "ppl_mlp_set_params", "ppl_mlp_get_params", "ppl_mlp_grad", "ppl_mlp_train_step",
            "ppl_mlp_sigma", "ppl_mlp_samples", "ppl_mlp_guess", "ppl_mlp_destroy", "Batch",
            "ppl_batch_plan", "ppl_batch_query", "ppl_batch_bind_workspace", "ppl_batch_build",
-           "ppl_batch_autotune", "ppl_batch_contract", "ppl_batch_graph_capture", "ppl_batch_graph_launch",
-           "ppl_batch_destroy"]
+           "ppl_batch_autotune", "ppl_batch_contract", "ppl_batch_graph_capture", "ppl_batch_graph_capture_build",
+           "ppl_batch_graph_launch", "ppl_batch_destroy"]
 
 
 class PPL:
@@ -237,9 +237,14 @@ class Batch:
     def contract(self, t2s, Rs):
         ppl_batch_contract(self.h, t2s, Rs)
 
-    def capture(self, t2s, Rs):
-        self._graph_args = (list(t2s), list(Rs))
-        ppl_batch_graph_capture(self.h, t2s, Rs)
+    def capture(self, t2s, Rs, Ls=None):
+        """Record the contraction (or, with Ls, the integral builds and the contraction) into a graph."""
+        if Ls is None:
+            self._graph_args = (list(t2s), list(Rs))
+            ppl_batch_graph_capture(self.h, t2s, Rs)
+        else:
+            self._graph_args = (list(Ls), list(t2s), list(Rs))
+            ppl_batch_graph_capture_build(self.h, Ls, t2s, Rs)
 
     def replay(self):
         ppl_batch_graph_launch(self.h)

@@ -117,6 +117,8 @@ SIGNATURES = {
     "ppl_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ppl_batch_contract": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "ppl_batch_graph_capture": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "ppl_batch_graph_capture_build": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                                     ctypes.POINTER(_P)]),
     "ppl_batch_graph_launch": (ctypes.c_int, [_P]),
     "ppl_batch_destroy": (ctypes.c_int, [_P]),
     "ppl_set_contract_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -536,6 +538,12 @@ def ppl_batch_graph_capture(batch, t2s, Rs):
     sh = _dims(batch, "batch")
     _check(load().ppl_batch_graph_capture(batch, _ptr_array(t2s, sh, "t2"), _ptr_array(Rs, sh, "R")),
            "ppl_batch_graph_capture")
+
+
+def ppl_batch_graph_capture_build(batch, Ls, t2s, Rs):
+    sh = _dims(batch, "batch")
+    _check(load().ppl_batch_graph_capture_build(batch, _ptr_array(Ls, sh, "L"), _ptr_array(t2s, sh, "t2"),
+                                                _ptr_array(Rs, sh, "R")), "ppl_batch_graph_capture_build")
 
 
 def ppl_batch_graph_launch(batch):

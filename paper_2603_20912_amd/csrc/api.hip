@@ -248,7 +248,8 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   const uint64_t gbytes = std::max<uint64_t>(std::max<uint64_t>((uint64_t)gcap * v * v * g_acc_bytes(p),
                                                                p->contract_only ? 0 : (uint64_t)(o * v) * (o * v) * 8),
                                              hhl_scratch(p).bytes);
-  p->g = L.take(gbytes);
+  p->g_bytes_wanted = align256(gbytes);
+  p->g = L.take(p->g_external ? 0 : gbytes);
   if (p->ring) {
     RingLayout rl;
     ring_layout(p->o, p->v, p->naux, rl, p->ops[0].prec);
@@ -655,9 +656,48 @@ static bool diis_solve(const double (&B)[kDiisMax][kDiisMax], const std::vector<
   return true;
 }
 
+// the upper-triangle build relies on symmetric Cholesky vectors (V+- symmetric): PPL_E_ARG
+// when the virtual block of L is not symmetric to a relative Frobenius asymmetry of 1e-10
+// (synchronous: reads one reduction back)
+static int check_symmetric(ppl_plan_t p, const double* L) {
+  if (!p->sym_build) return PPL_OK;
+  double* partials = at<double>(p, p->red);
+  double h[4];
+  PPL_TRY(asymmetry_vv(p->stream, L, p->o, p->v, p->naux, partials, partials + kReduceBlocks * 4));
+  PPL_TRY(read_red(p, h));
+  if (!(h[0] <= 1e-20 * h[1]))
+    return fail(PPL_E_ARG, "Cholesky vectors are not symmetric in their virtual block (relative asymmetry %.3g)",
+                h[1] > 0.0 ? sqrt(h[0] / h[1]) : 0.0);
+  return PPL_OK;
+}
+
+// ppl_build_batch after its argument and symmetry checks
+static int build_checked(ppl_plan_t p, const double* L, int32_t batch) {
+  const int nb = (int)p->batches.size();
+  p->L_last = L;
+  if (!p->resident) return PPL_OK;       // streaming plans build inside ppl_contract
+  for (int k = 0; k < 2; ++k) {
+    OperandSet& s = p->ops[k];
+    if (!s.present) continue;
+    if (batch < 0) {
+      PPL_TRY(build_all(p, s, L));
+    } else {
+      PPL_TRY(build_one(p, s, L, batch, false));
+      // a resident plan counts as built once its last batch is built in order
+      if (batch == nb - 1) {
+        PPL_TRY(mirror_vpm(p, s));
+        s.built = true;
+      }
+    }
+  }
+  return PPL_OK;
+}
+
 }  // namespace ppl
 
 using namespace ppl;
+
+static int plan_create(const ppl_desc_t* d, ppl_plan_t* out, bool external_g);
 
 extern "C" {
 
@@ -692,7 +732,13 @@ void ppl_iter_opts_default(ppl_iter_opts_t* o) {
   o->ring = 0;
 }
 
-int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
+int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) { return plan_create(d, out, false); }
+
+}  // extern "C"
+
+// ppl_plan; with external_g the plan's layout leaves out its build scratch, which the caller
+// places and assigns (p->g) before the workspace is bound
+static int plan_create(const ppl_desc_t* d, ppl_plan_t* out, bool external_g) {
   g_err[0] = 0;
   if (!d || !out) return fail(PPL_E_ARG, "null argument");
   *out = nullptr;
@@ -720,6 +766,7 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   }
   ppl_plan_t p = new (std::nothrow) ppl_plan_s();
   if (!p) return fail(PPL_E_NOMEM, "host allocation failed");
+  p->g_external = external_g;
   p->o = d->o;
   p->v = d->v;
   p->naux = d->naux;
@@ -847,6 +894,8 @@ int ppl_plan(const ppl_desc_t* d, ppl_plan_t* out) {
   return PPL_OK;
 }
 
+extern "C" {
+
 int ppl_plan_query(ppl_plan_t p, ppl_plan_info_t* info) {
   PPL_TRY(check_plan(p));
   if (!info) return fail(PPL_E_ARG, "null info");
@@ -920,36 +969,12 @@ int ppl_build_batch(ppl_plan_t p, const double* L, int32_t batch) {
   if (!L) return fail(PPL_E_ARG, "null L");
   const int nb = (int)p->batches.size();
   if (batch < -1 || batch >= nb) return fail(PPL_E_ARG, "batch %d out of range [-1, %d)", batch, nb);
-  if (p->sym_build && batch <= 0) {
-    // the upper-triangle build relies on symmetric Cholesky vectors (V+- symmetric)
-    double* partials = at<double>(p, p->red);
-    double h[4];
-    PPL_TRY(asymmetry_vv(p->stream, L, p->o, p->v, p->naux, partials, partials + kReduceBlocks * 4));
-    PPL_TRY(read_red(p, h));
-    if (!(h[0] <= 1e-20 * h[1]))
-      return fail(PPL_E_ARG, "Cholesky vectors are not symmetric in their virtual block (relative asymmetry %.3g)",
-                  h[1] > 0.0 ? sqrt(h[0] / h[1]) : 0.0);
-  }
-  p->L_last = L;
-  if (!p->resident) return PPL_OK;       // streaming plans build inside ppl_contract
-  for (int k = 0; k < 2; ++k) {
-    OperandSet& s = p->ops[k];
-    if (!s.present) continue;
-    if (batch < 0) {
-      PPL_TRY(build_all(p, s, L));
-    } else {
-      PPL_TRY(build_one(p, s, L, batch, false));
-      // a resident plan counts as built once its last batch is built in order
-      if (batch == nb - 1) {
-        PPL_TRY(mirror_vpm(p, s));
-        s.built = true;
-      }
-    }
-  }
-  return PPL_OK;
+  if (batch <= 0) PPL_TRY(check_symmetric(p, L));
+  return build_checked(p, L, batch);
 }
 
 }  // extern "C"
+
 
 namespace ppl {
 // (ki|lj) from the occupied block of L and W+-_{ij,kl} = ((ki|lj) +- (li|kj)) / 2 on the
@@ -1840,6 +1865,14 @@ struct ppl_batch_s {
   bool built = false, prepared = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // integral builds of the instances run as concurrent branches, one per side stream, each a
+  // longest-first share of the instances; fork and join through events on the batch stream
+  static constexpr int kBranches = 4;
+  int n_branches = kBranches;                 // PPL_BATCH_BRANCHES (1 .. kBranches) at plan time
+  hipStream_t side[kBranches] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kBranches] = {};
+  std::vector<int> branch_of;                 // instance -> branch
+  ppl::Region g_branch[kBranches];            // the build scratch each branch's instances share
 };
 
 namespace ppl {
@@ -1949,6 +1982,43 @@ static int batch_enqueue(ppl_batch_t b, const double* const* t2, double* const* 
   return PPL_OK;
 }
 
+// Integral builds of every instance (staging, build steps, mirror) from L[k]; no host
+// synchronization (the symmetry of each L was checked by the eager ppl_batch_build). With
+// branches the builds are forked from the batch stream over the side streams and joined
+// back into it; without, they run in turn on the batch stream. Graph capture takes the
+// latter: replays of a captured graph with such branches left their workspace unreleased
+// after the graph and its memory were freed (measured: about one workspace per replayed
+// graph), which a single-stream graph does not.
+static int batch_build_branches(ppl_batch_t b, const double* const* L, bool branches) {
+  if (b->n_branches == 1 || !branches) {    // every build on the batch stream
+    for (int k = 0; k < b->n; ++k) PPL_TRY(build_checked(b->plans[k], L[k], -1));
+    return PPL_OK;
+  }
+  if (!b->ev_fork) {
+    PPL_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    for (int j = 0; j < ppl_batch_s::kBranches; ++j) {
+      PPL_HIP_TRY(hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking));
+      PPL_HIP_TRY(hipEventCreateWithFlags(&b->ev_join[j], hipEventDisableTiming));
+    }
+  }
+  PPL_HIP_TRY(hipEventRecord(b->ev_fork, b->stream));
+  for (int j = 0; j < ppl_batch_s::kBranches; ++j) PPL_HIP_TRY(hipStreamWaitEvent(b->side[j], b->ev_fork, 0));
+  int rc = PPL_OK;
+  for (int k = 0; k < b->n && rc == PPL_OK; ++k) {
+    ppl_plan_t p = b->plans[k];
+    hipStream_t own = p->stream;
+    p->stream = b->side[b->branch_of[k]];
+    rc = build_checked(p, L[k], -1);
+    p->stream = own;
+  }
+  // join every branch, also after a failure, so that the stream leaves no fork open
+  for (int j = 0; j < ppl_batch_s::kBranches; ++j) {
+    PPL_HIP_TRY(hipEventRecord(b->ev_join[j], b->side[j]));
+    PPL_HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_join[j], 0));
+  }
+  return rc;
+}
+
 static void batch_drop_graph(ppl_batch_t b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1982,9 +2052,10 @@ int ppl_batch_plan(int32_t n, const ppl_desc_t* descs, ppl_batch_t* out) {
     d.diis_max = 0;                      // batched instances are contracted, not iterated
     d.flags |= PPL_PLAN_CONTRACT_ONLY;
     if (d.hbm_budget == 0) d.hbm_budget = (uint64_t)1 << 62;
-    if (d.build_scratch == 0) d.build_scratch = (uint64_t)256 << 20;   // builds run one instance at a time
+    // the instances of one build branch build in turn and share one scratch (placed below)
+    if (d.build_scratch == 0) d.build_scratch = (uint64_t)2 << 30;
     ppl_plan_t p = nullptr;
-    const int rc = ppl_plan(&d, &p);
+    const int rc = plan_create(&d, &p, true);
     if (rc != PPL_OK) {
       ppl_batch_destroy(b);
       return rc;
@@ -1999,8 +2070,31 @@ int ppl_batch_plan(int32_t n, const ppl_desc_t* descs, ppl_batch_t* out) {
     // upper bound of items: the smallest grouped tiles (32 rows, 64 columns)
     max_items += ((p->Np + 31) / 32) * ((p->Pp + 63) / 64) + ((p->Nm + 31) / 32) * ((p->Pm + 63) / 64);
   }
+  {
+    const char* e = getenv("PPL_BATCH_BRANCHES");
+    if (e) b->n_branches = std::max(1, std::min(ppl_batch_s::kBranches, atoi(e)));
+    std::vector<int> order(n);
+    for (int k = 0; k < n; ++k) order[k] = k;
+    auto work = [&](int k) { return build_flops(b->plans[k], 0, b->plans[k]->v); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    double load[ppl_batch_s::kBranches] = {0};
+    b->branch_of.assign(n, 0);
+    for (int k : order) {
+      int j = 0;
+      for (int q = 1; q < b->n_branches; ++q)
+        if (load[q] < load[j]) j = q;
+      b->branch_of[k] = j;
+      load[j] += work(k);
+    }
+  }
   Layout L;
   L.cur = off;
+  for (int j = 0; j < b->n_branches; ++j) {
+    uint64_t gb = 0;
+    for (int k = 0; k < n; ++k)
+      if (b->branch_of[k] == j) gb = std::max<uint64_t>(gb, b->plans[k]->g_bytes_wanted);
+    b->g_branch[j] = L.take(gb);
+  }
   b->groups_r = L.take((uint64_t)2 * n * sizeof(GroupDesc));
   b->items_r = L.take((uint64_t)max_items * sizeof(int4));
   b->counter_r = L.take(256);
@@ -2022,8 +2116,14 @@ int ppl_batch_bind_workspace(ppl_batch_t b, void* dptr, uint64_t bytes) {
   if (!b || !dptr) return fail(PPL_E_ARG, "null argument");
   if (((uintptr_t)dptr) % 256 != 0) return fail(PPL_E_ARG, "workspace must be 256-byte aligned");
   if (bytes < b->need) return fail(PPL_E_NOMEM, "batch workspace needs %llu bytes", (unsigned long long)b->need);
-  for (int k = 0; k < b->n; ++k)
-    PPL_TRY(ppl_bind_workspace(b->plans[k], (char*)dptr + b->offs[k], b->plans[k]->ws_bytes_needed));
+  for (int k = 0; k < b->n; ++k) {
+    ppl_plan_t p = b->plans[k];
+    PPL_TRY(ppl_bind_workspace(p, (char*)dptr + b->offs[k], p->ws_bytes_needed));
+    // the branch's build scratch, addressed from the plan's part of the workspace
+    const Region& gb = b->g_branch[b->branch_of[k]];
+    p->g.off = gb.off - b->offs[k];
+    p->g.bytes = gb.bytes;
+  }
   b->ws = (char*)dptr;
   b->built = b->prepared = false;
   batch_drop_graph(b);
@@ -2036,8 +2136,9 @@ int ppl_batch_build(ppl_batch_t b, const double* const* L) {
   if (!L) return fail(PPL_E_ARG, "null L array");
   for (int k = 0; k < b->n; ++k) {
     if (!L[k]) return fail(PPL_E_ARG, "null L for instance %d", k);
-    PPL_TRY(ppl_build_batch(b->plans[k], L[k], -1));
+    PPL_TRY(check_symmetric(b->plans[k], L[k]));
   }
+  PPL_TRY(batch_build_branches(b, L, true));
   b->built = true;
   return batch_prepare(b);
 }
@@ -2134,6 +2235,36 @@ int ppl_batch_graph_capture(ppl_batch_t b, const double* const* t2, double* cons
   return PPL_OK;
 }
 
+int ppl_batch_graph_capture_build(ppl_batch_t b, const double* const* L, const double* const* t2,
+                                  double* const* R) {
+  g_err[0] = 0;
+  PPL_TRY(batch_check(b));
+  if (!L || !t2 || !R) return fail(PPL_E_ARG, "null pointer array");
+  for (int k = 0; k < b->n; ++k)
+    if (!L[k] || !t2[k] || !R[k]) return fail(PPL_E_ARG, "null L, t2 or R for instance %d", k);
+  if (!b->built || !b->prepared) return fail(PPL_E_STATE, "build the batch once (ppl_batch_build) before capturing");
+  if (b->stream == nullptr) return fail(PPL_E_ARG, "graph capture needs a non-default stream");
+  batch_drop_graph(b);
+  for (int k = 0; k < b->n; ++k) b->plans[k]->prof_on = false;
+  PPL_HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = batch_build_branches(b, L, false);
+  if (rc == PPL_OK) rc = batch_enqueue(b, t2, R);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc != PPL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PPL_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  b->graph = g;
+  const hipError_t e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    batch_drop_graph(b);
+    return fail(PPL_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
+  }
+  return PPL_OK;
+}
+
 int ppl_batch_graph_launch(ppl_batch_t b) {
   g_err[0] = 0;
   PPL_TRY(batch_check(b));
@@ -2145,6 +2276,14 @@ int ppl_batch_graph_launch(ppl_batch_t b) {
 int ppl_batch_destroy(ppl_batch_t b) {
   if (!b) return PPL_OK;
   batch_drop_graph(b);
+  for (int j = 0; j < ppl_batch_s::kBranches; ++j) {
+    if (b->side[j]) {
+      (void)hipStreamSynchronize(b->side[j]);
+      (void)hipStreamDestroy(b->side[j]);
+    }
+    if (b->ev_join[j]) (void)hipEventDestroy(b->ev_join[j]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   for (ppl_plan_t p : b->plans) ppl_destroy(p);
   delete b;
   return PPL_OK;

@@ -116,6 +116,9 @@ struct ppl_plan_s {
   uint64_t ws_bytes = 0;
   ppl::OperandSet ops[2];              // [0] = compute precision, [1] = FP64 refinement copy (if any)
   ppl::Region g;                       // build scratch G [pairs][v][v] (also the V-setup scratch)
+  bool g_external = false;             // G lies outside the plan's layout (batched instances share one per
+                                       // build branch); g_bytes_wanted is its size
+  uint64_t g_bytes_wanted = 0;
   ppl::Region rp, rm;                  // R+ [N+][ldp], R- [N-][ldm] (accumulator type of the GEMM)
   ppl::Region part;                    // split-K slices of one contraction GEMM
   ppl::Region s64, a64;                // FP64 master amplitudes in S'/A' form when ops[*] are not FP64
