@@ -8,6 +8,7 @@
 #include <mutex>
 #include <new>
 
+#include "diis_solve.h"
 #include "ppl_internal.h"
 
 namespace ppl {
@@ -73,6 +74,10 @@ static bool ring_layout(int64_t o, int64_t v, int64_t naux, RingLayout& r, int l
   uint64_t x;
   if (!mul_ok((uint64_t)(o * v), (uint64_t)r.ldk, &x) || !mul_ok(x, 16, &x)) return false;
   if (!mul_ok((uint64_t)(v * v), (uint64_t)r.ldx, &x) || !mul_ok(x, 16, &x)) return false;
+  // the regions together (below) must not overflow 64-bit byte counts either
+  const double total = 8.0 * ((double)(o * v + o * o + v * v) * (double)r.ldx + (double)(o * o) * (double)r.ldg +
+                              9.0 * (double)(o * v) * (double)r.ldk) + 12.0 * (double)(o * v) * (double)r.ldk;
+  if (total > 4.0e18) return false;
   Layout L;
   r.xov = L.take((uint64_t)o * v * r.ldx * 8).off;
   r.xoo = L.take((uint64_t)o * o * r.ldx * 8).off;
@@ -613,48 +618,6 @@ static int read_red(ppl_plan_t p, double out[4]) {
   return PPL_OK;
 }
 
-// DIIS coefficients of the subspace `ids` (oldest first) from the inner products B:
-// the system [B -1; -1^T 0][c; lambda] = [0; -1], with B scaled by its largest
-// diagonal entry, by Gaussian elimination with partial pivoting. Singular (false)
-// when a pivot falls below 1e-14 or the result is not finite.
-static bool diis_solve(const double (&B)[kDiisMax][kDiisMax], const std::vector<int>& ids, double* c) {
-  const int n = (int)ids.size(), N = n + 1;
-  double scale = 0.0;
-  for (int i = 0; i < n; ++i) scale = std::max(scale, fabs(B[ids[i]][ids[i]]));
-  if (!(scale > 0.0) || !isfinite(scale)) return false;
-  double A[kDiisMax + 1][kDiisMax + 2];
-  for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < n; ++j) A[i][j] = B[ids[i]][ids[j]] / scale;
-    A[i][n] = -1.0;
-    A[n][i] = -1.0;
-    A[i][N] = 0.0;
-  }
-  A[n][n] = 0.0;
-  A[n][N] = -1.0;
-  for (int col = 0; col < N; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < N; ++r)
-      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-    if (!(fabs(A[piv][col]) >= 1e-14)) return false;
-    if (piv != col)
-      for (int k = 0; k <= N; ++k) std::swap(A[piv][k], A[col][k]);
-    for (int r = col + 1; r < N; ++r) {
-      const double f = A[r][col] / A[col][col];
-      for (int k = col; k <= N; ++k) A[r][k] -= f * A[col][k];
-    }
-  }
-  double x[kDiisMax + 1];
-  for (int r = N - 1; r >= 0; --r) {
-    double acc = A[r][N];
-    for (int k = r + 1; k < N; ++k) acc -= A[r][k] * x[k];
-    x[r] = acc / A[r][r];
-  }
-  for (int i = 0; i < n; ++i) {
-    if (!isfinite(x[i])) return false;
-    c[i] = x[i];
-  }
-  return true;
-}
 
 // the upper-triangle build relies on symmetric Cholesky vectors (V+- symmetric): PPL_E_ARG
 // when the virtual block of L is not symmetric to a relative Frobenius asymmetry of 1e-10
