@@ -247,12 +247,16 @@ struct EpiBuildSym {
 #ifndef PPL_BF3_DIRECT
 #define PPL_BF3_DIRECT 1
 #endif
+#ifndef PPL_BF6_DIRECT
+#define PPL_BF6_DIRECT 1
+#endif
 constexpr int kLdsLayout = PPL_LDS_LAYOUT;
 constexpr int kFragVec = PPL_FRAG_VEC;
 constexpr int kSchedFence = PPL_SCHED_FENCE;
 constexpr int kDirectLds = PPL_DIRECT_LDS;   // 1: chunks go global -> LDS without registers (layout 1 only)
 constexpr int kPrefetch = PPL_PREFETCH;      // chunks in flight in registers: 1, 2, or 0 = per tile (below)
 constexpr int kBf3Direct = PPL_BF3_DIRECT;   // 1: BF16x3 chunks go global -> LDS, three stages, two in flight
+constexpr int kBf6Direct = PPL_BF6_DIRECT;   // 1: BF16x6 chunks go global -> LDS, two stages
 static_assert(!kDirectLds || kLdsLayout == 1, "direct LDS loads need the unpadded swizzled layout");
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
@@ -1015,6 +1019,7 @@ struct Bf6Geom {
   static constexpr int BUF_A = BM * LDSR, BUF_B = BN * LDSR;     // one buffer of one plane
   static constexpr int LDS_A = 6 * BUF_A, LDS_B = 6 * BUF_B;     // [plane][buffer]
   static_assert((LDS_A + LDS_B) * 2 <= 160 * 1024, "BF16x6 tile exceeds the LDS");
+  static constexpr int STAGE = 3 * (BM + BN) * LDSR;              // direct loads: all planes
 };
 
 template <int WM, int WN, int WAVES_M, int WAVES_N, class Epi>
@@ -1146,16 +1151,160 @@ __device__ __forceinline__ void bf6_tile_body(const TileJob& job, int64_t M, int
   }
 }
 
+// The BF16x6 tile with chunks moved straight from global memory into LDS, in two stages
+// (three planes of 224 + 128 rows leave no room for a third): step k issues chunk k+1
+// into the other stage, multiplies chunk k, then waits for its loads and meets the
+// other waves. One stage holds the hi, mid and lo planes of A, then those
+// of B; the instructions of a chunk are dealt over the waves as in the BF16x3 tile.
+template <int WM, int WN, int WAVES_M, int WAVES_N, class Epi>
+__device__ __forceinline__ void bf6_tile_body_direct(const TileJob& job, int64_t M, int64_t N, const __bf16* Ah,
+                                                     const __bf16* Am, int64_t lda, const __bf16* Bh,
+                                                     const __bf16* Bm, int64_t ldb, const Epi& epi,
+                                                     __bf16* __restrict__ st0, __bf16* __restrict__ st1) {
+  constexpr int KC = kKcBf6;
+  using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
+  constexpr int NW = WAVES_M * WAVES_N;
+  constexpr int BM = G::BM, BN = G::BN, LDSR = G::LDSR;
+  constexpr int VPR = KC / 8;                      // 4 vectors per staged row
+  constexpr int RPI = 64 / VPR;                    // staged rows per wave instruction
+  constexpr int GA = BM / RPI, GB = BN / RPI;      // instructions per plane and chunk
+  constexpr int GT = 3 * (GA + GB);                // instructions per chunk
+  constexpr int NI = (GT + NW - 1) / NW;           // per wave (the short waves repeat one)
+  static_assert(BM % RPI == 0 && BN % RPI == 0 && GT >= NW && NI < 16, "direct LDS geometry");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const int lr = lane / VPR, slot = lane % VPR;
+  auto key = [](int r) { return (r >> 1) & 3; };
+  auto plane_of = [](const __bf16* h, const __bf16* m, int q) { return q == 0 ? h : (q == 1 ? m : m + (m - h)); };
+
+  const __bf16* src[NI];
+  int dst[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    int q = wave + i * NW;
+    if (q >= GT) q -= GT;
+    if (q < 3 * GA) {
+      const int plane = q / GA, g = q % GA, r = g * RPI + lr;
+      int64_t gr = job.m0 + r;
+      if (gr > M - 1) gr = M - 1;
+      src[i] = plane_of(Ah, Am, plane) + epi.arow(gr) * lda + (slot ^ key(r)) * 8 + job.kc0 * KC;
+      dst[i] = (plane * BM + g * RPI) * LDSR;
+    } else {
+      const int plane = (q - 3 * GA) / GB, g = (q - 3 * GA) % GB, r = g * RPI + lr;
+      int64_t gr = job.n0 + r;
+      if (gr > N - 1) gr = N - 1;
+      src[i] = plane_of(Bh, Bm, plane) + epi.brow(gr) * ldb + (slot ^ key(r)) * 8 + job.kc0 * KC;
+      dst[i] = (3 * BM + plane * BN + g * RPI) * LDSR;
+    }
+  }
+  auto issue = [&](int64_t c, __bf16* st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      __builtin_amdgcn_global_load_lds((global_cvoid_t*)(src[i] + c * KC), (lds_void_t*)(st + dst[i]), 16, 0, 0);
+  };
+  // vmcnt(0) as a builtin (expcnt and lgkmcnt fields at their maxima), so that the
+  // compiler knows no load is pending; then the barrier without the fence of
+  // __syncthreads (the empty asm keeps LDS reads below it)
+  auto wait_meet = []() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
+  f4 acc[WM][WN], accx[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      acc[i][j] = f4{0, 0, 0, 0};
+      accx[i][j] = f4{0, 0, 0, 0};
+    }
+  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR;
+  const int brow = (3 * BM + wn * WN * 16 + (lane & 15)) * LDSR;
+  const int col = ((lane >> 4) ^ key(lane & 15)) * 8;   // this lane's 8-element fragment vector
+  const int64_t nk = job.kc1 - job.kc0;
+
+  // Multiply the chunk in st; when go, first issue chunk c into nx. The empty asm keeps
+  // the LDS reads, and with them the MFMAs, below the loads: left to itself the compiler
+  // sinks the loads below the MFMAs, and the wait that ends the step would then find
+  // them just issued.
+  auto compute = [&](const __bf16* __restrict__ st, bool go, int64_t c, __bf16* nx) __attribute__((always_inline)) {
+    if (go) issue(c, nx);
+    asm volatile("" ::: "memory");
+    bf8 a[3][WM], b[3][WN];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[q][i] = *reinterpret_cast<const bf8*>(&st[q * BM * LDSR + arow + i * 16 * LDSR + col]);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[q][j] = *reinterpret_cast<const bf8*>(&st[q * BN * LDSR + brow + j * 16 * LDSR + col]);
+    }
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        accx[i][j] = mfma16(a[2][i], b[0][j], accx[i][j]);
+        accx[i][j] = mfma16(a[0][i], b[2][j], accx[i][j]);
+        accx[i][j] = mfma16(a[1][i], b[1][j], accx[i][j]);
+        accx[i][j] = mfma16(a[1][i], b[0][j], accx[i][j]);
+        accx[i][j] = mfma16(a[0][i], b[1][j], accx[i][j]);
+        acc[i][j] = mfma16(a[0][i], b[0][j], acc[i][j]);
+      }
+  };
+
+  // chunk j lives in stage j mod 2
+  issue(0, st0);
+  wait_meet();
+  int64_t kt = 0;
+  for (; kt + 2 < nk; kt += 2) {
+    compute(st0, true, kt + 1, st1);
+    wait_meet();
+    compute(st1, true, kt + 2, st0);
+    wait_meet();
+  }
+  // one or two chunks remain, chunk kt in st0
+  compute(st0, kt + 1 < nk, kt + 1, st1);
+  if (kt + 1 < nk) {
+    wait_meet();
+    compute(st1, false, 0, st0);
+  }
+
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = job.m0 + wm * WM * 16 + i * 16 + AccOf<__bf16>::row(lane, r);
+      int64_t base;
+      bool ok;
+      epi.row(job.split, m, base, ok);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int64_t n = job.n0 + wn * WN * 16 + j * 16 + (lane & 15);
+        epi.put(base, ok, n, acc[i][j][r] + accx[i][j][r]);
+      }
+    }
+  }
+}
+
 template <int WM, int WN, int WAVES_M, int WAVES_N, class Epi, class Map>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
 gemm_nt_bf16x6_kernel(int64_t M, int64_t N, const __bf16* Ah, const __bf16* Am, int64_t lda, const __bf16* Bh,
                       const __bf16* Bm, int64_t ldb, Epi epi, Map map) {
   using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
-  __shared__ __attribute__((aligned(16))) __bf16 sA[G::LDS_A];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[G::LDS_B];
   TileJob job;
-  if (!map(blockIdx.x, job)) return;
-  bf6_tile_body<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
+  if constexpr (kBf6Direct) {
+    __shared__ __attribute__((aligned(16))) __bf16 st0[G::STAGE];
+    __shared__ __attribute__((aligned(16))) __bf16 st1[G::STAGE];
+    if (!map(blockIdx.x, job)) return;
+    bf6_tile_body_direct<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, st0, st1);
+  } else {
+    __shared__ __attribute__((aligned(16))) __bf16 sA[G::LDS_A];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[G::LDS_B];
+    if (!map(blockIdx.x, job)) return;
+    bf6_tile_body<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
+  }
 }
 
 // ------------------------------------------------------------------ tile configurations
@@ -1422,8 +1571,9 @@ gemm_streamk_bf16x6_kernel(int64_t M, int64_t N, const __bf16* Ah, const __bf16*
                            const __bf16* Bm, int64_t ldb, float* C, int64_t ldc, int64_t c_col0, float* part,
                            StreamK sk) {
   using G = Bf6Geom<WM, WN, WAVES_M, WAVES_N>;
-  __shared__ __attribute__((aligned(16))) __bf16 sA[G::LDS_A];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[G::LDS_B];
+  // (the direct body takes the two arrays as its two stages: 2 STAGE = LDS_A + LDS_B)
+  __shared__ __attribute__((aligned(16))) __bf16 sA[kBf6Direct ? G::STAGE : G::LDS_A];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[kBf6Direct ? G::STAGE : G::LDS_B];
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t begin = sk.start(w), end = sk.start(w + 1);
   const int64_t first_tile = begin / sk.nk;
@@ -1435,7 +1585,10 @@ gemm_streamk_bf16x6_kernel(int64_t M, int64_t N, const __bf16* Ah, const __bf16*
     EpiSK<float> epi{C, ldc, c_col0, M, N,
                      part + (w * 2 + (tile == first_tile ? 0 : 1)) * (int64_t)(G::BM * G::BN),
                      job.m0, job.n0, G::BN, !whole};
-    bf6_tile_body<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
+    if constexpr (kBf6Direct)
+      bf6_tile_body_direct<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
+    else
+      bf6_tile_body<WM, WN, WAVES_M, WAVES_N>(job, M, N, Ah, Am, lda, Bh, Bm, ldb, epi, sA, sB);
     it = t0 + k1;
     __syncthreads();   // the next tile refills the LDS buffers
   }
@@ -1712,16 +1865,16 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 // Relative per-tile throughput on large problems, measured with HIP events on
 // gfx950: best over 1, 2 and 4 K slices, averaged over R+ and R- at (30, 300, 900)
 // and (40, 400, 1200) (FP32 at the first only); 1.0 = best tile of the precision.
-// BF16x6: best of 1, 2 and 4 slices, averaged over R+ and R- at (40, 400, 1200) and
-// (30, 300, 900). FP32 tiles 0 and 6 re-measured on both contractions at (40, 400,
-// 1200), per padded flop: the FP32 tiles 0, 5, 8 and 9 run alike there (tile 6 at 0.91
-// of them). BF16x3 (three-stage direct loads): R+ and R- at (40, 400, 1200), best of 1
-// and 2 slices, per padded flop; the four-wave tiles reach 0.42-0.79 of tile 9.
+// FP32 tiles 0 and 6 re-measured on both contractions at (40, 400, 1200), per padded
+// flop: the FP32 tiles 0, 5, 8 and 9 run alike there (tile 6 at 0.91 of them). BF16x3
+// (three-stage direct loads): R+ and R- at (40, 400, 1200), best of 1 and 2 slices, per
+// padded flop. BF16x6 (two-stage direct loads): R+ and R- at (40, 400, 1200) in the 7
+// slices its error bound asks for there, per padded flop.
 static const double kTileEff[4][11] = {
     /* FP64   */ {1.00, 0.97, 0.87, 0.91, 0.99, 0.99, 0.95, 0.97, 1.00, 0.87, 0.83},
     /* FP32   */ {0.98, 0.92, 0.74, 0.90, 0.93, 0.96, 0.92, 0.97, 1.00, 0.81, 0.87},
-    /* BF16x3 */ {0.71, 0.79, 0.62, 0.42, 0.56, 0.68, 0.46, 0.46, 0.54, 1.00, 0.68},
-    /* BF16x6 */ {0.73, 0.76, 0.59, 0.48, 0.65, 0.71, 0.59, 0.68, 0.75, 1.00, 0.71}};
+    /* BF16x3 */ {0.71, 0.79, 0.61, 0.39, 0.53, 0.68, 0.46, 0.42, 0.51, 1.00, 0.68},
+    /* BF16x6 */ {0.84, 0.88, 0.63, 0.48, 0.66, 0.82, 0.53, 0.60, 0.69, 1.00, 0.68}};
 static_assert(sizeof(kTileEff[0]) / sizeof(double) == kNumContract, "one efficiency per tile");
 
 // BF16x6 products carry FP32's 24 bits, so its error is set by the length of each FP32
