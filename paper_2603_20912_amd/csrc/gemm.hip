@@ -250,6 +250,9 @@ struct EpiBuildSym {
 #ifndef PPL_BF6_DIRECT
 #define PPL_BF6_DIRECT 1
 #endif
+#ifndef PPL_FP_DIRECT3
+#define PPL_FP_DIRECT3 1
+#endif
 constexpr int kLdsLayout = PPL_LDS_LAYOUT;
 constexpr int kFragVec = PPL_FRAG_VEC;
 constexpr int kSchedFence = PPL_SCHED_FENCE;
@@ -257,6 +260,7 @@ constexpr int kDirectLds = PPL_DIRECT_LDS;   // 1: chunks go global -> LDS witho
 constexpr int kPrefetch = PPL_PREFETCH;      // chunks in flight in registers: 1, 2, or 0 = per tile (below)
 constexpr int kBf3Direct = PPL_BF3_DIRECT;   // 1: BF16x3 chunks go global -> LDS, three stages, two in flight
 constexpr int kBf6Direct = PPL_BF6_DIRECT;   // 1: BF16x6 chunks go global -> LDS, two stages
+constexpr int kFpDirect3 = PPL_FP_DIRECT3;   // 1: FP64 / FP32 contraction chunks go global -> LDS, three stages
 static_assert(!kDirectLds || kLdsLayout == 1, "direct LDS loads need the unpadded swizzled layout");
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
@@ -433,6 +437,141 @@ __device__ __forceinline__ void tile_body_direct(const TileJob& job, int64_t M, 
     consume_chunk<T, WM, WN, KC, LDSR>(acc, a1, b1, arow, brow, fq, key);
   } else {             // chunk kt (buffer 0) remains
     consume_chunk<T, WM, WN, KC, LDSR>(acc, a0, b0, arow, brow, fq, key);
+  }
+  store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
+}
+
+// The FP64 / FP32 tile with chunks moved straight from global memory into LDS in three
+// stages (the scheme of the BF16x3 tile below: step k reads its fragments of chunk k,
+// issues chunk k+2 into the stage chunk k-1 left, multiplies, then waits for its part of
+// chunk k+1 and meets the other waves). One stage holds BM rows of A, then BN rows of B.
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
+__device__ __forceinline__ void tile_body_direct3(const TileJob& job, int64_t M, int64_t N, const T* __restrict__ A,
+                                                  int64_t lda, const T* __restrict__ B, int64_t ldb, const Epi& epi,
+                                                  T* __restrict__ st0, T* __restrict__ st1, T* __restrict__ st2) {
+  using accv = typename AccOf<T>::vec;
+  constexpr int NW = WAVES_M * WAVES_N;
+  constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int LDSR = KC;
+  constexpr int VPR = KC / VEC;                   // 16-byte vectors per staged row
+  constexpr int RPI = 64 / VPR;                   // staged rows per wave instruction
+  constexpr int GA = BM / RPI, GB = BN / RPI;
+  constexpr int GT = GA + GB;                     // instructions per chunk
+  constexpr int NI = (GT + NW - 1) / NW;          // per wave (the short waves repeat one)
+  static_assert(kLdsLayout == 1 && 64 % VPR == 0 && BM % RPI == 0 && BN % RPI == 0 && GT >= NW && NI < 16,
+                "direct LDS geometry");
+  static_assert(KC % (4 * VEC) == 0 && 16 % VPR == 0, "bad KC");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const int lr = lane / VPR, slot = lane % VPR;
+
+  const T* src[NI];
+  int dst[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    int q = wave + i * NW;
+    if (q >= GT) q -= GT;
+    if (q < GA) {
+      const int r = q * RPI + lr;
+      int64_t gr = job.m0 + r;
+      if (gr > M - 1) gr = M - 1;
+      src[i] = A + epi.arow(gr) * lda + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
+      dst[i] = q * RPI * LDSR;
+    } else {
+      const int r = (q - GA) * RPI + lr;
+      int64_t gr = job.n0 + r;
+      if (gr > N - 1) gr = N - 1;
+      src[i] = B + epi.brow(gr) * ldb + (slot ^ (r % VPR)) * VEC + job.kc0 * KC;
+      dst[i] = (BM + (q - GA) * RPI) * LDSR;
+    }
+  }
+  auto issue = [&](int64_t c, T* st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      __builtin_amdgcn_global_load_lds((global_cvoid_t*)(src[i] + c * KC), (lds_void_t*)(st + dst[i]), 16, 0, 0);
+  };
+  auto wait_one = []() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0x0F70 | NI);
+    asm volatile("" ::: "memory");
+  };
+  auto wait_all = []() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    asm volatile("" ::: "memory");
+  };
+  auto meet = []() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
+  accv acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = accv{0, 0, 0, 0};
+  const int arow = (wm * WM * 16 + (lane & 15)) * LDSR;
+  const int brow = (BM + wn * WN * 16 + (lane & 15)) * LDSR;
+  const int fq = lane >> 4;
+  const int key = (lane & 15) % VPR;
+  const int64_t nk = job.kc1 - job.kc0;
+
+  auto compute = [&](const T* __restrict__ st, bool go, int64_t c, T* nx) __attribute__((always_inline)) {
+#pragma unroll
+    for (int kg = 0; kg < KC / (4 * VEC); ++kg) {
+      const int col = ((kg * 4 + fq) ^ key) * VEC;
+      union U { uint4 u; T e[VEC]; };
+      U a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i].u = *reinterpret_cast<const uint4*>(&st[arow + i * 16 * LDSR + col]);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j].u = *reinterpret_cast<const uint4*>(&st[brow + j * 16 * LDSR + col]);
+      if (kg == 0) {
+        asm volatile("" ::: "memory");
+        if (go) issue(c, nx);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i].e[e], b[j].e[e], acc[i][j]);
+    }
+  };
+
+  issue(0, st0);
+  if (nk > 1) {
+    issue(1, st1);
+    wait_one();
+  } else {
+    wait_all();
+  }
+  meet();
+  int64_t kt = 0;
+  for (; kt + 7 < nk; kt += 6) {   // six steps whose k+2 exists
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      compute(st0, true, kt + 3 * u + 2, st2);
+      wait_one();
+      meet();
+      compute(st1, true, kt + 3 * u + 3, st0);
+      wait_one();
+      meet();
+      compute(st2, true, kt + 3 * u + 4, st1);
+      wait_one();
+      meet();
+    }
+  }
+  for (int64_t j = kt; j < nk; ++j) {
+    const int sj = (int)((j - kt) % 3);
+    const T* cur = sj == 0 ? st0 : (sj == 1 ? st1 : st2);
+    T* nx = sj == 0 ? st2 : (sj == 1 ? st0 : st1);
+    compute(cur, j + 2 < nk, j + 2, nx);
+    if (j + 1 < nk) {
+      if (j + 2 < nk) wait_one();
+      else wait_all();
+      meet();
+    }
   }
   store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
 }
@@ -619,14 +758,25 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_
 gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int64_t lda,
                const T* __restrict__ B, int64_t ldb, Epi epi, Map map) {
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
-  __shared__ __attribute__((aligned(16))) T sA0[G::BUF_A];
-  __shared__ __attribute__((aligned(16))) T sA1[G::BUF_A];
-  __shared__ __attribute__((aligned(16))) T sB0[G::BUF_B];
-  __shared__ __attribute__((aligned(16))) T sB1[G::BUF_B];
   (void)Kpad;
   TileJob job;
-  if (!map(blockIdx.x, job)) return;
-  tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA0, sA1, sB0, sB1);
+  // the contractions take the three-stage direct loads; the integral builds keep the
+  // register-staged loop (measured faster for them: 13.9 against 15.1 ms per FP64 build
+  // at (20, 200, 600))
+  if constexpr (kFpDirect3 && std::is_same_v<Epi, EpiStore<T>>) {
+    __shared__ __attribute__((aligned(16))) T st0[G::BUF_A + G::BUF_B];
+    __shared__ __attribute__((aligned(16))) T st1[G::BUF_A + G::BUF_B];
+    __shared__ __attribute__((aligned(16))) T st2[G::BUF_A + G::BUF_B];
+    if (!map(blockIdx.x, job)) return;
+    tile_body_direct3<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, st0, st1, st2);
+  } else {
+    __shared__ __attribute__((aligned(16))) T sA0[G::BUF_A];
+    __shared__ __attribute__((aligned(16))) T sA1[G::BUF_A];
+    __shared__ __attribute__((aligned(16))) T sB0[G::BUF_B];
+    __shared__ __attribute__((aligned(16))) T sB1[G::BUF_B];
+    if (!map(blockIdx.x, job)) return;
+    tile_body<T, WM, WN, WAVES_M, WAVES_N, KC>(job, M, N, A, lda, B, ldb, epi, sA0, sA1, sB0, sB1);
+  }
 }
 
 // ------------------------------------------------------------------ the kernel (BF16 x 3)
@@ -1863,16 +2013,16 @@ int64_t contract_jobs(int tile, int prec, int64_t Nrows, int64_t Prows, int64_t 
 }
 
 // Relative per-tile throughput on large problems, measured with HIP events on
-// gfx950: best over 1, 2 and 4 K slices, averaged over R+ and R- at (30, 300, 900)
-// and (40, 400, 1200) (FP32 at the first only); 1.0 = best tile of the precision.
-// FP32 tiles 0 and 6 re-measured on both contractions at (40, 400, 1200), per padded
-// flop: the FP32 tiles 0, 5, 8 and 9 run alike there (tile 6 at 0.91 of them). BF16x3
+// gfx950, per padded flop; 1.0 = best tile of the precision. FP64 and FP32
+// (three-stage direct loads): best over 1, 2 and 4 K slices, averaged over R+ and R-
+// at (30, 300, 900) and (40, 400, 1200) (FP32 at the first only; at (40, 400, 1200)
+// FP32 ranks tiles 9, 8 and 0 the same way). BF16x3
 // (three-stage direct loads): R+ and R- at (40, 400, 1200), best of 1 and 2 slices, per
 // padded flop. BF16x6 (two-stage direct loads): R+ and R- at (40, 400, 1200) in the 7
 // slices its error bound asks for there, per padded flop.
 static const double kTileEff[4][11] = {
-    /* FP64   */ {1.00, 0.97, 0.87, 0.91, 0.99, 0.99, 0.95, 0.97, 1.00, 0.87, 0.83},
-    /* FP32   */ {0.98, 0.92, 0.74, 0.90, 0.93, 0.96, 0.92, 0.97, 1.00, 0.81, 0.87},
+    /* FP64   */ {0.90, 0.91, 0.85, 0.83, 0.85, 0.91, 0.90, 0.95, 0.97, 0.98, 1.00},
+    /* FP32   */ {0.94, 0.96, 0.87, 0.82, 0.90, 0.92, 0.92, 0.95, 0.97, 1.00, 0.93},
     /* BF16x3 */ {0.71, 0.79, 0.61, 0.39, 0.53, 0.68, 0.46, 0.42, 0.51, 1.00, 0.68},
     /* BF16x6 */ {0.84, 0.88, 0.63, 0.48, 0.66, 0.82, 0.53, 0.60, 0.69, 1.00, 0.68}};
 static_assert(sizeof(kTileEff[0]) / sizeof(double) == kNumContract, "one efficiency per tile");
