@@ -253,6 +253,9 @@ struct EpiBuildSym {
 #ifndef PPL_FP_DIRECT3
 #define PPL_FP_DIRECT3 1
 #endif
+#ifndef PPL_BUILD_DIRECT3
+#define PPL_BUILD_DIRECT3 1
+#endif
 constexpr int kLdsLayout = PPL_LDS_LAYOUT;
 constexpr int kFragVec = PPL_FRAG_VEC;
 constexpr int kSchedFence = PPL_SCHED_FENCE;
@@ -760,10 +763,15 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
   (void)Kpad;
   TileJob job;
-  // the contractions take the three-stage direct loads; the integral builds keep the
-  // register-staged loop (measured faster for them: 13.9 against 15.1 ms per FP64 build
-  // at (20, 200, 600))
-  if constexpr (kFpDirect3 && std::is_same_v<Epi, EpiStore<T>>) {
+  // The contractions take the three-stage direct loads, and so do the FP64 integral
+  // builds on their 64 x 128 tile (13.1 against 13.7 ms per build at (20, 200, 600), 307
+  // against 321 ms at (40, 400, 1200), for the register-staged loop on the 128 x 128
+  // tile); the other builds keep the register-staged loop (FP32 on 128 x 128: 171
+  // against 195 ms with direct loads at (40, 400, 1200); the FP64 copy of a mixed plan,
+  // built on the 96 x 128 tile of its low-precision operands).
+  constexpr bool kBuild64 = PPL_BUILD_DIRECT3 && sizeof(T) == 8 && WM == 4 && WN == 2 && WAVES_M == 1 && WAVES_N == 4;
+  constexpr bool kDirect = std::is_same_v<Epi, EpiStore<T>> || kBuild64;
+  if constexpr (kFpDirect3 && kDirect) {
     __shared__ __attribute__((aligned(16))) T st0[G::BUF_A + G::BUF_B];
     __shared__ __attribute__((aligned(16))) T st1[G::BUF_A + G::BUF_B];
     __shared__ __attribute__((aligned(16))) T st2[G::BUF_A + G::BUF_B];
@@ -1507,7 +1515,7 @@ int contract_tile_default(int prec, int64_t Nrows) {
 }
 
 // The integral build runs on one of these contraction tiles (ids as in kContract).
-bool build_tile_ok(int tile) { return tile == 0 || tile == 1 || tile == 5 || tile == 8; }
+bool build_tile_ok(int tile) { return tile == 0 || tile == 1 || tile == 5 || tile == 8 || tile == 9 || tile == 10; }
 
 int build_tile_dims(int tile, int* bm, int* bn) {
   if (!build_tile_ok(tile)) return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
@@ -2151,6 +2159,8 @@ int gemm_build_sym(hipStream_t s, int prec, int tile, int v, int a0, int a1, int
     case 1: return build_sym_cfg<4, 4, 2, 2>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
     case 5: return build_sym_cfg<6, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
     case 8: return build_sym_cfg<4, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
+    case 9: return build_sym_cfg<7, 2, 2, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
+    case 10: return build_sym_cfg<7, 1, 2, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
     default: return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
   }
 }
@@ -2163,6 +2173,8 @@ int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t
     case 1: return build_cfg<4, 4, 2, 2>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
     case 5: return build_cfg<6, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
     case 8: return build_cfg<4, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
+    case 9: return build_cfg<7, 2, 2, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
+    case 10: return build_cfg<7, 1, 2, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles);
     default: return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
   }
 }

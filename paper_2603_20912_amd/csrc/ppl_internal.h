@@ -196,12 +196,18 @@ int contract_min_splits(int prec, int64_t Kpad);
 // *tile_out >= 0 on entry fixes the tile and only chooses the split count
 void contract_choose(int prec, int64_t Nrows, int64_t Prows, int64_t Kpad, int max_splits, int* tile_out,
                      int* splits_out);
-// contraction tile the integral build GEMM of a plan runs on (measured at (20, 200, 600)
-// and (30, 300, 900): 128 x 128 for FP64 and FP32 operands, 96 x 128 for BF16x3)
+// contraction tile the integral build GEMM of a plan runs on (measured at (20, 200, 600),
+// (30, 300, 900) and (40, 400, 1200): 64 x 128 with direct loads for FP64 operands,
+// 128 x 128 for FP32, 96 x 128 for BF16x3 and BF16x6)
 #ifndef PPL_BUILD_TILE
-#define PPL_BUILD_TILE 1     // FP64 / FP32 integral-build tile (contraction tile id)
+#define PPL_BUILD_TILE 1     // FP32 integral-build tile (contraction tile id)
 #endif
-inline int build_tile_for_prec(int prec) { return prec == PPL_BF16X3 || prec == PPL_BF16X6 ? 5 : PPL_BUILD_TILE; }
+#ifndef PPL_BUILD_TILE_F64
+#define PPL_BUILD_TILE_F64 8 // FP64 integral-build tile
+#endif
+inline int build_tile_for_prec(int prec) {
+  return prec == PPL_BF16X3 || prec == PPL_BF16X6 ? 5 : (prec == PPL_FP64 ? PPL_BUILD_TILE_F64 : PPL_BUILD_TILE);
+}
 constexpr int kMaxSplits = 8;          // split-K slices 1 .. kMaxSplits; 0 selects stream-K
 constexpr int64_t kStreamKMaxGrid = 1024;   // stream-K workgroups at most (partial slots: 2 each)
 constexpr int64_t kStreamKMinChunks = 8;    // and at least this many K chunks per workgroup
