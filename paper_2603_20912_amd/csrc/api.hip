@@ -322,18 +322,24 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   return L.cur;
 }
 
+// Build tile lists per step: set 0 for the plan's operands, set 1 for the FP64 copy of
+// a mixed plan when that builds on another tile.
 static void make_tile_tables(ppl_plan_t p) {
   p->tiles_host.clear();
   p->tiles_off.clear();
   p->tiles_n.clear();
-  for (const Batch& b : p->batches) {
-    std::vector<int> list;
-    int nmt, nnt;
-    if (p->sym_build) build_tile_table_sym(p->tile_build, p->v, b.a0, b.a1, list, nmt, nnt);
-    else build_tile_table(p->tile_build, p->v, b.a0, b.a1, list, nmt, nnt);
-    p->tiles_off.push_back((int64_t)p->tiles_host.size());
-    p->tiles_n.push_back((int64_t)list.size() / 2);
-    p->tiles_host.insert(p->tiles_host.end(), list.begin(), list.end());
+  p->tile_sets = (p->ops[1].present && p->tile_build64 != p->tile_build) ? 2 : 1;
+  for (int set = 0; set < p->tile_sets; ++set) {
+    const int tile = set ? p->tile_build64 : p->tile_build;
+    for (const Batch& b : p->batches) {
+      std::vector<int> list;
+      int nmt, nnt;
+      if (p->sym_build) build_tile_table_sym(tile, p->v, b.a0, b.a1, list, nmt, nnt);
+      else build_tile_table(tile, p->v, b.a0, b.a1, list, nmt, nnt);
+      p->tiles_off.push_back((int64_t)p->tiles_host.size());
+      p->tiles_n.push_back((int64_t)list.size() / 2);
+      p->tiles_host.insert(p->tiles_host.end(), list.begin(), list.end());
+    }
   }
 }
 
@@ -414,8 +420,12 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
     PPL_TRY(stage_vv(st, s.prec, L, p->o, p->v, p->naux, p->ldx, at<void>(p, s.xt),
                      s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr));
   }
-  const int* dtiles = at<int>(p, p->tiles) + p->tiles_off[bi];
-  const int64_t nvalid = p->tiles_n[bi];
+  // the FP64 copy of a mixed plan builds on the FP64 build tile, with its own lists
+  const int set = (&s == &p->ops[1] && p->tile_sets == 2) ? 1 : 0;
+  const int tile = (&s == &p->ops[1]) ? p->tile_build64 : p->tile_build;
+  const size_t ti = (size_t)set * p->batches.size() + (size_t)bi;
+  const int* dtiles = at<int>(p, p->tiles) + p->tiles_off[ti];
+  const int64_t nvalid = p->tiles_n[ti];
   // every write of this step must stay inside its region
   const uint64_t g_need = (uint64_t)(b.p1 - b.p0) * p->v * p->v * acc_bytes(s.prec);
   if (g_need > p->g.bytes)
@@ -431,7 +441,7 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
   if (p->sym_build) {
     {
       ProfScope ps(p, PPL_PROF_BUILD_GEMM, build_flops(p, b.a0, b.a1));
-      PPL_TRY(gemm_build_sym(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
+      PPL_TRY(gemm_build_sym(st, s.prec, tile, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
                              s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dtiles,
                              nvalid, at<int>(p, p->tab_vp), at<int>(p, p->cols)));
     }
@@ -444,7 +454,7 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
   }
   {
     ProfScope ps(p, PPL_PROF_BUILD_GEMM, build_flops(p, b.a0, b.a1));
-    PPL_TRY(gemm_build(st, s.prec, p->tile_build, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
+    PPL_TRY(gemm_build(st, s.prec, tile, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
                        s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dtiles,
                        nvalid));
   }
@@ -751,6 +761,7 @@ static int plan_create(const ppl_desc_t* d, ppl_plan_t* out, bool external_g) {
   p->ops[1].prec = PPL_FP64;
   p->ops[1].present = p->keep_fp64 != 0;
   p->tile_build = build_tile_for_prec(p->prec);
+  p->tile_build64 = p->ops[1].present ? build_tile_for_prec(PPL_FP64) : p->tile_build;
   {
     int t = d->tile_contract, sp = 1;
     contract_choose(p->prec, p->Np, p->Pp, p->ldp, kMaxSplits, &t, &sp);

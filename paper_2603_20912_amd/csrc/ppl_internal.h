@@ -109,6 +109,7 @@ struct ppl_plan_s {
   int64_t ld_part = 0;                 // row length of split-K partial slices (streaming: one batch wide)
   // tiles
   int tile_build = 0, tile_contract = 0;
+  int tile_build64 = 0;                // build tile of the FP64 copy of a mixed plan (ops[1])
   int split_p = 1, tile_m = 0, split_m = 1;   // split-K of the R+ GEMM; tile and split-K of the R- GEMM
   // workspace
   uint64_t ws_bytes_needed = 0;
@@ -145,8 +146,9 @@ struct ppl_plan_s {
   ppl::Region cols;                    // operand rows of the upper-triangle build's columns (int32, v^2)
   std::vector<int> cols_host;
   std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
-  std::vector<int64_t> tiles_off;      // element offset of each batch's list in `tiles`
-  std::vector<int64_t> tiles_n;        // tiles in each batch's list
+  std::vector<int64_t> tiles_off;      // element offset of each batch's list in `tiles`, [set][batch]
+  std::vector<int64_t> tiles_n;        // tiles in each batch's list, [set][batch]
+  int tile_sets = 1;                   // 2 when the FP64 copy builds on a tile of its own
   const double* L_last = nullptr;
   bool setup_done = false;
   // kernel timing
