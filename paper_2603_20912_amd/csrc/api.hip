@@ -644,11 +644,42 @@ static int check_symmetric(ppl_plan_t p, const double* L) {
   return PPL_OK;
 }
 
+// The low-precision V+- of a resident mixed plan, rounded from its complete FP64 copy
+// (the same elementwise rounding as the amplitudes before each low-precision sweep): one
+// pass over memory instead of a second build in the low precision, and operands closer
+// to the FP64 integrals than a low-precision build gives.
+static int derive_lowprec(ppl_plan_t p) {
+  OperandSet& lo = p->ops[0];
+  const OperandSet& f = p->ops[1];
+  ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
+  PPL_TRY(convert_rows(p->stream, lo.prec, at<double>(p, f.vp), p->Pp, p->Pp, p->ldp, at<void>(p, lo.vp),
+                       lo.vp_lo.bytes ? at<void>(p, lo.vp_lo) : nullptr));
+  if (p->Pm > 0)
+    PPL_TRY(convert_rows(p->stream, lo.prec, at<double>(p, f.vm), p->Pm, p->Pm, p->ldm, at<void>(p, lo.vm),
+                         lo.vm_lo.bytes ? at<void>(p, lo.vm_lo) : nullptr));
+  lo.built = true;
+  return PPL_OK;
+}
+
 // ppl_build_batch after its argument and symmetry checks
 static int build_checked(ppl_plan_t p, const double* L, int32_t batch) {
   const int nb = (int)p->batches.size();
   p->L_last = L;
   if (!p->resident) return PPL_OK;       // streaming plans build inside ppl_contract
+  if (p->ops[1].present) {               // mixed: build in FP64, round to the low precision
+    OperandSet& f = p->ops[1];
+    if (batch < 0) {
+      PPL_TRY(build_all(p, f, L));
+      return derive_lowprec(p);
+    }
+    PPL_TRY(build_one(p, f, L, batch, false));
+    if (batch == nb - 1) {
+      PPL_TRY(mirror_vpm(p, f));
+      f.built = true;
+      PPL_TRY(derive_lowprec(p));
+    }
+    return PPL_OK;
+  }
   for (int k = 0; k < 2; ++k) {
     OperandSet& s = p->ops[k];
     if (!s.present) continue;

@@ -136,7 +136,13 @@ def test_c3_mixed_learned_diis_certified_by_oracle(P):
                                                              for _ in range(47)]) for ij in pairs]
     d = sampled_residual(s, t_m, pairs_idx)
     n_all = o * o * v * v
-    r_est = float(np.sqrt(np.mean(d * d) * n_all))
+    # The full-tensor estimate comes from the uniformly drawn entries only (random pairs x
+    # random (a, b)): the fixed extreme entries, (i, j) = (o-1, o-1) with a = b = 0 among
+    # them, have the smallest denominators and carry most of the residual of an iterate
+    # near convergence, so counting them as typical overstates the norm by an order of
+    # magnitude. Each of them is held to the norm bound on its own.
+    uni = d.reshape(len(pairs_idx), -1)[4:, 3:]
+    r_est = float(np.sqrt(np.mean(uni * uni) * n_all))
     # the returned t is the last sweep's output t' = (V + PPL(t_k)) / D, so its own residual is
     # D^-1 K (t' - t_k): at most sqrt(max|D| / min|D|) rho times the reported one (rho < 1 for
     # this generator); the sampled estimate carries sampling noise, hence the factor 1.5
@@ -144,8 +150,8 @@ def test_c3_mixed_learned_diis_certified_by_oracle(P):
     Dmin = -2 * s["e_occ"][-1] + 2 * s["e_vir"][0]
     bound = 1.5 * np.sqrt(Dmax / Dmin) * rep_m["residual"]
     say(f"  oracle residual at {d.size} entries: max {np.abs(d).max():.2e}, full-tensor estimate {r_est:.2e} "
-        f"(reported {rep_m['residual']:.2e}, bound {bound:.2e})")
-    assert np.isfinite(d).all() and r_est < bound
+        f"from {uni.size} uniform entries (reported {rep_m['residual']:.2e}, bound {bound:.2e})")
+    assert np.isfinite(d).all() and r_est < bound and np.abs(d).max() < bound
     # the oracle's energy of the returned amplitudes, over the whole tensor
     V, _ = O.mp2_parts(s["L"], o, s["e_occ"], s["e_vir"])
     E = O.energy(V, t_m.cpu().numpy())
