@@ -256,6 +256,9 @@ struct EpiBuildSym {
 #ifndef PPL_BUILD_DIRECT3
 #define PPL_BUILD_DIRECT3 1
 #endif
+#ifndef PPL_GROUPED_DIRECT3
+#define PPL_GROUPED_DIRECT3 1
+#endif
 constexpr int kLdsLayout = PPL_LDS_LAYOUT;
 constexpr int kFragVec = PPL_FRAG_VEC;
 constexpr int kSchedFence = PPL_SCHED_FENCE;
@@ -2220,7 +2223,23 @@ template <class T>
 struct GroupedLds {       // LDS of the largest allowed tile (208 x 64 rows staged, 272 in all)
   static constexpr int KC = sizeof(T) == 8 ? kKcF64 : kKcF32;
   static constexpr int bytes = TileGeom<T, 13, 1, 1, 4, KC>::LDS_BYTES;
+  static constexpr int stage = 272 * KC;   // elements of one direct-load stage of that tile
 };
+
+// The same item with the three-stage direct loads: the stages are three distinct LDS
+// arrays of the kernel (so that the compiler tells the loads into one stage from the
+// reads of another), and the function is inlined into it for the same reason.
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
+__device__ __forceinline__ void grouped_tile_direct(const GroupDesc& g, int m0, int n0, T* st0, T* st1, T* st2,
+                                                    global_char_t* base) {
+  static_assert((16 * WM * WAVES_M + 16 * WN * WAVES_N) * KC <= GroupedLds<T>::stage, "tile exceeds the stages");
+  static_assert(64 * WAVES_M * WAVES_N == 256, "grouped tiles use 256 threads");
+  TileJob job{m0, n0, 0, g.nk, 0};
+  const T* A = (const T*)(base + g.a_off);
+  const T* B = (const T*)(base + g.b_off);
+  EpiStore<T> epi{(T*)(base + g.c_off), g.ldc, 0, g.M, g.N, 1.0, 0.0, 0};
+  tile_body_direct3<T, WM, WN, WAVES_M, WAVES_N, KC>(job, g.M, g.N, A, g.lda, B, g.ldb, epi, st0, st1, st2);
+}
 
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC>
 __device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, char* smem, global_char_t* base) {
@@ -2244,7 +2263,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_grouped_kernel(char* base, const GroupDesc* __restrict__ groups, const int4* __restrict__ items,
                     const int* __restrict__ q_begin, int* counters) {
   constexpr int KC = GroupedLds<T>::KC;
-  __shared__ __attribute__((aligned(16))) char smem[GroupedLds<T>::bytes];
+  constexpr bool kDirect = kFpDirect3 && PPL_GROUPED_DIRECT3;
+  __shared__ __attribute__((aligned(16))) char smem[kDirect ? 16 : GroupedLds<T>::bytes];
+  __shared__ __attribute__((aligned(16))) T st0[kDirect ? GroupedLds<T>::stage : 2];
+  __shared__ __attribute__((aligned(16))) T st1[kDirect ? GroupedLds<T>::stage : 2];
+  __shared__ __attribute__((aligned(16))) T st2[kDirect ? GroupedLds<T>::stage : 2];
   __shared__ int s_item;
   global_char_t* const gbase = (global_char_t*)base;
   // queue q holds items [q_begin[q], q_begin[q + 1]); a workgroup drains the queue of
@@ -2261,6 +2284,18 @@ gemm_grouped_kernel(char* base, const GroupDesc* __restrict__ groups, const int4
       if (it >= e) break;
       const int4 w = items[it];
       const GroupDesc g = groups[w.x];
+      if constexpr (kDirect) {
+        switch (g.cfg) {
+          case 0: grouped_tile_direct<T, 7, 2, 1, 4, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+          case 1: grouped_tile_direct<T, 4, 4, 2, 2, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+          case 2: grouped_tile_direct<T, 13, 1, 1, 4, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+          case 5: grouped_tile_direct<T, 6, 2, 1, 4, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+          case 6: grouped_tile_direct<T, 2, 2, 1, 4, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+          case 7: grouped_tile_direct<T, 3, 2, 1, 4, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+          default: grouped_tile_direct<T, 4, 2, 1, 4, KC>(g, w.y, w.z, st0, st1, st2, gbase); break;
+        }
+        continue;
+      }
       switch (g.cfg) {
         case 0: grouped_tile<T, 7, 2, 1, 4, KC>(g, w.y, w.z, smem, gbase); break;
         case 1: grouped_tile<T, 4, 4, 2, 2, KC>(g, w.y, w.z, smem, gbase); break;
