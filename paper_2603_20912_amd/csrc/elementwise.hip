@@ -462,7 +462,7 @@ int add_transposed(hipStream_t s, int c_prec, void* C, int64_t ldc, const double
 // block pair per workgroup: block (I, J), I >= J, reads rows J and columns I (upper) through
 // LDS and writes rows I and columns J (lower), both along contiguous rows.
 template <class E>
-__global__ void __launch_bounds__(256) mirror_lower_kernel(E* V, int64_t n, int64_t ld) {
+__global__ void __launch_bounds__(256) mirror_lower_kernel(E* V, int64_t n, int64_t ld, int vec_ok) {
   __shared__ E sh[64][65];
   const int64_t t = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -471,6 +471,28 @@ __global__ void __launch_bounds__(256) mirror_lower_kernel(E* V, int64_t n, int6
   const int64_t J = t - I * (I + 1) / 2;
   const int tid = threadIdx.x;
   const int64_t r0 = I * 64, q0 = J * 64;
+  if (vec_ok && I > J && r0 + 64 <= n) {
+    // a whole block below the diagonal: 16-byte vectors along both rows (rows 16-byte
+    // aligned, checked on the host), the transposition in LDS element by element
+    constexpr int VE = 16 / (int)sizeof(E), VR = 64 / VE;
+    union Vec { uint4 u; E e[VE]; };
+    for (int x = tid; x < 64 * VR; x += 256) {
+      const int ql = x / VR, vv = x % VR;
+      Vec y;
+      y.u = *reinterpret_cast<const uint4*>(&V[(q0 + ql) * ld + r0 + vv * VE]);
+#pragma unroll
+      for (int k = 0; k < VE; ++k) sh[ql][vv * VE + k] = y.e[k];
+    }
+    __syncthreads();
+    for (int x = tid; x < 64 * VR; x += 256) {
+      const int rl = x / VR, vv = x % VR;
+      Vec y;
+#pragma unroll
+      for (int k = 0; k < VE; ++k) y.e[k] = sh[vv * VE + k][rl];
+      *reinterpret_cast<uint4*>(&V[(r0 + rl) * ld + q0 + vv * VE]) = y.u;
+    }
+    return;
+  }
   for (int e = tid; e < 64 * 64; e += 256) {
     const int ql = e >> 6, rl = e & 63;                  // read row q0 + ql, column r0 + rl
     const int64_t q = q0 + ql, r = r0 + rl;
@@ -488,12 +510,17 @@ int mirror_lower(hipStream_t s, int elem_bytes, void* V, int64_t n, int64_t ld) 
   if (n <= 1) return PPL_OK;
   const int64_t T = (n + 63) / 64, blocks = T * (T + 1) / 2;
   if (blocks > 0x7fffffffLL) return fail(PPL_E_ARG, "mirror of %lld rows too large", (long long)n);
+  // 16-byte vectors need every row and every 64-element block start 16-byte aligned
+  const int vec_ok = ((uintptr_t)V % 16 == 0) && ((uint64_t)ld * elem_bytes % 16 == 0);
   if (elem_bytes == 8)
-    hipLaunchKernelGGL(mirror_lower_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t*)V, n, ld);
+    hipLaunchKernelGGL(mirror_lower_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t*)V, n, ld,
+                       vec_ok);
   else if (elem_bytes == 4)
-    hipLaunchKernelGGL(mirror_lower_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)V, n, ld);
+    hipLaunchKernelGGL(mirror_lower_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)V, n, ld,
+                       vec_ok);
   else if (elem_bytes == 2)
-    hipLaunchKernelGGL(mirror_lower_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint16_t*)V, n, ld);
+    hipLaunchKernelGGL(mirror_lower_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint16_t*)V, n, ld,
+                       vec_ok);
   else
     return fail(PPL_E_ARG, "mirror of %d-byte elements", elem_bytes);
   PPL_LAUNCH_CHECK();
