@@ -260,30 +260,45 @@ pack_vpm_sym_kernel(int v, int a0, int64_t pair0, const Tg* __restrict__ G, cons
   const double dscale = half_diag ? 0.25 : 0.5;
   const int tid = threadIdx.x;
   const int nt = (v - a + 31) / 32;            // 32-wide tiles of c and d, starting at a
-  for (int ci = 0; ci < nt; ++ci) {
-    for (int di = ci; di < nt; ++di) {
-      const int cB = a + ci * 32, dB = a + di * 32;
-      for (int e = tid; e < 1024; e += 256) {
-        const int r = e >> 5, q = e & 31;
-        const int c1 = cB + r, d1 = dB + q;
-        t1[r][q] = (c1 < v && d1 < v) ? (double)g[(int64_t)(c1 - a0) * W + (d1 - a0)] : 0.0;
-        const int c2 = dB + r, d2 = cB + q;   // row d, col c
-        t2[q][r] = (c2 < v && d2 < v) ? (double)g[(int64_t)(c2 - a0) * W + (d2 - a0)] : 0.0;
-      }
-      __syncthreads();
-      for (int e = tid; e < 1024; e += 256) {
-        const int r = e >> 5, q = e & 31;
-        const int c = cB + r, d = dB + q;
-        if (c < v && d < v && c <= d && (c > a || d >= b)) {
-          const double gcd = t1[r][q], gdc = t2[r][q];
-          const bool diag = c == a && d == b;
-          Store<PREC>::put(vp, vp_lo, rowp * ldp + pair_plus(c, d, v), (diag ? dscale : 0.5) * (gcd + gdc));
-          if (has_minus && c < d)
-            Store<PREC>::put(vm, vm_lo, rowm * ldm + pair_minus(c, d, v), (diag ? dscale : 0.5) * (gcd - gdc));
-        }
-      }
-      __syncthreads();
+  // the tile pairs (ci, di >= ci) in turn; the G values of the next pair are fetched into
+  // registers before the current pair is written, so that their latency overlaps it
+  double n1[4], n2[4];
+  auto fetch = [&](int ci, int di) __attribute__((always_inline)) {
+    const int cB = a + ci * 32, dB = a + di * 32;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k, r = e >> 5, q = e & 31;
+      const int c1 = cB + r, d1 = dB + q;
+      n1[k] = (c1 < v && d1 < v) ? (double)g[(int64_t)(c1 - a0) * W + (d1 - a0)] : 0.0;
+      const int c2 = dB + r, d2 = cB + q;     // row d, col c
+      n2[k] = (c2 < v && d2 < v) ? (double)g[(int64_t)(c2 - a0) * W + (d2 - a0)] : 0.0;
     }
+  };
+  int ci = 0, di = 0;
+  fetch(ci, di);
+  while (ci < nt) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k, r = e >> 5, q = e & 31;
+      t1[r][q] = n1[k];
+      t2[q][r] = n2[k];
+    }
+    __syncthreads();
+    const int cB = a + ci * 32, dB = a + di * 32;
+    if (++di == nt) di = ++ci;                 // the next pair
+    if (ci < nt) fetch(ci, di);
+    for (int e = tid; e < 1024; e += 256) {
+      const int r = e >> 5, q = e & 31;
+      const int c = cB + r, d = dB + q;
+      if (c < v && d < v && c <= d && (c > a || d >= b)) {
+        const double gcd = t1[r][q], gdc = t2[r][q];
+        const bool diag = c == a && d == b;
+        Store<PREC>::put(vp, vp_lo, rowp * ldp + pair_plus(c, d, v), (diag ? dscale : 0.5) * (gcd + gdc));
+        if (has_minus && c < d)
+          Store<PREC>::put(vm, vm_lo, rowm * ldm + pair_minus(c, d, v), (diag ? dscale : 0.5) * (gcd - gdc));
+      }
+    }
+    __syncthreads();
   }
   for (int64_t k = Pp + tid; k < ldp; k += 256) Store<PREC>::put(vp, vp_lo, rowp * ldp + k, 0.0);
   if (has_minus)
