@@ -1005,21 +1005,42 @@ int energy_only(hipStream_t s, int o, int v, const double* vs, const double* va,
 }
 
 // Sums of (L^P_ac - L^P_ca)^2 and (L^P_ac)^2 + (L^P_ca)^2 over the virtual block, a < c
-// (red_out[0], red_out[1]): the relative asymmetry of the Cholesky vectors.
+// (red_out[0], red_out[1]): the relative asymmetry of the Cholesky vectors. Work items are
+// 32 x 32 block pairs (P, A <= C): block (A, C) and block (C, A) are both read along rows
+// and the second is transposed through LDS, so that every read is coalesced.
 __global__ void __launch_bounds__(kReduceThreads)
 asym_kernel(const double* __restrict__ L, int n, int o, int v, int naux, double* partials) {
+  static_assert(kReduceThreads == 256, "four elements of a 32 x 32 block per thread");
+  __shared__ double tr[32][33];
   double d2 = 0.0, l2 = 0.0;
-  const int64_t total = (int64_t)naux * v * v;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
-    const int c = (int)(x % v);
-    const int64_t y = x / v;
-    const int a = (int)(y % v);
-    const int64_t P = y / v;
-    if (a >= c) continue;
-    const double lac = L[(P * n + o + a) * n + o + c], lca = L[(P * n + o + c) * n + o + a];
-    d2 += (lac - lca) * (lac - lca);
-    l2 += lac * lac + lca * lca;
+  const int nb = (v + 31) / 32;
+  const int64_t per_p = (int64_t)nb * (nb + 1) / 2;
+  const int64_t items = (int64_t)naux * per_p;
+  const int tid = threadIdx.x;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t P = it / per_p;
+    int k = (int)(it % per_p), A = 0;
+    while (k >= nb - A) k -= nb - A++;           // block pair (A, C = A + k)
+    const int C = A + k;
+    const double* Lp = L + P * n * n;
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {             // block (C, A) by rows, stored transposed
+      const int e = tid + 256 * e4, r = e >> 5, q = e & 31;
+      const int c = C * 32 + r, a = A * 32 + q;
+      tr[q][r] = (c < v && a < v) ? Lp[(int64_t)(o + c) * n + o + a] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {             // block (A, C) by rows, against it
+      const int e = tid + 256 * e4, r = e >> 5, q = e & 31;
+      const int a = A * 32 + r, c = C * 32 + q;
+      if (a < c && c < v) {
+        const double lac = Lp[(int64_t)(o + a) * n + o + c], lca = tr[r][q];
+        d2 += (lac - lca) * (lac - lca);
+        l2 += lac * lac + lca * lca;
+      }
+    }
+    __syncthreads();
   }
   double vals[3] = {d2, l2, 0.0};
   block_reduce_store<3>(vals, partials);

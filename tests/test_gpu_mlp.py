@@ -237,3 +237,29 @@ def test_checked_start_falls_back_to_mp2(P, kind):
     assert abs(rep["energy"] - rep_ref["energy"]) < 1e-13 * abs(rep_ref["energy"])
     if kind in ("nan", "inf"):
         assert abs(rep["energy_start"] - rep_ref["energy_start"]) < 1e-14 * abs(rep_ref["energy_start"])
+
+
+def test_committed_weights_gain_on_held_out_instance(P):
+    """The committed network (weights/mlp_start.f32) on one held-out (30, 300, 900)
+    instance of the contractive generator (seed 3000, outside the training seeds): from its
+    guess the FP64 iteration reaches 1e-7 in fewer sweeps than from the first-order
+    amplitudes (24 against 30 when the weights were committed), at the same fixed point."""
+    import os
+    from paper_2603_20912_amd import learned as Lr
+    weights = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                           "paper_2603_20912_amd", "weights", "mlp_start.f32")
+    say("committed weights: held-out (30,300,900) seed 3000, FP64 sweeps to 1e-7, MP2 vs learned")
+    sysd = S.make_system(30, 300, 900, 3000, "contractive")
+    mlp = P.MLP(max_batch=1024)
+    mlp.set_params(np.fromfile(weights, dtype="<f4"))
+    r_m, t_m = Lr.time_to_tol(sysd, "mp2", tol=1e-7)
+    r_l, t_l = Lr.time_to_tol(sysd, "learned", mlp=mlp, tol=1e-7)
+    mlp.close()
+    say(f"  sweeps mp2 {r_m['sweeps']} ({r_m['seconds']:.2f} s), learned {r_l['sweeps']} ({r_l['seconds']:.2f} s); "
+        f"E {r_m['energy']:.10f} vs {r_l['energy']:.10f}")
+    assert r_m["status"] == 0 and r_l["status"] == 0
+    assert r_l["sweeps"] <= r_m["sweeps"] - 3
+    assert abs(r_m["energy"] - r_l["energy"]) < 1e-7 * abs(r_m["energy"])
+    assert rel(t_l.cpu().numpy(), t_m.cpu().numpy()) < 1e-5
+    del t_m, t_l
+    torch.cuda.empty_cache()
