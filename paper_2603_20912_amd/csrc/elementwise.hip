@@ -640,69 +640,98 @@ int convert_rows(hipStream_t s, int prec, const double* src, int64_t rows, int64
 }
 
 // ------------------------------------------------------------------ unpack R and t
-template <class Tr>
-__global__ void unpack_r_kernel(int o, int v, const Tr* __restrict__ rp, int64_t ldp,
-                                const Tr* __restrict__ rm, int64_t ldm, double* R, double alpha,
-                                double beta) {
-  const int64_t total = (int64_t)o * o * v * v;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
-    const int b = (int)(x % v);
-    const int64_t y = x / v;
-    const int a = (int)(y % v);
-    const int64_t z = y / v;
-    const int j = (int)(z % o), i = (int)(z / o);
-    const int i0 = i < j ? i : j, j0 = i < j ? j : i;
-    const int a0 = a < b ? a : b, b0 = a < b ? b : a;
-    double r = (double)rp[pair_plus(i0, j0, o) * ldp + pair_plus(a0, b0, v)];
-    if (i != j && a != b) {
-      const double m = (double)rm[pair_minus(i0, j0, o) * ldm + pair_minus(a0, b0, v)];
-      r += ((i < j) == (a < b)) ? m : -m;
+// Both unpackings over tiles: a work item is one occupied pair (i0 <= j0) and one 32 x 32
+// block pair (A <= B) of virtual indices. The packed values of (a, b), a <= b, are read
+// along their rows once and give the four entries (i0 j0 a b), (i0 j0 b a), (j0 i0 a b) and
+// (j0 i0 b a); the (b a) entries are written from an LDS transpose, so that reads and
+// writes both run along contiguous rows. MODE 0 unpacks R (R = alpha r + beta R), MODE 1
+// the amplitudes (s = S' / (2 - delta_ab), a = A' / 2).
+template <class Tr, int MODE>
+__global__ void __launch_bounds__(256)
+unpack_tiled_kernel(int o, int v, const Tr* __restrict__ xp, int64_t ldp, const Tr* __restrict__ xm, int64_t ldm,
+                    double* out, double alpha, double beta) {
+  __shared__ double sp_[32][33], sm_[32][33];
+  const int nb = (v + 31) / 32;
+  const int64_t per = (int64_t)nb * (nb + 1) / 2;
+  const int64_t items = npairs_plus(o) * per;
+  const int tid = threadIdx.x;
+  auto put = [&](int64_t x, double val) __attribute__((always_inline)) {
+    out[x] = (MODE == 1 || beta == 0.0) ? alpha * val : alpha * val + beta * out[x];
+  };
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t pr = it / per;
+    int k = (int)(it % per), A = 0;
+    while (k >= nb - A) k -= nb - A++;          // block pair (A, B = A + k)
+    const int B = A + k;
+    int i0 = 0;                                 // occupied pair pr = (i0, j0), i0 <= j0
+    while (pair_plus(i0 + 1, i0 + 1, o) <= pr) ++i0;
+    const int j0 = i0 + (int)(pr - pair_plus(i0, i0, o));
+    const bool offd = i0 < j0;
+    const int64_t qr = offd ? pair_minus(i0, j0, o) : 0;
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+      const int e = tid + 256 * e4, r = e >> 5, c = e & 31;
+      const int a = A * 32 + r, b = B * 32 + c;
+      const bool ok = a < v && b < v && a <= b;
+      double pv = ok ? (double)xp[pr * ldp + pair_plus(a, b, v)] : 0.0;
+      double mv = (ok && offd && a < b) ? (double)xm[qr * ldm + pair_minus(a, b, v)] : 0.0;
+      if (MODE == 1) {
+        if (a != b) pv *= 0.5;
+        mv *= 0.5;
+      }
+      sp_[r][c] = pv;
+      sm_[r][c] = mv;
     }
-    R[x] = (beta == 0.0) ? alpha * r : alpha * r + beta * R[x];
+    __syncthreads();
+    const int64_t row_ij = ((int64_t)i0 * o + j0) * v, row_ji = ((int64_t)j0 * o + i0) * v;
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {            // entries (a, b), a <= b
+      const int e = tid + 256 * e4, r = e >> 5, c = e & 31;
+      const int a = A * 32 + r, b = B * 32 + c;
+      if (a < v && b < v && a <= b) {
+        const double pv = sp_[r][c], mv = sm_[r][c];
+        put((row_ij + a) * v + b, pv + mv);
+        if (offd) put((row_ji + a) * v + b, pv - mv);
+      }
+    }
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {            // entries (b, a), a < b, from the transpose
+      const int e = tid + 256 * e4, rb = e >> 5, ca = e & 31;
+      const int b = B * 32 + rb, a = A * 32 + ca;
+      if (b < v && a < b) {
+        const double pv = sp_[ca][rb], mv = sm_[ca][rb];
+        put((row_ij + b) * v + a, pv - mv);
+        if (offd) put((row_ji + b) * v + a, pv + mv);
+      }
+    }
+    __syncthreads();
   }
+}
+
+static int64_t unpack_grid(int o, int v) {
+  const int64_t nb = (v + 31) / 32, items = npairs_plus(o) * (nb * (nb + 1) / 2);
+  return items < 8192 ? items : 8192;
 }
 
 int unpack_r(hipStream_t s, int acc_prec, int o, int v, const void* rp, int64_t ldp, const void* rm,
              int64_t ldm, double* R, double alpha, double beta) {
-  const int64_t total = (int64_t)o * o * v * v;
+  if (o <= 0 || v <= 0) return PPL_OK;
+  const unsigned g = (unsigned)unpack_grid(o, v);
   if (acc_prec == PPL_FP64)
-    hipLaunchKernelGGL(unpack_r_kernel<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v,
-                       (const double*)rp, ldp, (const double*)rm, ldm, R, alpha, beta);
+    hipLaunchKernelGGL((unpack_tiled_kernel<double, 0>), dim3(g), dim3(256), 0, s, o, v, (const double*)rp, ldp,
+                       (const double*)rm, ldm, R, alpha, beta);
   else
-    hipLaunchKernelGGL(unpack_r_kernel<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v,
-                       (const float*)rp, ldp, (const float*)rm, ldm, R, alpha, beta);
+    hipLaunchKernelGGL((unpack_tiled_kernel<float, 0>), dim3(g), dim3(256), 0, s, o, v, (const float*)rp, ldp,
+                       (const float*)rm, ldm, R, alpha, beta);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }
 
-__global__ void unpack_t_kernel(int o, int v, const double* __restrict__ sp, int64_t ldp,
-                                const double* __restrict__ am, int64_t ldm, double* t2) {
-  const int64_t total = (int64_t)o * o * v * v;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += st) {
-    const int b = (int)(x % v);
-    const int64_t y = x / v;
-    const int a = (int)(y % v);
-    const int64_t z = y / v;
-    const int j = (int)(z % o), i = (int)(z / o);
-    const int i0 = i < j ? i : j, j0 = i < j ? j : i;
-    const int a0 = a < b ? a : b, b0 = a < b ? b : a;
-    const double spv = sp[pair_plus(i0, j0, o) * ldp + pair_plus(a0, b0, v)];
-    double t = (a == b) ? spv : 0.5 * spv;        // s = S' / (2 - delta_ab)
-    if (i != j && a != b) {
-      const double h = 0.5 * am[pair_minus(i0, j0, o) * ldm + pair_minus(a0, b0, v)];  // a = A'/2
-      t += ((i < j) == (a < b)) ? h : -h;
-    }
-    t2[x] = t;
-  }
-}
-
 int unpack_t(hipStream_t s, int o, int v, const double* sp, int64_t ldp, const double* am,
              int64_t ldm, double* t2) {
-  const int64_t total = (int64_t)o * o * v * v;
-  hipLaunchKernelGGL(unpack_t_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, o, v, sp, ldp, am,
-                     ldm, t2);
+  if (o <= 0 || v <= 0) return PPL_OK;
+  hipLaunchKernelGGL((unpack_tiled_kernel<double, 1>), dim3((unsigned)unpack_grid(o, v)), dim3(256), 0, s, o, v,
+                     sp, ldp, am, ldm, t2, 1.0, 0.0);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

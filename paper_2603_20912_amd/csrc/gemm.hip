@@ -759,8 +759,19 @@ __device__ __forceinline__ void tile_body(const TileJob& job, int64_t M, int64_t
   store_acc<T, WM, WN>(acc, job, epi, wm, wn, lane);
 }
 
+// Two workgroups' waves per SIMD where two workgroups fit in LDS; one where the three
+// stages of the direct loads leave room for a single workgroup
+template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi>
+struct GemmOccupancy {
+  static constexpr bool build64 = PPL_BUILD_DIRECT3 && sizeof(T) == 8 && WM == 4 && WN == 2 && WAVES_M == 1 && WAVES_N == 4;
+  static constexpr bool direct = kFpDirect3 && (std::is_same_v<Epi, EpiStore<T>> || build64);
+  static constexpr int lds = 3 * 16 * (WM * WAVES_M + WN * WAVES_N) * KC * (int)sizeof(T);
+  static constexpr int waves = (direct && 2 * lds > 160 * 1024) ? 1 : 2;
+};
+
 template <class T, int WM, int WN, int WAVES_M, int WAVES_N, int KC, class Epi, class Map>
-__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N)
+__attribute__((amdgpu_waves_per_eu(GemmOccupancy<T, WM, WN, WAVES_M, WAVES_N, KC, Epi>::waves)))
 gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int64_t lda,
                const T* __restrict__ B, int64_t ldb, Epi epi, Map map) {
   using G = TileGeom<T, WM, WN, WAVES_M, WAVES_N, KC>;
@@ -772,9 +783,7 @@ gemm_nt_kernel(int64_t M, int64_t N, int64_t Kpad, const T* __restrict__ A, int6
   // tile); the other builds keep the register-staged loop (FP32 on 128 x 128: 171
   // against 195 ms with direct loads at (40, 400, 1200); the FP64 copy of a mixed plan,
   // built on the 96 x 128 tile of its low-precision operands).
-  constexpr bool kBuild64 = PPL_BUILD_DIRECT3 && sizeof(T) == 8 && WM == 4 && WN == 2 && WAVES_M == 1 && WAVES_N == 4;
-  constexpr bool kDirect = std::is_same_v<Epi, EpiStore<T>> || kBuild64;
-  if constexpr (kFpDirect3 && kDirect) {
+  if constexpr (GemmOccupancy<T, WM, WN, WAVES_M, WAVES_N, KC, Epi>::direct) {
     __shared__ __attribute__((aligned(16))) T st0[G::BUF_A + G::BUF_B];
     __shared__ __attribute__((aligned(16))) T st1[G::BUF_A + G::BUF_B];
     __shared__ __attribute__((aligned(16))) T st2[G::BUF_A + G::BUF_B];
@@ -2259,7 +2268,7 @@ __device__ __noinline__ void grouped_tile(const GroupDesc& g, int m0, int n0, ch
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFpDirect3 && PPL_GROUPED_DIRECT3 ? 1 : 2)))
 gemm_grouped_kernel(char* base, const GroupDesc* __restrict__ groups, const int4* __restrict__ items,
                     const int* __restrict__ q_begin, int* counters) {
   constexpr int KC = GroupedLds<T>::KC;
