@@ -414,13 +414,16 @@ def study_batched(args):
 PAPER_C_SPLIT = {(100, 700, 4000): {"CuPy GH200": 306.6, "PyTorch GH200": 355.9, "CuPy H100": 461.5,
                                     "PyTorch H100": 330.5},
                  (100, 800, 4500): {"CuPy GH200": 495.0, "PyTorch GH200": 587.1, "CuPy H100": 809.7,
-                                    "PyTorch H100": 496.2}}
+                                    "PyTorch H100": 496.2},
+                 (50, 950, 10000): {"CuPy GH200": 763.0, "PyTorch GH200": 574.6, "CuPy H100": 1006.4,
+                                    "PyTorch H100": 673.0}}
 
 
 def study_paper(args):
     """One FP64 PPL evaluation at a shape of the paper's contraction benchmark
     (Tab. xc-split: N = 800, nocc = 100, nvec = 5N = 4000, nvir = 700 by default; with
-    --paper-shape 100,800,4500 the N = 900 one), on one GPU.
+    --paper-shape 100,800,4500 the N = 900 one, with 50,950,10000 the N = 1000 one with
+    nocc = 50 and nvec = 10N), on one GPU.
 
     V+- would take about 960 GB, so the plan streams: each row batch is built from the
     Cholesky vectors and contracted at once, with t, R and L resident in HBM. Inputs are
