@@ -9,8 +9,8 @@ literal input generator (seed 1), all inputs already resident in HBM:
     residual and energy each),
   * one more PPL evaluation R = PPL(t) of the final amplitudes, unpacked to
     the caller's [o][o][v][v] array.
-value = useful flops of the pair method (one build of the upper triangle of V+-,
-2 naux P+^2, + 11 contractions) / step time. The dominant kernel is the R+ contraction GEMM; its roofline entry uses
+value = useful flops of the pair method (one build of the upper triangle of V+-
+over packed column pairs, naux (P+^2 + v(v+1)(2v+1)/6), + 11 contractions) / step time. The dominant kernel is the R+ contraction GEMM; its roofline entry uses
 HIP-event timings of its launches inside the timed region.
 
 The same JSON line carries the metric's second half under "time_to_residual": wall time
@@ -40,11 +40,13 @@ SWEEPS = 10
 
 def nominal(o, v, naux, upper=True):
     """Useful flops of the pair method. FP64 plans build the upper triangle of V+-
-    (rows (a, c >= a), columns (b >= a, d >= a): 2 naux P+^2); streaming plans of the
-    other precisions build every row in full (2 naux v^2 P+)."""
+    (rows (a, c >= a), columns the packed pairs (b <= d) with b >= a: 2 naux (v - a)^2
+    (v - a + 1) / 2 per virtual a, i.e. naux (P+^2 + v(v+1)(2v+1)/6)); streaming plans of
+    the other precisions build every row in full (2 naux v^2 P+)."""
     Pp, Pm = v * (v + 1) // 2, v * (v - 1) // 2
     Np, Nm = o * (o + 1) // 2, o * (o - 1) // 2
-    build = 2.0 * naux * Pp * Pp if upper else 2.0 * naux * v * v * Pp
+    sq = v * (v + 1) * (2 * v + 1) // 6
+    build = float(naux) * (Pp * Pp + sq) if upper else 2.0 * naux * v * v * Pp
     return {"build": build, "contract": 2.0 * (Pp * Pp * Np + Pm * Pm * Nm),
             "contract_plus": 2.0 * Pp * Pp * Np, "contract_minus": 2.0 * Pm * Pm * Nm}
 
@@ -452,7 +454,7 @@ def study_paper(args):
     if args.contract_config:
         eng.set_contract_config(*[int(x) for x in args.contract_config.split(",")])
     info = eng.info
-    # useful flops as the plan executes them (upper-triangle build steps: 2 naux P+^2)
+    # useful flops as the plan executes them (upper-triangle build steps over packed columns)
     out["useful_flops"] = info["flops_build"] + info["flops_contract"]
     out["useful_flops_build"] = info["flops_build"]
     out["plan"] = {k: info[k] for k in ("resident", "n_batches", "max_step_pairs", "workspace_bytes",

@@ -307,7 +307,7 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
     p->diis_t = p->diis_e = p->diis_red = Region{};
   }
   p->tiles = L.take((uint64_t)p->tiles_host.size() * 4);
-  p->cols = p->sym_build ? L.take((uint64_t)v * v * 4) : Region{};
+  p->cols = p->sym_build ? L.take((uint64_t)npairs_plus(v) * 4) : Region{};
   p->r2p = p->r2m = p->ut = Region{};
   if (p->sym_build && !resident) {
     // the K range of a step starts at its first pair rounded down to 64, so it spans at
@@ -383,13 +383,13 @@ struct ProfScope {
 
 // ------------------------------------------------------------------ build
 // Useful flops of building virtual rows a in [a0, a1): 2 naux v^2 per pair (a <= b) for full
-// rows; 2 naux (v - a)^3 per virtual a for the upper triangle (rows (a, c >= a), columns
-// (b >= a, d >= a)).
+// rows; 2 naux (v - a)^2 (v - a + 1) / 2 per virtual a for the upper triangle (rows
+// (a, c >= a), columns the packed pairs (b <= d) with b >= a).
 static double build_flops(ppl_plan_t p, int a0, int a1) {
   double f = 0.0;
   for (int a = a0; a < a1; ++a) {
     const double w = (double)(p->v - a);
-    f += p->sym_build ? w * w * w : (double)p->v * p->v * w;
+    f += p->sym_build ? w * w * (w + 1.0) / 2.0 : (double)p->v * p->v * w;
   }
   return 2.0 * p->naux * f;
 }

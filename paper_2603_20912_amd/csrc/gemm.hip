@@ -188,9 +188,10 @@ struct EpiBuild {        // G[pair(a,b) - pair(a0,a0)][c][d] for b >= a
 };
 
 // Upper-triangle build of a resident plan. Rows are the packed pairs (a, c), c >= a, of
-// the step's virtuals a in [a0, a1) (packed pairs pr0 + m); columns are the operand rows
-// b * v + d listed in `cols` (ordered by min(b, d), starting at min(b, d) = a0). Only
-// (ac|bd) with b >= a and d >= a is kept: G[pair(a,b) - pr0][c - a0][d - a0], W = v - a0.
+// the step's virtuals a in [a0, a1) (packed pairs pr0 + m); columns are the packed pairs
+// (b, d), b <= d, as operand rows b * v + d listed in `cols` (ordered by b, starting at
+// b = a0). Only (ac|bd) with b, d >= a is kept: G[pair(a,b) - pr0][c - a0][d - a0] and its
+// mirror G[pair(a,d) - pr0][c - a0][b - a0], W = v - a0.
 template <class Tg>
 struct EpiBuildSym {
   Tg* G;
@@ -209,14 +210,17 @@ struct EpiBuildSym {
     const int ac = ok ? tab[pr0 + m] : 0;
     base = ((int64_t)pair_first(ac) << 20) | pair_second(ac);
   }
+  // Column n is the packed pair (b <= d); (ac|bd) = (ac|db) for symmetric Cholesky vectors,
+  // so the product fills G_ab[c][d] and G_ad[c][b].
   __device__ void put(int64_t base, bool ok, int64_t n, Tg x) const {
     if (!ok || n >= N) return;
     const int a = (int)(base >> 20), c = (int)(base & ((1 << 20) - 1));
     const int bd = cols[n];
     const int b = bd / v, d = bd - b * v;
-    if (b < a || d < a) return;
-    const int64_t pr = pair_plus(a, b, v) - pr0;
-    G[(pr * W + (c - a0)) * W + (d - a0)] = x;
+    if (b < a) return;
+    const int64_t cr = c - a0;
+    G[((pair_plus(a, b, v) - pr0) * W + cr) * W + (d - a0)] = x;
+    if (d != b) G[((pair_plus(a, d, v) - pr0) * W + cr) * W + (b - a0)] = x;
   }
 };
 
@@ -1527,6 +1531,11 @@ int contract_tile_default(int prec, int64_t Nrows) {
 }
 
 // The integral build runs on one of these contraction tiles (ids as in kContract).
+// Row tiles per group in the launch order of the build tiles.
+#ifndef PPL_BUILD_GROUP
+#define PPL_BUILD_GROUP 8
+#endif
+
 bool build_tile_ok(int tile) { return tile == 0 || tile == 1 || tile == 5 || tile == 8 || tile == 9 || tile == 10; }
 
 int build_tile_dims(int tile, int* bm, int* bn) {
@@ -1543,7 +1552,7 @@ int build_tile_dims(int tile, int* bm, int* bn) {
 // A row tile starting at a (relative to a0) needs the column tiles from the one
 // holding b = a on; the earlier ones lie wholly below the diagonal b >= a.
 void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mt, int& n_nt) {
-  constexpr int kBuildGroup = 8;
+  constexpr int kBuildGroup = PPL_BUILD_GROUP;
   int bm, bn;
   build_tile_dims(tile, &bm, &bn);
   const int64_t M = (int64_t)(a1 - a0) * v, N = (int64_t)(v - a0) * v;
@@ -1564,20 +1573,20 @@ void build_tile_table(int tile, int v, int a0, int a1, std::vector<int>& tiles, 
 }
 
 // The upper-triangle build of one step (see EpiBuildSym): row tiles over the packed pairs
-// (a, c >= a) of a in [a0, a1), column tiles over the (v - a0)^2 columns ordered by
-// min(b, d). Columns with min(b, d) >= a start at v^2 - (v - a)^2 of that order, so a row
+// (a, c >= a) of a in [a0, a1), column tiles over the packed pairs (b <= d) of b >= a0,
+// ordered by b. Columns with b >= a start at a v - a (a - 1) / 2 of that order, so a row
 // tile whose first virtual is a needs only the column tiles from there on. Launch order
 // as in build_tile_table (groups of row tiles walked column tile by column tile).
 void build_tile_table_sym(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mt, int& n_nt) {
-  constexpr int kBuildGroup = 8;
+  constexpr int kBuildGroup = PPL_BUILD_GROUP;
   int bm, bn;
   build_tile_dims(tile, &bm, &bn);
   const int64_t pr0 = pair_plus(a0, a0, v);
   const int64_t pr1 = a1 >= v ? npairs_plus(v) : pair_plus(a1, a1, v);
-  const int64_t M = pr1 - pr0, W = v - a0, N = W * W;
+  const int64_t M = pr1 - pr0, W = v - a0, N = W * (W + 1) / 2;
   n_mt = (int)((M + bm - 1) / bm);
   n_nt = (int)((N + bn - 1) / bn);
-  auto sfx = [&](int64_t a) { return (int64_t)v * v - (int64_t)(v - a) * (v - a); };
+  auto sfx = [&](int64_t a) { return a * v - a * (a - 1) / 2; };
   std::vector<int> nt_first(n_mt);
   int a = a0;
   for (int mt = 0; mt < n_mt; ++mt) {
@@ -1597,16 +1606,12 @@ void build_tile_table_sym(int tile, int v, int a0, int a1, std::vector<int>& til
   }
 }
 
-// Operand rows b * v + d of every (b, d) ordered by m = min(b, d): for each m the pair
-// (m, m), then (m, d) for d > m, then (b, m) for b > m.
+// Operand rows b * v + d of the packed pairs b <= d, ordered by b, then d.
 void build_column_order(int v, std::vector<int>& cols) {
   cols.clear();
-  cols.reserve((size_t)v * v);
-  for (int m = 0; m < v; ++m) {
-    cols.push_back(m * v + m);
-    for (int d = m + 1; d < v; ++d) cols.push_back(m * v + d);
-    for (int b = m + 1; b < v; ++b) cols.push_back(b * v + m);
-  }
+  cols.reserve((size_t)v * (v + 1) / 2);
+  for (int b = 0; b < v; ++b)
+    for (int d = b; d < v; ++d) cols.push_back(b * v + d);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -2134,8 +2139,8 @@ static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t
   const int64_t pr0 = pair_plus(a0, a0, v);
   const int64_t pr1 = a1 >= v ? npairs_plus(v) : pair_plus(a1, a1, v);
   const int W = v - a0;
-  const int64_t M = pr1 - pr0, N = (int64_t)W * W;
-  const int* cstep = cols + ((int64_t)v * v - N);       // first column with min(b, d) = a0
+  const int64_t M = pr1 - pr0, N = (int64_t)W * (W + 1) / 2;
+  const int* cstep = cols + (npairs_plus(v) - N);       // first column with b = a0
   MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
   map.nk = Kpad / kc_of(prec, BM, BN);
   if (prec == PPL_FP64) {

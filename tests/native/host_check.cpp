@@ -2,8 +2,8 @@
 // the host code (tests/test_host_sanitizers.py builds and runs it on the CPU; no GPU is
 // used): the planner over many shapes, precisions, budgets and flags, the tune-cache parser
 // on malformed files, the batched and MLP handles, argument and state errors of the device
-// entry points (which must fail before touching a device), and the DIIS subspace solve on
-// well-posed, singular and malformed systems.
+// entry points (which must fail before touching a device), the DIIS subspace solve on
+// well-posed, singular and malformed systems, and the tile plans of the upper-triangle build.
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -17,6 +17,12 @@
 
 #include "diis_solve.h"
 #include "ppl.h"
+
+namespace ppl {   // host-side build planning of the library (not part of the C ABI)
+int build_tile_dims(int tile, int* bm, int* bn);
+void build_tile_table_sym(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mtiles, int& n_ntiles);
+void build_column_order(int v, std::vector<int>& cols);
+}  // namespace ppl
 
 static int failures = 0;
 static int checks = 0;
@@ -277,7 +283,65 @@ static void check_diis() {
   CHECK(!ppl::diis_solve(B, too_many, c));
 }
 
+// Upper-triangle build plan of one step: replaying the epilogue over every listed tile
+// (rows the packed pairs (a, c >= a) of a in [a0, a1), columns the packed pairs (b <= d)
+// from b = a0 on, products kept for b >= a, each written to G_ab[c][d] and G_ad[c][b])
+// must write every entry G_ab[c][d] with b, c, d >= a exactly once, and no tile twice.
+static void check_build_tables() {
+  const int tiles[] = {0, 1, 5, 8, 9, 10};
+  for (int v : {1, 2, 7, 40, 75})
+    for (int tile : tiles)
+      for (int nsteps : {1, 3}) {
+        std::vector<int> cols;
+        ppl::build_column_order(v, cols);
+        CHECK((int64_t)cols.size() == (int64_t)v * (v + 1) / 2);
+        int bm = 0, bn = 0;
+        CHECK(ppl::build_tile_dims(tile, &bm, &bn) == PPL_OK);
+        auto pp = [&](int64_t a, int64_t b) { return a * v - a * (a + 1) / 2 + b; };
+        for (int k = 0; k < nsteps; ++k) {
+          const int a0 = v * k / nsteps, a1 = v * (k + 1) / nsteps;
+          if (a0 == a1) continue;
+          const int W = v - a0;
+          const int64_t pr0 = pp(a0, a0), pr1 = a1 >= v ? (int64_t)v * (v + 1) / 2 : pp(a1, a1);
+          const int64_t M = pr1 - pr0, N = (int64_t)W * (W + 1) / 2;
+          std::vector<int> list;
+          int nmt = 0, nnt = 0;
+          ppl::build_tile_table_sym(tile, v, a0, a1, list, nmt, nnt);
+          CHECK(nmt == (int)((M + bm - 1) / bm) && nnt == (int)((N + bn - 1) / bn));
+          std::vector<int> rows_a(M), rows_c(M);
+          for (int a = 0, m = 0; a < v; ++a)
+            for (int c = a; c < v; ++c, ++m)
+              if (m >= pr0 && m < pr1) { rows_a[m - pr0] = a; rows_c[m - pr0] = c; }
+          std::vector<char> seen((size_t)nmt * nnt, 0);
+          std::vector<int> hits((size_t)M * W * W, 0);   // G[pair(a,b) - pr0][c - a0][d - a0]
+          bool in_range = true, once = true;
+          for (size_t q = 0; q + 1 < list.size(); q += 2) {
+            const int mt = list[q], nt = list[q + 1];
+            if (mt < 0 || mt >= nmt || nt < 0 || nt >= nnt) { in_range = false; continue; }
+            if (seen[(size_t)mt * nnt + nt]++) once = false;
+            for (int64_t m = (int64_t)mt * bm; m < std::min<int64_t>(M, (int64_t)(mt + 1) * bm); ++m)
+              for (int64_t n = (int64_t)nt * bn; n < std::min<int64_t>(N, (int64_t)(nt + 1) * bn); ++n) {
+                const int a = rows_a[m], c = rows_c[m];
+                const int bd = cols[pp(a0, a0) + n], b = bd / v, d = bd % v;
+                if (b < a) continue;
+                hits[((size_t)(pp(a, b) - pr0) * W + (c - a0)) * W + (d - a0)]++;
+                if (d != b) hits[((size_t)(pp(a, d) - pr0) * W + (c - a0)) * W + (b - a0)]++;
+              }
+          }
+          CHECK(in_range && once);
+          bool exact = true;
+          for (int a = a0; a < a1; ++a)
+            for (int b = a; b < v; ++b)
+              for (int c = a; c < v; ++c)
+                for (int d = a; d < v; ++d)
+                  if (hits[((size_t)(pp(a, b) - pr0) * W + (c - a0)) * W + (d - a0)] != 1) exact = false;
+          CHECK(exact);
+        }
+      }
+}
+
 int main() {
+  check_build_tables();
   check_planner();
   check_tune_cache();
   check_batch_and_mlp();

@@ -53,9 +53,12 @@ def test_pair_counts_and_flops(P):
         i = plan_info(P, o, v, naux, hbm_budget=1 << 40)
         assert i["p_plus"] == v * (v + 1) // 2 and i["p_minus"] == v * (v - 1) // 2
         assert i["n_plus"] == o * (o + 1) // 2 and i["n_minus"] == o * (o - 1) // 2
-        # resident plans build the upper triangle of V+-: rows (a, c >= a) times columns
-        # (b >= a, d >= a), sum_a (v - a)^3 = P+^2 entries of 2 naux flops each
-        assert i["resident"] == 1 and i["flops_build"] == 2.0 * naux * i["p_plus"] ** 2
+        # resident plans build the upper triangle of V+-: rows (a, c >= a) times the packed
+        # column pairs (b <= d) with b >= a, sum_{w=1..v} w^2 (w + 1) / 2 products of 2 naux
+        # flops each; counted here by brute force over the (row, column) pairs kept
+        kept = sum(1 for a in range(v) for c in range(a, v) for b in range(a, v) for d in range(b, v)) \
+            if v <= 33 else sum((v - a) ** 2 * (v - a + 1) // 2 for a in range(v))
+        assert i["resident"] == 1 and i["flops_build"] == 2.0 * naux * kept
         assert i["flops_contract"] == 2.0 * (i["p_plus"] ** 2 * i["n_plus"] + i["p_minus"] ** 2 * i["n_minus"])
 
 
@@ -76,7 +79,7 @@ def test_budget_forces_streaming_batches(P):
     assert i["workspace_bytes"] <= 1 << 30
     # FP64 streaming steps build the upper triangle as well (contracted as U and U^T);
     # other precisions stream full rows (2 naux v^2 flops per pair a <= b)
-    assert i["flops_build"] == 2.0 * 600 * i["p_plus"] ** 2
+    assert i["flops_build"] == 600.0 * (i["p_plus"] ** 2 + 200 * 201 * 401 // 6)
     f32 = plan_info(P, 20, 200, 600, prec="fp32", hbm_budget=1 << 30)
     assert f32["resident"] == 0 and f32["flops_build"] == 2.0 * 600 * 200 * 200 * f32["p_plus"]
 
