@@ -9,7 +9,16 @@
 #include <new>
 
 #include "diis_solve.h"
+#include "pack_cubes.h"
 #include "ppl_internal.h"
+
+// Resident upper-triangle builds write the GEMM's natural layout and pack whole V+- rows,
+// mirror entries included, in one pass (0: G blocks, packing of the upper triangle, then a
+// separate mirror pass, as streaming steps still do).
+#ifndef PPL_PACK_CUBES
+#define PPL_PACK_CUBES 1
+#endif
+constexpr bool kPackCubes = PPL_PACK_CUBES;
 
 namespace ppl {
 
@@ -308,6 +317,7 @@ static uint64_t assign_layout(ppl_plan_t p, int64_t gcap, bool resident, int64_t
   }
   p->tiles = L.take((uint64_t)p->tiles_host.size() * 4);
   p->cols = p->sym_build ? L.take((uint64_t)npairs_plus(v) * 4) : Region{};
+  p->cube_off = (p->sym_build && resident && kPackCubes) ? L.take((uint64_t)(v + 1) * 8) : Region{};
   p->r2p = p->r2m = p->ut = Region{};
   if (p->sym_build && !resident) {
     // the K range of a step starts at its first pair rounded down to 64, so it spans at
@@ -395,7 +405,7 @@ static double build_flops(ppl_plan_t p, int a0, int a1) {
 }
 
 static int mirror_vpm(ppl_plan_t p, OperandSet& s) {
-  if (!p->sym_build) return PPL_OK;
+  if (!p->sym_build || kPackCubes) return PPL_OK;   // the cube packing writes the mirror entries itself
   ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
   const int w = elem_bytes(s.prec);
   const int np = planes(s.prec);
@@ -437,6 +447,20 @@ static int build_one(ppl_plan_t p, OperandSet& s, const double* L, int bi, bool 
     if ((uint64_t)(r0p + (b.p1 - b.p0)) * p->ldp * w > s.vp.bytes ||
         (uint64_t)(r0m + (b.q1 - b.q0)) * p->ldm * w > s.vm.bytes)
       return fail(PPL_E_STATE, "build step %d exceeds the V+- rows of the plan", bi);
+  }
+  if (p->sym_build && p->resident && kPackCubes) {
+    // natural GEMM layout, then whole rows and their mirror entries in one packing pass
+    {
+      ProfScope ps(p, PPL_PROF_BUILD_GEMM, build_flops(p, b.a0, b.a1));
+      PPL_TRY(gemm_build_natural(st, s.prec, tile, p->v, b.a0, b.a1, p->ldx, at<void>(p, s.xt),
+                                 s.xt_lo.bytes ? at<void>(p, s.xt_lo) : nullptr, p->ldx, at<void>(p, p->g), dtiles,
+                                 nvalid, at<int>(p, p->tab_vp), at<int>(p, p->cols)));
+    }
+    ProfScope ps(p, PPL_PROF_BUILD_PACK, 0.0);
+    const int64_t W = p->v - b.a0;
+    return pack_vpm_cubes(st, s.prec, p->v, b.a0, b.a1, at<void>(p, p->g), W * (W + 1) / 2,
+                          at<int64_t>(p, p->cube_off), at<void>(p, s.vp), s.vp_lo.bytes ? at<void>(p, s.vp_lo) : nullptr,
+                          p->ldp, at<void>(p, s.vm), s.vm_lo.bytes ? at<void>(p, s.vm_lo) : nullptr, p->ldm);
   }
   if (p->sym_build) {
     {
@@ -963,6 +987,13 @@ int ppl_bind_workspace(ppl_plan_t p, void* dptr, uint64_t bytes) {
   if (p->sym_build)
     PPL_HIP_TRY(hipMemcpyAsync(at<int>(p, p->cols), p->cols_host.data(), p->cols_host.size() * 4,
                                hipMemcpyHostToDevice, st));
+  std::vector<int64_t> cube_off;
+  if (p->cube_off.bytes) {
+    cube_off.assign((size_t)p->v + 1, 0);
+    for (int a = 0; a < p->v; ++a) cube_off[a + 1] = cube_off[a] + cubes_of(p->v, a);
+    PPL_HIP_TRY(hipMemcpyAsync(at<int64_t>(p, p->cube_off), cube_off.data(), cube_off.size() * 8,
+                               hipMemcpyHostToDevice, st));
+  }
   PPL_HIP_TRY(hipStreamSynchronize(st));   // the host tile table must not be reused before the copy ends
   p->setup_done = true;
   return PPL_OK;

@@ -14,6 +14,7 @@
 // The Fock denominator D_ij^ab = e_i + e_j - e_a - e_b is symmetric in (a,b) and
 // (i,j), so the update t <- (V + R)/D acts on each part separately.
 #include "ppl_internal.h"
+#include "pack_cubes.h"
 
 namespace ppl {
 
@@ -335,6 +336,125 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
                        zp, zm);
   else
     return fail(PPL_E_ARG, "pack_vpm_sym: unknown precision %d", prec);
+  PPL_LAUNCH_CHECK();
+  return PPL_OK;
+}
+
+// Whole V+- rows of a resident build step from the natural build output T, with no separate
+// mirror pass: T[(pair(a, r) - pr0) * ldt + pair(x, y) - pr0] = (ar|xy) for the step's virtuals
+// a in [a0, a1), r >= a and a <= x <= y (pr0 = pair(a0, a0)); T is symmetric in (x, y) since the
+// Cholesky vectors are. For the entry of row (ab), column (cd) with (cd) >= (ab) in packed order
+//   V+[ab][cd] = ((ac|bd) + (ad|bc)) / 2,   V-[ab][cd] = ((ac|bd) - (ad|bc)) / 2  (a < b, c < d),
+// and the same value goes to the mirror entry [cd][ab], so every entry of V+- is written once
+// (pack_cubes.h). One workgroup per cube of 16 x 16 x 16 indices (b, c, d): it stages
+// (ac|bd) as s1[c][b][d] and (ad|bc) as s2[d][b][c] (each read from T along its contiguous
+// index), then writes the rows (ab) along d and the mirror rows (cd) along b. The cube with
+// ci == di == 0 also zeroes the padding columns of the rows (ab).
+template <class Tg, int PREC>
+__global__ void __launch_bounds__(256)
+pack_vpm_cubes_kernel(int v, int a0, int a1, const Tg* __restrict__ T, int64_t ldt, const int64_t* __restrict__ off,
+                      int64_t g0, int64_t ncubes, void* vp, void* vp_lo, int64_t ldp, void* vm, void* vm_lo,
+                      int64_t ldm, int64_t Pp, int64_t Pm) {
+  constexpr int C = kCube, CP = kCube + 1;
+  __shared__ Tg s1[C][CP][CP], s2[C][CP][CP];
+  const int64_t g = g0 + cube_of_slot(blockIdx.x, ncubes);
+  const int a = cube_virtual(off, a0, a1, g);
+  const int nt = cube_blocks(v, a);
+  int bi, ci, di;
+  cube_decode(g - off[a], nt, bi, ci, di);
+  const int b0 = a + C * bi, c0 = a + C * ci, d0 = a + C * di;
+  const int64_t pr0 = pair_plus(a0, a0, v);
+  const int tid = threadIdx.x;
+  // s[rl][bl][yl] = (a r | b y) for r = r0 + rl, b = b0 + bl, y = y0 + yl (zero outside v);
+  // element e = tid + 256 k of the cube, read along its contiguous index. All reads of a
+  // thread are issued before its first LDS store, so their latencies overlap.
+  constexpr int K = C * C * C / 256;
+  auto slot = [&](int k, bool bfast, int& rl, int& bl, int& yl) __attribute__((always_inline)) {
+    const int e = tid + 256 * k, m = (e >> 4) & 15, f = e & 15;
+    rl = e >> 8;
+    bl = bfast ? f : m;
+    yl = bfast ? m : f;
+  };
+  auto fetch = [&](Tg (&x)[K], int r0, int y0) __attribute__((always_inline)) {
+    const bool bfast = b0 > y0;              // pairs (y, b): contiguous along b
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      int rl, bl, yl;
+      slot(k, bfast, rl, bl, yl);
+      const int r = r0 + rl, b = b0 + bl, y = y0 + yl;
+      const int lo = b < y ? b : y, hi = b < y ? y : b;
+      x[k] = (r < v && b < v && y < v) ? T[(pair_plus(a, r, v) - pr0) * ldt + (pair_plus(lo, hi, v) - pr0)] : Tg(0);
+    }
+  };
+  auto keep = [&](Tg (*s)[CP][CP], const Tg (&x)[K], int y0) __attribute__((always_inline)) {
+    const bool bfast = b0 > y0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      int rl, bl, yl;
+      slot(k, bfast, rl, bl, yl);
+      s[rl][bl][yl] = x[k];
+    }
+  };
+  Tg x1[K], x2[K];
+  fetch(x1, c0, d0);
+  if (ci != di) fetch(x2, d0, c0);
+  keep(s1, x1, d0);
+  if (ci != di) keep(s2, x2, c0);
+  __syncthreads();
+  const Tg (*t2)[CP][CP] = ci != di ? s2 : s1;   // (ad|bc) = t2[d][b][c]
+  // rows (ab), along d
+  for (int e = tid; e < C * C * C; e += 256) {
+    const int bl = e >> 8, cl = (e >> 4) & 15, dl = e & 15;
+    const int b = b0 + bl, c = c0 + cl, d = d0 + dl;
+    if (b >= v || d >= v || c > d || (c == a && d < b)) continue;
+    const double gcd = (double)s1[cl][bl][dl], gdc = (double)t2[dl][bl][cl];
+    Store<PREC>::put(vp, vp_lo, pair_plus(a, b, v) * ldp + pair_plus(c, d, v), 0.5 * (gcd + gdc));
+    if (a < b && c < d) Store<PREC>::put(vm, vm_lo, pair_minus(a, b, v) * ldm + pair_minus(c, d, v), 0.5 * (gcd - gdc));
+  }
+  // mirror rows (cd), along b
+  for (int e = tid; e < C * C * C; e += 256) {
+    const int cl = e >> 8, dl = (e >> 4) & 15, bl = e & 15;
+    const int b = b0 + bl, c = c0 + cl, d = d0 + dl;
+    if (b >= v || d >= v || c > d || (c == a && d <= b)) continue;
+    const double gcd = (double)s1[cl][bl][dl], gdc = (double)t2[dl][bl][cl];
+    Store<PREC>::put(vp, vp_lo, pair_plus(c, d, v) * ldp + pair_plus(a, b, v), 0.5 * (gcd + gdc));
+    if (a < b && c < d) Store<PREC>::put(vm, vm_lo, pair_minus(c, d, v) * ldm + pair_minus(a, b, v), 0.5 * (gcd - gdc));
+  }
+  if (ci == 0 && di == 0) {
+    const int64_t padp = ldp - Pp, padm = ldm - Pm;
+    for (int e = tid; e < C * padp; e += 256) {
+      const int b = b0 + (int)(e / padp);
+      if (b < v) Store<PREC>::put(vp, vp_lo, pair_plus(a, b, v) * ldp + Pp + e % padp, 0.0);
+    }
+    for (int e = tid; e < C * padm; e += 256) {
+      const int b = b0 + (int)(e / padm);
+      if (b < v && a < b) Store<PREC>::put(vm, vm_lo, pair_minus(a, b, v) * ldm + Pm + e % padm, 0.0);
+    }
+  }
+}
+
+int pack_vpm_cubes(hipStream_t s, int prec, int v, int a0, int a1, const void* T, int64_t ldt, const int64_t* off,
+                   void* vp, void* vp_lo, int64_t ldp, void* vm, void* vm_lo, int64_t ldm) {
+  int64_t g0 = 0, n = 0;
+  for (int a = 0; a < a1; ++a) (a < a0 ? g0 : n) += cubes_of(v, a);
+  if (n <= 0) return PPL_OK;
+  if (n > 0x7fffffffLL) return fail(PPL_E_ARG, "pack_vpm_cubes: %lld cubes", (long long)n);
+  const int64_t Pp = npairs_plus(v), Pm = npairs_minus(v);
+  const dim3 grid((unsigned)n);
+  if (prec == PPL_FP64)
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<double, PPL_FP64>), grid, dim3(256), 0, s, v, a0, a1, (const double*)T,
+                       ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else if (prec == PPL_FP32)
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_FP32>), grid, dim3(256), 0, s, v, a0, a1, (const float*)T,
+                       ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else if (prec == PPL_BF16X3)
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, a0, a1,
+                       (const float*)T, ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else if (prec == PPL_BF16X6)
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_BF16X6>), grid, dim3(256), 0, s, v, a0, a1,
+                       (const float*)T, ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
+  else
+    return fail(PPL_E_ARG, "pack_vpm_cubes: unknown precision %d", prec);
   PPL_LAUNCH_CHECK();
   return PPL_OK;
 }

@@ -238,6 +238,32 @@ struct EpiBuildSym {
   }
 };
 
+// Upper-triangle build of a resident plan in the GEMM's natural layout: rows and columns
+// as in EpiBuildSym, T[m * ldt + n] = (ac|bd) for row m = pair(a, c) - pr0 and column
+// n = pair(b, d) - pr0 (b <= d; computed for b >= a of the row tile's first virtual). The
+// packing (pack_vpm_cubes) reads both (ac|bd) and (ad|bc) from it.
+template <class Tg>
+struct EpiBuildT {
+  Tg* T;
+  int64_t M, N, ldt;
+  int v;
+  int64_t pr0;
+  const int* tab;        // packed pair -> (first << 16) | second
+  const int* cols;       // column n -> operand row b * v + d
+  __device__ int64_t arow(int64_t m) const {
+    const int ac = tab[pr0 + m];
+    return (int64_t)pair_first(ac) * v + pair_second(ac);
+  }
+  __device__ int64_t brow(int64_t n) const { return cols[n]; }
+  __device__ void row(int, int64_t m, int64_t& base, bool& ok) const {
+    ok = m < M;
+    base = m * ldt;
+  }
+  __device__ void put(int64_t base, bool ok, int64_t n, Tg x) const {
+    if (ok && n < N) T[base + n] = x;
+  }
+};
+
 // ------------------------------------------------------------------ the kernel (FP64 / FP32)
 // LDS layout of a staged K chunk (BM or BN rows of KC elements, moved as 16-byte vectors):
 //   0: each row padded by 16 bytes;
@@ -2145,7 +2171,15 @@ static int build_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpa
   return fail(PPL_E_ARG, "unknown precision %d", prec);
 }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+// epilogue of the upper-triangle build: G blocks (EpiBuildSym) or the natural layout (EpiBuildT)
+template <class Tg, bool NAT>
+static auto build_sym_epi(void* G, int64_t M, int64_t N, int v, int a0, int W, int64_t pr0, const int* tab_vp,
+                          const int* cstep) {
+  if constexpr (NAT) return EpiBuildT<Tg>{(Tg*)G, M, N, N, v, pr0, tab_vp, cstep};
+  else return EpiBuildSym<Tg>{(Tg*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, bool NAT>
 static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t Kpad, const void* Xt,
                          const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles,
                          const int* tab_vp, const int* cols) {
@@ -2158,23 +2192,23 @@ static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t
   MapBuild map{tile_list, n_valid_tiles, BM, BN, 0};
   map.nk = Kpad / kc_of(prec, BM, BN);
   if (prec == PPL_FP64) {
-    EpiBuildSym<double> epi{(double*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    auto epi = build_sym_epi<double, NAT>(G, M, N, v, a0, W, pr0, tab_vp, cstep);
     return launch<double, WM, WN, WAVES_M, WAVES_N, kKcF64>(s, n_valid_tiles, M, N, Kpad, (const double*)Xt, ldx,
                                                             (const double*)Xt, ldx, epi, map);
   }
   if (prec == PPL_FP32) {
-    EpiBuildSym<float> epi{(float*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    auto epi = build_sym_epi<float, NAT>(G, M, N, v, a0, W, pr0, tab_vp, cstep);
     return launch<float, WM, WN, WAVES_M, WAVES_N, kKcF32>(s, n_valid_tiles, M, N, Kpad, (const float*)Xt, ldx,
                                                            (const float*)Xt, ldx, epi, map);
   }
   if (prec == PPL_BF16X3) {
-    EpiBuildSym<float> epi{(float*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    auto epi = build_sym_epi<float, NAT>(G, M, N, v, a0, W, pr0, tab_vp, cstep);
     return launch_bf3<WM, WN, WAVES_M, WAVES_N, bf3_kc(BM, BN)>(s, n_valid_tiles, M, N, Kpad, (const __bf16*)Xt,
                                                                 (const __bf16*)Xt_lo, ldx, (const __bf16*)Xt,
                                                                 (const __bf16*)Xt_lo, ldx, epi, map);
   }
   if (prec == PPL_BF16X6) {
-    EpiBuildSym<float> epi{(float*)G, M, N, v, a0, W, pr0, tab_vp, cstep};
+    auto epi = build_sym_epi<float, NAT>(G, M, N, v, a0, W, pr0, tab_vp, cstep);
     return launch_bf6<WM, WN, WAVES_M, WAVES_N>(s, n_valid_tiles, M, N, Kpad, (const __bf16*)Xt,
                                                 (const __bf16*)Xt_lo, ldx, (const __bf16*)Xt, (const __bf16*)Xt_lo,
                                                 ldx, epi, map);
@@ -2182,18 +2216,33 @@ static int build_sym_cfg(hipStream_t s, int prec, int v, int a0, int a1, int64_t
   return fail(PPL_E_ARG, "unknown precision %d", prec);
 }
 
+template <bool NAT>
+static int build_sym_tile(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                          const void* Xt_lo, int64_t ldx, void* G, const int* tl, int64_t nv, const int* tab_vp,
+                          const int* cols) {
+  switch (tile) {
+    case 0: return build_sym_cfg<7, 2, 1, 4, NAT>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tl, nv, tab_vp, cols);
+    case 1: return build_sym_cfg<4, 4, 2, 2, NAT>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tl, nv, tab_vp, cols);
+    case 5: return build_sym_cfg<6, 2, 1, 4, NAT>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tl, nv, tab_vp, cols);
+    case 8: return build_sym_cfg<4, 2, 1, 4, NAT>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tl, nv, tab_vp, cols);
+    case 9: return build_sym_cfg<7, 2, 2, 4, NAT>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tl, nv, tab_vp, cols);
+    case 10: return build_sym_cfg<7, 1, 2, 4, NAT>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tl, nv, tab_vp, cols);
+    default: return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
+  }
+}
+
 int gemm_build_sym(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
                    const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles,
                    const int* tab_vp, const int* cols) {
-  switch (tile) {
-    case 0: return build_sym_cfg<7, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
-    case 1: return build_sym_cfg<4, 4, 2, 2>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
-    case 5: return build_sym_cfg<6, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
-    case 8: return build_sym_cfg<4, 2, 1, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
-    case 9: return build_sym_cfg<7, 2, 2, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
-    case 10: return build_sym_cfg<7, 1, 2, 4>(s, prec, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp, cols);
-    default: return fail(PPL_E_ARG, "tile %d is not a build tile", tile);
-  }
+  return build_sym_tile<false>(s, prec, tile, v, a0, a1, Kpad, Xt, Xt_lo, ldx, G, tile_list, n_valid_tiles, tab_vp,
+                               cols);
+}
+
+int gemm_build_natural(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                       const void* Xt_lo, int64_t ldx, void* T, const int* tile_list, int64_t n_valid_tiles,
+                       const int* tab_vp, const int* cols) {
+  return build_sym_tile<true>(s, prec, tile, v, a0, a1, Kpad, Xt, Xt_lo, ldx, T, tile_list, n_valid_tiles, tab_vp,
+                              cols);
 }
 
 int gemm_build(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad,

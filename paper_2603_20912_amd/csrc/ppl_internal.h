@@ -143,7 +143,8 @@ struct ppl_plan_s {
   int64_t ldk = 0;                     // row length of a transposed row block (its K range)
   ppl::Region r2p, r2m;                // streaming U^T term, transposed: [P+][ldq], [P-][ldqm] (FP64)
   ppl::Region ut;                      // one transposed row block of U+ or U-: [P+][ldk] (FP64)
-  ppl::Region cols;                    // operand rows of the upper-triangle build's columns (int32, v^2)
+  ppl::Region cols;                    // operand rows of the upper-triangle build's columns (int32, v(v+1)/2)
+  ppl::Region cube_off;                // resident upper-triangle builds: cubes below each virtual (int64, v + 1)
   std::vector<int> cols_host;
   std::vector<int> tiles_host;         // host copy of the tile tables (kept alive for the async copy)
   std::vector<int64_t> tiles_off;      // element offset of each batch's list in `tiles`, [set][batch]
@@ -247,6 +248,11 @@ int build_tile_dims(int tile, int* bm, int* bn);
 int gemm_build_sym(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
                    const void* Xt_lo, int64_t ldx, void* G, const int* tile_list, int64_t n_valid_tiles,
                    const int* tab_vp, const int* cols);
+// The same build in the GEMM's natural layout (resident plans): T[pair(a,c) - pr0][pair(b,d) - pr0]
+// = (ac|bd), row length (v - a0)(v - a0 + 1) / 2, pr0 = pair(a0, a0), for b <= d and b >= a.
+int gemm_build_natural(hipStream_t s, int prec, int tile, int v, int a0, int a1, int64_t Kpad, const void* Xt,
+                       const void* Xt_lo, int64_t ldx, void* T, const int* tile_list, int64_t n_valid_tiles,
+                       const int* tab_vp, const int* cols);
 void build_tile_table_sym(int tile, int v, int a0, int a1, std::vector<int>& tiles, int& n_mtiles,
                           int& n_ntiles);
 void build_column_order(int v, std::vector<int>& cols);
@@ -270,6 +276,10 @@ int pack_vpm(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void
 int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, void* vp, void* vp_lo,
                  int64_t ldp, void* vm, void* vm_lo, int64_t ldm, const int* tab_vp, int64_t vp_row0 = 0,
                  int64_t vm_row0 = 0, int half_diag = 0, int64_t zp = 0, int64_t zm = 0);
+// whole V+- rows (and their mirror entries) of a resident build step from gemm_build_natural's
+// T (row length ldt); off[a] = cubes of the virtuals below a (pack_cubes.h), v + 1 entries
+int pack_vpm_cubes(hipStream_t s, int prec, int v, int a0, int a1, const void* T, int64_t ldt, const int64_t* off,
+                   void* vp, void* vp_lo, int64_t ldp, void* vm, void* vm_lo, int64_t ldm);
 // C[q][p] += T[p][q] for q < nq, p < np (T FP64; C FP64 or FP32 by c_prec)
 int add_transposed(hipStream_t s, int c_prec, void* C, int64_t ldc, const double* T, int64_t ldt, int64_t nq,
                    int64_t np);

@@ -3,7 +3,8 @@
 // used): the planner over many shapes, precisions, budgets and flags, the tune-cache parser
 // on malformed files, the batched and MLP handles, argument and state errors of the device
 // entry points (which must fail before touching a device), the DIIS subspace solve on
-// well-posed, singular and malformed systems, and the tile plans of the upper-triangle build.
+// well-posed, singular and malformed systems, and the tile plans and cube packing of the
+// upper-triangle build.
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -16,6 +17,7 @@
 #include <vector>
 
 #include "diis_solve.h"
+#include "pack_cubes.h"
 #include "ppl.h"
 
 namespace ppl {   // host-side build planning of the library (not part of the C ABI)
@@ -340,7 +342,112 @@ static void check_build_tables() {
       }
 }
 
+// Cube packing of resident builds (pack_vpm_cubes_kernel): replaying its cube decode, its
+// staging reads of T and the conditions of its two write passes over all steps of a
+// partition must read only computed entries of T (row (a, r) of the step, column pair
+// (x <= y) with x >= a), hand every cube to exactly one workgroup, write every entry of
+// V+ and V- exactly once from the two integrals of its definition ((ac|bd) and (ad|bc) for
+// the entry of pairs (ab), (cd), either order), and zero the padding of every row once.
+static void check_pack_cubes() {
+  for (int v : {1, 2, 5, 16, 17, 40, 75})
+    for (int nsteps : {1, 3}) {
+      const int C = ppl::kCube;
+      auto pp = [&](int64_t a, int64_t b) { return a * v - a * (a + 1) / 2 + b; };
+      auto pm = [&](int64_t a, int64_t b) { return a * (v - 1) - a * (a + 1) / 2 + b - 1; };
+      const int64_t Pp = (int64_t)v * (v + 1) / 2, Pm = (int64_t)v * (v - 1) / 2;
+      std::vector<int> pfirst(Pp), psecond(Pp);
+      for (int x = 0; x < v; ++x)
+        for (int y = x; y < v; ++y) { pfirst[pp(x, y)] = x; psecond[pp(x, y)] = y; }
+      // the integral (pq|rs) up to its symmetries, as one number
+      auto key = [&](int64_t p, int64_t q, int64_t r, int64_t t) {
+        int64_t u = std::min(p, q) * v + std::max(p, q), w = std::min(r, t) * v + std::max(r, t);
+        return std::min(u, w) * v * v + std::max(u, w);
+      };
+      std::vector<int64_t> off(v + 1, 0);
+      for (int a = 0; a < v; ++a) off[a + 1] = off[a] + ppl::cubes_of(v, a);
+      std::vector<int> hp((size_t)(Pp * Pp), 0), hm((size_t)(Pm * Pm), 0), padp(Pp, 0), padm(Pm, 0);
+      bool reads_ok = true, values_ok = true, cubes_ok = true;
+      for (int k = 0; k < nsteps; ++k) {
+        const int a0 = v * k / nsteps, a1 = v * (k + 1) / nsteps;
+        if (a0 == a1) continue;
+        const int64_t pr0 = pp(a0, a0), W = v - a0, ldt = W * (W + 1) / 2;
+        const int64_t M = (a1 >= v ? Pp : pp(a1, a1)) - pr0;
+        int64_t g0 = 0, n = 0;
+        for (int a = 0; a < a1; ++a) (a < a0 ? g0 : n) += ppl::cubes_of(v, a);
+        CHECK(g0 == off[a0] && n == off[a1] - off[a0]);
+        std::vector<int> seen((size_t)n, 0);
+        std::vector<int64_t> s1((size_t)C * C * C), s2((size_t)C * C * C);
+        for (int64_t bid = 0; bid < n; ++bid) {
+          const int64_t g = g0 + ppl::cube_of_slot(bid, n);
+          if (g < g0 || g >= g0 + n) { cubes_ok = false; continue; }
+          seen[(size_t)(g - g0)]++;
+          const int a = ppl::cube_virtual(off.data(), a0, a1, g);
+          if (a < a0 || a >= a1 || g < off[a] || g >= off[a + 1]) { cubes_ok = false; continue; }
+          const int nt = ppl::cube_blocks(v, a);
+          int bi = -1, ci = -1, di = -1;
+          ppl::cube_decode(g - off[a], nt, bi, ci, di);
+          if (bi < 0 || bi >= nt || ci < 0 || ci > di || di >= nt) { cubes_ok = false; continue; }
+          const int b0 = a + C * bi, c0 = a + C * ci, d0 = a + C * di;
+          // staging as the kernel addresses T; each slot keeps the integral that address holds
+          auto load = [&](std::vector<int64_t>& st, int r0, int y0) {
+            for (int rl = 0; rl < C; ++rl)
+              for (int bl = 0; bl < C; ++bl)
+                for (int yl = 0; yl < C; ++yl) {
+                  const int r = r0 + rl, b = b0 + bl, y = y0 + yl;
+                  int64_t kx = -1;
+                  if (r < v && b < v && y < v) {
+                    const int lo = b < y ? b : y, hi = b < y ? y : b;
+                    const int64_t m = pp(a, r) - pr0, col = pp(lo, hi) - pr0;
+                    if (m < 0 || m >= M || col < 0 || col >= ldt) { reads_ok = false; continue; }
+                    const int ra = pfirst[m + pr0], rr = psecond[m + pr0];
+                    const int x = pfirst[col + pr0], x2 = psecond[col + pr0];
+                    if (ra < a0 || ra >= a1 || x < ra) reads_ok = false;   // not computed by the build
+                    kx = key(ra, rr, x, x2);
+                  }
+                  st[((size_t)rl * C + bl) * C + yl] = kx;
+                }
+          };
+          load(s1, c0, d0);
+          if (ci != di) load(s2, d0, c0);
+          const std::vector<int64_t>& t2 = ci != di ? s2 : s1;
+          for (int bl = 0; bl < C; ++bl)
+            for (int cl = 0; cl < C; ++cl)
+              for (int dl = 0; dl < C; ++dl) {
+                const int b = b0 + bl, c = c0 + cl, d = d0 + dl;
+                if (b >= v || d >= v || c > d) continue;
+                const int64_t gcd = s1[((size_t)cl * C + bl) * C + dl], gdc = t2[((size_t)dl * C + bl) * C + cl];
+                if (gcd != key(a, c, b, d) || gdc != key(a, d, b, c)) values_ok = false;
+                if (!(c == a && d < b)) {                         // row (ab), column (cd) >= (ab)
+                  hp[(size_t)(pp(a, b) * Pp + pp(c, d))]++;
+                  if (a < b && c < d) hm[(size_t)(pm(a, b) * Pm + pm(c, d))]++;
+                }
+                if (!(c == a && d <= b)) {                        // the mirror entry
+                  hp[(size_t)(pp(c, d) * Pp + pp(a, b))]++;
+                  if (a < b && c < d) hm[(size_t)(pm(c, d) * Pm + pm(a, b))]++;
+                }
+              }
+          if (ci == 0 && di == 0)
+            for (int bl = 0; bl < C; ++bl) {
+              const int b = b0 + bl;
+              if (b >= v) continue;
+              padp[pp(a, b)]++;
+              if (a < b) padm[pm(a, b)]++;
+            }
+        }
+        for (int x : seen) cubes_ok = cubes_ok && x == 1;
+      }
+      CHECK(cubes_ok && reads_ok && values_ok);
+      bool once = true;
+      for (int x : hp) once = once && x == 1;
+      for (int x : hm) once = once && x == 1;
+      for (int x : padp) once = once && x == 1;
+      for (int x : padm) once = once && x == 1;
+      CHECK(once);
+    }
+}
+
 int main() {
+  check_pack_cubes();
   check_build_tables();
   check_planner();
   check_tune_cache();
