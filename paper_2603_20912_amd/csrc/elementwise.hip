@@ -340,6 +340,13 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
   return PPL_OK;
 }
 
+// threads of one cube-packing workgroup (divides the 4096 elements of a cube)
+#ifndef PPL_PACK_THREADS
+#define PPL_PACK_THREADS 256
+#endif
+constexpr int kPackThreads = PPL_PACK_THREADS;
+static_assert(kCube * kCube * kCube % PPL_PACK_THREADS == 0, "threads must divide a cube");
+
 // Whole V+- rows of a resident build step from the natural build output T, with no separate
 // mirror pass: T[(pair(a, r) - pr0) * ldt + pair(x, y) - pr0] = (ar|xy) for the step's virtuals
 // a in [a0, a1), r >= a and a <= x <= y (pr0 = pair(a0, a0)); T is symmetric in (x, y) since the
@@ -351,7 +358,7 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
 // index), then writes the rows (ab) along d and the mirror rows (cd) along b. The cube with
 // ci == di == 0 also zeroes the padding columns of the rows (ab).
 template <class Tg, int PREC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kPackThreads)
 pack_vpm_cubes_kernel(int v, int a0, int a1, const Tg* __restrict__ T, int64_t ldt, const int64_t* __restrict__ off,
                       int64_t g0, int64_t ncubes, void* vp, void* vp_lo, int64_t ldp, void* vm, void* vm_lo,
                       int64_t ldm, int64_t Pp, int64_t Pm) {
@@ -366,11 +373,11 @@ pack_vpm_cubes_kernel(int v, int a0, int a1, const Tg* __restrict__ T, int64_t l
   const int64_t pr0 = pair_plus(a0, a0, v);
   const int tid = threadIdx.x;
   // s[rl][bl][yl] = (a r | b y) for r = r0 + rl, b = b0 + bl, y = y0 + yl (zero outside v);
-  // element e = tid + 256 k of the cube, read along its contiguous index. All reads of a
+  // element e = tid + kPackThreads k of the cube, read along its contiguous index. All reads of a
   // thread are issued before its first LDS store, so their latencies overlap.
-  constexpr int K = C * C * C / 256;
+  constexpr int K = C * C * C / kPackThreads;
   auto slot = [&](int k, bool bfast, int& rl, int& bl, int& yl) __attribute__((always_inline)) {
-    const int e = tid + 256 * k, m = (e >> 4) & 15, f = e & 15;
+    const int e = tid + kPackThreads * k, m = (e >> 4) & 15, f = e & 15;
     rl = e >> 8;
     bl = bfast ? f : m;
     yl = bfast ? m : f;
@@ -403,7 +410,7 @@ pack_vpm_cubes_kernel(int v, int a0, int a1, const Tg* __restrict__ T, int64_t l
   __syncthreads();
   const Tg (*t2)[CP][CP] = ci != di ? s2 : s1;   // (ad|bc) = t2[d][b][c]
   // rows (ab), along d
-  for (int e = tid; e < C * C * C; e += 256) {
+  for (int e = tid; e < C * C * C; e += kPackThreads) {
     const int bl = e >> 8, cl = (e >> 4) & 15, dl = e & 15;
     const int b = b0 + bl, c = c0 + cl, d = d0 + dl;
     if (b >= v || d >= v || c > d || (c == a && d < b)) continue;
@@ -412,7 +419,7 @@ pack_vpm_cubes_kernel(int v, int a0, int a1, const Tg* __restrict__ T, int64_t l
     if (a < b && c < d) Store<PREC>::put(vm, vm_lo, pair_minus(a, b, v) * ldm + pair_minus(c, d, v), 0.5 * (gcd - gdc));
   }
   // mirror rows (cd), along b
-  for (int e = tid; e < C * C * C; e += 256) {
+  for (int e = tid; e < C * C * C; e += kPackThreads) {
     const int cl = e >> 8, dl = (e >> 4) & 15, bl = e & 15;
     const int b = b0 + bl, c = c0 + cl, d = d0 + dl;
     if (b >= v || d >= v || c > d || (c == a && d <= b)) continue;
@@ -422,11 +429,11 @@ pack_vpm_cubes_kernel(int v, int a0, int a1, const Tg* __restrict__ T, int64_t l
   }
   if (ci == 0 && di == 0) {
     const int64_t padp = ldp - Pp, padm = ldm - Pm;
-    for (int e = tid; e < C * padp; e += 256) {
+    for (int e = tid; e < C * padp; e += kPackThreads) {
       const int b = b0 + (int)(e / padp);
       if (b < v) Store<PREC>::put(vp, vp_lo, pair_plus(a, b, v) * ldp + Pp + e % padp, 0.0);
     }
-    for (int e = tid; e < C * padm; e += 256) {
+    for (int e = tid; e < C * padm; e += kPackThreads) {
       const int b = b0 + (int)(e / padm);
       if (b < v && a < b) Store<PREC>::put(vm, vm_lo, pair_minus(a, b, v) * ldm + Pm + e % padm, 0.0);
     }
@@ -442,16 +449,16 @@ int pack_vpm_cubes(hipStream_t s, int prec, int v, int a0, int a1, const void* T
   const int64_t Pp = npairs_plus(v), Pm = npairs_minus(v);
   const dim3 grid((unsigned)n);
   if (prec == PPL_FP64)
-    hipLaunchKernelGGL((pack_vpm_cubes_kernel<double, PPL_FP64>), grid, dim3(256), 0, s, v, a0, a1, (const double*)T,
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<double, PPL_FP64>), grid, dim3(kPackThreads), 0, s, v, a0, a1, (const double*)T,
                        ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
   else if (prec == PPL_FP32)
-    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_FP32>), grid, dim3(256), 0, s, v, a0, a1, (const float*)T,
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_FP32>), grid, dim3(kPackThreads), 0, s, v, a0, a1, (const float*)T,
                        ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
   else if (prec == PPL_BF16X3)
-    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_BF16X3>), grid, dim3(256), 0, s, v, a0, a1,
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_BF16X3>), grid, dim3(kPackThreads), 0, s, v, a0, a1,
                        (const float*)T, ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
   else if (prec == PPL_BF16X6)
-    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_BF16X6>), grid, dim3(256), 0, s, v, a0, a1,
+    hipLaunchKernelGGL((pack_vpm_cubes_kernel<float, PPL_BF16X6>), grid, dim3(kPackThreads), 0, s, v, a0, a1,
                        (const float*)T, ldt, off, g0, n, vp, vp_lo, ldp, vm, vm_lo, ldm, Pp, Pm);
   else
     return fail(PPL_E_ARG, "pack_vpm_cubes: unknown precision %d", prec);
