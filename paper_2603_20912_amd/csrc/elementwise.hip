@@ -907,6 +907,18 @@ struct PairGeom {
   const int *tab_op, *tab_om, *tab_vp, *tab_vm;
 };
 
+// q = x / d, p = x - q d for x >= 0, d > 0; in 32 bits when the caller knows x < 2^31
+// (the quotient is the same, the instruction sequence much shorter)
+__device__ inline void row_col(int64_t x, int64_t d, bool narrow, int64_t& q, int64_t& p) {
+  if (narrow) {
+    const uint32_t q32 = (uint32_t)x / (uint32_t)d;
+    q = q32;
+  } else {
+    q = x / d;
+  }
+  p = x - q * d;
+}
+
 // Denominator of a packed element
 __device__ inline double denom(const double* e_occ, const double* e_vir, int ij, int ab) {
   return e_occ[pair_first(ij)] + e_occ[pair_second(ij)] - e_vir[pair_first(ab)] - e_vir[pair_second(ab)];
@@ -928,9 +940,11 @@ sweep_kernel(PairGeom g, const double* __restrict__ e_occ, const double* __restr
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   // "+" part: weights (2 - d_ij)(2 - d_ab) turn packed sums into full-tensor sums
-  const int64_t totp = g.Np * g.ldp;
+  const int64_t totp = g.Np * g.ldp, totm = g.Nm * g.ldm;
+  const bool narrow = totp < 0x7fffffffLL && totm < 0x7fffffffLL;
   for (int64_t x = tid0; x < totp; x += st) {
-    const int64_t q = x / g.ldp, p = x - q * g.ldp;
+    int64_t q, p;
+    row_col(x, g.ldp, narrow, q, p);
     if (p >= g.Pp) continue;
     const int ij = g.tab_op[q], ab = g.tab_vp[p];
     const bool dij = pair_first(ij) == pair_second(ij), dab = pair_first(ab) == pair_second(ab);
@@ -958,9 +972,9 @@ sweep_kernel(PairGeom g, const double* __restrict__ e_occ, const double* __restr
     en += w * vsx * snew;
   }
   // "-" part: every packed (i<j, a<b) entry stands for 4 full-tensor entries
-  const int64_t totm = g.Nm * g.ldm;
   for (int64_t x = tid0; x < totm; x += st) {
-    const int64_t q = x / g.ldm, p = x - q * g.ldm;
+    int64_t q, p;
+    row_col(x, g.ldm, narrow, q, p);
     if (p >= g.Pm) continue;
     const int ij = g.tab_om[q], ab = g.tab_vm[p];
     const double vax = va[x];
@@ -1054,9 +1068,11 @@ diis_dots_kernel(PairGeom g, const double* __restrict__ E, int64_t slot_n, DiisS
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const double* en = E + knew * slot_n;
-  const int64_t totp = g.Np * g.ldp;
+  const int64_t totp = g.Np * g.ldp, totm = g.Nm * g.ldm;
+  const bool narrow = totp < 0x7fffffffLL && totm < 0x7fffffffLL;
   for (int64_t x = tid0; x < totp; x += st) {
-    const int64_t q = x / g.ldp, p = x - q * g.ldp;
+    int64_t q, p;
+    row_col(x, g.ldp, narrow, q, p);
     if (p >= g.Pp) continue;
     const int ij = g.tab_op[q], ab = g.tab_vp[p];
     const double w = (pair_first(ij) == pair_second(ij) ? 1.0 : 2.0) /
@@ -1066,9 +1082,9 @@ diis_dots_kernel(PairGeom g, const double* __restrict__ E, int64_t slot_n, DiisS
     for (int i = 0; i < kDiisMax; ++i)
       if (i < set.n) acc[i] += a * E[set.id[i] * slot_n + x];
   }
-  const int64_t totm = g.Nm * g.ldm;
   for (int64_t x = tid0; x < totm; x += st) {
-    const int64_t p = x % g.ldm;
+    int64_t q, p;
+    row_col(x, g.ldm, narrow, q, p);
     if (p >= g.Pm) continue;
     const double a = en[totp + x];
 #pragma unroll
@@ -1124,17 +1140,19 @@ __global__ void diis_combine_kernel(PairGeom g, const double* __restrict__ T, in
                                     double* sp, double* am) {
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t totp = g.Np * g.ldp;
+  const int64_t totp = g.Np * g.ldp, totm = g.Nm * g.ldm;
+  const bool narrow = totp < 0x7fffffffLL && totm < 0x7fffffffLL;
   for (int64_t x = tid0; x < totp; x += st) {
-    const int64_t p = x % g.ldp;
+    int64_t q, p;
+    row_col(x, g.ldp, narrow, q, p);
     double y = 0.0;
     if (p < g.Pp)
       for (int i = 0; i < set.n; ++i) y += set.c[i] * T[set.id[i] * slot_n + x];
     sp[x] = y;
   }
-  const int64_t totm = g.Nm * g.ldm;
   for (int64_t x = tid0; x < totm; x += st) {
-    const int64_t p = x % g.ldm;
+    int64_t q, p;
+    row_col(x, g.ldm, narrow, q, p);
     double y = 0.0;
     if (p < g.Pm)
       for (int i = 0; i < set.n; ++i) y += set.c[i] * T[set.id[i] * slot_n + totp + x];
