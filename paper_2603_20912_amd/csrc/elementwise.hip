@@ -346,6 +346,7 @@ int pack_vpm_sym(hipStream_t s, int prec, int v, int a0, int a1, const void* G, 
 #endif
 constexpr int kPackThreads = PPL_PACK_THREADS;
 static_assert(kCube * kCube * kCube % PPL_PACK_THREADS == 0, "threads must divide a cube");
+static_assert(kCube == 16, "the cube packing splits an element index into 4-bit fields");
 
 // Whole V+- rows of a resident build step from the natural build output T, with no separate
 // mirror pass: T[(pair(a, r) - pr0) * ldt + pair(x, y) - pr0] = (ar|xy) for the step's virtuals
