@@ -109,8 +109,9 @@ typedef struct {
   int32_t  splits_contract_minus; /* split-K slices of the R- contraction GEMM (0 = stream-K) */
   uint64_t build_scratch_bytes;   /* bytes of the integral-build scratch */
   int64_t  max_step_pairs;        /* largest number of (a<=b) pairs one build step holds */
-  double   flops_build;       /* useful flops of one integral build: 2 naux P+^2 (resident, upper triangle)
-                                 or 2 naux v^2 P+ (streaming, full rows) */
+  double   flops_build;       /* useful flops of one integral build: naux (P+^2 + v(v+1)(2v+1)/6)
+                                 (upper triangle over packed column pairs: resident and FP64
+                                 streaming plans) or 2 naux v^2 P+ (other streaming plans, full rows) */
   double   flops_contract;    /* useful flops of one contraction: 2 (P+^2 N+ + P-^2 N-) */
 } ppl_plan_info_t;
 
@@ -144,7 +145,8 @@ int ppl_bind_workspace(ppl_plan_t plan, void* dptr, uint64_t bytes);
  * ppl_build_batch: form V+- rows from the Cholesky vectors (eq. (cholesky)).
  * Every L^P must be symmetric (real orbitals, as the paper assumes), which makes
  * V+ and V- symmetric matrices: a resident plan builds their upper triangle
- * (rows (a, c >= a) of the integrals) and mirrors it once its last batch is built;
+ * (rows (a, c >= a) of the integrals against the packed column pairs (b <= d), since
+ * (ac|bd) = (ac|db)) and writes each entry and its mirror entry as it packs a batch;
  * an FP64 streaming plan builds upper-triangle steps as well (contracted as U and
  * U^T), other streaming plans build full rows. Plans that build upper triangles
  * first check (batch 0 or -1) that the virtual block of L is symmetric to a relative
@@ -402,7 +404,7 @@ int ppl_batch_contract(ppl_batch_t batch, const double* const* t2, double* const
 int ppl_batch_graph_capture(ppl_batch_t batch, const double* const* t2, double* const* R);
 /*
  * ppl_batch_graph_capture_build: record the whole evaluation of every instance into one graph
- * (replaces a previous one): the integral builds from L[k] (staging, build steps, mirror, one
+ * (replaces a previous one): the integral builds from L[k] (staging and build steps, one
  * instance after another on the batch stream) followed by the packing, the grouped
  * contraction and the unpacking of ppl_batch_contract. One replay
  * (ppl_batch_graph_launch) computes R_k = PPL_k(t2_k) from L and t2. L, t2, R: host arrays of
