@@ -24,17 +24,37 @@ PPL_HD inline int64_t cubes_of(int v, int a) {
   return nt * nt * (nt + 1) / 2;
 }
 
-// The r-th cube of a virtual with nt blocks: bi slowest, then (ci, di >= ci) row-major.
+// The r-th cube of a virtual with nt blocks. Cubes (x, ci, y) and (y, ci, x) stage the same
+// integrals (ac|bd) (rows c of block ci, pairs {b, d} with one index in block x and one in
+// block y), so they are taken one after the other: ci slowest; for each ci first the cubes
+// with bi < ci (no such partner), then the square bi, di >= ci by unordered pairs {x <= y},
+// (x, x) alone and (x, y), (y, x) together. nt (nt - ci) cubes per ci.
 PPL_HD inline void cube_decode(int64_t r, int nt, int& bi, int& ci, int& di) {
-  const int64_t per = (int64_t)nt * (nt + 1) / 2;
-  bi = (int)(r / per);
-  int q = (int)(r - (int64_t)bi * per);
+  int64_t q = r;
   ci = 0;
-  while (q >= nt - ci) {
-    q -= nt - ci;
+  while (q >= (int64_t)nt * (nt - ci)) {
+    q -= (int64_t)nt * (nt - ci);
     ++ci;
   }
-  di = ci + q;
+  const int w = nt - ci;
+  if (q < (int64_t)ci * w) {
+    bi = (int)(q / w);
+    di = ci + (int)(q % w);
+    return;
+  }
+  int p = (int)(q - (int64_t)ci * w), x = 0;
+  while (p >= 1 + 2 * (w - 1 - x)) {
+    p -= 1 + 2 * (w - 1 - x);
+    ++x;
+  }
+  if (p == 0) {
+    bi = di = ci + x;
+    return;
+  }
+  const int y = x + 1 + (p - 1) / 2;
+  const bool swap = (p - 1) % 2 != 0;
+  bi = ci + (swap ? y : x);
+  di = ci + (swap ? x : y);
 }
 
 // Virtual a of cube g given the prefix table off (off[a] = cubes of all virtuals below a),
